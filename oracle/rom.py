@@ -1,0 +1,162 @@
+"""FP64 oracle of one reduced-order-model time step (Section 3.2,
+Algorithm 2) with Lagrangian-quadrature kinematics (Algorithm 3), the
+sample-point full-space dynamics (Algorithm 5) and the projection
+(Algorithm 6 or 7); plus the least-squares initial latents (Section 3.1,
+eq. essentialSpecInt) and the error metrics of Section 5.
+
+TEST INFRASTRUCTURE ONLY.
+
+Readings:
+  - The neighbour test uses stencil membership: a point touches node i when
+    i is one of the 3^d nodes base..base+2 of its stencil (a node whose
+    quadratic B-spline weight is exactly zero at a support edge is still in
+    the stencil; its contribution is zero either way).
+  - Quadrature points carry the particle mass m_p and reference volume
+    V0_p = m_p / rho0 (Algorithm 3, last step) and no affine velocity
+    (Algorithm 5 uses the plain transfer).
+  - The grid boundary band of the full-order model applies to the substep.
+"""
+import numpy as np
+
+from . import decoder as _dec
+from . import mpm as _mpm
+from . import project as _proj
+from . import sampler as _sampler
+
+
+def stencil_bases(dx, x):
+    """Stencil base node per point and dimension: floor(x/dx - 0.5)."""
+    return np.floor(np.asarray(x, dtype=np.float64) / dx - 0.5).astype(np.int64)
+
+
+def _linear(n, ijk):
+    idx = ijk[..., -1]
+    for a in range(ijk.shape[-1] - 2, -1, -1):
+        idx = idx * n[a] + ijk[..., a]
+    return idx
+
+
+def _offsets(dim):
+    grids = np.meshgrid(*([np.arange(3)] * dim), indexing="ij")
+    return np.stack([g.reshape(-1) for g in grids], axis=1)
+
+
+def neighbour_set(dim, n, dx, x_all, samples):
+    """Algorithm 3, steps 2-3.  Returns (I, Q, N): the sorted active node
+    indices, the sorted quadrature-point indices (samples and neighbours),
+    and the sorted neighbour indices alone."""
+    base = stencil_bases(dx, x_all)
+    n_arr = np.asarray(n)
+    if np.any(base < 0) or np.any(base + 2 > n_arr - 1):
+        raise _mpm.OracleDomainError("decoded point outside the lattice")
+    offs = _offsets(dim)
+    samples = np.asarray(samples, dtype=np.int64)
+    marked = np.zeros(int(np.prod(n)), dtype=bool)
+    for o in offs:
+        marked[_linear(n, base[samples] + o)] = True
+    touches = np.zeros(x_all.shape[0], dtype=bool)
+    for o in offs:
+        touches |= marked[_linear(n, base + o)]
+    is_sample = np.zeros(x_all.shape[0], dtype=bool)
+    is_sample[samples] = True
+    N = np.nonzero(touches & ~is_sample)[0]
+    Q = np.nonzero(touches | is_sample)[0]
+    I = np.nonzero(marked)[0]
+    return I, Q, N
+
+
+def neighbour_set_bruteforce(dim, n, dx, x_all, samples):
+    """Same sets by direct pairwise comparison of stencils (small inputs)."""
+    base = stencil_bases(dx, x_all)
+    offs = [tuple(o) for o in _offsets(dim)]
+    I = set()
+    for p in samples:
+        for o in offs:
+            I.add(tuple(int(base[p][a] + o[a]) for a in range(dim)))
+    S = set(int(s) for s in samples)
+    N = []
+    for q in range(x_all.shape[0]):
+        if q in S:
+            continue
+        st = set(tuple(int(base[q][a] + o[a]) for a in range(dim)) for o in offs)
+        if st & I:
+            N.append(q)
+    Il = sorted(int(_linear(n, np.array(i))) for i in I)
+    return np.array(Il), np.array(sorted(S | set(N))), np.array(N)
+
+
+def substep(scene, x_Q, F_Q, v_Q, m_Q, V0_Q, x_samples, dt):
+    """Algorithm 5: P2G over the quadrature points, grid update, trial G2P
+    for the sample points.  Returns (x_trial, v_trial)."""
+    dim, n, dx = scene["dim"], scene["n"], scene["dx"]
+    Qn = x_Q.shape[0]
+    zeroC = np.zeros((Qn, dim, dim))
+    gm, gmv, gf = _mpm.p2g(dim, n, dx, x_Q, v_Q, zeroC, F_Q, m_Q, V0_Q,
+                           scene["model"], scene["mu"], scene["la"], apic=False)
+    gv = _mpm.grid_update(dim, n, dt, scene["gravity"], scene["bound"],
+                          scene["floor_mode"], scene["mu_f"], gm, gmv, gf)
+    S = x_samples.shape[0]
+    return _mpm.g2p(dim, n, dx, dt, gv, x_samples, np.zeros((S, dim)),
+                    np.zeros((S, dim, dim)), np.tile(np.eye(dim), (S, 1, 1)),
+                    apic=False, trial=True)
+
+
+def rom_step(dec, scene, X_all, m_all, V0_all, zhat, zhat_prev, vhat, dt,
+             samples, opts):
+    """One ROM step (Algorithm 2).  Returns (zhat_next, vhat_next, info)."""
+    dim, n, dx = scene["dim"], scene["n"], scene["dx"]
+    samples = np.asarray(samples, dtype=np.int64)
+    x_all = _dec.decode(dec, X_all, zhat)
+    I, Q, N = neighbour_set(dim, n, dx, x_all, samples)
+    xQ, FQ, JQ, vQ = _dec.decode_jac(dec, X_all[Q], zhat, vhat)
+    pos = np.searchsorted(Q, samples)
+    x_trial, v_trial = substep(scene, xQ, FQ, vQ, np.asarray(m_all)[Q],
+                               np.asarray(V0_all)[Q], xQ[pos], dt)
+    z, vh, it, f, status = _proj.project(dec, X_all[samples], x_trial, v_trial,
+                                         zhat, zhat_prev, dt, opts)
+    info = {"I": I, "Q": Q, "N": N, "x_trial": x_trial, "v_trial": v_trial,
+            "iters": it, "objective": f, "status": status}
+    return z, vh, info
+
+
+def rom_init(dec, X, V, opts, z0=None):
+    """Least-squares initial latents (eq. essentialSpecInt by point
+    quadrature): xhat_0 minimises sum ||X - g(X; z)||^2 by Gauss-Newton
+    from z0 (zero by default); vhat_0 minimises sum ||V - J(X; xhat_0) v||^2.
+    Returns (xhat_0, vhat_0, status)."""
+    r = dec.r
+    z0 = np.zeros(r) if z0 is None else np.asarray(z0, dtype=np.float64)
+    z, _, _, status = _proj.gauss_newton(dec, X, np.asarray(X, dtype=np.float64), z0, opts)
+    _, _, J, _ = _dec.decode_jac(dec, X, z)
+    vh = _proj.velocity_ls(J, V, opts.damping)
+    return z, vh, status
+
+
+def sample_indices(seed, instance, step, n_samples, n_particles):
+    return np.array(_sampler.stratified_samples(seed, instance, step, n_samples,
+                                                n_particles), dtype=np.int64)
+
+
+class ErrorAccumulator:
+    """Accumulates the error sums of Section 5 over steps, particles and
+    instances: the paper's position error 100 sqrt(sum|x_rom - x|^2) /
+    sqrt(sum|x|^2) and the displacement-relative error
+    sqrt(sum|x_rom - x|^2) / sqrt(sum|x - X|^2)."""
+
+    def __init__(self):
+        self.num = 0.0
+        self.den_pos = 0.0
+        self.den_disp = 0.0
+
+    def add(self, x_rom, x_full, X):
+        x_rom = np.asarray(x_rom, dtype=np.float64)
+        x_full = np.asarray(x_full, dtype=np.float64)
+        self.num += float(np.sum((x_rom - x_full) ** 2))
+        self.den_pos += float(np.sum(x_full ** 2))
+        self.den_disp += float(np.sum((x_full - np.asarray(X, dtype=np.float64)) ** 2))
+
+    def position_percent(self):
+        return 100.0 * np.sqrt(self.num) / np.sqrt(self.den_pos)
+
+    def displacement_relative(self):
+        return np.sqrt(self.num) / np.sqrt(self.den_disp)
