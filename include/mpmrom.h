@@ -1,0 +1,328 @@
+/*
+ * mpmrom.h -- C ABI of libmpmrom.so, the MI355X (gfx950) implementation of
+ * the explicit material point method step and of the reduced-order model
+ * built on an implicit neural representation of the deformation map
+ * (Chen, Chiaramonte, Grinspun, Carlberg, "Model reduction for the material
+ * point method via an implicit neural representation of the deformation
+ * map", arXiv 2109.12390).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status.  Every function returns an int32 status: MR_OK (0) or a negative
+ *   MR_E* code.  MR_EINVAL: null pointer, bad size or enum, detected on the
+ *   host before anything is enqueued.  MR_EDEVICE: a HIP call failed.
+ *   Conditions found by the kernels themselves (a particle outside the node
+ *   lattice, a non-positive volume ratio, a singular normal matrix) are
+ *   asynchronous: they are OR-ed as MR_FLAG_* bits into a caller-provided
+ *   device int32 word (`status_flag`, nullable), which the caller reads after
+ *   synchronising the stream.
+ * Streams.  `stream` is a hipStream_t passed as void*; NULL is the null
+ *   stream.  Every call only enqueues work on that stream and returns; it
+ *   never synchronises, except the *_create functions (which copy
+ *   parameters to the device) and mr_sync_status.
+ * Memory.  Array arguments are device pointers owned by the caller (for
+ *   example PyTorch tensors); the library never frees or retains them past
+ *   the call.  Handles (mr_decoder, mr_rom) are owned by the library:
+ *   created by *_create, released by *_destroy.  Handles are not thread safe;
+ *   calls on one handle must be ordered on one stream.
+ * Layout.  Particle arrays are structure-of-arrays float32, component-major:
+ *   x[a*n + p]; d x d matrices are row-major per particle:
+ *   F[(a*d + b)*n + p].  The background grid is dense, node-major, 4 floats
+ *   per node: grid[4*i + c], c = 0 mass, c = 1..d momentum (after
+ *   mpm_p2g) or velocity (after mpm_grid_update); node (i, j, k) has linear
+ *   index i + n0*(j + n1*k) and sits at (i, j, k) * dx.  Latent vectors are
+ *   float64, instance-major [B][r].  Index lists are int32.
+ */
+#ifndef MPMROM_H
+#define MPMROM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes and device flag bits -------------------------------- */
+#define MR_OK 0
+#define MR_EINVAL (-1)
+#define MR_ENOMEM (-2)
+#define MR_EDEVICE (-3)
+#define MR_ESINGULAR (-4)
+#define MR_ENOCONV (-5)
+#define MR_EDOMAIN (-6)
+
+#define MR_FLAG_DOMAIN 1     /* stencil left the lattice, NaN, or J <= 0    */
+#define MR_FLAG_SINGULAR 2   /* Cholesky of a normal matrix failed          */
+#define MR_FLAG_NOCONV 4     /* Gauss-Newton step above tolerance at exit   */
+#define MR_FLAG_LINESEARCH 8 /* no step length passed the Armijo test       */
+
+/* ---- enums ------------------------------------------------------------- */
+#define MR_FLOOR_STICKY 0        /* every face of the boundary band sticky  */
+#define MR_FLOOR_COULOMB 1       /* low-y face Coulomb friction, rest sticky */
+#define MR_FIXED_COROTATED 0     /* 2D only                                  */
+#define MR_NEO_HOOKEAN 1
+
+/* mpm_p2g / mpm_g2p flags */
+#define MR_NO_AFFINE 1   /* plain (PIC) transfer: no C_p term / C_p := 0     */
+#define MR_ACCUMULATE 2  /* p2g: add into `grid` instead of overwriting it   */
+#define MR_TRIAL 4       /* g2p: write x_trial, v_trial; leave particles     */
+#define MR_NO_F_UPDATE 8 /* g2p: keep F_p                                    */
+#define MR_SORTED 16     /* p2g: particles are cell-sorted by mpm_cell_sort;
+                            enables the LDS-tiled scatter                    */
+
+/* decoder enums */
+#define MR_OUT_POSITION 0
+#define MR_OUT_DISPLACEMENT 1
+#define MR_PREC_FP32 0
+#define MR_PREC_BF16 1
+
+/* projection modes */
+#define MR_POS_VEL 0  /* Algorithm 6: velocity least squares + Gauss-Newton  */
+#define MR_VEL_ONLY 1 /* Algorithm 7: velocity least squares, x += dt v      */
+
+/* ---- plain descriptors -------------------------------------------------- */
+typedef struct {
+    int32_t dim;        /* 2 or 3                                              */
+    int32_t n[3];       /* nodes per dimension (n[2] ignored when dim == 2)   */
+    float dx;           /* node spacing                                        */
+    int32_t bound;      /* boundary band width in nodes (0 = no walls)         */
+    int32_t floor_mode; /* MR_FLOOR_STICKY or MR_FLOOR_COULOMB                 */
+    float mu_friction;  /* Coulomb coefficient of the floor                    */
+    float gravity[3];   /* body acceleration g                                 */
+} mr_grid;
+
+typedef struct {
+    int32_t model; /* MR_FIXED_COROTATED (dim 2) or MR_NEO_HOOKEAN           */
+    float E, nu;   /* Young's modulus and Poisson ratio                      */
+} mr_material;
+
+typedef struct {
+    int64_t n;            /* number of particles                              */
+    float *x, *v, *C, *F; /* device SoA arrays (C may be NULL with MR_NO_AFFINE) */
+    const float *m;       /* per-particle mass, or NULL to use m_uniform      */
+    const float *V0;      /* per-particle reference volume, or NULL           */
+    float m_uniform, V0_uniform;
+} mr_particles;
+
+/* ---- full-order MPM (paper Section 2.2, Algorithm 1) -------------------- */
+
+/* Particle-to-grid transfer (Algorithm 1, first step; Algorithm 5, first
+ * step, over quadrature points).  For the listed particles (all when
+ * subset == NULL) adds into node i
+ *   grid[4i]     += N_i(x_p) m_p
+ *   grid[4i+1+a] += N_i(x_p) m_p (v_p + C_p (x_i - x_p))_a
+ *                   - dt V0_p (tau_p grad N_i(x_p))_a
+ * where N is the quadratic B-spline, tau = P F^T the Kirchhoff stress of the
+ * material (so the internal force f^sigma of Algorithm 1 is folded into the
+ * momentum, scaled by dt) and the C_p term is the affine (APIC) transfer,
+ * dropped with MR_NO_AFFINE.  The grid is zeroed first unless
+ * MR_ACCUMULATE.  MR_SORTED requires that mpm_cell_sort ran on these
+ * particles with this grid (any later motion is handled).  Particles whose
+ * stencil leaves the lattice, or with J <= 0 under Neo-Hookean, are skipped
+ * and raise MR_FLAG_DOMAIN.  `workspace` (nullable unless MR_SORTED) must
+ * hold mpm_workspace_bytes(grid, n) bytes of device memory. */
+int32_t mpm_p2g(const mr_grid *grid_desc, const mr_material *mat,
+                const mr_particles *parts, const int32_t *subset,
+                int64_t n_subset, float dt, float *grid, int32_t flags,
+                void *workspace, int32_t *status_flag, void *stream);
+
+/* Grid update (Algorithm 1, second step): for nodes with mass,
+ *   v_i = grid[4i+1..]/m_i + dt g,
+ * then the boundary band (sticky faces set v = 0; the Coulomb floor
+ * projects v when it points into the floor).  Nodes without mass get v = 0.
+ * Converts grid momentum to velocity in place.  active (nullable) lists the
+ * n_active node indices to update; NULL updates every node. */
+int32_t mpm_grid_update(const mr_grid *grid_desc, float dt, float *grid,
+                        const int32_t *active, int64_t n_active, void *stream);
+
+/* Grid-to-particle transfer and advection (Algorithm 1, third and fourth
+ * steps):  v_p = sum_i N_i v_i;  C_p = (4/dx^2) sum_i N_i v_i (x_i - x_p)^T
+ * (0 with MR_NO_AFFINE);  F_p <- (I + dt sum_i v_i (x) grad N_i) F_p (kept
+ * with MR_NO_F_UPDATE);  x_p <- x_p + dt v_p, all at the old x_p.
+ * MR_TRIAL (Algorithm 5, last two steps): only writes
+ * v_trial[a*n_subset + s] = v_p and x_trial[a*n_subset + s] = x_p + dt v_p
+ * for the listed particles. */
+int32_t mpm_g2p(const mr_grid *grid_desc, mr_particles *parts,
+                const int32_t *subset, int64_t n_subset, float dt,
+                const float *grid, int32_t flags, float *x_trial,
+                float *v_trial, int32_t *status_flag, void *stream);
+
+/* Cell sort: reorders the particle arrays (x, v, C, F, and m / V0 when
+ * per-particle -- those are written through as well, so the caller must own
+ * them writable) so that particles are grouped by stencil base cell
+ * floor(x/dx - 0.5), cells in the tile-major order used by the sorted P2G,
+ * ties in their previous order (a stable sort).  perm_out (nullable, n
+ * int32) receives the old index of each new slot.  workspace: see
+ * mpm_workspace_bytes. */
+int32_t mpm_cell_sort(const mr_grid *grid_desc, mr_particles *parts,
+                      int32_t *perm_out, void *workspace, int32_t *status_flag,
+                      void *stream);
+
+/* Device workspace bytes needed by mpm_cell_sort and the sorted P2G for a
+ * grid and n particles. */
+int64_t mpm_workspace_bytes(const mr_grid *grid_desc, int64_t n);
+
+/* n_steps full-order steps (Algorithm 1 with the affine transfer unless
+ * MR_NO_AFFINE in flags): every sort_every steps (0: never) the particles
+ * are cell-sorted, and P2G uses the sorted tiled scatter.  grid: device
+ * scratch of 4 * nodes floats (holds the last grid velocities on return);
+ * workspace: mpm_step_workspace_bytes(grid, n) bytes.  perm_accum
+ * (nullable, n int32) receives, for every array slot on return, the index
+ * that particle had on entry.  Particles end with x, v, C, F of the last
+ * step. */
+int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
+                 mr_particles *parts, float dt, int32_t n_steps,
+                 int32_t sort_every, int32_t flags, float *grid,
+                 void *workspace, int32_t *perm_accum, int32_t *status_flag,
+                 void *stream);
+int64_t mpm_step_workspace_bytes(const mr_grid *grid_desc, int64_t n);
+
+/* Sort key of each particle in the order mpm_cell_sort produces
+ * (keys_out: n int32; -1 for particles outside the lattice). */
+int32_t mpm_cell_keys(const mr_grid *grid_desc, const mr_particles *parts,
+                      int32_t *keys_out, void *stream);
+
+/* ---- neural deformation-map decoder (Sections 3.1 and 4) --------------- */
+
+typedef struct mr_decoder mr_decoder;
+
+/* Creates a decoder g(X; xhat) = X + mean + std * y (MR_OUT_DISPLACEMENT) or
+ * mean + std * y (MR_OUT_POSITION), y the output of an MLP with n_hidden ELU
+ * layers of `width` units on the input [2 (X - in_min)/(in_max - in_min) - 1,
+ * xhat] (paper Section 4 network, Appendix B feature scaling).  params is a
+ * host float32 array [W_0 (width x (d+r), row-major), b_0, W_1, b_1, ...,
+ * W_L (d x width), b_L]; in_min, in_max, out_mean, out_std are host arrays of
+ * d floats.  precision MR_PREC_BF16 runs the width x width hidden layers on
+ * bf16 matrix cores with fp32 accumulation (first and last layers and all
+ * activations stay fp32); MR_PREC_FP32 runs every layer in fp32.
+ * Synchronous.  width <= 256, 1 <= n_hidden <= 8, d in {2, 3}, r <= 32. */
+int32_t rom_decoder_create(int32_t d, int32_t r, int32_t width,
+                           int32_t n_hidden, const float *params,
+                           const float *in_min, const float *in_max,
+                           const float *out_mean, const float *out_std,
+                           int32_t output_mode, int32_t precision,
+                           mr_decoder **out);
+void rom_decoder_destroy(mr_decoder *dec);
+
+/* Replaces the parameters of an existing decoder (same shapes); params is a
+ * device or host pointer as flagged by `params_on_device`.  Stream-ordered
+ * when on device. */
+int32_t rom_decoder_set_params(mr_decoder *dec, const float *params,
+                               int32_t params_on_device, void *stream);
+
+/* Kinematic restriction x = g(X; xhat) (Section 3.1, eq. kinematicRestriction)
+ * for B instances sharing the reference points.  X: device SoA [d][n_ref];
+ * idx (nullable): n int32 row indices into X (NULL: n == n_ref, row s).
+ * xhat: device float64 [B][r].  x_out: device float32 [B][d][n]. */
+int32_t rom_decode(const mr_decoder *dec, int32_t B, int64_t n_ref,
+                   const float *X, int64_t n, const int32_t *idx,
+                   const double *xhat, float *x_out, void *stream);
+
+/* Decoder with derivatives at the same points: x = g (nullable),
+ * F = dg/dX (Section 3.1, eq. defGrad; [B][d*d][n], nullable),
+ * v = (dg/dxhat) vhat (eq. timederOne; [B][d][n], nullable, needs vhat),
+ * Jz = dg/dxhat ([B][d*r][n], entry (a, k) at (a*r + k)*n + s; nullable).
+ * idx_per_instance != 0 means idx is [B][n] (one point list per instance). */
+int32_t rom_decode_jac(const mr_decoder *dec, int32_t B, int64_t n_ref,
+                       const float *X, int64_t n, const int32_t *idx,
+                       int32_t idx_per_instance, const double *xhat,
+                       const double *vhat, float *x, float *F, float *v,
+                       float *Jz, void *stream);
+
+/* ---- projection (Section 3.2.4, Algorithms 6 and 7) -------------------- */
+
+typedef struct {
+    int32_t mode;          /* MR_POS_VEL or MR_VEL_ONLY                        */
+    int32_t max_iter;      /* Gauss-Newton iterations (fixed count)            */
+    int32_t max_backtrack; /* halvings of the step in the Armijo search        */
+    double armijo_c;       /* sufficient-decrease constant                     */
+    double damping;        /* added to the normal-matrix diagonal (0: none)    */
+    double tol_step;       /* MR_FLAG_NOCONV when the last step exceeds
+                              tol_step (1 + |xhat|); <= 0 disables the test  */
+} mr_gn_opts;
+
+/* Reduced-space dynamics for B instances with ns sample points each
+ * (ns_per_instance, nullable device int32 [B], may lower the count per
+ * instance):  vhat_{n+1} = argmin sum_p |dg/dxhat(X_p; xhat_n) v - v_trial_p|^2
+ * by the normal equations and an fp64 Cholesky factorisation; with
+ * MR_POS_VEL, xhat_{n+1} = argmin sum_p |g(X_p; z) - x_trial_p|^2 by
+ * max_iter Gauss-Newton iterations from 2 xhat_n - xhat_prev, each with an
+ * Armijo backtracking search (a step that no length passes is discarded and
+ * raises MR_FLAG_LINESEARCH); with MR_VEL_ONLY, xhat_{n+1} = xhat_n + dt
+ * vhat_{n+1}.  sample_idx: device int32 [B][ns] rows of X; x_trial, v_trial:
+ * device float32 [B][d][ns]; latents device float64 [B][r]; iters_out and
+ * status_out device int32 [B], resid_out device float64 [B] (half the
+ * squared position residual at exit), all nullable.  A singular normal
+ * matrix leaves that instance's xhat_next = xhat_n, vhat_next = 0 and raises
+ * MR_FLAG_SINGULAR. */
+int32_t rom_project(const mr_decoder *dec, int32_t B, int64_t n_ref,
+                    const float *X, int64_t ns, const int32_t *sample_idx,
+                    const int32_t *ns_per_instance, const float *x_trial,
+                    const float *v_trial, const double *xhat_n,
+                    const double *xhat_prev, double dt, const mr_gn_opts *opts,
+                    double *xhat_next, double *vhat_next, int32_t *iters_out,
+                    double *resid_out, int32_t *status_out, void *stream);
+
+/* ---- reduced-order step (Section 3.2, Algorithm 2 with Algorithms 3, 5 and
+ * 6 or 7) ----------------------------------------------------------------- */
+
+typedef struct mr_rom mr_rom;
+
+typedef struct {
+    int32_t B;               /* parameter instances                          */
+    int64_t n_particles;     /* reference particles P                        */
+    int32_t n_samples_max;   /* largest sample count                         */
+    uint64_t seed;           /* sampler seed                                 */
+    float rho0;              /* reference density (V0 = m / rho0)            */
+    float m_uniform;         /* particle mass when m_all is NULL             */
+    int32_t model;           /* constitutive model                           */
+    float nu;                /* Poisson ratio (shared)                       */
+    int32_t sort_quadrature; /* non-zero: cell-sort the quadrature points    */
+} mr_rom_config;
+
+/* Creates the reduced-order model runner.  X_all: device SoA [d][P] reference
+ * positions; m_all (nullable) device masses; E: device float32 [B] Young's
+ * moduli; n_samples: device int32 [B] sample counts (r/d <= count <=
+ * n_samples_max).  The decoder, grid and option structs are copied.
+ * Allocates all workspace up front (synchronous). */
+int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
+                   const mr_rom_config *cfg, const float *X_all,
+                   const float *m_all, const float *E,
+                   const int32_t *n_samples, const mr_gn_opts *opts,
+                   mr_rom **out);
+void rom_destroy(mr_rom *rom);
+
+/* Advances every instance n_steps reduced-order steps of size dt, starting
+ * at step counter `step0` (the sampler's stream index): for each step, draw
+ * the sample points, decode every particle, mark the active nodes of the
+ * samples' stencils, collect the neighbour particles touching them
+ * (Algorithm 3), evaluate x, F, v at the quadrature points, run the
+ * sample-point MPM substep (Algorithm 5) and project (Algorithm 6 or 7).
+ * xhat, xhat_prev, vhat: device float64 [B][r], updated in place.
+ * status_out: device int32 [B] (nullable), OR of MR_FLAG_* over the steps.
+ * When use_graph != 0 the per-step launches are captured once into a HIP
+ * graph and replayed.  No host synchronisation inside. */
+int32_t rom_step(mr_rom *rom, int32_t n_steps, int64_t step0, double dt,
+                 double *xhat, double *xhat_prev, double *vhat,
+                 int32_t *status_out, int32_t use_graph, void *stream);
+
+/* Diagnostics of the last step of instance b: quadrature-point count |Q|
+ * and active-node count |I| (device values copied to the host; this call
+ * synchronises the stream). */
+int32_t rom_last_counts(const mr_rom *rom, int32_t b, int64_t *n_quad,
+                        int64_t *n_active, void *stream);
+
+/* Reads n device status words into host memory after synchronising the
+ * stream; returns the OR of their bits mapped to the first MR_E* code
+ * (MR_EDOMAIN, MR_ESINGULAR, MR_ENOCONV in that priority) or MR_OK. */
+int32_t mr_sync_status(void *stream, const int32_t *device_flags, int32_t n,
+                       int32_t *host_flags);
+
+/* Library version string (static storage). */
+const char *mr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPMROM_H */

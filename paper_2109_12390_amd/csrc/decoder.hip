@@ -1,0 +1,653 @@
+// Neural deformation-map decoder g(X; xhat) with forward-mode derivatives on
+// gfx950 matrix cores (paper Section 3.1, eqs. kinematicRestriction, defGrad
+// and timederOne; Section 4 network: MLP with ELU).
+//
+// One wave evaluates NP x 16 points of one instance together with S - 1
+// tangent streams per point (directions e_a in X for F = dg/dX, vhat for
+// v = (dg/dxhat) vhat, e_k in xhat for the latent Jacobian).  A column of the
+// wave's activation panel is one (point, stream) pair; the panel lives in LDS
+// as [column][unit] (unit-contiguous, row stride padded against bank
+// conflicts).  The width x width hidden layers are 16x16 MFMA tiles:
+//   bf16 operands with fp32 accumulation (v_mfma_f32_16x16x32_bf16), or
+//   fp32 operands (v_mfma_f32_16x16x4_f32) in the fp32 precision mode.
+// The first layer (d + r inputs, folded as W_X Xn + (W_z xhat + b) with the
+// latent part computed once per instance) and the last layer (width -> d),
+// the ELU and its derivative, stay in fp32 vector arithmetic.  Tangents
+// obey t' = ELU'(z) (W t), with z the primal pre-activation of the same
+// point, which the MFMA output layout places in the same lane and register.
+#include "internal.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct mr_decoder {
+    int d, r, width, W, nh, mode, prec;
+    float *dev;          // padded fp32 parameters (one allocation)
+    uint16_t *hid_bf16;  // hidden weights in bf16, (nh - 1) x W x W
+    size_t n_params;     // unpadded parameter count
+    float *staging;      // device copy of unpadded params for set_params
+    float scale[3], shift[3], mean[3], stdv[3];
+    // offsets (floats) inside dev
+    size_t oW0, ob0, oWh, obh, oWL, obL;
+};
+
+namespace mr {
+
+enum StreamKind { SK_PRIMAL = 0, SK_SPATIAL = 1, SK_VELOCITY = 2, SK_LATENT = 3, SK_ZERO = 4 };
+
+constexpr int MAXS = 9;
+
+struct DecK {
+    int d, r, W, nh, mode;
+    const float *W0, *b0, *Wh, *bh, *WL, *bL;
+    const uint16_t *Whb;
+    float scale[3], shift[3], mean[3], stdv[3];
+};
+
+struct StreamSpec {
+    int kind[MAXS];
+    int arg[MAXS];
+};
+
+struct DecIO {
+    int B;
+    int64_t n_ref, n;
+    const float *X;
+    const int32_t *idx;
+    int idx_per_inst;
+    int idx_div;  // idx row of instance b is b / idx_div (when idx_per_inst)
+    const int32_t *n_inst;  // nullable: points s >= n_inst[b] are skipped
+    const double *xhat, *vhat;
+    float *x, *F, *v, *Jz;
+    int jz_k0;  // first latent index of this launch's latent streams
+};
+
+__device__ __forceinline__ float elu(float z) { return z > 0.0f ? z : expm1f(z); }
+__device__ __forceinline__ float elu_d(float z) { return z > 0.0f ? 1.0f : expf(z); }
+
+// round-to-nearest-even fp32 -> bf16 bit pattern (finite inputs)
+__host__ __device__ __forceinline__ uint16_t bf16_bits(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+template <typename T>
+struct Elem;
+template <>
+struct Elem<float> {
+    static constexpr int KS = 4;    // k per MFMA
+    static constexpr int PAD = 4;   // row padding (elements)
+    __device__ static float make(float f) { return f; }
+    __device__ static float load_f(const float *p) { return *p; }
+};
+template <>
+struct Elem<uint16_t> {
+    static constexpr int KS = 32;
+    static constexpr int PAD = 8;
+    __device__ static uint16_t make(float f) { return bf16_bits(f); }
+    __device__ static float load_f(const uint16_t *p)
+    {
+        uint32_t u = ((uint32_t)*p) << 16;
+        float f;
+        memcpy(&f, &u, 4);
+        return f;
+    }
+};
+
+// One MFMA k-step: acc += A(16 x KS) * B(KS x 16).
+//  fp32:  lane l holds A[l%16][k0 + l/16], B[k0 + l/16][l%16]
+//  bf16:  lane l holds A[l%16][k0 + 8(l/16) + 0..7], B[k0 + 8(l/16) + 0..7][l%16]
+// A row-major in global memory (row stride W), B from the LDS panel
+// (column-major: B[k][j] at Hc[j*ld + k]).
+__device__ __forceinline__ f32x4 mfma_step(const float *Arow, const float *Bcol, f32x4 acc,
+                                           int lane)
+{
+    int g = lane >> 4;
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(Arow[g], Bcol[g], acc, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_step(const uint16_t *Arow, const uint16_t *Bcol, f32x4 acc,
+                                           int lane)
+{
+    int g = lane >> 4;
+    bf16x8 a = *reinterpret_cast<const bf16x8 *>(Arow + 8 * g);
+    bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bcol + 8 * g);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+}
+
+template <typename T, int W, int S, int NP, bool DB>
+__global__ void __launch_bounds__(256) decoder_kernel(DecK P, StreamSpec ss, DecIO io)
+{
+    using E = Elem<T>;
+    constexpr int NCT = NP * S;          // column tiles per wave
+    constexpr int COLS = NCT * 16;       // columns per wave
+    constexpr int LD = W + E::PAD;       // panel row stride
+    constexpr int NRT = W / 16;          // row tiles
+    constexpr int NKS = W / E::KS;       // k-steps per row tile
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int b = blockIdx.y;
+    const int64_t n_b = io.n_inst ? (int64_t)io.n_inst[b] : io.n;
+    // a block entirely past this instance's points leaves before any barrier
+    if ((int64_t)blockIdx.x * nwaves * (NP * 16) >= n_b) return;
+    // per-instance vectors: c0 = W_z xhat + b0, u = W_z vhat
+    float *c0 = reinterpret_cast<float *>(smem);
+    float *u = c0 + W;
+    T *panel = reinterpret_cast<T *>(smem + 2 * W * sizeof(float)) +
+               (size_t)wave * (DB ? 2 : 1) * COLS * LD;
+    T *pin = panel;
+    T *pout = DB ? panel + COLS * LD : panel;
+    const double *xh = io.xhat + (size_t)b * P.r;
+    const double *vh = io.vhat ? io.vhat + (size_t)b * P.r : nullptr;
+    for (int i = threadIdx.x; i < W; i += blockDim.x) {
+        double s0 = P.b0[i], s1 = 0.0;
+        for (int k = 0; k < P.r; ++k) {
+            double w = P.W0[(size_t)i * (P.d + P.r) + P.d + k];
+            s0 += w * xh[k];
+            if (vh) s1 += w * vh[k];
+        }
+        c0[i] = (float)s0;
+        u[i] = (float)s1;
+    }
+    __syncthreads();
+
+    // ---- first layer: lane handles point column j = lane % 16 of each point
+    // tile, units i = lane/16 + 4 m
+    const int64_t wbase = ((int64_t)blockIdx.x * nwaves + wave) * (NP * 16);
+    const int j = lane & 15;
+    const int g = lane >> 4;
+#pragma unroll
+    for (int pt = 0; pt < NP; ++pt) {
+        int64_t s = wbase + pt * 16 + j;
+        float Xn[3] = {0.0f, 0.0f, 0.0f};
+        if (s < n_b) {
+            int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * io.n : 0) + s] : s;
+            for (int a = 0; a < P.d; ++a) Xn[a] = io.X[a * io.n_ref + row] * P.scale[a] + P.shift[a];
+        }
+        for (int i = g; i < W; i += 4) {
+            const float *w0 = P.W0 + (size_t)i * (P.d + P.r);
+            float z = c0[i];
+            for (int a = 0; a < P.d; ++a) z += w0[a] * Xn[a];
+            float h = elu(z), e = elu_d(z);
+#pragma unroll
+            for (int st = 0; st < S; ++st) {
+                float val;
+                int kind = ss.kind[st], arg = ss.arg[st];
+                if (kind == SK_PRIMAL) val = h;
+                else if (kind == SK_SPATIAL) val = e * w0[arg] * P.scale[arg];
+                else if (kind == SK_VELOCITY) val = e * u[i];
+                else if (kind == SK_LATENT) val = e * w0[P.d + arg];
+                else val = 0.0f;
+                pin[((pt * S + st) * 16 + j) * LD + i] = E::make(val);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- hidden layers on matrix cores
+    for (int l = 0; l < P.nh - 1; ++l) {
+        const T *Wl;
+        if constexpr (sizeof(T) == 2)
+            Wl = reinterpret_cast<const T *>(P.Whb) + (size_t)l * W * W;
+        else
+            Wl = reinterpret_cast<const T *>(P.Wh) + (size_t)l * W * W;
+        const float *bl = P.bh + (size_t)l * W;
+        if constexpr (!DB) {
+            f32x4 acc[NRT][NCT];
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < NCT; ++ct) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt) {
+                const T *Arow = Wl + (size_t)(rt * 16 + j) * W;
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+                    for (int ct = 0; ct < NCT; ++ct)
+                        acc[rt][ct] = mfma_step(Arow + ks * E::KS,
+                                                pin + (ct * 16 + j) * LD + ks * E::KS, acc[rt][ct],
+                                                lane);
+            }
+            __syncthreads();  // every wave finished reading its panel
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    int i = rt * 16 + 4 * g + q;
+                    float bi = bl[i];
+#pragma unroll
+                    for (int pt = 0; pt < NP; ++pt) {
+                        float z = acc[rt][pt * S][q] + bi;
+                        float e = elu_d(z);
+                        pout[((pt * S) * 16 + j) * LD + i] = E::make(elu(z));
+#pragma unroll
+                        for (int st = 1; st < S; ++st)
+                            pout[((pt * S + st) * 16 + j) * LD + i] =
+                                E::make(e * acc[rt][pt * S + st][q]);
+                    }
+                }
+        } else {
+#pragma unroll 1
+            for (int rt = 0; rt < NRT; ++rt) {
+                f32x4 acc[NCT];
+#pragma unroll
+                for (int ct = 0; ct < NCT; ++ct) acc[ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                const T *Arow = Wl + (size_t)(rt * 16 + j) * W;
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+                    for (int ct = 0; ct < NCT; ++ct)
+                        acc[ct] = mfma_step(Arow + ks * E::KS,
+                                            pin + (ct * 16 + j) * LD + ks * E::KS, acc[ct], lane);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    int i = rt * 16 + 4 * g + q;
+                    float bi = bl[i];
+#pragma unroll
+                    for (int pt = 0; pt < NP; ++pt) {
+                        float z = acc[pt * S][q] + bi;
+                        float e = elu_d(z);
+                        pout[((pt * S) * 16 + j) * LD + i] = E::make(elu(z));
+#pragma unroll
+                        for (int st = 1; st < S; ++st)
+                            pout[((pt * S + st) * 16 + j) * LD + i] = E::make(e * acc[pt * S + st][q]);
+                    }
+                }
+            }
+            T *tmp = pin;
+            pin = pout;
+            pout = tmp;
+        }
+        __syncthreads();
+    }
+
+    // ---- output layer (fp32): y_a = WL[a] . h (+ bL[a] for the primal)
+    const int D = P.d;
+    const int total = NCT * 16 * D;
+    for (int it = lane; it < total; it += 64) {
+        int col = it / D, a = it % D;
+        int ct = col >> 4, jj = col & 15;
+        int pt = ct / S, st = ct % S;
+        int64_t s = wbase + pt * 16 + jj;
+        if (s >= n_b) continue;
+        const T *h = pin + (size_t)col * LD;
+        const float *wl = P.WL + (size_t)a * W;
+        float y = 0.0f;
+        for (int i = 0; i < W; ++i) y += wl[i] * E::load_f(h + i);
+        int kind = ss.kind[st], arg = ss.arg[st];
+        const int64_t n = io.n;
+        const size_t bo = (size_t)b;
+        if (kind == SK_PRIMAL) {
+            if (io.x) {
+                float val = P.mean[a] + P.stdv[a] * (y + P.bL[a]);
+                if (P.mode == MR_OUT_DISPLACEMENT) {
+                    int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * n : 0) + s] : s;
+                    val += io.X[a * io.n_ref + row];
+                }
+                io.x[(bo * D + a) * n + s] = val;
+            }
+        } else if (kind == SK_SPATIAL) {
+            if (io.F) {
+                float val = P.stdv[a] * y + ((P.mode == MR_OUT_DISPLACEMENT && a == arg) ? 1.0f : 0.0f);
+                io.F[(bo * D * D + a * D + arg) * n + s] = val;
+            }
+        } else if (kind == SK_VELOCITY) {
+            if (io.v) io.v[(bo * D + a) * n + s] = P.stdv[a] * y;
+        } else if (kind == SK_LATENT) {
+            if (io.Jz) io.Jz[(bo * D * P.r + (size_t)a * P.r + arg) * n + s] = P.stdv[a] * y;
+        }
+    }
+}
+
+template <typename T, int W, int S, int NP, bool DB>
+int32_t launch_one(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStream_t st)
+{
+    using E = Elem<T>;
+    constexpr int COLS = NP * S * 16;
+    size_t per_wave = (size_t)(DB ? 2 : 1) * COLS * (W + E::PAD) * sizeof(T);
+    size_t fixed = 2 * W * sizeof(float);
+    const size_t budget = 150 * 1024;
+    int wpb = (int)((budget - fixed) / per_wave);
+    if (wpb > 4) wpb = 4;
+    if (wpb < 1) return MR_EINVAL;
+    size_t lds = fixed + (size_t)wpb * per_wave;
+    int64_t pts_per_block = (int64_t)wpb * NP * 16;
+    dim3 grid((unsigned)ceil_div(io.n, pts_per_block), (unsigned)io.B);
+    auto kern = decoder_kernel<T, W, S, NP, DB>;
+    static bool attr_set = false;  // the LDS size of an instantiation is fixed
+    if (!attr_set) {
+        MR_CHECK_HIP(hipFuncSetAttribute((const void *)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    kern<<<grid, 64 * wpb, lds, st>>>(P, ss, io);
+    MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
+template <typename T, int W>
+int32_t launch_w(int cfg, const DecK &P, const StreamSpec &ss, const DecIO &io, hipStream_t st)
+{
+    if (cfg == 1) return launch_one<T, W, 1, 4, false>(P, ss, io, st);
+    if (cfg == 5) return launch_one<T, W, 5, 1, false>(P, ss, io, st);
+    return launch_one<T, W, 9, 1, true>(P, ss, io, st);
+}
+
+int32_t launch_cfg(const mr_decoder *dec, int cfg, const StreamSpec &ss, const DecIO &io,
+                   hipStream_t st)
+{
+    DecK P;
+    P.d = dec->d;
+    P.r = dec->r;
+    P.W = dec->W;
+    P.nh = dec->nh;
+    P.mode = dec->mode;
+    P.W0 = dec->dev + dec->oW0;
+    P.b0 = dec->dev + dec->ob0;
+    P.Wh = dec->dev + dec->oWh;
+    P.bh = dec->dev + dec->obh;
+    P.WL = dec->dev + dec->oWL;
+    P.bL = dec->dev + dec->obL;
+    P.Whb = dec->hid_bf16;
+    for (int a = 0; a < 3; ++a) {
+        P.scale[a] = dec->scale[a];
+        P.shift[a] = dec->shift[a];
+        P.mean[a] = dec->mean[a];
+        P.stdv[a] = dec->stdv[a];
+    }
+    bool bf = dec->prec == MR_PREC_BF16;
+    switch (dec->W) {
+    case 16: return bf ? launch_w<uint16_t, 16>(cfg, P, ss, io, st) : launch_w<float, 16>(cfg, P, ss, io, st);
+    case 32: return bf ? launch_w<uint16_t, 32>(cfg, P, ss, io, st) : launch_w<float, 32>(cfg, P, ss, io, st);
+    case 64: return bf ? launch_w<uint16_t, 64>(cfg, P, ss, io, st) : launch_w<float, 64>(cfg, P, ss, io, st);
+    case 128: return bf ? launch_w<uint16_t, 128>(cfg, P, ss, io, st) : launch_w<float, 128>(cfg, P, ss, io, st);
+    default: return MR_EINVAL;
+    }
+}
+
+// --- parameter packing: unpadded [W0, b0, W1, b1, ..., WL, bL] -> padded
+__global__ void pack_params_kernel(const float *src, float *dst, uint16_t *hid, int d, int r,
+                                   int width, int W, int nh, size_t oW0, size_t ob0, size_t oWh,
+                                   size_t obh, size_t oWL, size_t obL)
+{
+    const int in0 = d + r;
+    size_t total = (size_t)W * in0 + W + (size_t)(nh - 1) * (W * W + W) + (size_t)d * W + d;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (size_t)gridDim.x * blockDim.x) {
+        size_t q = t;
+        // source layout offsets
+        size_t s_W0 = 0, s_b0 = (size_t)width * in0;
+        size_t s_h = s_b0 + width;
+        size_t hsz = (size_t)width * width + width;
+        size_t s_WL = s_h + (size_t)(nh - 1) * hsz, s_bL = s_WL + (size_t)d * width;
+        float val = 0.0f;
+        if (q < (size_t)W * in0) {
+            int i = (int)(q / in0), k = (int)(q % in0);
+            if (i < width) val = src[s_W0 + (size_t)i * in0 + k];
+            dst[oW0 + q] = val;
+            continue;
+        }
+        q -= (size_t)W * in0;
+        if (q < (size_t)W) {
+            if ((int)q < width) val = src[s_b0 + q];
+            dst[ob0 + q] = val;
+            continue;
+        }
+        q -= W;
+        if (q < (size_t)(nh - 1) * W * W) {
+            int l = (int)(q / ((size_t)W * W));
+            size_t rem = q % ((size_t)W * W);
+            int i = (int)(rem / W), k = (int)(rem % W);
+            if (i < width && k < width) val = src[s_h + l * hsz + (size_t)i * width + k];
+            dst[oWh + q] = val;
+            hid[q] = bf16_bits(val);
+            continue;
+        }
+        q -= (size_t)(nh - 1) * W * W;
+        if (q < (size_t)(nh - 1) * W) {
+            int l = (int)(q / W), i = (int)(q % W);
+            if (i < width) val = src[s_h + l * hsz + (size_t)width * width + i];
+            dst[obh + q] = val;
+            continue;
+        }
+        q -= (size_t)(nh - 1) * W;
+        if (q < (size_t)d * W) {
+            int a = (int)(q / W), i = (int)(q % W);
+            if (i < width) val = src[s_WL + (size_t)a * width + i];
+            dst[oWL + q] = val;
+            continue;
+        }
+        q -= (size_t)d * W;
+        dst[obL + q] = src[s_bL + q];
+    }
+}
+
+}  // namespace mr
+
+using namespace mr;
+
+static size_t unpadded_count(int d, int r, int width, int nh)
+{
+    return (size_t)width * (d + r) + width + (size_t)(nh - 1) * ((size_t)width * width + width) +
+           (size_t)d * width + d;
+}
+
+extern "C" int32_t rom_decoder_set_params(mr_decoder *dec, const float *params,
+                                          int32_t params_on_device, void *stream)
+{
+    if (!dec || !params) return MR_EINVAL;
+    hipStream_t st = as_stream(stream);
+    const float *src = params;
+    if (!params_on_device) {
+        MR_CHECK_HIP(hipMemcpyAsync(dec->staging, params, dec->n_params * sizeof(float),
+                                    hipMemcpyHostToDevice, st));
+        src = dec->staging;
+    }
+    pack_params_kernel<<<256, 256, 0, st>>>(src, dec->dev, dec->hid_bf16, dec->d, dec->r, dec->width,
+                                            dec->W, dec->nh, dec->oW0, dec->ob0, dec->oWh, dec->obh,
+                                            dec->oWL, dec->obL);
+    MR_LAUNCH_CHECK();
+    if (!params_on_device) MR_CHECK_HIP(hipStreamSynchronize(st));
+    return MR_OK;
+}
+
+extern "C" int32_t rom_decoder_create(int32_t d, int32_t r, int32_t width, int32_t n_hidden,
+                                      const float *params, const float *in_min,
+                                      const float *in_max, const float *out_mean,
+                                      const float *out_std, int32_t output_mode,
+                                      int32_t precision, mr_decoder **out)
+{
+    if (!out || !params || !in_min || !in_max || !out_mean || !out_std) return MR_EINVAL;
+    if ((d != 2 && d != 3) || r < 1 || r > 32 || width < 1 || width > 128 || n_hidden < 1 ||
+        n_hidden > 8)
+        return MR_EINVAL;
+    if (output_mode != MR_OUT_POSITION && output_mode != MR_OUT_DISPLACEMENT) return MR_EINVAL;
+    if (precision != MR_PREC_FP32 && precision != MR_PREC_BF16) return MR_EINVAL;
+    for (int a = 0; a < d; ++a)
+        if (!(in_max[a] > in_min[a])) return MR_EINVAL;
+    // padded width: a power of two >= 16 (>= 32 with bf16, whose matrix-core
+    // step consumes 32 units of k); padded units have zero weights and bias,
+    // so they stay exactly zero through ELU and contribute nothing
+    int W = precision == MR_PREC_BF16 ? 32 : 16;
+    while (W < width) W *= 2;
+    mr_decoder *dec = (mr_decoder *)calloc(1, sizeof(mr_decoder));
+    if (!dec) return MR_ENOMEM;
+    dec->d = d;
+    dec->r = r;
+    dec->width = width;
+    dec->W = W;
+    dec->nh = n_hidden;
+    dec->mode = output_mode;
+    dec->prec = precision;
+    dec->n_params = unpadded_count(d, r, width, n_hidden);
+    for (int a = 0; a < 3; ++a) {
+        if (a < d) {
+            dec->scale[a] = 2.0f / (in_max[a] - in_min[a]);
+            dec->shift[a] = -2.0f * in_min[a] / (in_max[a] - in_min[a]) - 1.0f;
+            dec->mean[a] = out_mean[a];
+            dec->stdv[a] = out_std[a];
+        } else {
+            dec->scale[a] = dec->shift[a] = dec->mean[a] = dec->stdv[a] = 0.0f;
+        }
+    }
+    size_t off = 0;
+    auto take = [&](size_t nfl) {
+        size_t o = off;
+        off += (nfl + 63) & ~(size_t)63;
+        return o;
+    };
+    dec->oW0 = take((size_t)W * (d + r));
+    dec->ob0 = take(W);
+    dec->oWh = take((size_t)(n_hidden - 1) * W * W + 1);
+    dec->obh = take((size_t)(n_hidden - 1) * W + 1);
+    dec->oWL = take((size_t)d * W);
+    dec->obL = take(d);
+    if (hipMalloc(&dec->dev, off * sizeof(float)) != hipSuccess ||
+        hipMalloc(&dec->hid_bf16, ((size_t)(n_hidden - 1) * W * W + 8) * sizeof(uint16_t)) !=
+            hipSuccess ||
+        hipMalloc(&dec->staging, dec->n_params * sizeof(float)) != hipSuccess) {
+        rom_decoder_destroy(dec);
+        return MR_ENOMEM;
+    }
+    if (hipMemset(dec->dev, 0, off * sizeof(float)) != hipSuccess) {
+        rom_decoder_destroy(dec);
+        return MR_EDEVICE;
+    }
+    int32_t rc = rom_decoder_set_params(dec, params, 0, nullptr);
+    if (rc != MR_OK) {
+        rom_decoder_destroy(dec);
+        return rc;
+    }
+    *out = dec;
+    return MR_OK;
+}
+
+extern "C" void rom_decoder_destroy(mr_decoder *dec)
+{
+    if (!dec) return;
+    if (dec->dev) (void)hipFree(dec->dev);
+    if (dec->hid_bf16) (void)hipFree(dec->hid_bf16);
+    if (dec->staging) (void)hipFree(dec->staging);
+    free(dec);
+}
+
+static bool dec_io_ok(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X, int64_t n,
+                      const int32_t *idx, const double *xhat)
+{
+    if (!dec || B < 1 || B > 65535 || n_ref < 0 || n < 0 || !X || !xhat) return false;
+    if (!idx && n != n_ref) return false;
+    return true;
+}
+
+extern "C" int32_t rom_decode(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X,
+                              int64_t n, const int32_t *idx, const double *xhat, float *x_out,
+                              void *stream)
+{
+    if (!dec_io_ok(dec, B, n_ref, X, n, idx, xhat) || !x_out) return MR_EINVAL;
+    if (n == 0) return MR_OK;
+    DecIO io{};
+    io.B = B;
+    io.n_ref = n_ref;
+    io.n = n;
+    io.X = X;
+    io.idx = idx;
+    io.idx_per_inst = 0;
+    io.idx_div = 1;
+    io.xhat = xhat;
+    io.x = x_out;
+    StreamSpec ss{};
+    ss.kind[0] = SK_PRIMAL;
+    return launch_cfg(dec, 1, ss, io, as_stream(stream));
+}
+
+namespace mr {
+int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X, int64_t n,
+                      const int32_t *idx, int32_t idx_per_instance, const int32_t *n_inst,
+                      const double *xhat, const double *vhat, float *x, float *F, float *v,
+                      float *Jz, hipStream_t st)
+{
+    if (n == 0) return MR_OK;
+    DecIO io{};
+    io.n_inst = n_inst;
+    io.B = B;
+    io.n_ref = n_ref;
+    io.n = n;
+    io.X = X;
+    io.idx = idx;
+    io.idx_per_inst = idx_per_instance ? 1 : 0;
+    io.idx_div = idx_per_instance > 1 ? idx_per_instance : 1;
+    io.xhat = xhat;
+    io.vhat = vhat;
+    io.x = x;
+    io.F = F;
+    io.v = v;
+    int32_t rc;
+    bool wrote_x = false;
+    if (F || v) {
+        StreamSpec ss{};
+        ss.kind[0] = SK_PRIMAL;
+        for (int a = 0; a < 3; ++a) {
+            ss.kind[1 + a] = (a < dec->d && F) ? SK_SPATIAL : SK_ZERO;
+            ss.arg[1 + a] = a;
+        }
+        ss.kind[4] = v ? SK_VELOCITY : SK_ZERO;
+        rc = launch_cfg(dec, 5, ss, io, st);
+        if (rc != MR_OK) return rc;
+        wrote_x = true;
+    }
+    if (Jz) {
+        io.Jz = Jz;
+        io.F = nullptr;
+        io.v = nullptr;
+        for (int k0 = 0; k0 < dec->r; k0 += 8) {
+            StreamSpec ss{};
+            ss.kind[0] = SK_PRIMAL;
+            for (int q = 0; q < 8; ++q) {
+                ss.kind[1 + q] = (k0 + q < dec->r) ? SK_LATENT : SK_ZERO;
+                ss.arg[1 + q] = k0 + q;
+            }
+            io.x = wrote_x ? nullptr : x;
+            rc = launch_cfg(dec, 9, ss, io, st);
+            if (rc != MR_OK) return rc;
+            wrote_x = wrote_x || x;
+        }
+    }
+    if (!wrote_x && x) {
+        StreamSpec ss{};
+        ss.kind[0] = SK_PRIMAL;
+        io.x = x;
+        io.Jz = nullptr;
+        return launch_cfg(dec, 1, ss, io, st);
+    }
+    return MR_OK;
+}
+}  // namespace mr
+
+extern "C" int32_t rom_decode_jac(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X,
+                                  int64_t n, const int32_t *idx, int32_t idx_per_instance,
+                                  const double *xhat, const double *vhat, float *x, float *F,
+                                  float *v, float *Jz, void *stream)
+{
+    if (!dec_io_ok(dec, B, n_ref, X, n, idx, xhat)) return MR_EINVAL;
+    if (idx_per_instance && !idx) return MR_EINVAL;
+    if (idx_per_instance < 0 || (idx_per_instance > 1 && B % idx_per_instance != 0)) return MR_EINVAL;
+    if (v && !vhat) return MR_EINVAL;
+    return decode_jac_ex(dec, B, n_ref, X, n, idx, idx_per_instance, nullptr, xhat, vhat, x, F, v,
+                         Jz, as_stream(stream));
+}
+
+namespace mr {
+int decoder_dim(const mr_decoder *dec) { return dec->d; }
+int decoder_latent(const mr_decoder *dec) { return dec->r; }
+}  // namespace mr

@@ -1,0 +1,826 @@
+// Full-order MPM transfers on gfx950 (paper Section 2.2, Algorithm 1):
+// particle-to-grid scatter, grid update with boundary band, grid-to-particle
+// gather with deformation-gradient update, and the cell sort.
+//
+// Two P2G paths:
+//  * unsorted: one thread per particle, 3^d x (d+1) float atomics into the
+//    grid (L2 atomics) -- correct for any particle order;
+//  * sorted (MR_SORTED): one workgroup per 4x4x4 (2D: 8x8) tile of stencil
+//    base cells, whose particles the cell sort made contiguous and ordered
+//    slot-major (all first particles of the tile's cells, then all second
+//    ones, ...), so that the lanes of a wave sit in distinct cells.  The
+//    workgroup accumulates its particles into an LDS copy of the tile's node
+//    region (tile plus stencil reach plus one cell of drift margin on each
+//    side) with LDS float atomics, then flushes the region to HBM with one
+//    global atomic per non-zero node channel.  Particles that drifted beyond
+//    the margin since the sort fall back to global atomics.
+#include "mpm_kernels.h"
+
+#include <stdio.h>
+
+namespace mr {
+
+// ---------------------------------------------------------------------------
+// particle access helpers (SoA, component-major)
+
+template <int D>
+struct PartPtrs {
+    const float *x, *v, *C, *F, *m, *V0;
+    float m_u, V0_u;
+    int64_t n;
+};
+
+template <int D>
+__device__ __forceinline__ void load_payload(const PartPtrs<D> &pp, int64_t p, bool apic,
+                                             int model, float mu, float la, float dt,
+                                             const GridK &g, Stencil<D> &st, P2GPayload<D> &pl,
+                                             bool &ok)
+{
+    const int64_t n = pp.n;
+    float xp[D], vp[D], Fp[D * D], tau[D * D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        xp[a] = pp.x[a * n + p];
+        vp[a] = pp.v[a * n + p];
+    }
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Fp[k] = pp.F[k * n + p];
+    ok = make_stencil<D>(g, xp, st);
+    ok = kirchhoff<D>(model, mu, la, Fp, tau) && ok;
+    float m = pp.m ? pp.m[p] : pp.m_u;
+    float V0 = pp.V0 ? pp.V0[p] : pp.V0_u;
+    pl.m = m;
+#pragma unroll
+    for (int a = 0; a < D; ++a) pl.mv[a] = m * vp[a];
+    float sc = dt * V0;
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+        pl.mC[k] = apic ? m * pp.C[k * n + p] : 0.0f;
+        pl.S[k] = sc * tau[k];
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void scatter_global(const GridK &g, const Stencil<D> &st,
+                                               const P2GPayload<D> &pl, float *grid)
+{
+    const int oz = (D == 3) ? 3 : 1;
+    for (int o2 = 0; o2 < oz; ++o2)
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+            for (int o0 = 0; o0 < 3; ++o0) {
+                float mom[D];
+                float mw = p2g_node<D>(g, st, pl, o0, o1, o2, mom);
+                int64_t i = node_lin(g, st.base[0] + o0, st.base[1] + o1,
+                                     D == 3 ? st.base[2] + o2 : 0);
+                float *gp = grid + 4 * i;
+                atomicAdd(gp, mw);
+#pragma unroll
+                for (int a = 0; a < D; ++a) atomicAdd(gp + 1 + a, mom[a]);
+            }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) p2g_atomic_kernel(GridK g, PartPtrs<D> pp,
+                                                         const int32_t *subset, int64_t ns,
+                                                         int apic, int model, float mu,
+                                                         float la, float dt, float *grid,
+                                                         int32_t *flag)
+{
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    int64_t p = subset ? (int64_t)subset[s] : s;
+    Stencil<D> st;
+    P2GPayload<D> pl;
+    bool ok;
+    load_payload<D>(pp, p, apic != 0, model, mu, la, dt, g, st, pl, ok);
+    if (!ok) {
+        raise_flag(flag, MR_FLAG_DOMAIN);
+        return;
+    }
+    scatter_global<D>(g, st, pl, grid);
+}
+
+// ---------------------------------------------------------------------------
+// tiling used by the cell sort and the sorted P2G
+
+template <int D>
+struct Tiling {
+    static constexpr int TS = (D == 3) ? 4 : 8;          // cells per tile edge
+    static constexpr int CELLS = (D == 3) ? 64 : 64;     // cells per tile
+    static constexpr int R = TS + 4;                     // LDS node region edge
+    static constexpr int RN = (D == 3) ? R * R * R : R * R;
+};
+
+struct TileGeom {
+    int nt0, nt1, nt2;  // tiles per dimension
+    int64_t ntiles;
+};
+
+template <int D>
+inline TileGeom tile_geom(const GridK &g)
+{
+    // valid base cells are 0 .. n-3 per dimension
+    TileGeom t;
+    int TS = Tiling<D>::TS;
+    t.nt0 = (int)ceil_div(g.n0 - 2, TS);
+    t.nt1 = (int)ceil_div(g.n1 - 2, TS);
+    t.nt2 = D == 3 ? (int)ceil_div(g.n2 - 2, TS) : 1;
+    t.ntiles = (int64_t)t.nt0 * t.nt1 * t.nt2;
+    return t;
+}
+
+// tile-major cell key: tile * CELLS + local cell (x fastest); -1 if outside
+template <int D>
+__device__ __forceinline__ int32_t cell_key(const GridK &g, const TileGeom &tg, const float *xp)
+{
+    const int TS = Tiling<D>::TS;
+    const int n[3] = {g.n0, g.n1, g.n2};
+    int b[3] = {0, 0, 0};
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        float bf = floorf(xp[a] * g.inv_dx - 0.5f);
+        ok = ok && (bf >= 0.0f) && (bf + 2.0f <= (float)(n[a] - 1));
+        b[a] = ok ? (int)bf : 0;
+    }
+    if (!ok) return -1;
+    int t = (b[0] / TS) + tg.nt0 * ((b[1] / TS) + tg.nt1 * (D == 3 ? b[2] / TS : 0));
+    int c = (b[0] % TS) + TS * ((b[1] % TS) + (D == 3 ? TS * (b[2] % TS) : 0));
+    return t * Tiling<D>::CELLS + c;
+}
+
+template <int D>
+__global__ void cell_key_kernel(GridK g, TileGeom tg, const float *x, int64_t n, int32_t *keys,
+                                int32_t *counts, int32_t *flag)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    float xp[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) xp[a] = x[a * n + p];
+    int32_t k = cell_key<D>(g, tg, xp);
+    if (k < 0) {
+        raise_flag(flag, MR_FLAG_DOMAIN);
+        k = (int32_t)(tg.ntiles * Tiling<D>::CELLS);  // overflow bucket at the end
+    }
+    keys[p] = k;
+    if (counts) atomicAdd(counts + k, 1);
+}
+
+// --- exclusive scan of int32 (three phases) ---------------------------------
+constexpr int SCAN_BLOCK = 1024;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int *sh, int &total)
+{
+    // sh: blockDim.x ints; Hillis-Steele over LDS (blockDim = SCAN_BLOCK)
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        int add = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    total = sh[blockDim.x - 1];
+    int incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK) scan_blocks_kernel(const int32_t *in, int64_t n,
+                                                                  int32_t *out, int32_t *block_sums)
+{
+    __shared__ int sh[SCAN_BLOCK];
+    int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    int v = (i < n) ? in[i] : 0;
+    int total;
+    int ex = block_exclusive_scan(v, sh, total);
+    if (i < n) out[i] = ex;
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// single workgroup: exclusive scan of nb block sums in place (serial chunks)
+__global__ void __launch_bounds__(SCAN_BLOCK) scan_sums_kernel(int32_t *sums, int64_t nb,
+                                                                int32_t *grand_total)
+{
+    __shared__ int sh[SCAN_BLOCK];
+    int carry = 0;
+    for (int64_t base = 0; base < nb; base += SCAN_BLOCK) {
+        int64_t i = base + threadIdx.x;
+        int v = (i < nb) ? sums[i] : 0;
+        int total;
+        int ex = block_exclusive_scan(v, sh, total);
+        if (i < nb) sums[i] = ex + carry;
+        carry += total;
+    }
+    if (threadIdx.x == 0 && grand_total) *grand_total = carry;
+}
+
+__global__ void scan_add_kernel(int32_t *out, int64_t n, const int32_t *block_sums)
+{
+    int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    if (i < n) out[i] += block_sums[blockIdx.x];
+}
+
+int32_t exclusive_scan(const int32_t *in, int64_t n, int32_t *out, int32_t *block_sums,
+                       int32_t *grand_total, hipStream_t st)
+{
+    int64_t nb = ceil_div(n, SCAN_BLOCK);
+    scan_blocks_kernel<<<(unsigned)nb, SCAN_BLOCK, 0, st>>>(in, n, out, block_sums);
+    scan_sums_kernel<<<1, SCAN_BLOCK, 0, st>>>(block_sums, nb, grand_total);
+    scan_add_kernel<<<(unsigned)nb, SCAN_BLOCK, 0, st>>>(out, n, block_sums);
+    MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
+// --- counting sort into cells, then stable order inside each cell ----------
+__global__ void cell_scatter_kernel(const int32_t *keys, int64_t n, const int32_t *offsets,
+                                    int32_t *fill, int32_t *cell_sorted)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int k = keys[p];
+    int slot = offsets[k] + atomicAdd(fill + k, 1);
+    cell_sorted[slot] = (int32_t)p;
+}
+
+// insertion sort of each cell segment by particle index (restores the
+// previous order among particles of one cell: the sort is stable)
+__global__ void cell_segment_sort_kernel(const int32_t *offsets, const int32_t *counts,
+                                         int64_t ncells, int32_t *cell_sorted)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    int s = offsets[c], len = counts[c];
+    // cells hold a few tens of particles; a pathological pile-up (or the
+    // overflow bucket of flagged particles) keeps its arrival order rather
+    // than paying a quadratic sort in one thread
+    if (len > 1024) return;
+    for (int i = 1; i < len; ++i) {
+        int v = cell_sorted[s + i];
+        int j = i - 1;
+        while (j >= 0 && cell_sorted[s + j] > v) {
+            cell_sorted[s + j + 1] = cell_sorted[s + j];
+            --j;
+        }
+        cell_sorted[s + j + 1] = v;
+    }
+}
+
+// slot-major order inside a tile: the particle of rank k in local cell c goes
+// to tile_start + sum_c' min(cnt[c'], k) + #{c' < c : cnt[c'] > k}
+template <int D>
+__global__ void __launch_bounds__(64) tile_slot_kernel(const int32_t *offsets,
+                                                       const int32_t *counts,
+                                                       const int32_t *cell_sorted,
+                                                       int32_t *perm, int64_t ntiles)
+{
+    constexpr int NC = Tiling<D>::CELLS;
+    __shared__ int cnt[NC];
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    int c = threadIdx.x;
+    int64_t cell = t * NC + c;
+    cnt[c] = counts[cell];
+    __syncthreads();
+    int tile_start = offsets[t * NC];
+    int my_cnt = cnt[c];
+    int my_off = offsets[cell];
+    for (int k = 0; k < my_cnt; ++k) {
+        int pos = tile_start;
+        for (int q = 0; q < NC; ++q) {
+            int cq = cnt[q];
+            pos += (cq < k ? cq : k) + ((q < c && cq > k) ? 1 : 0);
+        }
+        perm[pos] = cell_sorted[my_off + k];
+    }
+}
+
+// overflow bucket (particles outside the lattice): keep their order at the end
+__global__ void tail_copy_kernel(const int32_t *cell_sorted, int32_t *perm, const int32_t *start,
+                                 int64_t n)
+{
+    int64_t i = (int64_t)(*start) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) perm[i] = cell_sorted[i];
+}
+
+__global__ void gather_plane_kernel(const float *src, float *dst, const int32_t *perm, int64_t n,
+                                    int planes)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t q = perm[i];
+    for (int k = 0; k < planes; ++k) dst[k * n + i] = src[k * n + q];
+}
+
+// ---------------------------------------------------------------------------
+// sorted, LDS-tiled P2G
+
+template <int D>
+__global__ void __launch_bounds__(256) p2g_tiled_kernel(GridK g, TileGeom tg, PartPtrs<D> pp,
+                                                        const int32_t *offsets, int apic,
+                                                        int model, float mu, float la,
+                                                        float dt, float *grid, int32_t *flag)
+{
+    using T = Tiling<D>;
+    constexpr int R = T::R, RN = T::RN;
+    __shared__ float acc[4 * RN];  // channel-major
+    const int64_t t = blockIdx.x;
+    for (int i = threadIdx.x; i < 4 * RN; i += blockDim.x) acc[i] = 0.0f;
+    const int t0 = (int)(t % tg.nt0);
+    const int t1 = (int)((t / tg.nt0) % tg.nt1);
+    const int t2 = D == 3 ? (int)(t / ((int64_t)tg.nt0 * tg.nt1)) : 0;
+    // region origin: tile origin minus one cell of drift margin
+    const int r0 = t0 * T::TS - 1, r1 = t1 * T::TS - 1, r2 = D == 3 ? t2 * T::TS - 1 : 0;
+    const int begin = offsets[t * T::CELLS];
+    const int end = offsets[(t + 1) * T::CELLS];
+    __syncthreads();
+    for (int64_t p = begin + threadIdx.x; p < end; p += blockDim.x) {
+        Stencil<D> st;
+        P2GPayload<D> pl;
+        bool ok;
+        load_payload<D>(pp, p, apic != 0, model, mu, la, dt, g, st, pl, ok);
+        if (!ok) {
+            raise_flag(flag, MR_FLAG_DOMAIN);
+            continue;
+        }
+        int l0 = st.base[0] - r0, l1 = st.base[1] - r1, l2 = D == 3 ? st.base[2] - r2 : 0;
+        bool inside = l0 >= 0 && l0 + 2 < R && l1 >= 0 && l1 + 2 < R &&
+                      (D == 2 || (l2 >= 0 && l2 + 2 < R));
+        if (!inside) {
+            scatter_global<D>(g, st, pl, grid);
+            continue;
+        }
+        const int oz = (D == 3) ? 3 : 1;
+        for (int o2 = 0; o2 < oz; ++o2)
+#pragma unroll
+            for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+                for (int o0 = 0; o0 < 3; ++o0) {
+                    float mom[D];
+                    float mw = p2g_node<D>(g, st, pl, o0, o1, o2, mom);
+                    int li = (l0 + o0) + R * ((l1 + o1) + (D == 3 ? R * (l2 + o2) : 0));
+                    atomicAdd(&acc[li], mw);
+#pragma unroll
+                    for (int a = 0; a < D; ++a) atomicAdd(&acc[(1 + a) * RN + li], mom[a]);
+                }
+    }
+    __syncthreads();
+    for (int li = threadIdx.x; li < RN; li += blockDim.x) {
+        float mw = acc[li];
+        if (mw == 0.0f) continue;  // no particle reached this node (weights are > 0 inside)
+        int i0 = li % R, i1 = (li / R) % R, i2 = D == 3 ? li / (R * R) : 0;
+        int gi = r0 + i0, gj = r1 + i1, gk = D == 3 ? r2 + i2 : 0;
+        if (gi < 0 || gj < 0 || gk < 0 || gi >= g.n0 || gj >= g.n1 || gk >= g.n2) continue;
+        float *gp = grid + 4 * node_lin(g, gi, gj, gk);
+        atomicAdd(gp, mw);
+#pragma unroll
+        for (int a = 0; a < D; ++a) atomicAdd(gp + 1 + a, acc[(1 + a) * RN + li]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// grid update
+
+template <int D>
+__global__ void grid_update_kernel(GridK g, float dt, float *grid, const int32_t *active,
+                                   int64_t count)
+{
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count) return;
+    int64_t i = active ? (int64_t)active[s] : s;
+    float4 *gp = reinterpret_cast<float4 *>(grid) + i;
+    float4 q = *gp;
+    if (!(q.x > 0.0f)) {
+        *gp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
+    }
+    float inv = 1.0f / q.x;
+    float v[3];
+    v[0] = q.y * inv + dt * g.g0;
+    v[1] = q.z * inv + dt * g.g1;
+    v[2] = (D == 3) ? q.w * inv + dt * g.g2 : 0.0f;
+    int i0 = (int)(i % g.n0);
+    int i1 = (int)((i / g.n0) % g.n1);
+    int i2 = (int)(i / ((int64_t)g.n0 * g.n1));
+    apply_bc<D>(g, i0, i1, i2, v);
+    *gp = make_float4(q.x, v[0], v[1], D == 3 ? v[2] : 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// G2P
+
+template <int D>
+__global__ void __launch_bounds__(256) g2p_kernel(GridK g, int64_t n, float *x, float *v,
+                                                  float *C, float *F, const int32_t *subset,
+                                                  int64_t ns, float dt, const float *grid,
+                                                  int apic, int update_F, int trial,
+                                                  float *x_trial, float *v_trial, int32_t *flag)
+{
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    int64_t p = subset ? (int64_t)subset[s] : s;
+    float xp[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) xp[a] = x[a * n + p];
+    Stencil<D> st;
+    if (!make_stencil<D>(g, xp, st)) {
+        raise_flag(flag, MR_FLAG_DOMAIN);
+        return;
+    }
+    float vp[D] = {}, Bp[D * D] = {}, gv[D * D] = {};
+    const float4 *g4 = reinterpret_cast<const float4 *>(grid);
+    const int oz = (D == 3) ? 3 : 1;
+    for (int o2 = 0; o2 < oz; ++o2)
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+            for (int o0 = 0; o0 < 3; ++o0) {
+                const int o[3] = {o0, o1, o2};
+                float w = 1.0f, grad[D], dxi[D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    w *= st.w[a][o[a]];
+                    dxi[a] = ((float)o[a] - st.f[a]) * g.dx;
+                }
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    float gb = 1.0f;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) gb *= (a == b) ? st.dw[a][o[a]] : st.w[a][o[a]];
+                    grad[b] = gb;
+                }
+                float4 q = g4[node_lin(g, st.base[0] + o0, st.base[1] + o1,
+                                       D == 3 ? st.base[2] + o2 : 0)];
+                const float vi[3] = {q.y, q.z, q.w};
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    vp[a] += w * vi[a];
+#pragma unroll
+                    for (int b = 0; b < D; ++b) {
+                        Bp[a * D + b] += w * vi[a] * dxi[b];
+                        gv[a * D + b] += vi[a] * grad[b];
+                    }
+                }
+            }
+    if (trial) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            v_trial[a * ns + s] = vp[a];
+            x_trial[a * ns + s] = xp[a] + dt * vp[a];
+        }
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a * n + p] = vp[a];
+    if (C) {
+        float sc = apic ? 4.0f * g.inv_dx * g.inv_dx : 0.0f;
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) C[k * n + p] = sc * Bp[k];
+    }
+    if (update_F) {
+        float Fp[D * D], Fn[D * D];
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) Fp[k] = F[k * n + p];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                float acc = Fp[a * D + b];
+#pragma unroll
+                for (int k = 0; k < D; ++k) acc += dt * gv[a * D + k] * Fp[k * D + b];
+                Fn[a * D + b] = acc;
+            }
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) F[k * n + p] = Fn[k];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a * n + p] = xp[a] + dt * vp[a];
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout of the cell sort / sorted P2G
+
+struct SortWorkspace {
+    int32_t *keys, *counts, *offsets, *fill, *cell_sorted, *perm, *block_sums, *total;
+    float *copy;
+    int64_t ncells;
+};
+
+template <int D>
+int64_t sort_ws_bytes(const GridK &g, int64_t n, SortWorkspace *ws, char *basep)
+{
+    TileGeom tg = tile_geom<D>(g);
+    int64_t ncells = tg.ntiles * Tiling<D>::CELLS + 1;  // + overflow bucket
+    int64_t nb = ceil_div(ncells + 1, SCAN_BLOCK);
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t o = off;
+        off += (bytes + 255) & ~(int64_t)255;
+        return o;
+    };
+    int64_t o_keys = take(4 * n), o_counts = take(4 * (ncells + 1)),
+            o_offsets = take(4 * (ncells + 1)), o_fill = take(4 * (ncells + 1)),
+            o_cs = take(4 * n), o_perm = take(4 * n), o_bs = take(4 * nb), o_tot = take(4),
+            o_copy = take(4 * n * (2 * D + 2 * D * D + 2));
+    if (ws) {
+        ws->keys = (int32_t *)(basep + o_keys);
+        ws->counts = (int32_t *)(basep + o_counts);
+        ws->offsets = (int32_t *)(basep + o_offsets);
+        ws->fill = (int32_t *)(basep + o_fill);
+        ws->cell_sorted = (int32_t *)(basep + o_cs);
+        ws->perm = (int32_t *)(basep + o_perm);
+        ws->block_sums = (int32_t *)(basep + o_bs);
+        ws->total = (int32_t *)(basep + o_tot);
+        ws->copy = (float *)(basep + o_copy);
+        ws->ncells = ncells;
+    }
+    return off;
+}
+
+template <int D>
+int32_t cell_sort_impl(const GridK &g, mr_particles *parts, int32_t *perm_out, void *workspace,
+                       int32_t *flag, hipStream_t st, int32_t *carry = nullptr)
+{
+    const int64_t n = parts->n;
+    SortWorkspace ws;
+    sort_ws_bytes<D>(g, n, &ws, (char *)workspace);
+    TileGeom tg = tile_geom<D>(g);
+    const int64_t ncells = ws.ncells;
+    MR_CHECK_HIP(hipMemsetAsync(ws.counts, 0, 4 * (ncells + 1), st));
+    MR_CHECK_HIP(hipMemsetAsync(ws.fill, 0, 4 * (ncells + 1), st));
+    if (n == 0) {
+        MR_CHECK_HIP(hipMemsetAsync(ws.offsets, 0, 4 * (ncells + 1), st));
+        return MR_OK;
+    }
+    const int TB = 256;
+    unsigned gb = (unsigned)ceil_div(n, TB);
+    cell_key_kernel<D><<<gb, TB, 0, st>>>(g, tg, parts->x, n, ws.keys, ws.counts, flag);
+    int32_t rc = exclusive_scan(ws.counts, ncells + 1, ws.offsets, ws.block_sums, ws.total, st);
+    if (rc != MR_OK) return rc;
+    cell_scatter_kernel<<<gb, TB, 0, st>>>(ws.keys, n, ws.offsets, ws.fill, ws.cell_sorted);
+    cell_segment_sort_kernel<<<(unsigned)ceil_div(ncells, TB), TB, 0, st>>>(
+        ws.offsets, ws.counts, ncells, ws.cell_sorted);
+    tile_slot_kernel<D><<<(unsigned)tg.ntiles, Tiling<D>::CELLS, 0, st>>>(
+        ws.offsets, ws.counts, ws.cell_sorted, ws.perm, tg.ntiles);
+    tail_copy_kernel<<<gb, TB, 0, st>>>(ws.cell_sorted, ws.perm,
+                                        ws.offsets + tg.ntiles * Tiling<D>::CELLS, n);
+    MR_LAUNCH_CHECK();
+    // gather every particle array through the permutation
+    struct Arr {
+        float *p;
+        int planes;
+    } arrs[7] = {{parts->x, D}, {parts->v, D}, {parts->C, D * D}, {parts->F, D * D},
+                 {const_cast<float *>(parts->m), 1}, {const_cast<float *>(parts->V0), 1},
+                 {reinterpret_cast<float *>(carry), 1}};
+    for (auto &a : arrs) {
+        if (!a.p) continue;
+        MR_CHECK_HIP(hipMemcpyAsync(ws.copy, a.p, 4 * n * a.planes, hipMemcpyDeviceToDevice, st));
+        gather_plane_kernel<<<gb, TB, 0, st>>>(ws.copy, a.p, ws.perm, n, a.planes);
+    }
+    MR_LAUNCH_CHECK();
+    if (perm_out)
+        MR_CHECK_HIP(hipMemcpyAsync(perm_out, ws.perm, 4 * n, hipMemcpyDeviceToDevice, st));
+    return MR_OK;
+}
+
+template <int D>
+PartPtrs<D> part_ptrs(const mr_particles *p)
+{
+    PartPtrs<D> pp;
+    pp.x = p->x;
+    pp.v = p->v;
+    pp.C = p->C;
+    pp.F = p->F;
+    pp.m = p->m;
+    pp.V0 = p->V0;
+    pp.m_u = p->m_uniform;
+    pp.V0_u = p->V0_uniform;
+    pp.n = p->n;
+    return pp;
+}
+
+template <int D>
+int32_t p2g_impl(const GridK &g, const mr_material *mat, const mr_particles *parts,
+                 const int32_t *subset, int64_t ns, float dt, float *grid, int32_t flags,
+                 void *workspace, int32_t *flag, hipStream_t st)
+{
+    Lame lm = lame_of(mat->E, mat->nu);
+    int apic = (flags & MR_NO_AFFINE) ? 0 : 1;
+    if (!(flags & MR_ACCUMULATE))
+        MR_CHECK_HIP(hipMemsetAsync(grid, 0, sizeof(float) * 4 * grid_nodes(g), st));
+    PartPtrs<D> pp = part_ptrs<D>(parts);
+    if ((flags & MR_SORTED) && !subset) {
+        SortWorkspace ws;
+        sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
+        TileGeom tg = tile_geom<D>(g);
+        if (tg.ntiles > 0)
+            p2g_tiled_kernel<D><<<(unsigned)tg.ntiles, 256, 0, st>>>(
+                g, tg, pp, ws.offsets, apic, mat->model, lm.mu, lm.la, dt, grid, flag);
+        // particles in the overflow bucket (outside the lattice at sort time)
+        // were flagged by the sort; the tiled kernel only covers tiles
+        MR_LAUNCH_CHECK();
+        return MR_OK;
+    }
+    if (ns > 0)
+        p2g_atomic_kernel<D><<<(unsigned)ceil_div(ns, 256), 256, 0, st>>>(
+            g, pp, subset, ns, apic, mat->model, lm.mu, lm.la, dt, grid, flag);
+    MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
+}  // namespace mr
+
+using namespace mr;
+
+static bool check_parts(const mr_particles *p, int dim, bool need_vCF)
+{
+    if (!p || p->n < 0) return false;
+    if (p->n == 0) return true;  // nothing is dereferenced
+    if (!p->x) return false;
+    if (need_vCF && (!p->v || !p->F)) return false;
+    (void)dim;
+    return true;
+}
+
+extern "C" int32_t mpm_p2g(const mr_grid *grid_desc, const mr_material *mat,
+                           const mr_particles *parts, const int32_t *subset, int64_t n_subset,
+                           float dt, float *grid, int32_t flags, void *workspace,
+                           int32_t *status_flag, void *stream)
+{
+    GridK g;
+    if (!grid_from_desc(grid_desc, g) || !mat || !grid || !check_parts(parts, grid_desc->dim, true))
+        return MR_EINVAL;
+    if (!(flags & MR_NO_AFFINE) && !parts->C && parts->n > 0) return MR_EINVAL;
+    if (mat->model == MR_FIXED_COROTATED && grid_desc->dim != 2) return MR_EINVAL;
+    if (mat->model != MR_FIXED_COROTATED && mat->model != MR_NEO_HOOKEAN) return MR_EINVAL;
+    if ((flags & MR_SORTED) && !workspace) return MR_EINVAL;
+    int64_t ns = subset ? n_subset : parts->n;
+    if (ns < 0) return MR_EINVAL;
+    hipStream_t st = as_stream(stream);
+    if (grid_desc->dim == 2)
+        return p2g_impl<2>(g, mat, parts, subset, ns, dt, grid, flags, workspace, status_flag, st);
+    return p2g_impl<3>(g, mat, parts, subset, ns, dt, grid, flags, workspace, status_flag, st);
+}
+
+extern "C" int32_t mpm_grid_update(const mr_grid *grid_desc, float dt, float *grid,
+                                   const int32_t *active, int64_t n_active, void *stream)
+{
+    GridK g;
+    if (!grid_from_desc(grid_desc, g) || !grid) return MR_EINVAL;
+    int64_t count = active ? n_active : grid_nodes(g);
+    if (count < 0) return MR_EINVAL;
+    if (count == 0) return MR_OK;
+    hipStream_t st = as_stream(stream);
+    unsigned gb = (unsigned)ceil_div(count, 256);
+    if (grid_desc->dim == 2)
+        grid_update_kernel<2><<<gb, 256, 0, st>>>(g, dt, grid, active, count);
+    else
+        grid_update_kernel<3><<<gb, 256, 0, st>>>(g, dt, grid, active, count);
+    MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
+extern "C" int32_t mpm_g2p(const mr_grid *grid_desc, mr_particles *parts, const int32_t *subset,
+                           int64_t n_subset, float dt, const float *grid, int32_t flags,
+                           float *x_trial, float *v_trial, int32_t *status_flag, void *stream)
+{
+    GridK g;
+    if (!grid_from_desc(grid_desc, g) || !grid || !parts || parts->n < 0 ||
+        (parts->n > 0 && !parts->x))
+        return MR_EINVAL;
+    bool trial = (flags & MR_TRIAL) != 0;
+    if (trial && (!x_trial || !v_trial)) return MR_EINVAL;
+    int update_F = (!trial && !(flags & MR_NO_F_UPDATE)) ? 1 : 0;
+    if (!trial && parts->n > 0 && (!parts->v || (update_F && !parts->F))) return MR_EINVAL;
+    int apic = (flags & MR_NO_AFFINE) ? 0 : 1;
+    int64_t ns = subset ? n_subset : parts->n;
+    if (ns < 0) return MR_EINVAL;
+    if (ns == 0) return MR_OK;
+    hipStream_t st = as_stream(stream);
+    unsigned gb = (unsigned)ceil_div(ns, 256);
+    if (grid_desc->dim == 2)
+        g2p_kernel<2><<<gb, 256, 0, st>>>(g, parts->n, parts->x, parts->v, parts->C, parts->F,
+                                          subset, ns, dt, grid, apic, update_F, trial ? 1 : 0,
+                                          x_trial, v_trial, status_flag);
+    else
+        g2p_kernel<3><<<gb, 256, 0, st>>>(g, parts->n, parts->x, parts->v, parts->C, parts->F,
+                                          subset, ns, dt, grid, apic, update_F, trial ? 1 : 0,
+                                          x_trial, v_trial, status_flag);
+    MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
+extern "C" int64_t mpm_workspace_bytes(const mr_grid *grid_desc, int64_t n)
+{
+    GridK g;
+    if (!grid_from_desc(grid_desc, g) || n < 0) return -1;
+    return grid_desc->dim == 2 ? sort_ws_bytes<2>(g, n, nullptr, nullptr)
+                               : sort_ws_bytes<3>(g, n, nullptr, nullptr);
+}
+
+extern "C" int32_t mpm_cell_sort(const mr_grid *grid_desc, mr_particles *parts, int32_t *perm_out,
+                                 void *workspace, int32_t *status_flag, void *stream)
+{
+    GridK g;
+    if (!grid_from_desc(grid_desc, g) || !workspace || !check_parts(parts, grid_desc->dim, false))
+        return MR_EINVAL;
+    if (parts->n > INT32_MAX) return MR_EINVAL;
+    hipStream_t st = as_stream(stream);
+    return grid_desc->dim == 2 ? cell_sort_impl<2>(g, parts, perm_out, workspace, status_flag, st)
+                               : cell_sort_impl<3>(g, parts, perm_out, workspace, status_flag, st);
+}
+
+extern "C" int32_t mpm_cell_keys(const mr_grid *grid_desc, const mr_particles *parts,
+                                 int32_t *keys_out, void *stream)
+{
+    GridK g;
+    if (!grid_from_desc(grid_desc, g) || !keys_out || !check_parts(parts, grid_desc->dim, false))
+        return MR_EINVAL;
+    if (parts->n == 0) return MR_OK;
+    hipStream_t st = as_stream(stream);
+    unsigned gb = (unsigned)ceil_div(parts->n, 256);
+    if (grid_desc->dim == 2) {
+        TileGeom tg = tile_geom<2>(g);
+        cell_key_kernel<2><<<gb, 256, 0, st>>>(g, tg, parts->x, parts->n, keys_out, nullptr, nullptr);
+    } else {
+        TileGeom tg = tile_geom<3>(g);
+        cell_key_kernel<3><<<gb, 256, 0, st>>>(g, tg, parts->x, parts->n, keys_out, nullptr, nullptr);
+    }
+    MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
+extern "C" int32_t mr_sync_status(void *stream, const int32_t *device_flags, int32_t n,
+                                  int32_t *host_flags)
+{
+    if (n < 0 || (n > 0 && (!device_flags || !host_flags))) return MR_EINVAL;
+    hipStream_t st = as_stream(stream);
+    if (n > 0)
+        MR_CHECK_HIP(hipMemcpyAsync(host_flags, device_flags, sizeof(int32_t) * n,
+                                    hipMemcpyDeviceToHost, st));
+    MR_CHECK_HIP(hipStreamSynchronize(st));
+    int32_t bits = 0;
+    for (int32_t i = 0; i < n; ++i) bits |= host_flags[i];
+    if (bits & MR_FLAG_DOMAIN) return MR_EDOMAIN;
+    if (bits & MR_FLAG_SINGULAR) return MR_ESINGULAR;
+    if (bits & (MR_FLAG_NOCONV | MR_FLAG_LINESEARCH)) return MR_ENOCONV;
+    return MR_OK;
+}
+
+extern "C" const char *mr_version(void) { return "mpmrom 0.1 gfx950"; }
+
+// ---------------------------------------------------------------------------
+// multi-step driver
+
+extern "C" int64_t mpm_step_workspace_bytes(const mr_grid *grid_desc, int64_t n)
+{
+    return mpm_workspace_bytes(grid_desc, n);
+}
+
+__global__ void iota_kernel(int32_t *a, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = (int32_t)i;
+}
+
+extern "C" int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
+                            mr_particles *parts, float dt, int32_t n_steps, int32_t sort_every,
+                            int32_t flags, float *grid, void *workspace, int32_t *perm_accum,
+                            int32_t *status_flag, void *stream)
+{
+    GridK g;
+    if (!grid_from_desc(grid_desc, g) || !mat || !grid || !workspace || n_steps < 0 ||
+        sort_every < 0 || !check_parts(parts, grid_desc->dim, true))
+        return MR_EINVAL;
+    if (!(flags & MR_NO_AFFINE) && !parts->C && parts->n > 0) return MR_EINVAL;
+    int32_t rc;
+    hipStream_t st = as_stream(stream);
+    if (perm_accum && parts->n > 0) {
+        iota_kernel<<<(unsigned)ceil_div(parts->n, 256), 256, 0, st>>>(perm_accum, parts->n);
+        MR_LAUNCH_CHECK();
+    }
+    for (int32_t s = 0; s < n_steps; ++s) {
+        bool sort_now = sort_every > 0 && (s % sort_every) == 0;
+        if (sort_now) {
+            if (parts->n > INT32_MAX) return MR_EINVAL;
+            rc = grid_desc->dim == 2
+                     ? cell_sort_impl<2>(g, parts, nullptr, workspace, status_flag, st, perm_accum)
+                     : cell_sort_impl<3>(g, parts, nullptr, workspace, status_flag, st, perm_accum);
+            if (rc != MR_OK) return rc;
+        }
+        int32_t pf = (flags & MR_NO_AFFINE) | (sort_every > 0 ? MR_SORTED : 0);
+        rc = mpm_p2g(grid_desc, mat, parts, nullptr, 0, dt, grid, pf, workspace, status_flag,
+                     stream);
+        if (rc != MR_OK) return rc;
+        rc = mpm_grid_update(grid_desc, dt, grid, nullptr, 0, stream);
+        if (rc != MR_OK) return rc;
+        rc = mpm_g2p(grid_desc, parts, nullptr, 0, dt, grid, flags & MR_NO_AFFINE, nullptr,
+                     nullptr, status_flag, stream);
+        if (rc != MR_OK) return rc;
+    }
+    return MR_OK;
+}

@@ -1,0 +1,414 @@
+// Reduced-space dynamics on gfx950 (paper Section 3.2.4, Algorithms 6 and 7):
+// velocity least squares and Gauss-Newton position projection over the
+// sample points, batched over B instances.
+//
+//  * normal equations: one workgroup per instance stages chunks of the
+//    latent Jacobian (fp32, from the decoder kernels) in LDS and accumulates
+//    J^T J, J^T y and 0.5 |y|^2 in fp64 (products of fp32 values are exact in
+//    fp64, so only the summation rounds);
+//  * the r x r solve is an fp64 Cholesky factorisation, one thread per
+//    instance;
+//  * backtracking: the max_backtrack + 1 trial step lengths 1, 1/2, 1/4, ...
+//    are decoded together in one launch (B (max_backtrack + 1) instances)
+//    and the first one passing the Armijo test is taken, so each iteration
+//    has a fixed launch sequence (no host decisions, graph-capturable).
+#include "project.h"
+
+namespace mr {
+
+constexpr int NE_THREADS = 256;
+
+__global__ void zero_i32_kernel(int32_t *a, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+constexpr int NE_CHUNK = 32;  // samples staged per pass
+
+// mode 0: rhs = J^T v (velocity);  mode 1: rhs = J^T (x - x_trial), f = 0.5|x - x_trial|^2
+template <int MODE>
+__global__ void __launch_bounds__(NE_THREADS) normal_eq_kernel(int d, int r, int64_t ns,
+                                                               const int32_t *ns_inst,
+                                                               const float *Jz, const float *y,
+                                                               const float *x, double *A,
+                                                               double *rhs, double *f)
+{
+    extern __shared__ __align__(8) float sm[];
+    const int b = blockIdx.x;
+    const int64_t cnt = ns_inst ? (int64_t)ns_inst[b] : ns;
+    const int dr = d * r;
+    float *Js = sm;                      // [dr][NE_CHUNK]
+    float *Ys = sm + dr * NE_CHUNK;      // [d][NE_CHUNK]
+    const float *Jb = Jz + (size_t)b * dr * ns;
+    const float *yb = y + (size_t)b * d * ns;
+    const float *xb = MODE == 1 ? x + (size_t)b * d * ns : nullptr;
+    const int nent = r * r + r + 1;
+    double acc[5] = {0, 0, 0, 0, 0};  // entries tid, tid + 256, ... (r <= 32 -> <= 5)
+    for (int64_t s0 = 0; s0 < cnt; s0 += NE_CHUNK) {
+        int len = (int)((cnt - s0) < NE_CHUNK ? (cnt - s0) : NE_CHUNK);
+        __syncthreads();
+        for (int t = threadIdx.x; t < dr * NE_CHUNK; t += blockDim.x) {
+            int row = t / NE_CHUNK, c = t % NE_CHUNK;
+            Js[t] = c < len ? Jb[(size_t)row * ns + s0 + c] : 0.0f;
+        }
+        for (int t = threadIdx.x; t < d * NE_CHUNK; t += blockDim.x) {
+            int a = t / NE_CHUNK, c = t % NE_CHUNK;
+            float val = 0.0f;
+            if (c < len) {
+                val = yb[(size_t)a * ns + s0 + c];
+                if (MODE == 1) val = xb[(size_t)a * ns + s0 + c] - val;
+            }
+            Ys[t] = val;
+        }
+        __syncthreads();
+        int q = 0;
+        for (int e = threadIdx.x; e < nent; e += blockDim.x, ++q) {
+            double sacc = 0.0;
+            if (e < r * r) {
+                int k1 = e / r, k2 = e % r;
+                for (int a = 0; a < d; ++a) {
+                    const float *p1 = Js + (a * r + k1) * NE_CHUNK;
+                    const float *p2 = Js + (a * r + k2) * NE_CHUNK;
+                    for (int c = 0; c < len; ++c) sacc += (double)p1[c] * (double)p2[c];
+                }
+            } else if (e < r * r + r) {
+                int k = e - r * r;
+                for (int a = 0; a < d; ++a) {
+                    const float *p1 = Js + (a * r + k) * NE_CHUNK;
+                    const float *py = Ys + a * NE_CHUNK;
+                    for (int c = 0; c < len; ++c) sacc += (double)p1[c] * (double)py[c];
+                }
+            } else if (MODE == 1) {
+                for (int a = 0; a < d; ++a)
+                    for (int c = 0; c < len; ++c) {
+                        double v = Ys[a * NE_CHUNK + c];
+                        sacc += 0.5 * v * v;
+                    }
+            }
+            acc[q] += sacc;
+        }
+    }
+    int q = 0;
+    for (int e = threadIdx.x; e < nent; e += blockDim.x, ++q) {
+        if (e < r * r)
+            A[(size_t)b * r * r + e] = acc[q];
+        else if (e < r * r + r)
+            rhs[(size_t)b * r + (e - r * r)] = acc[q];
+        else if (f)
+            f[b] = acc[q];
+    }
+}
+
+// 0.5 |x - x_trial|^2 per candidate instance c (samples of instance c / group)
+__global__ void __launch_bounds__(256) objective_kernel(int d, int64_t ns, int group,
+                                                        const int32_t *ns_inst, const float *x,
+                                                        const float *xt, double *f)
+{
+    __shared__ double red[256];
+    const int c = blockIdx.x;
+    const int b = c / group;
+    const int64_t cnt = ns_inst ? (int64_t)ns_inst[b] : ns;
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < cnt * d; t += blockDim.x) {
+        int a = (int)(t / cnt);
+        int64_t i = t % cnt;
+        double v = (double)x[((size_t)c * d + a) * ns + i] - (double)xt[((size_t)b * d + a) * ns + i];
+        s += 0.5 * v * v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) f[c] = red[0];
+}
+
+// Solve (A + damping I) y = sign * rhs by Cholesky, one thread per instance.
+__global__ void cholesky_solve_kernel(int B, int r, const double *A, const double *rhs,
+                                      double damping, double sign, double *y, double *L_ws,
+                                      int32_t *status, int32_t *singular)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const double *Ab = A + (size_t)b * r * r;
+    double *L = L_ws + (size_t)b * r * r;
+    double *yb = y + (size_t)b * r;
+    bool ok = true;
+    for (int i = 0; i < r && ok; ++i) {
+        for (int j2 = 0; j2 <= i; ++j2) {
+            double s = Ab[i * r + j2] + (i == j2 ? damping : 0.0);
+            for (int k = 0; k < j2; ++k) s -= L[i * r + k] * L[j2 * r + k];
+            if (i == j2) {
+                // a pivot that lost all but ~1e-12 of the diagonal is singular
+                if (!(s > 1e-12 * (Ab[i * r + i] + damping)) || !(s > 0.0)) {
+                    ok = false;
+                    break;
+                }
+                L[i * r + i] = sqrt(s);
+            } else {
+                L[i * r + j2] = s / L[j2 * r + j2];
+            }
+        }
+    }
+    if (!ok) {
+        for (int i = 0; i < r; ++i) yb[i] = 0.0;
+        if (status) status[b] |= MR_FLAG_SINGULAR;
+        if (singular) singular[b] = 1;
+        return;
+    }
+    // forward: L w = sign rhs ; backward: L^T y = w
+    for (int i = 0; i < r; ++i) {
+        double s = sign * rhs[(size_t)b * r + i];
+        for (int k = 0; k < i; ++k) s -= L[i * r + k] * yb[k];
+        yb[i] = s / L[i * r + i];
+    }
+    for (int i = r - 1; i >= 0; --i) {
+        double s = yb[i];
+        for (int k = i + 1; k < r; ++k) s -= L[k * r + i] * yb[k];
+        yb[i] = s / L[i * r + i];
+    }
+}
+
+__global__ void init_guess_kernel(int B, int r, int mode, double dt, const double *zn,
+                                  const double *zp, const double *vhat, const int32_t *singular,
+                                  double *z, double *vout)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B * r) return;
+    int b = t / r;
+    bool sing = singular[b] != 0;
+    double v = sing ? 0.0 : vhat[t];
+    vout[t] = v;
+    if (mode == MR_VEL_ONLY)
+        z[t] = zn[t] + dt * v;
+    else
+        z[t] = sing ? zn[t] : 2.0 * zn[t] - zp[t];
+}
+
+// candidate latents z + alpha_j delta, alpha_j = 2^-j, j = 0..nc-1
+__global__ void candidates_kernel(int B, int r, int nc, const double *z, const double *delta,
+                                  double *zc)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B * nc * r) return;
+    int k = t % r;
+    int c = t / r;
+    int b = c / nc, jj = c % nc;
+    double alpha = ldexp(1.0, -jj);
+    zc[t] = z[(size_t)b * r + k] + alpha * delta[(size_t)b * r + k];
+}
+
+// pick the first Armijo-admissible step; g = J^T res (gradient of f)
+__global__ void select_kernel(int B, int r, int nc, double c_armijo, double tol_step,
+                              const double *f, const double *g, const double *delta,
+                              const double *fc, const int32_t *singular, double *z,
+                              double *fnew, double *step_norm, int32_t *status, int last)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double slope = 0.0;
+    for (int k = 0; k < r; ++k) slope += g[(size_t)b * r + k] * delta[(size_t)b * r + k];
+    int pick = -1;
+    for (int jj = 0; jj < nc; ++jj) {
+        double alpha = ldexp(1.0, -jj);
+        if (fc[(size_t)b * nc + jj] <= f[b] + c_armijo * alpha * slope) {
+            pick = jj;
+            break;
+        }
+    }
+    double sn = 0.0, zn2 = 0.0;
+    if (pick >= 0 && !singular[b]) {
+        double alpha = ldexp(1.0, -pick);
+        for (int k = 0; k < r; ++k) {
+            double s = alpha * delta[(size_t)b * r + k];
+            z[(size_t)b * r + k] += s;
+            sn += s * s;
+            zn2 += z[(size_t)b * r + k] * z[(size_t)b * r + k];
+        }
+        fnew[b] = fc[(size_t)b * nc + pick];
+    } else {
+        fnew[b] = f[b];
+        if (pick < 0 && status) status[b] |= MR_FLAG_LINESEARCH;
+    }
+    step_norm[b] = sqrt(sn);
+    if (last && tol_step > 0.0 && sqrt(sn) > tol_step * (1.0 + sqrt(zn2)) && status)
+        status[b] |= MR_FLAG_NOCONV;
+}
+
+__global__ void finish_kernel(int B, int r, const double *z, const double *v, const double *fnew,
+                              int iters, double *z_out, double *v_out, int32_t *iters_out,
+                              double *resid_out, const int32_t *status_in, int32_t *status_out,
+                              int accumulate)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B * r) return;
+    z_out[t] = z[t];
+    v_out[t] = v[t];
+    if (t % r == 0) {
+        int b = t / r;
+        if (iters_out) iters_out[b] = iters;
+        if (resid_out) resid_out[b] = fnew ? fnew[b] : 0.0;
+        if (status_out) status_out[b] = accumulate ? (status_out[b] | status_in[b]) : status_in[b];
+    }
+}
+
+int64_t proj_ws_bytes(int d, int r, int B, int64_t ns, int max_backtrack)
+{
+    int nc = max_backtrack + 1;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t o = off;
+        off += (bytes + 255) & ~(int64_t)255;
+        return o;
+    };
+    take(4LL * B * d * r * ns);       // Jz
+    take(4LL * B * d * ns);           // x
+    take(4LL * B * nc * d * ns);      // candidate x
+    take(8LL * B * r * r);            // A
+    take(8LL * B * r * r);            // L
+    take(8LL * B * r);                // rhs / g
+    take(8LL * B * r);                // delta
+    take(8LL * B * r);                // z
+    take(8LL * B * r);                // v
+    take(8LL * B * nc * r);           // candidate z
+    take(8LL * B);                    // f
+    take(8LL * B * nc);               // fc
+    take(8LL * B);                    // fnew
+    take(8LL * B);                    // step norm
+    take(4LL * B);                    // status
+    take(4LL * B);                    // singular
+    return off;
+}
+
+ProjWS proj_ws_carve(void *base, int d, int r, int B, int64_t ns, int max_backtrack)
+{
+    int nc = max_backtrack + 1;
+    char *p = (char *)base;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        char *q = p + off;
+        off += (bytes + 255) & ~(int64_t)255;
+        return q;
+    };
+    ProjWS w;
+    w.Jz = (float *)take(4LL * B * d * r * ns);
+    w.x = (float *)take(4LL * B * d * ns);
+    w.xc = (float *)take(4LL * B * nc * d * ns);
+    w.A = (double *)take(8LL * B * r * r);
+    w.L = (double *)take(8LL * B * r * r);
+    w.g = (double *)take(8LL * B * r);
+    w.delta = (double *)take(8LL * B * r);
+    w.z = (double *)take(8LL * B * r);
+    w.v = (double *)take(8LL * B * r);
+    w.zc = (double *)take(8LL * B * nc * r);
+    w.f = (double *)take(8LL * B);
+    w.fc = (double *)take(8LL * B * nc);
+    w.fnew = (double *)take(8LL * B);
+    w.step = (double *)take(8LL * B);
+    w.status = (int32_t *)take(4LL * B);
+    w.singular = (int32_t *)take(4LL * B);
+    return w;
+}
+
+int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_ref, const float *X,
+                     int64_t ns, const int32_t *idx, const int32_t *ns_inst, const float *x_trial,
+                     const float *v_trial, const double *zn, const double *zp, double dt,
+                     const mr_gn_opts &o, double *z_out, double *v_out, int32_t *iters_out,
+                     double *resid_out, int32_t *status_out, const ProjWS &w, hipStream_t st,
+                     int accumulate)
+{
+    const int nc = o.max_backtrack + 1;
+    const int TB = 256;
+    int32_t rc;
+    size_t ne_lds = sizeof(float) * (size_t)(d * r + d) * NE_CHUNK;
+    zero_i32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>(w.status, B);
+    zero_i32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>(w.singular, B);
+    // velocity least squares at zn
+    rc = decode_jac_ex(dec, B, n_ref, X, ns, idx, 1, ns_inst, zn, nullptr, w.x, nullptr, nullptr,
+                       w.Jz, st);
+    if (rc != MR_OK) return rc;
+    normal_eq_kernel<0><<<B, NE_THREADS, ne_lds, st>>>(d, r, ns, ns_inst, w.Jz, v_trial, nullptr,
+                                                      w.A, w.g, nullptr);
+    cholesky_solve_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(B, r, w.A, w.g, o.damping, 1.0,
+                                                                    w.v, w.L, w.status, w.singular);
+    init_guess_kernel<<<(unsigned)ceil_div((int64_t)B * r, TB), TB, 0, st>>>(
+        B, r, o.mode, dt, zn, zp, w.v, w.singular, w.z, w.v);
+    MR_LAUNCH_CHECK();
+    int iters = 0;
+    const double *fres = nullptr;
+    if (o.mode == MR_POS_VEL) {
+        for (int it = 0; it < o.max_iter; ++it) {
+            rc = decode_jac_ex(dec, B, n_ref, X, ns, idx, 1, ns_inst, w.z, nullptr, w.x, nullptr,
+                               nullptr, w.Jz, st);
+            if (rc != MR_OK) return rc;
+            normal_eq_kernel<1><<<B, NE_THREADS, ne_lds, st>>>(d, r, ns, ns_inst, w.Jz, x_trial,
+                                                              w.x, w.A, w.g, w.f);
+            cholesky_solve_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(
+                B, r, w.A, w.g, o.damping, -1.0, w.delta, w.L, w.status, nullptr);
+            candidates_kernel<<<(unsigned)ceil_div((int64_t)B * nc * r, TB), TB, 0, st>>>(
+                B, r, nc, w.z, w.delta, w.zc);
+            MR_LAUNCH_CHECK();
+            rc = decode_jac_ex(dec, B * nc, n_ref, X, ns, idx, nc, nullptr, w.zc, nullptr, w.xc,
+                               nullptr, nullptr, nullptr, st);
+            if (rc != MR_OK) return rc;
+            objective_kernel<<<B * nc, 256, 0, st>>>(d, ns, nc, ns_inst, w.xc, x_trial, w.fc);
+            select_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(
+                B, r, nc, o.armijo_c, o.tol_step, w.f, w.g, w.delta, w.fc, w.singular, w.z, w.fnew,
+                w.step, w.status, it == o.max_iter - 1 ? 1 : 0);
+            MR_LAUNCH_CHECK();
+        }
+        iters = o.max_iter;
+        fres = o.max_iter > 0 ? w.fnew : nullptr;
+    }
+    finish_kernel<<<(unsigned)ceil_div((int64_t)B * r, TB), TB, 0, st>>>(
+        B, r, w.z, w.v, fres, iters, z_out, v_out, iters_out, resid_out, w.status, status_out,
+        accumulate);
+    MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
+bool opts_ok(const mr_gn_opts *o)
+{
+    return o && (o->mode == MR_POS_VEL || o->mode == MR_VEL_ONLY) && o->max_iter >= 0 &&
+           o->max_iter <= 64 && o->max_backtrack >= 0 && o->max_backtrack <= 30 &&
+           o->damping >= 0.0;
+}
+
+}  // namespace mr
+
+using namespace mr;
+
+// Workspace cached per process for the stand-alone entry point.
+static void *g_proj_ws = nullptr;
+static int64_t g_proj_ws_bytes = 0;
+
+extern "C" int32_t rom_project(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X,
+                               int64_t ns, const int32_t *sample_idx,
+                               const int32_t *ns_per_instance, const float *x_trial,
+                               const float *v_trial, const double *xhat_n,
+                               const double *xhat_prev, double dt, const mr_gn_opts *opts,
+                               double *xhat_next, double *vhat_next, int32_t *iters_out,
+                               double *resid_out, int32_t *status_out, void *stream)
+{
+    if (!dec || B < 1 || ns < 1 || !X || !sample_idx || !v_trial || !xhat_n || !opts_ok(opts) ||
+        !xhat_next || !vhat_next)
+        return MR_EINVAL;
+    if (opts->mode == MR_POS_VEL && (!x_trial || !xhat_prev)) return MR_EINVAL;
+    int d = decoder_dim(dec), r = decoder_latent(dec);
+    if ((int64_t)B * (opts->max_backtrack + 1) > 65535) return MR_EINVAL;
+    hipStream_t st = as_stream(stream);
+    int64_t need = proj_ws_bytes(d, r, B, ns, opts->max_backtrack);
+    if (need > g_proj_ws_bytes) {
+        MR_CHECK_HIP(hipStreamSynchronize(st));
+        if (g_proj_ws) (void)hipFree(g_proj_ws);
+        g_proj_ws = nullptr;
+        g_proj_ws_bytes = 0;
+        if (hipMalloc(&g_proj_ws, need) != hipSuccess) return MR_ENOMEM;
+        g_proj_ws_bytes = need;
+    }
+    ProjWS w = proj_ws_carve(g_proj_ws, d, r, B, ns, opts->max_backtrack);
+    return project_impl(dec, d, r, B, n_ref, X, ns, sample_idx, ns_per_instance, x_trial, v_trial,
+                        xhat_n, xhat_prev ? xhat_prev : xhat_n, dt, *opts, xhat_next, vhat_next,
+                        iters_out, resid_out, status_out, w, st);
+}

@@ -1,0 +1,550 @@
+// Reduced-order-model step on gfx950 (paper Section 3.2, Algorithm 2):
+// sample-point selection (Section 3.2.1), Lagrangian-quadrature kinematics
+// (Algorithm 3), sample-point MPM substep (Algorithm 5) and projection
+// (Algorithms 6 / 7), batched over B parameter instances with a fixed launch
+// sequence per step so that K steps can be captured in one HIP graph.
+//
+// Per step and instance b:
+//   1. samples: stratified counter-based draw (SplitMix64), no host input;
+//   2. decode every reference particle at xhat_n (needed to find the
+//      neighbours, Algorithm 3 step 3);
+//   3. mark the 3^d stencil nodes of every sample in a node bitmap (the
+//      active nodes I);
+//   4. a particle is a quadrature point when any node of its stencil is
+//      marked; quadrature points are compacted into Q_b (block scan plus one
+//      atomic per block: order inside Q_b is by block, which only permutes
+//      the float-atomic summation order of the next step);
+//   5. decode x, F = dg/dX, v = (dg/dxhat) vhat at Q_b;
+//   6. P2G of Q_b (plain transfer, C = 0, m_p, V0 = m_p / rho0, the
+//      instance's Young's modulus) into the instance's grid, skipping nodes
+//      outside I;
+//   7. for every sample, the grid update of its 3^d nodes (v = p/m + dt g,
+//      boundary band) fused into the trial G2P: v_trial, x_trial = x + dt v;
+//   8. projection of (x_trial, v_trial) onto the manifold.
+#include "mpm_kernels.h"
+#include "project.h"
+
+#include <stdlib.h>
+
+#include <vector>
+
+struct mr_rom {
+    const mr_decoder *dec;
+    int d, r;
+    mr::GridK g;
+    mr_rom_config cfg;
+    mr_gn_opts opts;
+    int B;
+    int64_t P, ns_max, q_cap, nodes, words;
+    float *X, *m, *E;
+    int32_t *n_samples;
+    int32_t *samples;   // [B][ns_max]
+    float *x_all;       // [B][d][P]
+    uint32_t *bitmap;   // [B][words]
+    int32_t *Q;         // [B][q_cap]
+    int32_t *q_count;   // [B]
+    int32_t *n_active;  // [B]
+    float *xQ, *FQ, *vQ;
+    float *grid;        // [B][nodes][4]
+    float *xs, *xt, *vt;
+    double *z_next, *v_next;
+    int32_t *status_step;  // [B]
+    int64_t *counter;      // device step counter
+    void *proj_ws;
+    hipStream_t cap_stream;
+    hipGraphExec_t graph;
+    int graph_steps;
+    double graph_dt;
+    double *graph_ptrs[3];
+    int32_t *graph_status;
+};
+
+namespace mr {
+
+__device__ __forceinline__ uint64_t mix64(uint64_t c)
+{
+    uint64_t z = c + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void sample_kernel(uint64_t seed, const int64_t *counter, int64_t P, int ns_max,
+                              const int32_t *n_samples, int32_t *samples)
+{
+    const int b = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ns_max) return;
+    const int64_t S = n_samples[b];
+    const uint64_t step = (uint64_t)(*counter);
+    const uint64_t key = mix64(mix64(mix64(seed) ^ (uint64_t)b) ^ step);
+    int32_t idx;
+    if (k < S) {
+        int64_t lo = ((int64_t)k * P) / S, hi = ((int64_t)(k + 1) * P) / S;
+        idx = (int32_t)(lo + (int64_t)(mix64(key ^ (uint64_t)k) % (uint64_t)(hi - lo)));
+    } else {
+        idx = 0;  // padding entry, masked by the per-instance count
+    }
+    samples[(int64_t)b * ns_max + k] = idx;
+}
+
+template <int D>
+__global__ void gather_mark_kernel(GridK g, int64_t P, int ns_max, const int32_t *n_samples,
+                                   const int32_t *samples, const float *x_all, float *xs,
+                                   uint32_t *bitmap, int64_t words, int32_t *status)
+{
+    const int b = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ns_max) return;
+    const int64_t q = samples[(int64_t)b * ns_max + k];
+    float xp[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        xp[a] = x_all[((int64_t)b * D + a) * P + q];
+        xs[((int64_t)b * D + a) * ns_max + k] = xp[a];
+    }
+    if (k >= n_samples[b]) return;
+    Stencil<D> st;
+    if (!make_stencil<D>(g, xp, st)) {
+        atomicOr(status + b, MR_FLAG_DOMAIN);
+        return;
+    }
+    uint32_t *bm = bitmap + (int64_t)b * words;
+    const int oz = (D == 3) ? 3 : 1;
+    for (int o2 = 0; o2 < oz; ++o2)
+        for (int o1 = 0; o1 < 3; ++o1)
+            for (int o0 = 0; o0 < 3; ++o0) {
+                int64_t i = node_lin(g, st.base[0] + o0, st.base[1] + o1, D == 3 ? st.base[2] + o2 : 0);
+                atomicOr(bm + (i >> 5), 1u << (i & 31));
+            }
+}
+
+__device__ __forceinline__ bool bit_set(const uint32_t *bm, int64_t i)
+{
+    return (bm[i >> 5] >> (i & 31)) & 1u;
+}
+
+constexpr int NB_BLOCK = 1024;
+
+template <int D>
+__global__ void __launch_bounds__(NB_BLOCK) neighbour_kernel(GridK g, int64_t P, int64_t words,
+                                                             const float *x_all,
+                                                             const uint32_t *bitmap, int32_t *Q,
+                                                             int64_t q_cap, int32_t *q_count,
+                                                             int32_t *status)
+{
+    __shared__ int sh[NB_BLOCK];
+    __shared__ int base_sh;
+    const int b = blockIdx.y;
+    const int64_t q = (int64_t)blockIdx.x * NB_BLOCK + threadIdx.x;
+    int flag = 0;
+    if (q < P) {
+        float xp[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) xp[a] = x_all[((int64_t)b * D + a) * P + q];
+        Stencil<D> st;
+        if (make_stencil<D>(g, xp, st)) {
+            const uint32_t *bm = bitmap + (int64_t)b * words;
+            const int oz = (D == 3) ? 3 : 1;
+            for (int o2 = 0; o2 < oz && !flag; ++o2)
+                for (int o1 = 0; o1 < 3 && !flag; ++o1)
+                    for (int o0 = 0; o0 < 3 && !flag; ++o0)
+                        flag = bit_set(bm, node_lin(g, st.base[0] + o0, st.base[1] + o1,
+                                                    D == 3 ? st.base[2] + o2 : 0));
+        }
+        // a decoded particle outside the lattice cannot touch the sample nodes
+    }
+    // block-wide exclusive scan of the flags (Hillis-Steele)
+    const int t = threadIdx.x;
+    sh[t] = flag;
+    __syncthreads();
+    for (int off = 1; off < NB_BLOCK; off <<= 1) {
+        int add = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int total = sh[NB_BLOCK - 1];
+    if (t == 0) base_sh = total ? atomicAdd(q_count + b, total) : 0;
+    __syncthreads();
+    if (flag) {
+        int64_t pos = (int64_t)base_sh + sh[t] - 1;
+        if (pos < q_cap)
+            Q[(int64_t)b * q_cap + pos] = (int32_t)q;
+        else
+            atomicOr(status + b, MR_FLAG_DOMAIN);  // quadrature capacity exceeded
+    }
+}
+
+__global__ void clamp_count_kernel(int B, int32_t *q_count, int64_t q_cap)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B && q_count[b] > q_cap) q_count[b] = (int32_t)q_cap;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) p2g_quad_kernel(GridK g, int64_t q_cap, int64_t words,
+                                                       const int32_t *q_count, const int32_t *Q,
+                                                       const float *xQ, const float *FQ,
+                                                       const float *vQ, const float *m_all,
+                                                       float m_uniform, float inv_rho0,
+                                                       const float *E, float nu, int model,
+                                                       float dt, const uint32_t *bitmap,
+                                                       float *grid, int64_t nodes, int32_t *status)
+{
+    const int b = blockIdx.y;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= q_count[b]) return;
+    float xp[D], vp[D], Fp[D * D], tau[D * D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        xp[a] = xQ[((int64_t)b * D + a) * q_cap + s];
+        vp[a] = vQ[((int64_t)b * D + a) * q_cap + s];
+    }
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Fp[k] = FQ[((int64_t)b * D * D + k) * q_cap + s];
+    Lame lm = lame_of(E[b], nu);
+    Stencil<D> st;
+    bool ok = make_stencil<D>(g, xp, st);
+    ok = kirchhoff<D>(model, lm.mu, lm.la, Fp, tau) && ok;
+    if (!ok) {
+        atomicOr(status + b, MR_FLAG_DOMAIN);
+        return;
+    }
+    const int32_t q = Q[(int64_t)b * q_cap + s];
+    float m = m_all ? m_all[q] : m_uniform;
+    P2GPayload<D> pl;
+    pl.m = m;
+    float sc = dt * m * inv_rho0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) pl.mv[a] = m * vp[a];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+        pl.mC[k] = 0.0f;
+        pl.S[k] = sc * tau[k];
+    }
+    const uint32_t *bm = bitmap + (int64_t)b * words;
+    float *gb = grid + (int64_t)b * nodes * 4;
+    const int oz = (D == 3) ? 3 : 1;
+    for (int o2 = 0; o2 < oz; ++o2)
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+            for (int o0 = 0; o0 < 3; ++o0) {
+                int64_t i = node_lin(g, st.base[0] + o0, st.base[1] + o1, D == 3 ? st.base[2] + o2 : 0);
+                if (!bit_set(bm, i)) continue;
+                float mom[D];
+                float mw = p2g_node<D>(g, st, pl, o0, o1, o2, mom);
+                float *gp = gb + 4 * i;
+                atomicAdd(gp, mw);
+#pragma unroll
+                for (int a = 0; a < D; ++a) atomicAdd(gp + 1 + a, mom[a]);
+            }
+}
+
+template <int D>
+__global__ void g2p_trial_kernel(GridK g, int ns_max, const int32_t *n_samples, const float *xs,
+                                 const float *grid, int64_t nodes, float dt, float *xt, float *vt)
+{
+    const int b = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ns_max) return;
+    float xp[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) xp[a] = xs[((int64_t)b * D + a) * ns_max + k];
+    Stencil<D> st;
+    float vp[D] = {};
+    if (k < n_samples[b] && make_stencil<D>(g, xp, st)) {
+        const float4 *gb = reinterpret_cast<const float4 *>(grid) + (int64_t)b * nodes;
+        const float gr[3] = {g.g0, g.g1, g.g2};
+        const int oz = (D == 3) ? 3 : 1;
+        for (int o2 = 0; o2 < oz; ++o2)
+            for (int o1 = 0; o1 < 3; ++o1)
+                for (int o0 = 0; o0 < 3; ++o0) {
+                    int i0 = st.base[0] + o0, i1 = st.base[1] + o1, i2 = D == 3 ? st.base[2] + o2 : 0;
+                    float4 q = gb[node_lin(g, i0, i1, i2)];
+                    if (!(q.x > 0.0f)) continue;
+                    float inv = 1.0f / q.x;
+                    float vi[3] = {q.y * inv + dt * gr[0], q.z * inv + dt * gr[1],
+                                   D == 3 ? q.w * inv + dt * gr[2] : 0.0f};
+                    apply_bc<D>(g, i0, i1, i2, vi);
+                    float w = st.w[0][o0] * st.w[1][o1] * (D == 3 ? st.w[2][o2] : 1.0f);
+#pragma unroll
+                    for (int a = 0; a < D; ++a) vp[a] += w * vi[a];
+                }
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        vt[((int64_t)b * D + a) * ns_max + k] = vp[a];
+        xt[((int64_t)b * D + a) * ns_max + k] = xp[a] + dt * vp[a];
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t *a, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0u;
+}
+
+__global__ void fill_f4_kernel(float4 *a, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+__global__ void advance_kernel(int B, int r, double *z, double *zp, double *v, const double *zn,
+                               const double *vn, const int32_t *status_step, int32_t *status_out,
+                               int64_t *counter)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < B * r) {
+        zp[t] = z[t];
+        z[t] = zn[t];
+        v[t] = vn[t];
+    }
+    if (t < B && status_out) status_out[t] |= status_step[t];
+    if (t == 0) *counter += 1;
+}
+
+__global__ void set_counter_kernel(int64_t *counter, int64_t v) { *counter = v; }
+
+int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, double *vhat,
+                     int32_t *status_out, hipStream_t st)
+{
+    const int B = R->B, d = R->d, r = R->r;
+    const GridK &g = R->g;
+    const int TB = 256;
+    int32_t rc;
+    dim3 gs((unsigned)ceil_div(R->ns_max, TB), (unsigned)B);
+    fill_u32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>((uint32_t *)R->status_step, B);
+    fill_u32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>((uint32_t *)R->q_count, B);
+    fill_u32_kernel<<<2048, TB, 0, st>>>(R->bitmap, (int64_t)B * R->words);
+    fill_f4_kernel<<<4096, TB, 0, st>>>(reinterpret_cast<float4 *>(R->grid), (int64_t)B * R->nodes);
+    sample_kernel<<<gs, TB, 0, st>>>(R->cfg.seed, R->counter, R->P, (int)R->ns_max, R->n_samples,
+                                      R->samples);
+    MR_LAUNCH_CHECK();
+    // Algorithm 3: decode every particle, mark I, collect Q
+    rc = rom_decode(R->dec, B, R->P, R->X, R->P, nullptr, xhat, R->x_all, st);
+    if (rc != MR_OK) return rc;
+    if (d == 2)
+        gather_mark_kernel<2><<<gs, TB, 0, st>>>(g, R->P, (int)R->ns_max, R->n_samples, R->samples,
+                                                 R->x_all, R->xs, R->bitmap, R->words, R->status_step);
+    else
+        gather_mark_kernel<3><<<gs, TB, 0, st>>>(g, R->P, (int)R->ns_max, R->n_samples, R->samples,
+                                                 R->x_all, R->xs, R->bitmap, R->words, R->status_step);
+    dim3 gn((unsigned)ceil_div(R->P, NB_BLOCK), (unsigned)B);
+    if (d == 2)
+        neighbour_kernel<2><<<gn, NB_BLOCK, 0, st>>>(g, R->P, R->words, R->x_all, R->bitmap, R->Q,
+                                                     R->q_cap, R->q_count, R->status_step);
+    else
+        neighbour_kernel<3><<<gn, NB_BLOCK, 0, st>>>(g, R->P, R->words, R->x_all, R->bitmap, R->Q,
+                                                     R->q_cap, R->q_count, R->status_step);
+    clamp_count_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>(B, R->q_count, R->q_cap);
+    MR_LAUNCH_CHECK();
+    // quadrature kinematics (Algorithm 3, step 4)
+    rc = decode_jac_ex(R->dec, B, R->P, R->X, R->q_cap, R->Q, 1, R->q_count, xhat, vhat, R->xQ,
+                       R->FQ, R->vQ, nullptr, st);
+    if (rc != MR_OK) return rc;
+    // Algorithm 5
+    dim3 gq((unsigned)ceil_div(R->q_cap, TB), (unsigned)B);
+    float inv_rho0 = 1.0f / R->cfg.rho0;
+    if (d == 2)
+        p2g_quad_kernel<2><<<gq, TB, 0, st>>>(g, R->q_cap, R->words, R->q_count, R->Q, R->xQ, R->FQ,
+                                              R->vQ, R->m, R->cfg.m_uniform, inv_rho0, R->E,
+                                              R->cfg.nu, R->cfg.model, (float)dt, R->bitmap,
+                                              R->grid, R->nodes, R->status_step);
+    else
+        p2g_quad_kernel<3><<<gq, TB, 0, st>>>(g, R->q_cap, R->words, R->q_count, R->Q, R->xQ, R->FQ,
+                                              R->vQ, R->m, R->cfg.m_uniform, inv_rho0, R->E,
+                                              R->cfg.nu, R->cfg.model, (float)dt, R->bitmap,
+                                              R->grid, R->nodes, R->status_step);
+    if (d == 2)
+        g2p_trial_kernel<2><<<gs, TB, 0, st>>>(g, (int)R->ns_max, R->n_samples, R->xs, R->grid,
+                                               R->nodes, (float)dt, R->xt, R->vt);
+    else
+        g2p_trial_kernel<3><<<gs, TB, 0, st>>>(g, (int)R->ns_max, R->n_samples, R->xs, R->grid,
+                                               R->nodes, (float)dt, R->xt, R->vt);
+    MR_LAUNCH_CHECK();
+    // Algorithm 6 / 7
+    ProjWS w = proj_ws_carve(R->proj_ws, d, r, B, R->ns_max, R->opts.max_backtrack);
+    rc = project_impl(R->dec, d, r, B, R->P, R->X, R->ns_max, R->samples, R->n_samples, R->xt,
+                      R->vt, xhat, xhat_prev, dt, R->opts, R->z_next, R->v_next, nullptr, nullptr,
+                      R->status_step, w, st, /*accumulate=*/1);
+    if (rc != MR_OK) return rc;
+    advance_kernel<<<(unsigned)ceil_div((int64_t)B * r, TB), TB, 0, st>>>(
+        B, r, xhat, xhat_prev, vhat, R->z_next, R->v_next, R->status_step, status_out, R->counter);
+    MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
+}  // namespace mr
+
+using namespace mr;
+
+extern "C" void rom_destroy(mr_rom *R)
+{
+    if (!R) return;
+    void *bufs[] = {R->X, R->m, R->E, R->n_samples, R->samples, R->x_all, R->bitmap, R->Q,
+                    R->q_count, R->n_active, R->xQ, R->FQ, R->vQ, R->grid, R->xs, R->xt, R->vt,
+                    R->z_next, R->v_next, R->status_step, R->counter, R->proj_ws};
+    for (void *p : bufs)
+        if (p) (void)hipFree(p);
+    if (R->graph) (void)hipGraphExecDestroy(R->graph);
+    if (R->cap_stream) (void)hipStreamDestroy(R->cap_stream);
+    free(R);
+}
+
+extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
+                              const mr_rom_config *cfg, const float *X_all, const float *m_all,
+                              const float *E, const int32_t *n_samples, const mr_gn_opts *opts,
+                              mr_rom **out)
+{
+    GridK g;
+    if (!dec || !out || !cfg || !X_all || !E || !n_samples || !opts_ok(opts) ||
+        !grid_from_desc(grid_desc, g))
+        return MR_EINVAL;
+    int d = decoder_dim(dec), r = decoder_latent(dec);
+    if (d != grid_desc->dim || cfg->B < 1 || cfg->B > 65535 || cfg->n_particles < 1 ||
+        cfg->n_particles > INT32_MAX || cfg->n_samples_max < 1 ||
+        cfg->n_samples_max > cfg->n_particles || !(cfg->rho0 > 0.0f))
+        return MR_EINVAL;
+    if (cfg->model == MR_FIXED_COROTATED && d != 2) return MR_EINVAL;
+    if ((int64_t)cfg->B * (opts->max_backtrack + 1) > 65535) return MR_EINVAL;
+    mr_rom *R = (mr_rom *)calloc(1, sizeof(mr_rom));
+    if (!R) return MR_ENOMEM;
+    R->dec = dec;
+    R->d = d;
+    R->r = r;
+    R->g = g;
+    R->cfg = *cfg;
+    R->opts = *opts;
+    R->B = cfg->B;
+    R->P = cfg->n_particles;
+    R->ns_max = cfg->n_samples_max;
+    R->nodes = grid_nodes(g);
+    R->words = ceil_div(R->nodes, 32);
+    // quadrature capacity: every sample's 3^d nodes are reached from a
+    // (5 cells)^d box; allow 16 particles per cell
+    int64_t per = (d == 3) ? 125 * 16 : 25 * 16;
+    R->q_cap = R->ns_max * per < R->P ? R->ns_max * per : R->P;
+    const int64_t B = R->B, P = R->P;
+    bool ok = true;
+    auto alloc = [&](void **p, int64_t bytes) {
+        if (ok && hipMalloc(p, bytes > 0 ? bytes : 4) != hipSuccess) ok = false;
+    };
+    alloc((void **)&R->X, 4 * d * P);
+    if (m_all) alloc((void **)&R->m, 4 * P);
+    alloc((void **)&R->E, 4 * B);
+    alloc((void **)&R->n_samples, 4 * B);
+    alloc((void **)&R->samples, 4 * B * R->ns_max);
+    alloc((void **)&R->x_all, 4 * B * d * P);
+    alloc((void **)&R->bitmap, 4 * B * R->words);
+    alloc((void **)&R->Q, 4 * B * R->q_cap);
+    alloc((void **)&R->q_count, 4 * B);
+    alloc((void **)&R->xQ, 4 * B * d * R->q_cap);
+    alloc((void **)&R->FQ, 4 * B * d * d * R->q_cap);
+    alloc((void **)&R->vQ, 4 * B * d * R->q_cap);
+    alloc((void **)&R->grid, 16 * B * R->nodes);
+    alloc((void **)&R->xs, 4 * B * d * R->ns_max);
+    alloc((void **)&R->xt, 4 * B * d * R->ns_max);
+    alloc((void **)&R->vt, 4 * B * d * R->ns_max);
+    alloc((void **)&R->z_next, 8 * B * r);
+    alloc((void **)&R->v_next, 8 * B * r);
+    alloc((void **)&R->status_step, 4 * B);
+    alloc((void **)&R->counter, 8);
+    alloc(&R->proj_ws, proj_ws_bytes(d, r, (int)B, R->ns_max, opts->max_backtrack));
+    if (!ok) {
+        rom_destroy(R);
+        return MR_ENOMEM;
+    }
+    std::vector<int32_t> ns_host(B);
+    if (hipMemcpy(ns_host.data(), n_samples, 4 * B, hipMemcpyDeviceToHost) != hipSuccess) {
+        rom_destroy(R);
+        return MR_EDEVICE;
+    }
+    for (int32_t v : ns_host)
+        if (v < 1 || v > R->ns_max) {
+            rom_destroy(R);
+            return MR_EINVAL;
+        }
+    bool cp = hipMemcpy(R->X, X_all, 4 * d * P, hipMemcpyDeviceToDevice) == hipSuccess &&
+              hipMemcpy(R->E, E, 4 * B, hipMemcpyDeviceToDevice) == hipSuccess &&
+              hipMemcpy(R->n_samples, n_samples, 4 * B, hipMemcpyDeviceToDevice) == hipSuccess &&
+              (!m_all || hipMemcpy(R->m, m_all, 4 * P, hipMemcpyDeviceToDevice) == hipSuccess);
+    if (!cp || hipStreamCreateWithFlags(&R->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        rom_destroy(R);
+        return MR_EDEVICE;
+    }
+    *out = R;
+    return MR_OK;
+}
+
+extern "C" int32_t rom_step(mr_rom *R, int32_t n_steps, int64_t step0, double dt, double *xhat,
+                            double *xhat_prev, double *vhat, int32_t *status_out, int32_t use_graph,
+                            void *stream)
+{
+    if (!R || n_steps < 0 || !xhat || !xhat_prev || !vhat || step0 < 0) return MR_EINVAL;
+    hipStream_t st = as_stream(stream);
+    set_counter_kernel<<<1, 1, 0, st>>>(R->counter, step0);
+    MR_LAUNCH_CHECK();
+    if (n_steps == 0) return MR_OK;
+    if (!use_graph) {
+        for (int32_t s = 0; s < n_steps; ++s) {
+            int32_t rc = rom_one_step(R, dt, xhat, xhat_prev, vhat, status_out, st);
+            if (rc != MR_OK) return rc;
+        }
+        return MR_OK;
+    }
+    bool reuse = R->graph && R->graph_steps == n_steps && R->graph_dt == dt &&
+                 R->graph_ptrs[0] == xhat && R->graph_ptrs[1] == xhat_prev &&
+                 R->graph_ptrs[2] == vhat && R->graph_status == status_out;
+    if (!reuse) {
+        if (R->graph) {
+            (void)hipGraphExecDestroy(R->graph);
+            R->graph = nullptr;
+        }
+        hipGraph_t graph;
+        MR_CHECK_HIP(hipStreamBeginCapture(R->cap_stream, hipStreamCaptureModeThreadLocal));
+        int32_t rc = MR_OK;
+        for (int32_t s = 0; s < n_steps && rc == MR_OK; ++s)
+            rc = rom_one_step(R, dt, xhat, xhat_prev, vhat, status_out, R->cap_stream);
+        hipError_t e = hipStreamEndCapture(R->cap_stream, &graph);
+        if (rc != MR_OK) return rc;
+        if (e != hipSuccess) return MR_EDEVICE;
+        e = hipGraphInstantiate(&R->graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            R->graph = nullptr;
+            return MR_EDEVICE;
+        }
+        R->graph_steps = n_steps;
+        R->graph_dt = dt;
+        R->graph_ptrs[0] = xhat;
+        R->graph_ptrs[1] = xhat_prev;
+        R->graph_ptrs[2] = vhat;
+        R->graph_status = status_out;
+    }
+    MR_CHECK_HIP(hipGraphLaunch(R->graph, st));
+    return MR_OK;
+}
+
+extern "C" int32_t rom_last_counts(const mr_rom *R, int32_t b, int64_t *n_quad, int64_t *n_active,
+                                   void *stream)
+{
+    if (!R || b < 0 || b >= R->B || !n_quad || !n_active) return MR_EINVAL;
+    hipStream_t st = as_stream(stream);
+    int32_t q = 0;
+    MR_CHECK_HIP(hipMemcpyAsync(&q, R->q_count + b, 4, hipMemcpyDeviceToHost, st));
+    // active nodes: population count of the instance's bitmap
+    std::vector<uint32_t> bm(R->words);
+    MR_CHECK_HIP(hipMemcpyAsync(bm.data(), R->bitmap + (int64_t)b * R->words, 4 * R->words,
+                                hipMemcpyDeviceToHost, st));
+    MR_CHECK_HIP(hipStreamSynchronize(st));
+    int64_t cnt = 0;
+    for (uint32_t w : bm) cnt += __builtin_popcount(w);
+    *n_quad = q;
+    *n_active = cnt;
+    return MR_OK;
+}

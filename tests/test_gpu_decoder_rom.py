@@ -1,0 +1,272 @@
+"""Parity of the HIP decoder (rom_decode, rom_decode_jac), projection
+(rom_project) and reduced-order step (rom_step) with the FP64 oracle.
+
+Tolerances.  fp32 mode: each output is a chain of fp32 dot products of
+length <= 128 through <= 6 layers; errors are compared against the scale of
+the quantity (max |std * y| for positions, max |F - I|, max |J|) and must stay
+below 1e-4 of it.  bf16 mode: the hidden-layer operands are rounded to bf16
+(unit roundoff 2^-9 = 2e-3) for activations and weights of 4 layers, so the
+network output carries a relative error of order sqrt(8) * 2e-3 ~ 6e-3 of its
+scale; the bound used is 3e-2 of the scale, and the measured error is
+printed.  Projection and ROM-step outputs inherit the fp32 decoder error
+amplified by the conditioning of the r x r normal matrix; they are compared
+to 1e-3 of the latent scale."""
+import numpy as np
+import pytest
+
+from oracle import decoder as OD
+from oracle import project as OP
+from oracle import rom as OR
+from paper_2109_12390_amd import binding as B
+from paper_2109_12390_amd import scenes
+from tests.helpers import oracle_scene, soa
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+dev = "cuda"
+
+
+def T(a, dtype=torch.float32):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=dev)
+
+
+def make_decoder(d, r, width, nh, seed, X, out_std=0.05, mode=OD.OUT_DISPLACEMENT, prec=B.PREC_FP32,
+                 scale=1.0):
+    Ws, bs = scenes.random_decoder(d, r, width, nh, seed, scale=scale, bias_scale=0.1)
+    lo = X.min(0).astype(np.float32)
+    hi = X.max(0).astype(np.float32)
+    rng = np.random.default_rng(seed + 7)
+    mean = (0.01 * rng.standard_normal(d)).astype(np.float32)
+    std = np.full(d, out_std, dtype=np.float32)
+    odec = OD.Decoder(Ws, bs, lo, hi, mean, std, mode)
+    gdec = B.Decoder(Ws, bs, lo, hi, mean, std,
+                     B.OUT_DISPLACEMENT if mode == OD.OUT_DISPLACEMENT else B.OUT_POSITION, prec)
+    return odec, gdec
+
+
+def scaled_err(got, ref, scale):
+    return float(np.max(np.abs(np.asarray(got, np.float64) - ref)) / scale)
+
+
+CASES = [(3, 16, 128, 5), (3, 4, 8, 3), (2, 3, 32, 2), (3, 16, 64, 4)]
+
+
+@pytest.mark.parametrize("prec", [B.PREC_FP32, B.PREC_BF16])
+@pytest.mark.parametrize("d,r,width,nh", CASES)
+def test_decode_and_jacobians(gpu, d, r, width, nh, prec):
+    rng = np.random.default_rng(d * 100 + r + width)
+    n = 1000 + 37      # several tiles plus a ragged tail
+    X = rng.uniform(0.2, 0.8, size=(n, d)).astype(np.float32)
+    odec, gdec = make_decoder(d, r, width, nh, 5 + r, X, prec=prec)
+    Bn = 2
+    z = (0.5 * rng.standard_normal((Bn, r)))
+    vh = rng.standard_normal((Bn, r))
+    Xg = T(soa(X))
+    x = torch.zeros(Bn, d, n, device=dev)
+    F = torch.zeros(Bn, d * d, n, device=dev)
+    v = torch.zeros(Bn, d, n, device=dev)
+    J = torch.zeros(Bn, d * r, n, device=dev)
+    B.rom_decode_jac(gdec, Xg, T(z, torch.float64), vhat=T(vh, torch.float64), x=x, F=F, v=v, Jz=J)
+    x2 = torch.zeros(Bn, d, n, device=dev)
+    B.rom_decode(gdec, Xg, T(z, torch.float64), x2)
+    tol = 1e-4 if prec == B.PREC_FP32 else 3e-2
+    for b in range(Bn):
+        xo, Fo, Jo, vo = OD.decode_jac(odec, X.astype(np.float64), z[b], vh[b])
+        sx = np.max(np.abs(xo - X))
+        ex = scaled_err(x[b].cpu().numpy().T, xo, sx)
+        ex2 = scaled_err(x2[b].cpu().numpy().T, xo, sx)
+        eF = scaled_err(F[b].cpu().numpy().T.reshape(n, d, d), Fo, np.max(np.abs(Fo - np.eye(d))))
+        eJ = scaled_err(J[b].cpu().numpy().T.reshape(n, d, r), Jo, np.max(np.abs(Jo)))
+        ev = scaled_err(v[b].cpu().numpy().T, vo, np.max(np.abs(vo)))
+        print("prec %d d%d r%d w%d: x %.2e x(decode) %.2e F %.2e J %.2e v %.2e" %
+              (prec, d, r, width, ex, ex2, eF, eJ, ev))
+        assert max(ex, ex2, eF, eJ, ev) <= tol
+
+
+def test_decode_with_index_lists(gpu):
+    d, r = 3, 16
+    rng = np.random.default_rng(3)
+    X = rng.uniform(0.2, 0.8, size=(500, d)).astype(np.float32)
+    odec, gdec = make_decoder(d, r, 32, 3, 9, X)
+    idx = rng.integers(0, 500, size=(3, 77)).astype(np.int32)
+    z = 0.3 * rng.standard_normal((3, r))
+    x = torch.zeros(3, d, 77, device=dev)
+    J = torch.zeros(3, d * r, 77, device=dev)
+    B.rom_decode_jac(gdec, T(soa(X)), T(z, torch.float64), idx=T(idx, torch.int32), idx_per_instance=1,
+                     x=x, Jz=J)
+    for b in range(3):
+        xo, _, Jo, _ = OD.decode_jac(odec, X[idx[b]].astype(np.float64), z[b])
+        assert scaled_err(x[b].cpu().numpy().T, xo, np.max(np.abs(xo - X[idx[b]]))) < 1e-4
+        assert scaled_err(J[b].cpu().numpy().T.reshape(77, d, r), Jo, np.max(np.abs(Jo))) < 1e-4
+    # one shared index list
+    xs = torch.zeros(2, d, 77, device=dev)
+    B.rom_decode(gdec, T(soa(X)), T(z[:2], torch.float64), xs, idx=T(idx[0], torch.int32))
+    xo = OD.decode(odec, X[idx[0]].astype(np.float64), z[1])
+    assert scaled_err(xs[1].cpu().numpy().T, xo, np.max(np.abs(xo - X[idx[0]]))) < 1e-4
+
+
+@pytest.mark.parametrize("mode", [B.POS_VEL, B.VEL_ONLY])
+def test_projection_matches_oracle(gpu, mode):
+    d, r, ns, Bn = 3, 6, 64, 3
+    rng = np.random.default_rng(11)
+    P = 2000
+    X = rng.uniform(0.2, 0.8, size=(P, d)).astype(np.float32)
+    odec, gdec = make_decoder(d, r, 16, 3, 21, X, out_std=0.1, scale=1.5)
+    idx = np.sort(rng.choice(P, size=(Bn, ns), replace=True), axis=1).astype(np.int32)
+    zn = 0.4 * rng.standard_normal((Bn, r))
+    zp = zn - 0.01 * rng.standard_normal((Bn, r))
+    dt = 1e-2
+    xt = np.zeros((Bn, d, ns), np.float32)
+    vt = np.zeros((Bn, d, ns), np.float32)
+    for b in range(Bn):
+        zs = zn[b] + dt * rng.standard_normal(r)
+        xt[b] = (OD.decode(odec, X[idx[b]].astype(np.float64), zs) + 1e-4 * rng.standard_normal((ns, d))).T
+        vt[b] = rng.standard_normal((d, ns))
+    opts = B.gn_opts(mode=mode, max_iter=3)
+    zo = torch.zeros(Bn, r, dtype=torch.float64, device=dev)
+    vo = torch.zeros(Bn, r, dtype=torch.float64, device=dev)
+    st = torch.zeros(Bn, dtype=torch.int32, device=dev)
+    it = torch.zeros(Bn, dtype=torch.int32, device=dev)
+    B.rom_project(gdec, T(soa(X)), T(idx, torch.int32), T(xt), T(vt), T(zn, torch.float64),
+                  T(zp, torch.float64), dt, opts, zo, vo, iters=it, status=st)
+    oopts = OP.GNOptions(mode=OP.MODE_POS_VEL if mode == B.POS_VEL else OP.MODE_VEL_ONLY, max_iter=3,
+                         fixed_iters=True)
+    for b in range(Bn):
+        zr, vr, _, _, status = OP.project(odec, X[idx[b]].astype(np.float64), xt[b].T.astype(np.float64),
+                                          vt[b].T.astype(np.float64), zn[b], zp[b], dt, oopts)
+        ez = np.max(np.abs(zo[b].cpu().numpy() - zr)) / max(np.max(np.abs(zr - zn[b])), 1e-12)
+        ev = np.max(np.abs(vo[b].cpu().numpy() - vr)) / np.max(np.abs(vr))
+        print("mode %d b%d: latent step err %.2e velocity err %.2e status %d" % (mode, b, ez, ev, st[b].item()))
+        assert ez < 1e-3 and ev < 1e-3
+        assert st[b].item() == 0
+
+
+def test_projection_appendix_a_identity_on_gpu(gpu):
+    """One Gauss-Newton iteration from xhat_n with x_trial = g(X; xhat_n) +
+    dt v_trial equals the velocity-only update (exact in exact arithmetic)."""
+    d, r, ns = 3, 5, 48
+    rng = np.random.default_rng(12)
+    X = rng.uniform(0.2, 0.8, size=(300, d)).astype(np.float32)
+    odec, gdec = make_decoder(d, r, 16, 2, 31, X, out_std=0.1)
+    idx = rng.choice(300, size=(1, ns), replace=False).astype(np.int32)
+    zn = 0.2 * rng.standard_normal((1, r))
+    dt = 1e-3
+    xg = torch.zeros(1, d, ns, device=dev)
+    B.rom_decode(gdec, T(soa(X)), T(zn, torch.float64), xg, idx=T(idx[0], torch.int32))
+    vt = rng.standard_normal((1, d, ns)).astype(np.float32)
+    xt = xg + dt * T(vt)
+    outs = []
+    for mode in (B.POS_VEL, B.VEL_ONLY):
+        zo = torch.zeros(1, r, dtype=torch.float64, device=dev)
+        vo = torch.zeros(1, r, dtype=torch.float64, device=dev)
+        B.rom_project(gdec, T(soa(X)), T(idx, torch.int32), xt.contiguous(), T(vt), T(zn, torch.float64),
+                      T(zn, torch.float64), dt, B.gn_opts(mode=mode, max_iter=1), zo, vo)
+        outs.append(zo.cpu().numpy()[0])
+    step = np.max(np.abs(outs[1] - zn[0]))
+    print("Appendix A: |GN - vel-only| / step = %.2e" % (np.max(np.abs(outs[0] - outs[1])) / step))
+    assert np.max(np.abs(outs[0] - outs[1])) <= 1e-3 * step
+
+
+def test_projection_singular_sample_set(gpu):
+    d, r = 3, 6
+    rng = np.random.default_rng(13)
+    X = rng.uniform(0.2, 0.8, size=(50, d)).astype(np.float32)
+    _, gdec = make_decoder(d, r, 16, 2, 41, X)
+    idx = np.array([[7]], dtype=np.int32)            # 1 sample < r / d
+    zn = torch.zeros(1, r, dtype=torch.float64, device=dev)
+    zo = torch.zeros_like(zn)
+    vo = torch.zeros_like(zn)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    xt = torch.zeros(1, d, 1, device=dev)
+    B.rom_project(gdec, T(soa(X)), T(idx, torch.int32), xt, xt.clone(), zn, zn, 1e-3, B.gn_opts(), zo, vo,
+                  status=st)
+    assert st.item() & B.FLAG_SINGULAR
+    rc, _ = B.sync_status(st)
+    assert rc == B.MR_ESINGULAR
+
+
+def _rom_inputs(n=32, cube=8, seed=4):
+    s = scenes.scene_3d(n=n, cube_cells=cube, seed=seed)
+    return s
+
+
+def test_rom_step_translation_manifold_closed_form(gpu):
+    """Decoder g = X + xhat (r = 3): the ROM reproduces the free-fall
+    symplectic-Euler closed form exactly (to fp32 rounding)."""
+    s = _rom_inputs()
+    d = 3
+    W = np.concatenate([np.zeros((d, d)), np.eye(d)], axis=1).astype(np.float32)
+    X = s["X"]
+    lo, hi = X.min(0), X.max(0)
+    gdec = B.Decoder([W], [np.zeros(d, np.float32)], lo, hi, np.zeros(d), np.ones(d))
+    grid = B.Grid(3, s["n"], s["dx"], 0, B.FLOOR_STICKY, 0.0, s["gravity"])
+    E = T(np.array([5e4, 1e4], np.float32))
+    ns = T(np.array([16, 8], np.int32), torch.int32)
+    for use_graph in (False, True):
+        for mode in (B.POS_VEL, B.VEL_ONLY):
+            rom = B.Rom(gdec, grid, T(soa(X)), E, ns, B.gn_opts(mode=mode, max_iter=2), seed=3, rho0=1000.0,
+                        m_uniform=float(s["m"]))
+            z = torch.zeros(2, 3, dtype=torch.float64, device=dev)
+            zp = z.clone()
+            v0 = np.array([[0.1, -0.5, 0.2], [0.0, 0.3, -0.1]])
+            vh = T(v0, torch.float64)
+            st = torch.zeros(2, dtype=torch.int32, device=dev)
+            nst = 6
+            rom.step(nst, 0, s["dt"], z, zp, vh, status=st, use_graph=use_graph)
+            g = np.array(s["gravity"])
+            dt = s["dt"]
+            vexp = v0 + nst * dt * g
+            zexp = nst * dt * v0 + dt * dt * g * nst * (nst + 1) / 2
+            ev = np.max(np.abs(vh.cpu().numpy() - vexp))
+            ez = np.max(np.abs(z.cpu().numpy() - zexp))
+            print("graph %d mode %d: |v - closed form| %.2e |z - closed form| %.2e" % (use_graph, mode, ev, ez))
+            assert st.cpu().numpy().tolist() == [0, 0]
+            assert ev < 1e-5 and ez < 1e-8
+            rom.close()
+
+
+def test_rom_step_matches_oracle(gpu):
+    """Random fp32 decoder, 3D scene on a 32^3 grid (4,096 particles), two
+    instances with different Young's moduli and sample counts, 3 steps of the
+    position-velocity scheme against the oracle's ROM step."""
+    s = _rom_inputs(seed=6)
+    d, r = 3, 8
+    X = s["X"]
+    odec, gdec = make_decoder(d, r, 32, 3, 51, X, out_std=0.01)
+    grid = B.Grid(3, s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
+    Es = np.array([5e4, 2e4], np.float32)
+    nss = np.array([24, 12], np.int32)
+    opts = B.gn_opts(mode=B.POS_VEL, max_iter=3)
+    rom = B.Rom(gdec, grid, T(soa(X)), T(Es), T(nss, torch.int32), opts, seed=99, rho0=1000.0,
+                m_uniform=float(s["m"]))
+    rng = np.random.default_rng(52)
+    z0 = 0.2 * rng.standard_normal((2, r))
+    v0 = 0.5 * rng.standard_normal((2, r))
+    z = T(z0, torch.float64)
+    zp = T(z0, torch.float64)
+    vh = T(v0, torch.float64)
+    st = torch.zeros(2, dtype=torch.int32, device=dev)
+    nst = 3
+    rom.step(nst, 0, s["dt"], z, zp, vh, status=st)
+    q, a = rom.last_counts(0)
+    sc = oracle_scene(s)
+    P = s["P"]
+    Xd = X.astype(np.float64)
+    for b in range(2):
+        sc_b = dict(sc)
+        from oracle import mpm as OM
+        sc_b["mu"], sc_b["la"] = OM.lame(float(Es[b]), s["nu"])
+        zz, zzp, vv = z0[b].copy(), z0[b].copy(), v0[b].copy()
+        oopts = OP.GNOptions(mode=OP.MODE_POS_VEL, max_iter=3, fixed_iters=True)
+        for k in range(nst):
+            samples = OR.sample_indices(99, b, k, int(nss[b]), P)
+            zn, vn, info = OR.rom_step(odec, sc_b, Xd, sc["m"], sc["V0"], zz, zzp, vv, s["dt"], samples, oopts)
+            zzp, zz, vv = zz, zn, vn
+            if b == 0 and k == nst - 1:
+                print("oracle |Q| %d |I| %d ; gpu |Q| %d |I| %d" % (len(info["Q"]), len(info["I"]), q, a))
+        ez = np.max(np.abs(z.cpu().numpy()[b] - zz)) / np.max(np.abs(zz - z0[b]))
+        ev = np.max(np.abs(vh.cpu().numpy()[b] - vv)) / np.max(np.abs(vv))
+        print("instance %d: latent err / latent change %.2e, velocity err %.2e" % (b, ez, ev))
+        assert ez < 1e-3 and ev < 1e-3
+    assert st.cpu().numpy().tolist() == [0, 0]
+    rom.close()

@@ -1,0 +1,321 @@
+"""Parity of the HIP MPM kernels (mpm_p2g, mpm_grid_update, mpm_g2p,
+mpm_cell_sort, mpm_step) with the FP64 oracle on the same seeded inputs.
+
+Tolerances (fp32 kernels against fp64 on fp32-rounded inputs): every node or
+particle value is a short sum of fp32 products (a few ulps each, 2^-24 =
+6e-8 relative), so single-kernel outputs are compared per element with an
+absolute tolerance of 2e-5 times the largest magnitude of that channel
+(momentum and force terms cancel, so a relative bound per element would be
+meaningless).  Whole steps use the stated targets: relative L2 of particle
+positions <= 1e-5 after one step and <= 1e-3 after 100 steps, plus the
+stricter checks on velocities listed in each test."""
+import numpy as np
+import pytest
+
+from oracle import mpm as OM
+from paper_2109_12390_amd import binding as B
+from paper_2109_12390_amd import scenes
+from tests.helpers import aos, oracle_scene, rel_l2, soa, tile_slot_order
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+dev = "cuda"
+
+
+def T(a, dtype=torch.float32):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=dev)
+
+
+def make_parts(_B, x, v, C, F, m=None, V0=None, m_u=0.0, V0_u=0.0):
+    return B.Particles(T(soa(x)), T(soa(v)), T(soa(C)), T(soa(F)),
+                       None if m is None else T(np.asarray(m, dtype=np.float32)),
+                       None if V0 is None else T(np.asarray(V0, dtype=np.float32)), m_u, V0_u)
+
+
+def random_state(rng, dim, P, lo=0.3, hi=0.7, Fs=0.05):
+    x = rng.uniform(lo, hi, size=(P, dim)).astype(np.float32)
+    v = rng.standard_normal((P, dim)).astype(np.float32)
+    C = (5 * rng.standard_normal((P, dim, dim))).astype(np.float32)
+    F = (np.eye(dim) + Fs * rng.standard_normal((P, dim, dim))).astype(np.float32)
+    m = rng.uniform(0.5, 2.0, size=P).astype(np.float32) * 1e-3
+    V0 = rng.uniform(0.5, 2.0, size=P).astype(np.float32) * 1e-6
+    return x, v, C, F, m, V0
+
+
+def close_channels(got, ref, frac=2e-5, name=""):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.max(np.abs(ref), axis=0, keepdims=True)
+    scale = np.where(scale > 0, scale, 1.0)
+    err = np.max(np.abs(got - ref) / scale)
+    print("%s: max err / channel scale = %.3e" % (name, err))
+    assert err <= frac, name
+
+
+@pytest.mark.parametrize("dim,model,apic", [(2, 0, True), (3, 1, True), (3, 1, False), (2, 1, False)])
+@pytest.mark.parametrize("P", [1, 777, 5000])
+def test_p2g_matches_oracle(gpu, dim, model, apic, P):
+    rng = np.random.default_rng(10 + dim + P)
+    n = [24] * dim
+    dx = 1.0 / 24
+    x, v, C, F, m, V0 = random_state(rng, dim, P)
+    mu, la = OM.lame(1e4, 0.3)
+    dt = 1e-4
+    gm, gmv, gf = OM.p2g(dim, n, dx, x, v, C, F, m, V0, model, mu, la, apic=apic)
+    grid = B.Grid(dim, n, dx, bound=3)
+    gbuf = torch.full((int(np.prod(n)) * 4,), 7.0, device=dev)   # p2g must overwrite
+    parts = make_parts(B, x, v, C, F, m, V0)
+    B.mpm_p2g(grid, (model, 1e4, 0.3), parts, gbuf, dt, flags=0 if apic else B.NO_AFFINE)
+    g = gbuf.cpu().numpy().reshape(-1, 4)
+    close_channels(g[:, 0], gm, name="mass")
+    close_channels(g[:, 1:1 + dim], gmv + dt * gf, name="momentum")
+    assert np.all(g[:, 1 + dim:] == 0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_grid_update_matches_oracle(gpu, dim):
+    rng = np.random.default_rng(20 + dim)
+    n = [16] * dim
+    nn = 16 ** dim
+    g = np.zeros((nn, 4), dtype=np.float32)
+    mask = rng.random(nn) < 0.7
+    g[mask, 0] = rng.uniform(0.1, 2.0, size=mask.sum())
+    g[mask, 1:1 + dim] = rng.standard_normal((mask.sum(), dim))
+    gravity = [0.0, -9.8, 0.0][:dim] if dim == 3 else [0.0, -9.8]
+    for floor_mode, muf in [(0, 0.0), (1, 0.3)]:
+        if dim == 2 and floor_mode == 1:
+            floor_mode = 0
+        gv = OM.grid_update(dim, n, 1e-2, gravity, 3, floor_mode, muf, g[:, 0].astype(np.float64),
+                            g[:, 1:1 + dim].astype(np.float64), np.zeros((nn, dim)))
+        gbuf = T(g.reshape(-1))
+        B.mpm_grid_update(B.Grid(dim, n, 1 / 16, 3, floor_mode, muf, gravity), 1e-2, gbuf)
+        out = gbuf.cpu().numpy().reshape(-1, 4)
+        close_channels(out[:, 1:1 + dim], gv, name="grid velocity")
+        np.testing.assert_array_equal(out[:, 0], g[:, 0])
+    # active-list form: only listed nodes change
+    act = np.sort(rng.choice(nn, size=50, replace=False)).astype(np.int32)
+    gbuf = T(g.reshape(-1))
+    B.mpm_grid_update(B.Grid(dim, n, 1 / 16, 3, 0, 0.0, gravity), 1e-2, gbuf, active=T(act, torch.int32))
+    out = gbuf.cpu().numpy().reshape(-1, 4)
+    untouched = np.setdiff1d(np.arange(nn), act)
+    np.testing.assert_array_equal(out[untouched], g[untouched])
+
+
+@pytest.mark.parametrize("dim,apic", [(2, True), (3, True), (3, False)])
+def test_g2p_matches_oracle(gpu, dim, apic):
+    rng = np.random.default_rng(30 + dim)
+    n = [24] * dim
+    dx = 1 / 24
+    P = 3000
+    x, v, C, F, m, V0 = random_state(rng, dim, P)
+    gv = rng.standard_normal((24 ** dim, dim)).astype(np.float32)
+    gbuf = np.zeros((24 ** dim, 4), dtype=np.float32)
+    gbuf[:, 0] = 1.0
+    gbuf[:, 1:1 + dim] = gv
+    dt = 1e-3
+    xo, vo, Co, Fo = OM.g2p(dim, n, dx, dt, gv.astype(np.float64), x, v, C, F, apic=apic)
+    parts = make_parts(B, x, v, C, F)
+    B.mpm_g2p(B.Grid(dim, n, dx), parts, dt, T(gbuf.reshape(-1)), flags=0 if apic else B.NO_AFFINE)
+    close_channels(aos(parts.v.cpu().numpy(), dim), vo, name="v")
+    close_channels(aos(parts.C.cpu().numpy(), dim, True).reshape(P, -1), Co.reshape(P, -1), name="C")
+    np.testing.assert_allclose(aos(parts.F.cpu().numpy(), dim, True), Fo, atol=2e-6)
+    np.testing.assert_allclose(aos(parts.x.cpu().numpy(), dim), xo, atol=2e-7)
+    # trial mode on a subset (Algorithm 5, last steps)
+    sub = np.sort(rng.choice(P, size=100, replace=False))
+    xt, vt = OM.g2p(dim, n, dx, dt, gv.astype(np.float64), x, v, C, F, subset=sub, trial=True)
+    parts = make_parts(B, x, v, C, F)
+    x_tr = torch.zeros(dim * 100, device=dev)
+    v_tr = torch.zeros(dim * 100, device=dev)
+    B.mpm_g2p(B.Grid(dim, n, dx), parts, dt, T(gbuf.reshape(-1)), subset=T(sub, torch.int32),
+              flags=B.TRIAL, x_trial=x_tr, v_trial=v_tr)
+    np.testing.assert_allclose(x_tr.cpu().numpy().reshape(dim, 100).T, xt, atol=2e-7)
+    close_channels(v_tr.cpu().numpy().reshape(dim, 100).T, vt, name="v_trial")
+    np.testing.assert_array_equal(parts.x.cpu().numpy(), soa(x))   # untouched
+
+
+@pytest.mark.parametrize("dim,P", [(3, 4096), (3, 20000), (2, 4096), (3, 0)])
+def test_cell_sort_permutation_is_bit_exact(gpu, dim, P):
+    rng = np.random.default_rng(40 + P)
+    n = [32] * dim
+    dx = 1 / 32
+    x, v, C, F, m, V0 = random_state(rng, dim, P, lo=0.12, hi=0.88)
+    if P > 10:
+        x[5] = x[7]        # shared cells keep their order
+        x[9] = 0.01        # outside the lattice: last, flagged
+    grid = B.Grid(dim, n, dx)
+    parts = make_parts(B, x, v, C, F, m, V0)
+    ws = B.new_workspace(grid, P)
+    perm = torch.zeros(max(P, 1), dtype=torch.int32, device=dev)[:P]
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    B.mpm_cell_sort(grid, parts, ws, perm_out=perm if P else None, status=flag)
+    if P == 0:
+        return
+    expect = tile_slot_order(dim, n, dx, x)
+    got = perm.cpu().numpy()
+    np.testing.assert_array_equal(got, expect)
+    np.testing.assert_array_equal(parts.x.cpu().numpy(), soa(x[expect]))
+    np.testing.assert_array_equal(parts.F.cpu().numpy(), soa(F[expect]))
+    np.testing.assert_array_equal(parts.m.cpu().numpy(), m[expect])
+    assert flag.item() & B.FLAG_DOMAIN
+
+
+@pytest.mark.parametrize("dim,P", [(3, 20000), (2, 6000)])
+def test_sorted_tiled_p2g_matches_oracle(gpu, dim, P):
+    """Cell-sort, move the particles by up to 1.4 cells (beyond the drift
+    margin for some, exercising the global fallback), then the tiled P2G."""
+    rng = np.random.default_rng(50 + dim)
+    n = [40] * dim
+    dx = 1 / 40
+    x, v, C, F, m, V0 = random_state(rng, dim, P, lo=0.2, hi=0.8)
+    grid = B.Grid(dim, n, dx)
+    parts = make_parts(B, x, v, C, F, m, V0)
+    ws = B.new_workspace(grid, P)
+    perm = torch.zeros(P, dtype=torch.int32, device=dev)
+    B.mpm_cell_sort(grid, parts, ws, perm_out=perm)
+    p = perm.cpu().numpy()
+    xs = x[p] + (rng.uniform(-1.4, 1.4, size=(P, dim)) * dx).astype(np.float32)
+    parts.x.copy_(T(soa(xs)))
+    model = 0 if dim == 2 else 1
+    mu, la = OM.lame(1e4, 0.3)
+    gm, gmv, gf = OM.p2g(dim, n, dx, xs, v[p], C[p], F[p], m[p], V0[p], model, mu, la)
+    gbuf = torch.zeros(int(np.prod(n)) * 4, device=dev)
+    B.mpm_p2g(grid, (model, 1e4, 0.3), parts, gbuf, 1e-4, flags=B.SORTED, workspace=ws)
+    g = gbuf.cpu().numpy().reshape(-1, 4)
+    close_channels(g[:, 0], gm, name="mass")
+    close_channels(g[:, 1:1 + dim], gmv + 1e-4 * gf, name="momentum")
+
+
+def _run_oracle(sc, st, dt, steps):
+    st = {k: np.asarray(v, dtype=np.float64) for k, v in st.items()}
+    for _ in range(steps):
+        st = OM.step(sc, st, dt)
+    return st
+
+
+def _gpu_scene(B, s):
+    return B.Grid(s["dim"], s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
+
+
+@pytest.mark.parametrize("steps,sort_every", [(1, 0), (100, 0), (100, 10)])
+def test_two_dimensional_scene_trajectory(gpu, steps, sort_every):
+    s = scenes.scene_2d()
+    st0 = scenes.initial_state(s)
+    ref = _run_oracle(oracle_scene(s), st0, s["dt"], steps)
+    parts = make_parts(B, st0["x"], st0["v"], st0["C"], st0["F"], m_u=float(s["m"]), V0_u=float(s["V0"]))
+    grid = _gpu_scene(B, s)
+    gbuf = torch.zeros(grid.nodes() * 4, device=dev)
+    ws = torch.zeros(B.mpm_step_workspace_bytes(grid, s["P"]), dtype=torch.uint8, device=dev)
+    perm = torch.zeros(s["P"], dtype=torch.int32, device=dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    B.mpm_step(grid, (s["model"], s["E"], s["nu"]), parts, s["dt"], steps, sort_every, 0, gbuf, ws,
+               perm_accum=perm, status=flag)
+    p = perm.cpu().numpy()
+    inv = np.empty_like(p)
+    inv[p] = np.arange(len(p))
+    x = aos(parts.x.cpu().numpy(), 2)[inv]
+    v = aos(parts.v.cpu().numpy(), 2)[inv]
+    F = aos(parts.F.cpu().numpy(), 2, True)[inv]
+    ex = rel_l2(x, ref["x"])
+    ev = rel_l2(v, ref["v"])
+    eF = rel_l2(F - np.eye(2), ref["F"] - np.eye(2))
+    ed = rel_l2(x - s["X"], ref["x"] - s["X"])
+    print("2D steps=%d sort=%d: x %.3e  v %.3e  F-I %.3e  displacement %.3e" % (steps, sort_every, ex, ev, eF, ed))
+    assert flag.item() == 0
+    assert ex <= (1e-5 if steps == 1 else 1e-3)
+    assert ev <= (1e-4 if steps == 1 else 1e-2)
+    assert eF <= (1e-3 if steps == 1 else 1e-2)
+
+
+def test_three_dimensional_scene_small(gpu):
+    """3D Neo-Hookean cube on a Coulomb floor, 20^3... 8^3-cell cube on a
+    32^3 grid, 100 steps with sorting every 10."""
+    s = scenes.scene_3d(n=32, cube_cells=8, seed=5, v0=(0.3, -2.0, 0.1))
+    st0 = scenes.initial_state(s)
+    steps = 100
+    ref = _run_oracle(oracle_scene(s), st0, s["dt"], steps)
+    parts = make_parts(B, st0["x"], st0["v"], st0["C"], st0["F"], m_u=float(s["m"]), V0_u=float(s["V0"]))
+    grid = _gpu_scene(B, s)
+    gbuf = torch.zeros(grid.nodes() * 4, device=dev)
+    ws = torch.zeros(B.mpm_step_workspace_bytes(grid, s["P"]), dtype=torch.uint8, device=dev)
+    perm = torch.zeros(s["P"], dtype=torch.int32, device=dev)
+    B.mpm_step(grid, (s["model"], s["E"], s["nu"]), parts, s["dt"], steps, 10, 0, gbuf, ws, perm_accum=perm)
+    p = perm.cpu().numpy()
+    inv = np.empty_like(p)
+    inv[p] = np.arange(len(p))
+    x = aos(parts.x.cpu().numpy(), 3)[inv]
+    v = aos(parts.v.cpu().numpy(), 3)[inv]
+    ex, ev = rel_l2(x, ref["x"]), rel_l2(v, ref["v"])
+    ed = rel_l2(x - s["X"], ref["x"] - s["X"])
+    print("3D small 100 steps: x %.3e v %.3e displacement %.3e" % (ex, ev, ed))
+    assert ex <= 1e-3 and ev <= 1e-2 and ed <= 1e-2
+
+
+def test_three_dimensional_full_size_one_step(gpu):
+    """The 2,097,152-particle scene in the benchmark's launch configuration
+    (mpm_step with cell sorting), one step against the oracle on every
+    particle."""
+    s = scenes.scene_3d()
+    st0 = scenes.initial_state(s)
+    ref = _run_oracle(oracle_scene(s), st0, s["dt"], 1)
+    parts = make_parts(B, st0["x"], st0["v"], st0["C"], st0["F"], m_u=float(s["m"]), V0_u=float(s["V0"]))
+    grid = _gpu_scene(B, s)
+    gbuf = torch.zeros(grid.nodes() * 4, device=dev)
+    ws = torch.zeros(B.mpm_step_workspace_bytes(grid, s["P"]), dtype=torch.uint8, device=dev)
+    perm = torch.zeros(s["P"], dtype=torch.int32, device=dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    B.mpm_step(grid, (s["model"], s["E"], s["nu"]), parts, s["dt"], 1, 10, 0, gbuf, ws,
+               perm_accum=perm, status=flag)
+    p = perm.cpu().numpy()
+    assert np.array_equal(np.sort(p), np.arange(s["P"]))
+    inv = np.empty_like(p)
+    inv[p] = np.arange(len(p))
+    x = aos(parts.x.cpu().numpy(), 3)[inv]
+    v = aos(parts.v.cpu().numpy(), 3)[inv]
+    ex, ev = rel_l2(x, ref["x"]), rel_l2(v, ref["v"])
+    print("3D full one step: x %.3e v %.3e" % (ex, ev))
+    assert flag.item() == 0
+    assert ex <= 1e-5 and ev <= 1e-4
+
+
+def test_domain_errors_are_flagged(gpu):
+    rng = np.random.default_rng(60)
+    x, v, C, F, m, V0 = random_state(rng, 3, 10)
+    x[3] = [0.01, 0.5, 0.5]                    # stencil leaves the lattice
+    F[4] = np.diag([-1.0, 1.0, 1.0])           # J < 0 under Neo-Hookean
+    grid = B.Grid(3, [16] * 3, 1 / 16)
+    gbuf = torch.zeros(16 ** 3 * 4, device=dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    B.mpm_p2g(grid, (B.NEO_HOOKEAN, 1e4, 0.3), make_parts(B, x, v, C, F, m, V0), gbuf, 1e-4, status=flag)
+    assert flag.item() & B.FLAG_DOMAIN
+    keep = np.array([i for i in range(10) if i not in (3, 4)])
+    mu, la = OM.lame(1e4, 0.3)
+    gm, _, _ = OM.p2g(3, [16] * 3, 1 / 16, x[keep], v[keep], C[keep], F[keep], m[keep], V0[keep], 1, mu, la)
+    close_channels(gbuf.cpu().numpy().reshape(-1, 4)[:, 0], gm, name="mass without bad particles")
+    rc, _ = B.sync_status(flag)
+    assert rc == B.MR_EDOMAIN
+
+
+def test_invalid_arguments_rejected(gpu):
+    rng = np.random.default_rng(61)
+    x, v, C, F, m, V0 = random_state(rng, 3, 10)
+    gbuf = torch.zeros(16 ** 3 * 4, device=dev)
+    with pytest.raises(B.MrError) as e:
+        B.mpm_p2g(B.Grid(3, [16] * 3, 1 / 16), (B.FIXED_COROTATED, 1e4, 0.3),
+                  make_parts(B, x, v, C, F, m, V0), gbuf, 1e-4)
+    assert e.value.code == B.MR_EINVAL
+    with pytest.raises(B.MrError):
+        B.mpm_p2g(B.Grid(3, [16] * 3, 1 / 16), (B.NEO_HOOKEAN, 1e4, 0.3),
+                  make_parts(B, x, v, C, F, m, V0), gbuf, 1e-4, flags=B.SORTED)
+
+
+def test_empty_particle_set(gpu):
+    z = torch.zeros(3, 0, device=dev)
+    z9 = torch.zeros(9, 0, device=dev)
+    parts = B.Particles(z, z.clone(), z9, z9.clone(), m_uniform=1.0, V0_uniform=1.0)
+    gbuf = torch.full((16 ** 3 * 4,), 3.0, device=dev)
+    grid = B.Grid(3, [16] * 3, 1 / 16)
+    B.mpm_p2g(grid, (B.NEO_HOOKEAN, 1e4, 0.3), parts, gbuf, 1e-4)
+    assert float(gbuf.abs().sum()) == 0.0
+    B.mpm_g2p(grid, parts, 1e-4, gbuf)
+    torch.cuda.synchronize()
