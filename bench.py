@@ -1,0 +1,180 @@
+"""Benchmark of the full-order MPM step on the 3D scene: 128^3 nodes,
+2,097,152 particles (8 per cell) in a jittered Neo-Hookean cube (E = 5e4,
+nu = 0.3, density 1000) dropped onto a Coulomb floor (mu = 0.3), dt = 5e-5,
+particles cell-sorted every 10 steps.  Synthetic, seeded input.
+
+The timed region is one mpm_step call (C ABI) advancing K steps: a cell
+sort every 10th step followed by P2G (sorted, LDS-tiled), and in between the
+fused gather-of-step-n / scatter-of-step-n+1 kernel, each followed by the
+grid update.  HIP events bracket the whole region; the library's launch
+timer records an event pair around every launch inside it on the same
+stream, which gives the per-kernel average durations of the roofline entry.
+Prints one JSON line on stdout.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SORT_EVERY = 10
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("mpm.hip", "mpm_kernels.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2109_12390_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, src_hash):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    only if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = data.get(kernel)
+    if not ent or ent.get("source_hash") != src_hash:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(scene, steps=2):
+    """The FP64 oracle (plain single-threaded C) on `steps` steps of the same
+    full-size scene."""
+    from oracle import mpm as OM
+    st = {k: v.astype(np.float64) for k, v in __import__(
+        "paper_2109_12390_amd.scenes", fromlist=["x"]).initial_state(scene).items()}
+    mu, la = OM.lame(scene["E"], scene["nu"])
+    sc = dict(dim=3, n=scene["n"], dx=scene["dx"], bound=scene["bound"],
+              floor_mode=scene["floor_mode"], mu_f=scene["mu_f"], gravity=scene["gravity"],
+              model=scene["model"], mu=mu, la=la,
+              m=np.full(scene["P"], float(scene["m"])), V0=np.full(scene["P"], float(scene["V0"])))
+    OM.step(sc, st, scene["dt"])           # warm-up (builds / loads the oracle)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = OM.step(sc, st, scene["dt"])
+    el = time.perf_counter() - t0
+    return {"value": scene["P"] * steps / el, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d steps of the full %d-particle scene, FP64, single thread" % (steps, scene["P"])}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2109_12390_amd import binding as B
+    from paper_2109_12390_amd import scenes
+
+    B.load()
+    dev = "cuda:0"
+    s = scenes.scene_3d()
+    P = s["P"]
+    st = scenes.initial_state(s)
+    soa = lambda a: torch.tensor(np.ascontiguousarray(a.reshape(P, -1).T), device=dev)
+    parts = B.Particles(soa(st["x"]), soa(st["v"]), soa(st["C"]), soa(st["F"]),
+                        m_uniform=float(s["m"]), V0_uniform=float(s["V0"]))
+    grid = B.Grid(3, s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
+    gbuf = torch.zeros(grid.nodes() * 4, device=dev)
+    ws = torch.zeros(B.mpm_step_workspace_bytes(grid, P), dtype=torch.uint8, device=dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    mat = (s["model"], s["E"], s["nu"])
+    dt = s["dt"]
+
+    timing = B.Timing(capacity=16 * (args.steps + 8))
+    # untimed warm-up: compiles nothing, but brings the caches, the
+    # allocator and the clocks to steady state
+    B.mpm_step(grid, mat, parts, dt, args.warmup, SORT_EVERY, 0, gbuf, ws, status=flag)
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record()
+    B.mpm_step(grid, mat, parts, dt, args.steps, SORT_EVERY, 0, gbuf, ws, status=flag, timing=timing)
+    t_end.record()
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    rc, fl = B.sync_status(flag)
+    if rc != 0:
+        log("status flags raised during the run:", fl)
+    per_kernel = {k: {"launches": n, "avg_ms": ms / n, "total_ms": ms}
+                  for k, (n, ms) in timing.read().items()}
+    log("per-kernel:", json.dumps(per_kernel))
+
+    # algorithmic bytes per launch (float32 particle state; the grid region
+    # touched is measured from the node masses)
+    g = gbuf.view(-1, 4)
+    active_nodes = int((g[:, 0] > 0).sum().item())
+    grid_bytes = 16 * active_nodes
+    algo = {
+        "g2p2g": 96 * P + 2 * grid_bytes,           # read and write x, F; read and flush the touched nodes
+        "p2g": 96 * P + grid_bytes,                 # read x, v, C, F; flush the touched nodes
+        "g2p": 48 * P + grid_bytes + 96 * P,        # read x, F and the grid; write x, v, C, F
+        "grid_update": 32 * grid.nodes(),           # read and write every node
+        "zero_grid": 16 * grid.nodes(),             # clear the second grid
+        "cell_sort": (2 * 96 + 16) * P,             # gather-permute the state, keys and indices
+    }
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["total_ms"])
+    achieved = algo[dom] / (per_kernel[dom]["avg_ms"] * 1e-3) / 1e9
+    src_hash = kernel_source_hash()
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom, src_hash),
+                "algorithmic_bytes_per_launch": algo[dom]}
+    ms_per_step = total_ms / args.steps
+    value = P * args.steps / (total_ms * 1e-3)
+    out = {
+        "metric": "MPM particle-steps/s",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3D full-order MPM, 128^3 grid, 2,097,152 particles, Neo-Hookean "
+                               "cube on a Coulomb floor, dt 5e-5, cell sort every 10 steps",
+                   "particles": P, "grid": s["n"], "sort_every": SORT_EVERY},
+        "roofline": roofline,
+        "per_kernel_ms": {k: round(v["avg_ms"], 5) for k, v in per_kernel.items()},
+        "active_nodes": active_nodes,
+        "kernel_source_hash": src_hash,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(s)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -70,6 +70,16 @@ extern "C" {
 #define MR_NO_F_UPDATE 8 /* g2p: keep F_p                                    */
 #define MR_SORTED 16     /* p2g: particles are cell-sorted by mpm_cell_sort;
                             enables the LDS-tiled scatter                    */
+#define MR_NO_VC_OUT 32  /* g2p2g: do not store v_p and C_p                  */
+
+/* kernel classes of the launch timer (mr_timing_read) */
+#define MR_KC_SORT 0     /* cell sort (all of its launches)                  */
+#define MR_KC_P2G 1      /* particle-to-grid scatter (with grid zeroing)     */
+#define MR_KC_GRID 2     /* grid update                                      */
+#define MR_KC_G2P 3      /* grid-to-particle gather                          */
+#define MR_KC_G2P2G 4    /* fused gather of step n and scatter of step n + 1 */
+#define MR_KC_ZERO 5     /* zeroing of the second grid of the fused path     */
+#define MR_KC_COUNT 6
 
 /* decoder enums */
 #define MR_OUT_POSITION 0
@@ -163,19 +173,46 @@ int32_t mpm_cell_sort(const mr_grid *grid_desc, mr_particles *parts,
  * grid and n particles. */
 int64_t mpm_workspace_bytes(const mr_grid *grid_desc, int64_t n);
 
+/* Launch timer: HIP events recorded on the launching stream around every
+ * kernel launch of an mpm_step call, tagged with an MR_KC_* class.  Used for
+ * tracing and for per-kernel bandwidth figures; adds one event pair per
+ * launch.  capacity: number of launches recorded (later ones are not). */
+typedef struct mr_timing mr_timing;
+int32_t mr_timing_create(int32_t capacity, mr_timing **out);
+void mr_timing_destroy(mr_timing *t);
+int32_t mr_timing_reset(mr_timing *t);
+/* Synchronises on the recorded events; per class c < n_classes returns the
+ * number of launches and their summed duration in milliseconds. */
+int32_t mr_timing_read(mr_timing *t, int32_t n_classes, int64_t *launches,
+                       double *total_ms);
+
+/* Fused grid-to-particle transfer of step n (Algorithm 1, third and fourth
+ * steps, from grid_in velocities) and particle-to-grid transfer of step
+ * n + 1 (Algorithm 1, first step, at the updated particle state, added into
+ * grid_out).  The particles must be in the order of the last mpm_cell_sort
+ * with this workspace (motion since then is handled).  x and F are updated
+ * in place; v and C are stored unless MR_NO_VC_OUT.  grid_out is zeroed
+ * first unless MR_ACCUMULATE; grid_in and grid_out must differ. */
+int32_t mpm_g2p2g(const mr_grid *grid_desc, const mr_material *mat,
+                  mr_particles *parts, float dt, const float *grid_in,
+                  float *grid_out, int32_t flags, void *workspace,
+                  int32_t *status_flag, void *stream);
+
 /* n_steps full-order steps (Algorithm 1 with the affine transfer unless
- * MR_NO_AFFINE in flags): every sort_every steps (0: never) the particles
- * are cell-sorted, and P2G uses the sorted tiled scatter.  grid: device
- * scratch of 4 * nodes floats (holds the last grid velocities on return);
- * workspace: mpm_step_workspace_bytes(grid, n) bytes.  perm_accum
- * (nullable, n int32) receives, for every array slot on return, the index
- * that particle had on entry.  Particles end with x, v, C, F of the last
- * step. */
+ * MR_NO_AFFINE in flags).  With sort_every > 0 the particles are
+ * cell-sorted before step 0 and every sort_every steps, P2G uses the sorted
+ * tiled scatter, and in between the gather of one step and the scatter of
+ * the next run as one fused kernel (mpm_g2p2g).  grid: device scratch of
+ * 4 * nodes floats (contents on return unspecified); workspace:
+ * mpm_step_workspace_bytes(grid, n) bytes.  perm_accum (nullable, n int32)
+ * receives, for every array slot on return, the index that particle had on
+ * entry.  timing (nullable) records every launch.  Particles end with x, v,
+ * C, F of the last step. */
 int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
                  mr_particles *parts, float dt, int32_t n_steps,
                  int32_t sort_every, int32_t flags, float *grid,
                  void *workspace, int32_t *perm_accum, int32_t *status_flag,
-                 void *stream);
+                 mr_timing *timing, void *stream);
 int64_t mpm_step_workspace_bytes(const mr_grid *grid_desc, int64_t n);
 
 /* Sort key of each particle in the order mpm_cell_sort produces

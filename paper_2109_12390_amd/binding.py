@@ -84,7 +84,13 @@ SIGNATURES = {
     "mpm_cell_keys": (_i32, [ctypes.POINTER(MrGrid), ctypes.POINTER(MrParticles), _vp, _vp]),
     "mpm_step": (_i32, [ctypes.POINTER(MrGrid), ctypes.POINTER(MrMaterial),
                         ctypes.POINTER(MrParticles), _f32, _i32, _i32, _i32, _vp, _vp, _vp,
-                        _vp, _vp]),
+                        _vp, _vp, _vp]),
+    "mpm_g2p2g": (_i32, [ctypes.POINTER(MrGrid), ctypes.POINTER(MrMaterial),
+                         ctypes.POINTER(MrParticles), _f32, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "mr_timing_create": (_i32, [_i32, ctypes.POINTER(_vp)]),
+    "mr_timing_destroy": (None, [_vp]),
+    "mr_timing_reset": (_i32, [_vp]),
+    "mr_timing_read": (_i32, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_f64)]),
     "mpm_step_workspace_bytes": (_i64, [ctypes.POINTER(MrGrid), _i64]),
     "rom_decoder_create": (_i32, [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _i32,
                                   ctypes.POINTER(_vp)]),
@@ -245,15 +251,60 @@ def mpm_step_workspace_bytes(grid, n):
     return int(load().mpm_step_workspace_bytes(ctypes.byref(grid.c()), n))
 
 
+NO_VC_OUT = 32
+KC_NAMES = ["cell_sort", "p2g", "grid_update", "g2p", "g2p2g", "zero_grid"]
+
+
+class Timing:
+    """Launch timer (mr_timing_*): per-kernel-class launch counts and times."""
+
+    def __init__(self, capacity=65536):
+        h = ctypes.c_void_p()
+        _check("mr_timing_create", load().mr_timing_create(capacity, ctypes.byref(h)))
+        self.handle = h
+
+    def reset(self):
+        _check("mr_timing_reset", load().mr_timing_reset(self.handle))
+
+    def read(self):
+        n = len(KC_NAMES)
+        la = (_i64 * n)()
+        ms = (_f64 * n)()
+        _check("mr_timing_read", load().mr_timing_read(self.handle, n, la, ms))
+        return {KC_NAMES[i]: (la[i], ms[i]) for i in range(n) if la[i] > 0}
+
+    def close(self):
+        if self.handle:
+            load().mr_timing_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def mpm_step(grid, material, parts, dt, n_steps, sort_every, flags, grid_buf, workspace,
-             perm_accum=None, status=None, stream=None):
+             perm_accum=None, status=None, timing=None, stream=None):
     lib = load()
     p = parts.c()
     _check("mpm_step", lib.mpm_step(ctypes.byref(grid.c()), ctypes.byref(MrMaterial(*material)),
                                     ctypes.byref(p), dt, n_steps, sort_every, flags,
                                     _ptr(grid_buf, torch.float32), _ptr(workspace),
                                     _ptr(perm_accum, torch.int32), _ptr(status, torch.int32),
+                                    timing.handle if timing is not None else None,
                                     _stream(stream)))
+
+
+def mpm_g2p2g(grid, material, parts, dt, grid_in, grid_out, workspace, flags=0, status=None,
+              stream=None):
+    lib = load()
+    p = parts.c()
+    _check("mpm_g2p2g", lib.mpm_g2p2g(ctypes.byref(grid.c()), ctypes.byref(MrMaterial(*material)),
+                                      ctypes.byref(p), dt, _ptr(grid_in, torch.float32),
+                                      _ptr(grid_out, torch.float32), flags, _ptr(workspace),
+                                      _ptr(status, torch.int32), _stream(stream)))
 
 
 def sync_status(flags_dev, stream=None):

@@ -15,7 +15,7 @@
 // the ELU and its derivative, stay in fp32 vector arithmetic.  Tangents
 // obey t' = ELU'(z) (W t), with z the primal pre-activation of the same
 // point, which the MFMA output layout places in the same lane and register.
-#include "internal.h"
+#include "project.h"
 
 #include <stdlib.h>
 #include <string.h>
@@ -62,6 +62,7 @@ struct DecIO {
     int idx_per_inst;
     int idx_div;  // idx row of instance b is b / idx_div (when idx_per_inst)
     const int32_t *n_inst;  // nullable: points s >= n_inst[b] are skipped
+    int disp_only;          // displacement mode: write g - X instead of g
     const double *xhat, *vhat;
     float *x, *F, *v, *Jz;
     int jz_k0;  // first latent index of this launch's latent streams
@@ -291,7 +292,7 @@ __global__ void __launch_bounds__(256) decoder_kernel(DecK P, StreamSpec ss, Dec
         if (kind == SK_PRIMAL) {
             if (io.x) {
                 float val = P.mean[a] + P.stdv[a] * (y + P.bL[a]);
-                if (P.mode == MR_OUT_DISPLACEMENT) {
+                if (P.mode == MR_OUT_DISPLACEMENT && !io.disp_only) {
                     int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * n : 0) + s] : s;
                     val += io.X[a * io.n_ref + row];
                 }
@@ -344,6 +345,50 @@ int32_t launch_w(int cfg, const DecK &P, const StreamSpec &ss, const DecIO &io, 
     return launch_one<T, W, 9, 1, true>(P, ss, io, st);
 }
 
+// Decoder without hidden layers (the linear manifold): y = W0 [Xn, xhat] + b0.
+// One thread per (instance, point) writes every requested output.
+__global__ void linear_decoder_kernel(DecK P, DecIO io)
+{
+    const int b = blockIdx.y;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n_b = io.n_inst ? (int64_t)io.n_inst[b] : io.n;
+    if (s >= n_b) return;
+    const int D = P.d, in0 = P.d + P.r;
+    const int64_t n = io.n;
+    const int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * n : 0) + s] : s;
+    const double *xh = io.xhat + (size_t)b * P.r;
+    const double *vh = io.vhat ? io.vhat + (size_t)b * P.r : nullptr;
+    float Xr[3], Xn[3];
+    for (int a = 0; a < D; ++a) {
+        Xr[a] = io.X[a * io.n_ref + row];
+        Xn[a] = Xr[a] * P.scale[a] + P.shift[a];
+    }
+    const size_t bo = (size_t)b;
+    for (int a = 0; a < D; ++a) {
+        const float *w = P.W0 + (size_t)a * in0;
+        if (io.x) {
+            double y = P.b0[a];
+            for (int k = 0; k < D; ++k) y += (double)w[k] * Xn[k];
+            for (int k = 0; k < P.r; ++k) y += (double)w[D + k] * xh[k];
+            float val = P.mean[a] + P.stdv[a] * (float)y;
+            if (P.mode == MR_OUT_DISPLACEMENT && !io.disp_only) val += Xr[a];
+            io.x[(bo * D + a) * n + s] = val;
+        }
+        if (io.F)
+            for (int c = 0; c < D; ++c)
+                io.F[(bo * D * D + a * D + c) * n + s] =
+                    P.stdv[a] * w[c] * P.scale[c] + ((P.mode == MR_OUT_DISPLACEMENT && a == c) ? 1.0f : 0.0f);
+        if (io.v && vh) {
+            double y = 0.0;
+            for (int k = 0; k < P.r; ++k) y += (double)w[D + k] * vh[k];
+            io.v[(bo * D + a) * n + s] = P.stdv[a] * (float)y;
+        }
+        if (io.Jz)
+            for (int k = 0; k < P.r; ++k)
+                io.Jz[(bo * D * P.r + (size_t)a * P.r + k) * n + s] = P.stdv[a] * w[D + k];
+    }
+}
+
 int32_t launch_cfg(const mr_decoder *dec, int cfg, const StreamSpec &ss, const DecIO &io,
                    hipStream_t st)
 {
@@ -366,6 +411,12 @@ int32_t launch_cfg(const mr_decoder *dec, int cfg, const StreamSpec &ss, const D
         P.mean[a] = dec->mean[a];
         P.stdv[a] = dec->stdv[a];
     }
+    if (dec->nh == 0) {
+        dim3 grid((unsigned)ceil_div(io.n, 256), (unsigned)io.B);
+        linear_decoder_kernel<<<grid, 256, 0, st>>>(P, io);
+        MR_LAUNCH_CHECK();
+        return MR_OK;
+    }
     bool bf = dec->prec == MR_PREC_BF16;
     switch (dec->W) {
     case 16: return bf ? launch_w<uint16_t, 16>(cfg, P, ss, io, st) : launch_w<float, 16>(cfg, P, ss, io, st);
@@ -382,6 +433,17 @@ __global__ void pack_params_kernel(const float *src, float *dst, uint16_t *hid, 
                                    size_t obh, size_t oWL, size_t obL)
 {
     const int in0 = d + r;
+    if (nh == 0) {  // linear decoder: dense (d x in0) matrix and d biases
+        size_t tot = (size_t)d * in0 + d;
+        for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
+             t += (size_t)gridDim.x * blockDim.x) {
+            if (t < (size_t)d * in0)
+                dst[oW0 + t] = src[t];
+            else
+                dst[ob0 + (t - (size_t)d * in0)] = src[t];
+        }
+        return;
+    }
     size_t total = (size_t)W * in0 + W + (size_t)(nh - 1) * (W * W + W) + (size_t)d * W + d;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (size_t)gridDim.x * blockDim.x) {
@@ -439,6 +501,7 @@ using namespace mr;
 
 static size_t unpadded_count(int d, int r, int width, int nh)
 {
+    if (nh == 0) return (size_t)d * (d + r) + d;
     return (size_t)width * (d + r) + width + (size_t)(nh - 1) * ((size_t)width * width + width) +
            (size_t)d * width + d;
 }
@@ -469,7 +532,7 @@ extern "C" int32_t rom_decoder_create(int32_t d, int32_t r, int32_t width, int32
                                       int32_t precision, mr_decoder **out)
 {
     if (!out || !params || !in_min || !in_max || !out_mean || !out_std) return MR_EINVAL;
-    if ((d != 2 && d != 3) || r < 1 || r > 32 || width < 1 || width > 128 || n_hidden < 1 ||
+    if ((d != 2 && d != 3) || r < 1 || r > 32 || width < 1 || width > 128 || n_hidden < 0 ||
         n_hidden > 8)
         return MR_EINVAL;
     if (output_mode != MR_OUT_POSITION && output_mode != MR_OUT_DISPLACEMENT) return MR_EINVAL;
@@ -509,12 +572,13 @@ extern "C" int32_t rom_decoder_create(int32_t d, int32_t r, int32_t width, int32
     };
     dec->oW0 = take((size_t)W * (d + r));
     dec->ob0 = take(W);
-    dec->oWh = take((size_t)(n_hidden - 1) * W * W + 1);
-    dec->obh = take((size_t)(n_hidden - 1) * W + 1);
+    const size_t nhh = n_hidden > 0 ? (size_t)(n_hidden - 1) : 0;
+    dec->oWh = take(nhh * W * W + 1);
+    dec->obh = take(nhh * W + 1);
     dec->oWL = take((size_t)d * W);
     dec->obL = take(d);
     if (hipMalloc(&dec->dev, off * sizeof(float)) != hipSuccess ||
-        hipMalloc(&dec->hid_bf16, ((size_t)(n_hidden - 1) * W * W + 8) * sizeof(uint16_t)) !=
+        hipMalloc(&dec->hid_bf16, (nhh * W * W + 8) * sizeof(uint16_t)) !=
             hipSuccess ||
         hipMalloc(&dec->staging, dec->n_params * sizeof(float)) != hipSuccess) {
         rom_decoder_destroy(dec);
@@ -575,11 +639,12 @@ namespace mr {
 int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X, int64_t n,
                       const int32_t *idx, int32_t idx_per_instance, const int32_t *n_inst,
                       const double *xhat, const double *vhat, float *x, float *F, float *v,
-                      float *Jz, hipStream_t st)
+                      float *Jz, hipStream_t st, int disp_only)
 {
     if (n == 0) return MR_OK;
     DecIO io{};
     io.n_inst = n_inst;
+    io.disp_only = disp_only;
     io.B = B;
     io.n_ref = n_ref;
     io.n = n;
@@ -650,4 +715,5 @@ extern "C" int32_t rom_decode_jac(const mr_decoder *dec, int32_t B, int64_t n_re
 namespace mr {
 int decoder_dim(const mr_decoder *dec) { return dec->d; }
 int decoder_latent(const mr_decoder *dec) { return dec->r; }
+int decoder_output_mode(const mr_decoder *dec) { return dec->mode; }
 }  // namespace mr

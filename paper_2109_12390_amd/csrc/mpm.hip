@@ -774,11 +774,330 @@ extern "C" int32_t mr_sync_status(void *stream, const int32_t *device_flags, int
 extern "C" const char *mr_version(void) { return "mpmrom 0.1 gfx950"; }
 
 // ---------------------------------------------------------------------------
+// fused grid-to-particle (step n) and particle-to-grid (step n + 1)
+//
+// One workgroup per tile of cells of the last cell sort.  The tile's region of
+// the incoming grid velocities (the tile's cells plus stencil reach plus one
+// cell of drift margin) is staged in LDS; every particle gathers its G2P
+// stencil from there (or from HBM if it drifted beyond the margin), updates
+// v, C (affine), F and x in registers, evaluates the stress at the new F and
+// scatters the P2G contributions of the next step into an LDS copy of the
+// outgoing grid region, which is flushed with one global atomic per non-zero
+// node channel.  Per particle and step only x and F travel through HBM
+// (48 bytes read, 48 written); v and C are produced and consumed in
+// registers and stored only when v_out / C_out are given.
+
+namespace mr {
+
+template <int D>
+__global__ void __launch_bounds__(256) g2p2g_kernel(GridK g, TileGeom tg, float *x, float *F,
+                                                    const float *m, const float *V0, float m_u,
+                                                    float V0_u, int64_t n,
+                                                    const int32_t *offsets, int apic, int model,
+                                                    float mu, float la, float dt,
+                                                    const float *grid_in, float *grid_out,
+                                                    float *v_out, float *C_out, int32_t *flag)
+{
+    using T = Tiling<D>;
+    constexpr int R = T::R, RN = T::RN;
+    __shared__ float4 vin[RN];
+    __shared__ float acc[4 * RN];
+    const int64_t t = blockIdx.x;
+    const int t0 = (int)(t % tg.nt0);
+    const int t1 = (int)((t / tg.nt0) % tg.nt1);
+    const int t2 = D == 3 ? (int)(t / ((int64_t)tg.nt0 * tg.nt1)) : 0;
+    const int r0 = t0 * T::TS - 1, r1 = t1 * T::TS - 1, r2 = D == 3 ? t2 * T::TS - 1 : 0;
+    const int begin = offsets[t * T::CELLS];
+    const int end = offsets[(t + 1) * T::CELLS];
+    if (begin == end) return;  // empty tile: nothing to gather or scatter (block-uniform)
+    const float4 *gin4 = reinterpret_cast<const float4 *>(grid_in);
+    for (int li = threadIdx.x; li < RN; li += blockDim.x) {
+        int gi = r0 + li % R, gj = r1 + (li / R) % R, gk = D == 3 ? r2 + li / (R * R) : 0;
+        float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (gi >= 0 && gj >= 0 && gk >= 0 && gi < g.n0 && gj < g.n1 && gk < g.n2)
+            q = gin4[node_lin(g, gi, gj, gk)];
+        vin[li] = q;
+    }
+    for (int i = threadIdx.x; i < 4 * RN; i += blockDim.x) acc[i] = 0.0f;
+    __syncthreads();
+    const float cscale = apic ? 4.0f * g.inv_dx * g.inv_dx : 0.0f;
+    const int oz = (D == 3) ? 3 : 1;
+    for (int64_t p = begin + threadIdx.x; p < end; p += blockDim.x) {
+        float xp[D], Fp[D * D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) xp[a] = x[a * n + p];
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) Fp[k] = F[k * n + p];
+        Stencil<D> st;
+        if (!make_stencil<D>(g, xp, st)) {
+            raise_flag(flag, MR_FLAG_DOMAIN);
+            continue;
+        }
+        int l0 = st.base[0] - r0, l1 = st.base[1] - r1, l2 = D == 3 ? st.base[2] - r2 : 0;
+        bool in_old = l0 >= 0 && l0 + 2 < R && l1 >= 0 && l1 + 2 < R &&
+                      (D == 2 || (l2 >= 0 && l2 + 2 < R));
+        // ---- G2P from the staged region
+        float vp[D] = {}, Bp[D * D] = {}, gv[D * D] = {};
+        for (int o2 = 0; o2 < oz; ++o2)
+#pragma unroll
+            for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+                for (int o0 = 0; o0 < 3; ++o0) {
+                    const int o[3] = {o0, o1, o2};
+                    float w = 1.0f, grad[D], dxi[D];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        w *= st.w[a][o[a]];
+                        dxi[a] = ((float)o[a] - st.f[a]) * g.dx;
+                    }
+#pragma unroll
+                    for (int b = 0; b < D; ++b) {
+                        float gb = 1.0f;
+#pragma unroll
+                        for (int a = 0; a < D; ++a) gb *= (a == b) ? st.dw[a][o[a]] : st.w[a][o[a]];
+                        grad[b] = gb;
+                    }
+                    float4 q;
+                    if (in_old)
+                        q = vin[(l0 + o0) + R * ((l1 + o1) + (D == 3 ? R * (l2 + o2) : 0))];
+                    else
+                        q = gin4[node_lin(g, st.base[0] + o0, st.base[1] + o1,
+                                          D == 3 ? st.base[2] + o2 : 0)];
+                    const float vi[3] = {q.y, q.z, q.w};
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        vp[a] += w * vi[a];
+#pragma unroll
+                        for (int b = 0; b < D; ++b) {
+                            Bp[a * D + b] += w * vi[a] * dxi[b];
+                            gv[a * D + b] += vi[a] * grad[b];
+                        }
+                    }
+                }
+        float Fn[D * D], Cp[D * D], xn[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                float s = Fp[a * D + b];
+#pragma unroll
+                for (int k = 0; k < D; ++k) s += dt * gv[a * D + k] * Fp[k * D + b];
+                Fn[a * D + b] = s;
+            }
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) Cp[k] = cscale * Bp[k];
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = xp[a] + dt * vp[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a * n + p] = xn[a];
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) F[k * n + p] = Fn[k];
+        if (v_out)
+#pragma unroll
+            for (int a = 0; a < D; ++a) v_out[a * n + p] = vp[a];
+        if (C_out)
+#pragma unroll
+            for (int k = 0; k < D * D; ++k) C_out[k * n + p] = Cp[k];
+        // ---- P2G of the next step at the new state
+        Stencil<D> sn;
+        float tau[D * D];
+        bool ok = make_stencil<D>(g, xn, sn);
+        ok = kirchhoff<D>(model, mu, la, Fn, tau) && ok;
+        if (!ok) {
+            raise_flag(flag, MR_FLAG_DOMAIN);
+            continue;
+        }
+        P2GPayload<D> pl;
+        const float mp = m ? m[p] : m_u;
+        const float sc = dt * (V0 ? V0[p] : V0_u);
+        pl.m = mp;
+#pragma unroll
+        for (int a = 0; a < D; ++a) pl.mv[a] = mp * vp[a];
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) {
+            pl.mC[k] = mp * Cp[k];
+            pl.S[k] = sc * tau[k];
+        }
+        int m0 = sn.base[0] - r0, m1 = sn.base[1] - r1, m2 = D == 3 ? sn.base[2] - r2 : 0;
+        bool in_new = m0 >= 0 && m0 + 2 < R && m1 >= 0 && m1 + 2 < R &&
+                      (D == 2 || (m2 >= 0 && m2 + 2 < R));
+        if (!in_new) {
+            scatter_global<D>(g, sn, pl, grid_out);
+            continue;
+        }
+        for (int o2 = 0; o2 < oz; ++o2)
+#pragma unroll
+            for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+                for (int o0 = 0; o0 < 3; ++o0) {
+                    float mom[D];
+                    float mw = p2g_node<D>(g, sn, pl, o0, o1, o2, mom);
+                    int li = (m0 + o0) + R * ((m1 + o1) + (D == 3 ? R * (m2 + o2) : 0));
+                    atomicAdd(&acc[li], mw);
+#pragma unroll
+                    for (int a = 0; a < D; ++a) atomicAdd(&acc[(1 + a) * RN + li], mom[a]);
+                }
+    }
+    __syncthreads();
+    for (int li = threadIdx.x; li < RN; li += blockDim.x) {
+        float mw = acc[li];
+        if (mw == 0.0f) continue;
+        int i0 = li % R, i1 = (li / R) % R, i2 = D == 3 ? li / (R * R) : 0;
+        int gi = r0 + i0, gj = r1 + i1, gk = D == 3 ? r2 + i2 : 0;
+        if (gi < 0 || gj < 0 || gk < 0 || gi >= g.n0 || gj >= g.n1 || gk >= g.n2) continue;
+        float *gp = grid_out + 4 * node_lin(g, gi, gj, gk);
+        atomicAdd(gp, mw);
+#pragma unroll
+        for (int a = 0; a < D; ++a) atomicAdd(gp + 1 + a, acc[(1 + a) * RN + li]);
+    }
+}
+
+template <int D>
+int32_t g2p2g_impl(const GridK &g, const mr_material *mat, mr_particles *parts, float dt,
+                   const float *grid_in, float *grid_out, int32_t flags, void *workspace,
+                   float *v_out, float *C_out, int32_t *flag, hipStream_t st)
+{
+    Lame lm = lame_of(mat->E, mat->nu);
+    int apic = (flags & MR_NO_AFFINE) ? 0 : 1;
+    if (!(flags & MR_ACCUMULATE))
+        MR_CHECK_HIP(hipMemsetAsync(grid_out, 0, sizeof(float) * 4 * grid_nodes(g), st));
+    SortWorkspace ws;
+    sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
+    TileGeom tg = tile_geom<D>(g);
+    if (tg.ntiles > 0 && parts->n > 0)
+        g2p2g_kernel<D><<<(unsigned)tg.ntiles, 256, 0, st>>>(
+            g, tg, parts->x, parts->F, parts->m, parts->V0, parts->m_uniform, parts->V0_uniform,
+            parts->n, ws.offsets, apic, mat->model, lm.mu, lm.la, dt, grid_in, grid_out, v_out,
+            C_out, flag);
+    MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
+}  // namespace mr
+
+extern "C" int32_t mpm_g2p2g(const mr_grid *grid_desc, const mr_material *mat,
+                             mr_particles *parts, float dt, const float *grid_in, float *grid_out,
+                             int32_t flags, void *workspace, int32_t *status_flag, void *stream)
+{
+    GridK g;
+    if (!grid_from_desc(grid_desc, g) || !mat || !grid_in || !grid_out || grid_in == grid_out ||
+        !workspace || !check_parts(parts, grid_desc->dim, true))
+        return MR_EINVAL;
+    if (mat->model == MR_FIXED_COROTATED && grid_desc->dim != 2) return MR_EINVAL;
+    if (mat->model != MR_FIXED_COROTATED && mat->model != MR_NEO_HOOKEAN) return MR_EINVAL;
+    hipStream_t st = as_stream(stream);
+    float *vo = (flags & MR_NO_VC_OUT) ? nullptr : parts->v;
+    float *co = ((flags & MR_NO_VC_OUT) || (flags & MR_NO_AFFINE)) ? nullptr : parts->C;
+    if (!(flags & MR_NO_AFFINE) && !(flags & MR_NO_VC_OUT) && !parts->C && parts->n > 0)
+        return MR_EINVAL;
+    return grid_desc->dim == 2
+               ? g2p2g_impl<2>(g, mat, parts, dt, grid_in, grid_out, flags, workspace, vo, co,
+                               status_flag, st)
+               : g2p2g_impl<3>(g, mat, parts, dt, grid_in, grid_out, flags, workspace, vo, co,
+                               status_flag, st);
+}
+
+// ---------------------------------------------------------------------------
+// launch timing (HIP events recorded around each launch on its stream)
+
+struct mr_timing {
+    int32_t cap, count;
+    hipEvent_t *ev;  // 2 per record
+    int32_t *cls;
+};
+
+extern "C" int32_t mr_timing_create(int32_t capacity, mr_timing **out)
+{
+    if (capacity < 1 || !out) return MR_EINVAL;
+    mr_timing *t = (mr_timing *)calloc(1, sizeof(mr_timing));
+    if (!t) return MR_ENOMEM;
+    t->cap = capacity;
+    t->ev = (hipEvent_t *)calloc(2 * (size_t)capacity, sizeof(hipEvent_t));
+    t->cls = (int32_t *)calloc((size_t)capacity, sizeof(int32_t));
+    if (!t->ev || !t->cls) {
+        free(t->ev);
+        free(t->cls);
+        free(t);
+        return MR_ENOMEM;
+    }
+    for (int32_t i = 0; i < 2 * capacity; ++i)
+        if (hipEventCreate(&t->ev[i]) != hipSuccess) {
+            for (int32_t j = 0; j < i; ++j) (void)hipEventDestroy(t->ev[j]);
+            free(t->ev);
+            free(t->cls);
+            free(t);
+            return MR_EDEVICE;
+        }
+    *out = t;
+    return MR_OK;
+}
+
+extern "C" void mr_timing_destroy(mr_timing *t)
+{
+    if (!t) return;
+    for (int32_t i = 0; i < 2 * t->cap; ++i) (void)hipEventDestroy(t->ev[i]);
+    free(t->ev);
+    free(t->cls);
+    free(t);
+}
+
+extern "C" int32_t mr_timing_reset(mr_timing *t)
+{
+    if (!t) return MR_EINVAL;
+    t->count = 0;
+    return MR_OK;
+}
+
+extern "C" int32_t mr_timing_read(mr_timing *t, int32_t n_classes, int64_t *launches,
+                                  double *total_ms)
+{
+    if (!t || n_classes < 1 || !launches || !total_ms) return MR_EINVAL;
+    for (int32_t c = 0; c < n_classes; ++c) {
+        launches[c] = 0;
+        total_ms[c] = 0.0;
+    }
+    for (int32_t i = 0; i < t->count; ++i) {
+        MR_CHECK_HIP(hipEventSynchronize(t->ev[2 * i + 1]));
+        float ms = 0.0f;
+        MR_CHECK_HIP(hipEventElapsedTime(&ms, t->ev[2 * i], t->ev[2 * i + 1]));
+        int32_t c = t->cls[i];
+        if (c >= 0 && c < n_classes) {
+            launches[c] += 1;
+            total_ms[c] += ms;
+        }
+    }
+    return MR_OK;
+}
+
+namespace mr {
+struct TimedLaunch {
+    mr_timing *t;
+    int idx;
+    hipStream_t st;
+    TimedLaunch(mr_timing *tm, int cls, hipStream_t s) : t(tm), idx(-1), st(s)
+    {
+        if (t && t->count < t->cap) {
+            idx = t->count++;
+            t->cls[idx] = cls;
+            (void)hipEventRecord(t->ev[2 * idx], st);
+        }
+    }
+    ~TimedLaunch()
+    {
+        if (idx >= 0) (void)hipEventRecord(t->ev[2 * idx + 1], st);
+    }
+};
+}  // namespace mr
+
+// ---------------------------------------------------------------------------
 // multi-step driver
 
 extern "C" int64_t mpm_step_workspace_bytes(const mr_grid *grid_desc, int64_t n)
 {
-    return mpm_workspace_bytes(grid_desc, n);
+    GridK g;
+    if (!grid_from_desc(grid_desc, g) || n < 0) return -1;
+    int64_t sort_bytes = mpm_workspace_bytes(grid_desc, n);
+    return sort_bytes + 16 * grid_nodes(g) + 256;  // + second grid for the fused path
 }
 
 __global__ void iota_kernel(int32_t *a, int64_t n)
@@ -790,37 +1109,71 @@ __global__ void iota_kernel(int32_t *a, int64_t n)
 extern "C" int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
                             mr_particles *parts, float dt, int32_t n_steps, int32_t sort_every,
                             int32_t flags, float *grid, void *workspace, int32_t *perm_accum,
-                            int32_t *status_flag, void *stream)
+                            int32_t *status_flag, mr_timing *timing, void *stream)
 {
     GridK g;
     if (!grid_from_desc(grid_desc, g) || !mat || !grid || !workspace || n_steps < 0 ||
         sort_every < 0 || !check_parts(parts, grid_desc->dim, true))
         return MR_EINVAL;
     if (!(flags & MR_NO_AFFINE) && !parts->C && parts->n > 0) return MR_EINVAL;
-    int32_t rc;
+    if (sort_every > 0 && parts->n > INT32_MAX) return MR_EINVAL;
+    const int dim = grid_desc->dim;
+    int32_t rc = MR_OK;
     hipStream_t st = as_stream(stream);
     if (perm_accum && parts->n > 0) {
         iota_kernel<<<(unsigned)ceil_div(parts->n, 256), 256, 0, st>>>(perm_accum, parts->n);
         MR_LAUNCH_CHECK();
     }
-    for (int32_t s = 0; s < n_steps; ++s) {
-        bool sort_now = sort_every > 0 && (s % sort_every) == 0;
-        if (sort_now) {
-            if (parts->n > INT32_MAX) return MR_EINVAL;
-            rc = grid_desc->dim == 2
-                     ? cell_sort_impl<2>(g, parts, nullptr, workspace, status_flag, st, perm_accum)
-                     : cell_sort_impl<3>(g, parts, nullptr, workspace, status_flag, st, perm_accum);
+    if (n_steps == 0) return MR_OK;
+    const bool sorted = sort_every > 0;
+    const int32_t naff = flags & MR_NO_AFFINE;
+    float *gA = grid;
+    float *gB = (float *)((char *)workspace + ((mpm_workspace_bytes(grid_desc, parts->n) + 255) &
+                                               ~(int64_t)255));
+    auto do_sort = [&]() -> int32_t {
+        TimedLaunch tl(timing, MR_KC_SORT, st);
+        return dim == 2 ? cell_sort_impl<2>(g, parts, nullptr, workspace, status_flag, st, perm_accum)
+                        : cell_sort_impl<3>(g, parts, nullptr, workspace, status_flag, st, perm_accum);
+    };
+    auto do_p2g = [&]() -> int32_t {
+        TimedLaunch tl(timing, MR_KC_P2G, st);
+        return mpm_p2g(grid_desc, mat, parts, nullptr, 0, dt, gA, naff | (sorted ? MR_SORTED : 0),
+                       workspace, status_flag, stream);
+    };
+    auto do_update = [&]() -> int32_t {
+        TimedLaunch tl(timing, MR_KC_GRID, st);
+        return mpm_grid_update(grid_desc, dt, gA, nullptr, 0, stream);
+    };
+    auto do_g2p = [&]() -> int32_t {
+        TimedLaunch tl(timing, MR_KC_G2P, st);
+        return mpm_g2p(grid_desc, parts, nullptr, 0, dt, gA, naff, nullptr, nullptr, status_flag,
+                       stream);
+    };
+    if (sorted && (rc = do_sort()) != MR_OK) return rc;
+    if ((rc = do_p2g()) != MR_OK) return rc;
+    if ((rc = do_update()) != MR_OK) return rc;
+    for (int32_t s = 1; s < n_steps; ++s) {
+        if (!sorted || s % sort_every == 0) {
+            if ((rc = do_g2p()) != MR_OK) return rc;
+            if (sorted && (rc = do_sort()) != MR_OK) return rc;
+            if ((rc = do_p2g()) != MR_OK) return rc;
+        } else {
+            {
+                TimedLaunch tl(timing, MR_KC_ZERO, st);
+                if (hipMemsetAsync(gB, 0, sizeof(float) * 4 * grid_nodes(g), st) != hipSuccess)
+                    return MR_EDEVICE;
+            }
+            {
+                TimedLaunch tl(timing, MR_KC_G2P2G, st);
+                rc = mpm_g2p2g(grid_desc, mat, parts, dt, gA, gB,
+                               naff | MR_NO_VC_OUT | MR_ACCUMULATE, workspace, status_flag, stream);
+            }
             if (rc != MR_OK) return rc;
+            float *tmp = gA;
+            gA = gB;
+            gB = tmp;
         }
-        int32_t pf = (flags & MR_NO_AFFINE) | (sort_every > 0 ? MR_SORTED : 0);
-        rc = mpm_p2g(grid_desc, mat, parts, nullptr, 0, dt, grid, pf, workspace, status_flag,
-                     stream);
-        if (rc != MR_OK) return rc;
-        rc = mpm_grid_update(grid_desc, dt, grid, nullptr, 0, stream);
-        if (rc != MR_OK) return rc;
-        rc = mpm_g2p(grid_desc, parts, nullptr, 0, dt, grid, flags & MR_NO_AFFINE, nullptr,
-                     nullptr, status_flag, stream);
-        if (rc != MR_OK) return rc;
+        if ((rc = do_update()) != MR_OK) return rc;
     }
-    return MR_OK;
+    return do_g2p();
 }

@@ -7,13 +7,14 @@ namespace mr {
 
 int decoder_dim(const mr_decoder *dec);
 int decoder_latent(const mr_decoder *dec);
+int decoder_output_mode(const mr_decoder *dec);
 int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X, int64_t n,
                       const int32_t *idx, int32_t idx_per_instance, const int32_t *n_inst,
                       const double *xhat, const double *vhat, float *x, float *F, float *v,
-                      float *Jz, hipStream_t st);
+                      float *Jz, hipStream_t st, int disp_only = 0);
 
 struct ProjWS {
-    float *Jz, *x, *xc;
+    float *Jz, *x, *xc, *xt;
     double *A, *L, *g, *delta, *z, *v, *zc, *f, *fc, *fnew, *step;
     int32_t *status, *singular;
 };

@@ -170,6 +170,14 @@ __global__ void cholesky_solve_kernel(int B, int r, const double *A, const doubl
     }
 }
 
+// trial point of Algorithm 5 from the decoded current point: x_n + dt v_trial
+__global__ void trial_from_velocity_kernel(int64_t total, double dt, const float *xn,
+                                           const float *vt, float *xt)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < total) xt[i] = xn[i] + (float)dt * vt[i];
+}
+
 __global__ void init_guess_kernel(int B, int r, int mode, double dt, const double *zn,
                                   const double *zp, const double *vhat, const int32_t *singular,
                                   double *z, double *vout)
@@ -265,6 +273,7 @@ int64_t proj_ws_bytes(int d, int r, int B, int64_t ns, int max_backtrack)
     take(4LL * B * d * r * ns);       // Jz
     take(4LL * B * d * ns);           // x
     take(4LL * B * nc * d * ns);      // candidate x
+    take(4LL * B * d * ns);           // trial positions / displacements
     take(8LL * B * r * r);            // A
     take(8LL * B * r * r);            // L
     take(8LL * B * r);                // rhs / g
@@ -295,6 +304,7 @@ ProjWS proj_ws_carve(void *base, int d, int r, int B, int64_t ns, int max_backtr
     w.Jz = (float *)take(4LL * B * d * r * ns);
     w.x = (float *)take(4LL * B * d * ns);
     w.xc = (float *)take(4LL * B * nc * d * ns);
+    w.xt = (float *)take(4LL * B * d * ns);
     w.A = (double *)take(8LL * B * r * r);
     w.L = (double *)take(8LL * B * r * r);
     w.g = (double *)take(8LL * B * r);
@@ -324,10 +334,23 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
     size_t ne_lds = sizeof(float) * (size_t)(d * r + d) * NE_CHUNK;
     zero_i32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>(w.status, B);
     zero_i32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>(w.singular, B);
+    // With x_trial == NULL the trial positions are those of Algorithm 5,
+    // g(X_p; xhat_n) + dt v_trial, and with a displacement-mode decoder the
+    // whole position projection runs on displacements g - X: the residual
+    // g(X; z) - x_trial is then formed from numbers of the size of the
+    // motion, not of the coordinates, so fp32 keeps its relative accuracy.
+    const int disp = (!x_trial && decoder_output_mode(dec) == MR_OUT_DISPLACEMENT) ? 1 : 0;
     // velocity least squares at zn
     rc = decode_jac_ex(dec, B, n_ref, X, ns, idx, 1, ns_inst, zn, nullptr, w.x, nullptr, nullptr,
-                       w.Jz, st);
+                       w.Jz, st, disp);
     if (rc != MR_OK) return rc;
+    const float *xtp = x_trial;
+    if (!x_trial) {
+        int64_t tot = (int64_t)B * d * ns;
+        trial_from_velocity_kernel<<<(unsigned)ceil_div(tot, TB), TB, 0, st>>>(tot, dt, w.x, v_trial,
+                                                                                w.xt);
+        xtp = w.xt;
+    }
     normal_eq_kernel<0><<<B, NE_THREADS, ne_lds, st>>>(d, r, ns, ns_inst, w.Jz, v_trial, nullptr,
                                                       w.A, w.g, nullptr);
     cholesky_solve_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(B, r, w.A, w.g, o.damping, 1.0,
@@ -340,9 +363,9 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
     if (o.mode == MR_POS_VEL) {
         for (int it = 0; it < o.max_iter; ++it) {
             rc = decode_jac_ex(dec, B, n_ref, X, ns, idx, 1, ns_inst, w.z, nullptr, w.x, nullptr,
-                               nullptr, w.Jz, st);
+                               nullptr, w.Jz, st, disp);
             if (rc != MR_OK) return rc;
-            normal_eq_kernel<1><<<B, NE_THREADS, ne_lds, st>>>(d, r, ns, ns_inst, w.Jz, x_trial,
+            normal_eq_kernel<1><<<B, NE_THREADS, ne_lds, st>>>(d, r, ns, ns_inst, w.Jz, xtp,
                                                               w.x, w.A, w.g, w.f);
             cholesky_solve_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(
                 B, r, w.A, w.g, o.damping, -1.0, w.delta, w.L, w.status, nullptr);
@@ -350,9 +373,9 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
                 B, r, nc, w.z, w.delta, w.zc);
             MR_LAUNCH_CHECK();
             rc = decode_jac_ex(dec, B * nc, n_ref, X, ns, idx, nc, nullptr, w.zc, nullptr, w.xc,
-                               nullptr, nullptr, nullptr, st);
+                               nullptr, nullptr, nullptr, st, disp);
             if (rc != MR_OK) return rc;
-            objective_kernel<<<B * nc, 256, 0, st>>>(d, ns, nc, ns_inst, w.xc, x_trial, w.fc);
+            objective_kernel<<<B * nc, 256, 0, st>>>(d, ns, nc, ns_inst, w.xc, xtp, w.fc);
             select_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(
                 B, r, nc, o.armijo_c, o.tol_step, w.f, w.g, w.delta, w.fc, w.singular, w.z, w.fnew,
                 w.step, w.status, it == o.max_iter - 1 ? 1 : 0);
@@ -394,7 +417,7 @@ extern "C" int32_t rom_project(const mr_decoder *dec, int32_t B, int64_t n_ref, 
     if (!dec || B < 1 || ns < 1 || !X || !sample_idx || !v_trial || !xhat_n || !opts_ok(opts) ||
         !xhat_next || !vhat_next)
         return MR_EINVAL;
-    if (opts->mode == MR_POS_VEL && (!x_trial || !xhat_prev)) return MR_EINVAL;
+    if (opts->mode == MR_POS_VEL && !xhat_prev) return MR_EINVAL;
     int d = decoder_dim(dec), r = decoder_latent(dec);
     if ((int64_t)B * (opts->max_backtrack + 1) > 65535) return MR_EINVAL;
     hipStream_t st = as_stream(stream);

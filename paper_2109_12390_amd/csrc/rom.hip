@@ -369,7 +369,7 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
     MR_LAUNCH_CHECK();
     // Algorithm 6 / 7
     ProjWS w = proj_ws_carve(R->proj_ws, d, r, B, R->ns_max, R->opts.max_backtrack);
-    rc = project_impl(R->dec, d, r, B, R->P, R->X, R->ns_max, R->samples, R->n_samples, R->xt,
+    rc = project_impl(R->dec, d, r, B, R->P, R->X, R->ns_max, R->samples, R->n_samples, nullptr,
                       R->vt, xhat, xhat_prev, dt, R->opts, R->z_next, R->v_next, nullptr, nullptr,
                       R->status_step, w, st, /*accumulate=*/1);
     if (rc != MR_OK) return rc;

@@ -11,7 +11,8 @@ def soa(a):
     """(P, d) or (P, d, d) -> (d, P) or (d*d, P) float32."""
     a = np.asarray(a)
     P = a.shape[0]
-    return np.ascontiguousarray(a.reshape(P, -1).T.astype(np.float32))
+    k = int(np.prod(a.shape[1:]))
+    return np.ascontiguousarray(a.reshape(P, k).T.astype(np.float32))
 
 
 def aos(a, dim, mat=False):

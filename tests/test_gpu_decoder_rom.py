@@ -270,3 +270,28 @@ def test_rom_step_matches_oracle(gpu):
         assert ez < 1e-3 and ev < 1e-3
     assert st.cpu().numpy().tolist() == [0, 0]
     rom.close()
+
+
+def test_linear_decoder_matches_oracle(gpu):
+    """Decoder without hidden layers (the linear-manifold baseline)."""
+    d, r = 3, 6
+    rng = np.random.default_rng(14)
+    X = rng.uniform(0.2, 0.8, size=(333, d)).astype(np.float32)
+    W = (0.3 * rng.standard_normal((d, d + r))).astype(np.float32)
+    b = (0.1 * rng.standard_normal(d)).astype(np.float32)
+    lo, hi = X.min(0), X.max(0)
+    mean, std = np.zeros(d, np.float32), np.full(d, 0.05, np.float32)
+    odec = OD.Decoder([W], [b], lo, hi, mean, std)
+    gdec = B.Decoder([W], [b], lo, hi, mean, std)
+    z = rng.standard_normal((1, r))
+    vh = rng.standard_normal((1, r))
+    x = torch.zeros(1, d, 333, device=dev)
+    F = torch.zeros(1, d * d, 333, device=dev)
+    v = torch.zeros(1, d, 333, device=dev)
+    J = torch.zeros(1, d * r, 333, device=dev)
+    B.rom_decode_jac(gdec, T(soa(X)), T(z, torch.float64), vhat=T(vh, torch.float64), x=x, F=F, v=v, Jz=J)
+    xo, Fo, Jo, vo = OD.decode_jac(odec, X.astype(np.float64), z[0], vh[0])
+    assert scaled_err(x[0].cpu().numpy().T, xo, np.max(np.abs(xo - X))) < 1e-5
+    assert scaled_err(F[0].cpu().numpy().T.reshape(333, d, d), Fo, np.max(np.abs(Fo - np.eye(d)))) < 1e-5
+    assert scaled_err(J[0].cpu().numpy().T.reshape(333, d, r), Jo, np.max(np.abs(Jo))) < 1e-5
+    assert scaled_err(v[0].cpu().numpy().T, vo, np.max(np.abs(vo))) < 1e-5

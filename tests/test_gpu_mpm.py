@@ -218,13 +218,15 @@ def test_two_dimensional_scene_trajectory(gpu, steps, sort_every):
     F = aos(parts.F.cpu().numpy(), 2, True)[inv]
     ex = rel_l2(x, ref["x"])
     ev = rel_l2(v, ref["v"])
-    eF = rel_l2(F - np.eye(2), ref["F"] - np.eye(2))
+    # F - I after one step is ~1e-6, below fp32 resolution of F itself
+    # (ulp(1) = 1.2e-7), so F is compared in absolute terms
+    eF = float(np.max(np.abs(F - ref["F"])))
     ed = rel_l2(x - s["X"], ref["x"] - s["X"])
-    print("2D steps=%d sort=%d: x %.3e  v %.3e  F-I %.3e  displacement %.3e" % (steps, sort_every, ex, ev, eF, ed))
+    print("2D steps=%d sort=%d: x %.3e  v %.3e  max|dF| %.3e  displacement %.3e" % (steps, sort_every, ex, ev, eF, ed))
     assert flag.item() == 0
     assert ex <= (1e-5 if steps == 1 else 1e-3)
     assert ev <= (1e-4 if steps == 1 else 1e-2)
-    assert eF <= (1e-3 if steps == 1 else 1e-2)
+    assert eF <= (1e-6 if steps == 1 else 1e-4)
 
 
 def test_three_dimensional_scene_small(gpu):
@@ -307,6 +309,50 @@ def test_invalid_arguments_rejected(gpu):
     with pytest.raises(B.MrError):
         B.mpm_p2g(B.Grid(3, [16] * 3, 1 / 16), (B.NEO_HOOKEAN, 1e4, 0.3),
                   make_parts(B, x, v, C, F, m, V0), gbuf, 1e-4, flags=B.SORTED)
+
+
+@pytest.mark.parametrize("dim,apic", [(3, True), (2, True), (3, False)])
+def test_fused_g2p2g_matches_oracle(gpu, dim, apic):
+    """mpm_g2p2g = G2P from grid_in (Algorithm 1, steps 3-4) followed by P2G
+    at the updated state (Algorithm 1, step 1), on sorted particles whose
+    positions were then jittered by up to 1.4 cells (some beyond the drift
+    margin, exercising the HBM fallbacks of both halves)."""
+    rng = np.random.default_rng(70 + dim)
+    n = [32] * dim
+    dx = 1 / 32
+    P = 12000 if dim == 3 else 3000
+    x, v, C, F, m, V0 = random_state(rng, dim, P, lo=0.2, hi=0.8)
+    grid = B.Grid(dim, n, dx)
+    parts = make_parts(B, x, v, C, F, m, V0)
+    ws = B.new_workspace(grid, P)
+    perm = torch.zeros(P, dtype=torch.int32, device=dev)
+    B.mpm_cell_sort(grid, parts, ws, perm_out=perm)
+    p = perm.cpu().numpy()
+    xs = x[p] + (rng.uniform(-1.4, 1.4, size=(P, dim)) * dx).astype(np.float32)
+    parts.x.copy_(T(soa(xs)))
+    gv = (0.5 * rng.standard_normal((32 ** dim, dim))).astype(np.float32)
+    gin = np.zeros((32 ** dim, 4), np.float32)
+    gin[:, 0] = 1.0
+    gin[:, 1:1 + dim] = gv
+    dt = 1e-3
+    model = 0 if dim == 2 else 1
+    mu, la = OM.lame(1e4, 0.3)
+    xo, vo, Co, Fo = OM.g2p(dim, n, dx, dt, gv.astype(np.float64), xs, v[p], C[p], F[p], apic=apic)
+    gm, gmv, gf = OM.p2g(dim, n, dx, xo, vo, Co, Fo, m[p], V0[p], model, mu, la, apic=apic)
+    gout = torch.full((32 ** dim * 4,), 5.0, device=dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    B.mpm_g2p2g(grid, (model, 1e4, 0.3), parts, dt, T(gin.reshape(-1)), gout, ws,
+                flags=0 if apic else B.NO_AFFINE, status=flag)
+    g = gout.cpu().numpy().reshape(-1, 4)
+    assert flag.item() == 0
+    close_channels(g[:, 0], gm, name="fused mass")
+    close_channels(g[:, 1:1 + dim], gmv + dt * gf, name="fused momentum")
+    np.testing.assert_allclose(aos(parts.x.cpu().numpy(), dim), xo, atol=2e-7)
+    np.testing.assert_allclose(aos(parts.F.cpu().numpy(), dim, True), Fo, atol=2e-6)
+    close_channels(aos(parts.v.cpu().numpy(), dim), vo, name="fused v")
+    if apic:
+        close_channels(aos(parts.C.cpu().numpy(), dim, True).reshape(P, -1), Co.reshape(P, -1),
+                       name="fused C")
 
 
 def test_empty_particle_set(gpu):
