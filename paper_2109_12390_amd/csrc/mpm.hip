@@ -317,68 +317,197 @@ __global__ void gather_plane_kernel(const float *src, float *dst, const int32_t 
 }
 
 // ---------------------------------------------------------------------------
-// sorted, LDS-tiled P2G
+// sorted P2G: one wave per tile, one lane per home cell
+//
+// The cell sort orders each tile's particles slot-major: the first particle
+// of every cell of the tile (in cell order), then the second ones, ...  A
+// wave owns one tile and lane c owns local cell c: at rank k the active lanes
+// (cells with more than k particles) read consecutive particles, so the loads
+// are coalesced, and their stencil bases are distinct, so for any one stencil
+// offset the 64 lanes touch 64 distinct nodes.  The wave accumulates into a
+// private LDS copy of the tile's node region with plain float4
+// read-modify-write (LDS float atomics are far slower on this part); the
+// accesses of one wave are kept in program order by a compiler barrier after
+// every node, which the in-order LDS pipeline then preserves across lanes.
+// Particles that drifted out of their sort-time cell may share a base cell
+// with another lane; when a wave has any such particle, lanes claim their
+// base cell in an owner table and the losers retry in a later round.  A
+// particle whose stencil left the region entirely goes to HBM atomics.  The
+// padded region layout (row stride 12 / 24 float4) keeps the 16 lanes of a
+// LDS cycle on distinct banks.
 
 template <int D>
-__global__ void __launch_bounds__(256) p2g_tiled_kernel(GridK g, TileGeom tg, PartPtrs<D> pp,
-                                                        const int32_t *offsets, int apic,
-                                                        int model, float mu, float la,
-                                                        float dt, float *grid, int32_t *flag)
+struct CellTile {
+    static constexpr int TS = Tiling<D>::TS;        // cells per tile edge
+    static constexpr int R = TS + 4;                // region nodes per edge
+    static constexpr int RC = TS + 2;               // region cells per edge
+    static constexpr int SY = (D == 3) ? 12 : 24;   // padded row stride (float4)
+    static constexpr int SZ = (D == 3) ? SY * R : 0;
+    static constexpr int RNP = (D == 3) ? SZ * R : SY * R;
+    static constexpr int RCN = (D == 3) ? RC * RC * RC : RC * RC;
+    static constexpr int WPB = 4;                   // waves (tiles) per workgroup
+};
+
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
+
+template <int D, bool FUSED>
+__global__ void __launch_bounds__(256) tile_scatter_kernel(
+    GridK g, TileGeom tg, float *x, float *v, float *C, float *F, const float *m, const float *V0,
+    float m_u, float V0_u, int64_t n, const int32_t *offsets, const int32_t *counts, int apic,
+    int model, float mu, float la, float dt, const float *grid_in, float *grid_out, float *v_out,
+    float *C_out, int32_t *flag)
 {
-    using T = Tiling<D>;
-    constexpr int R = T::R, RN = T::RN;
-    __shared__ float acc[4 * RN];  // channel-major
-    const int64_t t = blockIdx.x;
-    for (int i = threadIdx.x; i < 4 * RN; i += blockDim.x) acc[i] = 0.0f;
-    const int t0 = (int)(t % tg.nt0);
-    const int t1 = (int)((t / tg.nt0) % tg.nt1);
-    const int t2 = D == 3 ? (int)(t / ((int64_t)tg.nt0 * tg.nt1)) : 0;
-    // region origin: tile origin minus one cell of drift margin
-    const int r0 = t0 * T::TS - 1, r1 = t1 * T::TS - 1, r2 = D == 3 ? t2 * T::TS - 1 : 0;
-    const int begin = offsets[t * T::CELLS];
-    const int end = offsets[(t + 1) * T::CELLS];
-    __syncthreads();
-    for (int64_t p = begin + threadIdx.x; p < end; p += blockDim.x) {
-        Stencil<D> st;
+    using CT = CellTile<D>;
+    __shared__ float4 acc_all[CT::WPB][CT::RNP];
+    __shared__ int owner_all[CT::WPB][CT::RCN];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float4 *acc = acc_all[wave];
+    int *owner = owner_all[wave];
+    const int64_t t = (int64_t)blockIdx.x * CT::WPB + wave;
+    if (t >= tg.ntiles) return;                    // wave-uniform; no block barriers below
+    const int64_t c0 = offsets[t * Tiling<D>::CELLS];
+    const int64_t c1 = offsets[(t + 1) * Tiling<D>::CELLS];
+    if (c0 == c1) return;
+    for (int i = lane; i < CT::RNP; i += 64) acc[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    lds_order();
+    const int tt0 = (int)(t % tg.nt0);
+    const int tt1 = (int)((t / tg.nt0) % tg.nt1);
+    const int tt2 = D == 3 ? (int)(t / ((int64_t)tg.nt0 * tg.nt1)) : 0;
+    const int r0 = tt0 * CT::TS - 1, r1 = tt1 * CT::TS - 1, r2 = D == 3 ? tt2 * CT::TS - 1 : 0;
+    // home cell of this lane, relative to the region origin
+    const int h0 = lane % CT::TS + 1;
+    const int h1 = (lane / CT::TS) % CT::TS + 1;
+    const int h2 = D == 3 ? lane / (CT::TS * CT::TS) + 1 : 0;
+    const int cnt = counts[t * Tiling<D>::CELLS + lane];
+    const float cscale = apic ? 4.0f * g.inv_dx * g.inv_dx : 0.0f;
+    const float4 *gin4 = reinterpret_cast<const float4 *>(grid_in);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t base = c0;
+    for (int k = 0;; ++k) {
+        const bool act = k < cnt;
+        const uint64_t mask = __ballot(act);
+        if (mask == 0) break;
+        const int64_t p = base + __popcll(mask & below);
+        base += __popcll(mask);
+        bool scat = false, inreg = false;
+        Stencil<D> sn;
         P2GPayload<D> pl;
-        bool ok;
-        load_payload<D>(pp, p, apic != 0, model, mu, la, dt, g, st, pl, ok);
-        if (!ok) {
-            raise_flag(flag, MR_FLAG_DOMAIN);
-            continue;
-        }
-        int l0 = st.base[0] - r0, l1 = st.base[1] - r1, l2 = D == 3 ? st.base[2] - r2 : 0;
-        bool inside = l0 >= 0 && l0 + 2 < R && l1 >= 0 && l1 + 2 < R &&
-                      (D == 2 || (l2 >= 0 && l2 + 2 < R));
-        if (!inside) {
-            scatter_global<D>(g, st, pl, grid);
-            continue;
-        }
-        const int oz = (D == 3) ? 3 : 1;
-        for (int o2 = 0; o2 < oz; ++o2)
+        int m0 = 0, m1 = 0, m2 = 0;
+        if (act) {
+            float xn[D], vp[D], Cp[D * D], Fn[D * D];
+            bool ok = true;
+            if (FUSED) {
+                float xp[D], Fp[D * D];
 #pragma unroll
-            for (int o1 = 0; o1 < 3; ++o1)
+                for (int a = 0; a < D; ++a) xp[a] = x[a * n + p];
 #pragma unroll
-                for (int o0 = 0; o0 < 3; ++o0) {
-                    float mom[D];
-                    float mw = p2g_node<D>(g, st, pl, o0, o1, o2, mom);
-                    int li = (l0 + o0) + R * ((l1 + o1) + (D == 3 ? R * (l2 + o2) : 0));
-                    atomicAdd(&acc[li], mw);
+                for (int q = 0; q < D * D; ++q) Fp[q] = F[q * n + p];
+                Stencil<D> so;
+                ok = make_stencil<D>(g, xp, so);
+                if (ok) {
+                    float Bp[D * D], gv[D * D];
+                    g2p_separable<D>(g, so, [&](int o0, int o1, int o2) {
+                        return gin4[node_lin(g, so.base[0] + o0, so.base[1] + o1,
+                                             D == 3 ? so.base[2] + o2 : 0)];
+                    }, vp, Bp, gv);
+                    mr::update_F<D>(gv, Fp, dt, Fn);
 #pragma unroll
-                    for (int a = 0; a < D; ++a) atomicAdd(&acc[(1 + a) * RN + li], mom[a]);
+                    for (int q = 0; q < D * D; ++q) Cp[q] = cscale * Bp[q];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) xn[a] = xp[a] + dt * vp[a];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) x[a * n + p] = xn[a];
+#pragma unroll
+                    for (int q = 0; q < D * D; ++q) F[q * n + p] = Fn[q];
+                    if (v_out)
+#pragma unroll
+                        for (int a = 0; a < D; ++a) v_out[a * n + p] = vp[a];
+                    if (C_out)
+#pragma unroll
+                        for (int q = 0; q < D * D; ++q) C_out[q * n + p] = Cp[q];
                 }
-    }
-    __syncthreads();
-    for (int li = threadIdx.x; li < RN; li += blockDim.x) {
-        float mw = acc[li];
-        if (mw == 0.0f) continue;  // no particle reached this node (weights are > 0 inside)
-        int i0 = li % R, i1 = (li / R) % R, i2 = D == 3 ? li / (R * R) : 0;
-        int gi = r0 + i0, gj = r1 + i1, gk = D == 3 ? r2 + i2 : 0;
-        if (gi < 0 || gj < 0 || gk < 0 || gi >= g.n0 || gj >= g.n1 || gk >= g.n2) continue;
-        float *gp = grid + 4 * node_lin(g, gi, gj, gk);
-        atomicAdd(gp, mw);
+            } else {
 #pragma unroll
-        for (int a = 0; a < D; ++a) atomicAdd(gp + 1 + a, acc[(1 + a) * RN + li]);
+                for (int a = 0; a < D; ++a) {
+                    xn[a] = x[a * n + p];
+                    vp[a] = v[a * n + p];
+                }
+#pragma unroll
+                for (int q = 0; q < D * D; ++q) {
+                    Fn[q] = F[q * n + p];
+                    Cp[q] = apic ? C[q * n + p] : 0.0f;
+                }
+            }
+            float tau[D * D];
+            if (ok) {
+                ok = make_stencil<D>(g, xn, sn);
+                ok = kirchhoff<D>(model, mu, la, Fn, tau) && ok;
+            }
+            if (!ok) {
+                raise_flag(flag, MR_FLAG_DOMAIN);
+            } else {
+                const float mp = m ? m[p] : m_u;
+                const float sc = dt * (V0 ? V0[p] : V0_u);
+                pl.m = mp;
+#pragma unroll
+                for (int a = 0; a < D; ++a) pl.mv[a] = mp * vp[a];
+#pragma unroll
+                for (int q = 0; q < D * D; ++q) {
+                    pl.mC[q] = mp * Cp[q];
+                    pl.S[q] = sc * tau[q];
+                }
+                scat = true;
+                m0 = sn.base[0] - r0;
+                m1 = sn.base[1] - r1;
+                m2 = D == 3 ? sn.base[2] - r2 : 0;
+                inreg = m0 >= 0 && m0 < CT::RC && m1 >= 0 && m1 < CT::RC &&
+                        (D == 2 || (m2 >= 0 && m2 < CT::RC));
+                if (!inreg) scatter_global<D>(g, sn, pl, grid_out);
+            }
+        }
+        bool pending = scat && inreg;
+        const bool drifted = pending && (m0 != h0 || m1 != h1 || (D == 3 && m2 != h2));
+        const bool any_drift = __ballot(drifted) != 0;
+        const int key = m0 + CT::RC * (m1 + (D == 3 ? CT::RC * m2 : 0));
+        const int nb = m0 + CT::SY * m1 + (D == 3 ? CT::SZ * m2 : 0);
+        while (__ballot(pending) != 0) {
+            bool go = pending;
+            if (any_drift) {
+                if (pending) owner[key] = lane;
+                lds_order();
+                go = pending && owner[key] == lane;
+                lds_order();
+            }
+            if (go) {
+                p2g_separable<D>(g, sn, pl, [&](int o0, int o1, int o2, float mw, float q0,
+                                                 float q1, float q2) {
+                    float4 *a4 = acc + nb + o0 + CT::SY * o1 + (D == 3 ? CT::SZ * o2 : 0);
+                    float4 q = *a4;
+                    q.x += mw;
+                    q.y += q0;
+                    q.z += q1;
+                    q.w += q2;
+                    *a4 = q;
+                    lds_order();
+                });
+                pending = false;
+            }
+        }
+    }
+    lds_order();
+    // flush the region: one global atomic per non-zero node channel
+    constexpr int RN = (D == 3) ? CT::R * CT::R * CT::R : CT::R * CT::R;
+    for (int li = lane; li < RN; li += 64) {
+        const int i0 = li % CT::R, i1 = (li / CT::R) % CT::R, i2 = D == 3 ? li / (CT::R * CT::R) : 0;
+        const float4 q = acc[i0 + CT::SY * i1 + (D == 3 ? CT::SZ * i2 : 0)];
+        if (q.x == 0.0f) continue;
+        const int gi = r0 + i0, gj = r1 + i1, gk = D == 3 ? r2 + i2 : 0;
+        if (gi < 0 || gj < 0 || gk < 0 || gi >= g.n0 || gj >= g.n1 || gk >= g.n2) continue;
+        float *gp = grid_out + 4 * node_lin(g, gi, gj, gk);
+        atomicAdd(gp, q.x);
+        atomicAdd(gp + 1, q.y);
+        atomicAdd(gp + 2, q.z);
+        if (D == 3) atomicAdd(gp + 3, q.w);
     }
 }
 
@@ -431,41 +560,11 @@ __global__ void __launch_bounds__(256) g2p_kernel(GridK g, int64_t n, float *x, 
         raise_flag(flag, MR_FLAG_DOMAIN);
         return;
     }
-    float vp[D] = {}, Bp[D * D] = {}, gv[D * D] = {};
+    float vp[D], Bp[D * D], gv[D * D];
     const float4 *g4 = reinterpret_cast<const float4 *>(grid);
-    const int oz = (D == 3) ? 3 : 1;
-    for (int o2 = 0; o2 < oz; ++o2)
-#pragma unroll
-        for (int o1 = 0; o1 < 3; ++o1)
-#pragma unroll
-            for (int o0 = 0; o0 < 3; ++o0) {
-                const int o[3] = {o0, o1, o2};
-                float w = 1.0f, grad[D], dxi[D];
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    w *= st.w[a][o[a]];
-                    dxi[a] = ((float)o[a] - st.f[a]) * g.dx;
-                }
-#pragma unroll
-                for (int b = 0; b < D; ++b) {
-                    float gb = 1.0f;
-#pragma unroll
-                    for (int a = 0; a < D; ++a) gb *= (a == b) ? st.dw[a][o[a]] : st.w[a][o[a]];
-                    grad[b] = gb;
-                }
-                float4 q = g4[node_lin(g, st.base[0] + o0, st.base[1] + o1,
-                                       D == 3 ? st.base[2] + o2 : 0)];
-                const float vi[3] = {q.y, q.z, q.w};
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    vp[a] += w * vi[a];
-#pragma unroll
-                    for (int b = 0; b < D; ++b) {
-                        Bp[a * D + b] += w * vi[a] * dxi[b];
-                        gv[a * D + b] += vi[a] * grad[b];
-                    }
-                }
-            }
+    g2p_separable<D>(g, st, [&](int o0, int o1, int o2) {
+        return g4[node_lin(g, st.base[0] + o0, st.base[1] + o1, D == 3 ? st.base[2] + o2 : 0)];
+    }, vp, Bp, gv);
     if (trial) {
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -485,15 +584,7 @@ __global__ void __launch_bounds__(256) g2p_kernel(GridK g, int64_t n, float *x, 
         float Fp[D * D], Fn[D * D];
 #pragma unroll
         for (int k = 0; k < D * D; ++k) Fp[k] = F[k * n + p];
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                float acc = Fp[a * D + b];
-#pragma unroll
-                for (int k = 0; k < D; ++k) acc += dt * gv[a * D + k] * Fp[k * D + b];
-                Fn[a * D + b] = acc;
-            }
+        mr::update_F<D>(gv, Fp, dt, Fn);
 #pragma unroll
         for (int k = 0; k < D * D; ++k) F[k * n + p] = Fn[k];
     }
@@ -618,8 +709,10 @@ int32_t p2g_impl(const GridK &g, const mr_material *mat, const mr_particles *par
         sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
         TileGeom tg = tile_geom<D>(g);
         if (tg.ntiles > 0)
-            p2g_tiled_kernel<D><<<(unsigned)tg.ntiles, 256, 0, st>>>(
-                g, tg, pp, ws.offsets, apic, mat->model, lm.mu, lm.la, dt, grid, flag);
+            tile_scatter_kernel<D, false><<<(unsigned)ceil_div(tg.ntiles, CellTile<D>::WPB), 256, 0, st>>>(
+                g, tg, parts->x, parts->v, parts->C, parts->F, parts->m, parts->V0, parts->m_uniform,
+                parts->V0_uniform, parts->n, ws.offsets, ws.counts, apic, mat->model, lm.mu, lm.la, dt,
+                nullptr, grid, nullptr, nullptr, flag);
         // particles in the overflow bucket (outside the lattice at sort time)
         // were flagged by the sort; the tiled kernel only covers tiles
         MR_LAUNCH_CHECK();
@@ -774,183 +867,14 @@ extern "C" int32_t mr_sync_status(void *stream, const int32_t *device_flags, int
 extern "C" const char *mr_version(void) { return "mpmrom 0.1 gfx950"; }
 
 // ---------------------------------------------------------------------------
-// fused grid-to-particle (step n) and particle-to-grid (step n + 1)
-//
-// One workgroup per tile of cells of the last cell sort.  The tile's region of
-// the incoming grid velocities (the tile's cells plus stencil reach plus one
-// cell of drift margin) is staged in LDS; every particle gathers its G2P
-// stencil from there (or from HBM if it drifted beyond the margin), updates
-// v, C (affine), F and x in registers, evaluates the stress at the new F and
-// scatters the P2G contributions of the next step into an LDS copy of the
-// outgoing grid region, which is flushed with one global atomic per non-zero
-// node channel.  Per particle and step only x and F travel through HBM
-// (48 bytes read, 48 written); v and C are produced and consumed in
-// registers and stored only when v_out / C_out are given.
+// fused grid-to-particle (step n) and particle-to-grid (step n + 1): the same
+// tile kernel, with each lane first gathering its particle's G2P stencil from
+// the incoming grid (HBM / L2), updating v, C, F and x in registers and then
+// scattering the next step's contributions at the new state.  Per particle
+// and step only x and F travel through HBM (48 bytes read, 48 written); v and
+// C are stored only when v_out / C_out are given.
 
 namespace mr {
-
-template <int D>
-__global__ void __launch_bounds__(256) g2p2g_kernel(GridK g, TileGeom tg, float *x, float *F,
-                                                    const float *m, const float *V0, float m_u,
-                                                    float V0_u, int64_t n,
-                                                    const int32_t *offsets, int apic, int model,
-                                                    float mu, float la, float dt,
-                                                    const float *grid_in, float *grid_out,
-                                                    float *v_out, float *C_out, int32_t *flag)
-{
-    using T = Tiling<D>;
-    constexpr int R = T::R, RN = T::RN;
-    __shared__ float4 vin[RN];
-    __shared__ float acc[4 * RN];
-    const int64_t t = blockIdx.x;
-    const int t0 = (int)(t % tg.nt0);
-    const int t1 = (int)((t / tg.nt0) % tg.nt1);
-    const int t2 = D == 3 ? (int)(t / ((int64_t)tg.nt0 * tg.nt1)) : 0;
-    const int r0 = t0 * T::TS - 1, r1 = t1 * T::TS - 1, r2 = D == 3 ? t2 * T::TS - 1 : 0;
-    const int begin = offsets[t * T::CELLS];
-    const int end = offsets[(t + 1) * T::CELLS];
-    if (begin == end) return;  // empty tile: nothing to gather or scatter (block-uniform)
-    const float4 *gin4 = reinterpret_cast<const float4 *>(grid_in);
-    for (int li = threadIdx.x; li < RN; li += blockDim.x) {
-        int gi = r0 + li % R, gj = r1 + (li / R) % R, gk = D == 3 ? r2 + li / (R * R) : 0;
-        float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (gi >= 0 && gj >= 0 && gk >= 0 && gi < g.n0 && gj < g.n1 && gk < g.n2)
-            q = gin4[node_lin(g, gi, gj, gk)];
-        vin[li] = q;
-    }
-    for (int i = threadIdx.x; i < 4 * RN; i += blockDim.x) acc[i] = 0.0f;
-    __syncthreads();
-    const float cscale = apic ? 4.0f * g.inv_dx * g.inv_dx : 0.0f;
-    const int oz = (D == 3) ? 3 : 1;
-    for (int64_t p = begin + threadIdx.x; p < end; p += blockDim.x) {
-        float xp[D], Fp[D * D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) xp[a] = x[a * n + p];
-#pragma unroll
-        for (int k = 0; k < D * D; ++k) Fp[k] = F[k * n + p];
-        Stencil<D> st;
-        if (!make_stencil<D>(g, xp, st)) {
-            raise_flag(flag, MR_FLAG_DOMAIN);
-            continue;
-        }
-        int l0 = st.base[0] - r0, l1 = st.base[1] - r1, l2 = D == 3 ? st.base[2] - r2 : 0;
-        bool in_old = l0 >= 0 && l0 + 2 < R && l1 >= 0 && l1 + 2 < R &&
-                      (D == 2 || (l2 >= 0 && l2 + 2 < R));
-        // ---- G2P from the staged region
-        float vp[D] = {}, Bp[D * D] = {}, gv[D * D] = {};
-        for (int o2 = 0; o2 < oz; ++o2)
-#pragma unroll
-            for (int o1 = 0; o1 < 3; ++o1)
-#pragma unroll
-                for (int o0 = 0; o0 < 3; ++o0) {
-                    const int o[3] = {o0, o1, o2};
-                    float w = 1.0f, grad[D], dxi[D];
-#pragma unroll
-                    for (int a = 0; a < D; ++a) {
-                        w *= st.w[a][o[a]];
-                        dxi[a] = ((float)o[a] - st.f[a]) * g.dx;
-                    }
-#pragma unroll
-                    for (int b = 0; b < D; ++b) {
-                        float gb = 1.0f;
-#pragma unroll
-                        for (int a = 0; a < D; ++a) gb *= (a == b) ? st.dw[a][o[a]] : st.w[a][o[a]];
-                        grad[b] = gb;
-                    }
-                    float4 q;
-                    if (in_old)
-                        q = vin[(l0 + o0) + R * ((l1 + o1) + (D == 3 ? R * (l2 + o2) : 0))];
-                    else
-                        q = gin4[node_lin(g, st.base[0] + o0, st.base[1] + o1,
-                                          D == 3 ? st.base[2] + o2 : 0)];
-                    const float vi[3] = {q.y, q.z, q.w};
-#pragma unroll
-                    for (int a = 0; a < D; ++a) {
-                        vp[a] += w * vi[a];
-#pragma unroll
-                        for (int b = 0; b < D; ++b) {
-                            Bp[a * D + b] += w * vi[a] * dxi[b];
-                            gv[a * D + b] += vi[a] * grad[b];
-                        }
-                    }
-                }
-        float Fn[D * D], Cp[D * D], xn[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                float s = Fp[a * D + b];
-#pragma unroll
-                for (int k = 0; k < D; ++k) s += dt * gv[a * D + k] * Fp[k * D + b];
-                Fn[a * D + b] = s;
-            }
-#pragma unroll
-        for (int k = 0; k < D * D; ++k) Cp[k] = cscale * Bp[k];
-#pragma unroll
-        for (int a = 0; a < D; ++a) xn[a] = xp[a] + dt * vp[a];
-#pragma unroll
-        for (int a = 0; a < D; ++a) x[a * n + p] = xn[a];
-#pragma unroll
-        for (int k = 0; k < D * D; ++k) F[k * n + p] = Fn[k];
-        if (v_out)
-#pragma unroll
-            for (int a = 0; a < D; ++a) v_out[a * n + p] = vp[a];
-        if (C_out)
-#pragma unroll
-            for (int k = 0; k < D * D; ++k) C_out[k * n + p] = Cp[k];
-        // ---- P2G of the next step at the new state
-        Stencil<D> sn;
-        float tau[D * D];
-        bool ok = make_stencil<D>(g, xn, sn);
-        ok = kirchhoff<D>(model, mu, la, Fn, tau) && ok;
-        if (!ok) {
-            raise_flag(flag, MR_FLAG_DOMAIN);
-            continue;
-        }
-        P2GPayload<D> pl;
-        const float mp = m ? m[p] : m_u;
-        const float sc = dt * (V0 ? V0[p] : V0_u);
-        pl.m = mp;
-#pragma unroll
-        for (int a = 0; a < D; ++a) pl.mv[a] = mp * vp[a];
-#pragma unroll
-        for (int k = 0; k < D * D; ++k) {
-            pl.mC[k] = mp * Cp[k];
-            pl.S[k] = sc * tau[k];
-        }
-        int m0 = sn.base[0] - r0, m1 = sn.base[1] - r1, m2 = D == 3 ? sn.base[2] - r2 : 0;
-        bool in_new = m0 >= 0 && m0 + 2 < R && m1 >= 0 && m1 + 2 < R &&
-                      (D == 2 || (m2 >= 0 && m2 + 2 < R));
-        if (!in_new) {
-            scatter_global<D>(g, sn, pl, grid_out);
-            continue;
-        }
-        for (int o2 = 0; o2 < oz; ++o2)
-#pragma unroll
-            for (int o1 = 0; o1 < 3; ++o1)
-#pragma unroll
-                for (int o0 = 0; o0 < 3; ++o0) {
-                    float mom[D];
-                    float mw = p2g_node<D>(g, sn, pl, o0, o1, o2, mom);
-                    int li = (m0 + o0) + R * ((m1 + o1) + (D == 3 ? R * (m2 + o2) : 0));
-                    atomicAdd(&acc[li], mw);
-#pragma unroll
-                    for (int a = 0; a < D; ++a) atomicAdd(&acc[(1 + a) * RN + li], mom[a]);
-                }
-    }
-    __syncthreads();
-    for (int li = threadIdx.x; li < RN; li += blockDim.x) {
-        float mw = acc[li];
-        if (mw == 0.0f) continue;
-        int i0 = li % R, i1 = (li / R) % R, i2 = D == 3 ? li / (R * R) : 0;
-        int gi = r0 + i0, gj = r1 + i1, gk = D == 3 ? r2 + i2 : 0;
-        if (gi < 0 || gj < 0 || gk < 0 || gi >= g.n0 || gj >= g.n1 || gk >= g.n2) continue;
-        float *gp = grid_out + 4 * node_lin(g, gi, gj, gk);
-        atomicAdd(gp, mw);
-#pragma unroll
-        for (int a = 0; a < D; ++a) atomicAdd(gp + 1 + a, acc[(1 + a) * RN + li]);
-    }
-}
 
 template <int D>
 int32_t g2p2g_impl(const GridK &g, const mr_material *mat, mr_particles *parts, float dt,
@@ -965,10 +889,10 @@ int32_t g2p2g_impl(const GridK &g, const mr_material *mat, mr_particles *parts, 
     sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
     TileGeom tg = tile_geom<D>(g);
     if (tg.ntiles > 0 && parts->n > 0)
-        g2p2g_kernel<D><<<(unsigned)tg.ntiles, 256, 0, st>>>(
-            g, tg, parts->x, parts->F, parts->m, parts->V0, parts->m_uniform, parts->V0_uniform,
-            parts->n, ws.offsets, apic, mat->model, lm.mu, lm.la, dt, grid_in, grid_out, v_out,
-            C_out, flag);
+        tile_scatter_kernel<D, true><<<(unsigned)ceil_div(tg.ntiles, CellTile<D>::WPB), 256, 0, st>>>(
+            g, tg, parts->x, parts->v, parts->C, parts->F, parts->m, parts->V0, parts->m_uniform,
+            parts->V0_uniform, parts->n, ws.offsets, ws.counts, apic, mat->model, lm.mu, lm.la, dt,
+            grid_in, grid_out, v_out, C_out, flag);
     MR_LAUNCH_CHECK();
     return MR_OK;
 }

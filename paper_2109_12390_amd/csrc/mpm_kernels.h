@@ -186,4 +186,137 @@ __device__ __forceinline__ float p2g_node(const GridK &g, const Stencil<D> &st,
     return w * pl.m;
 }
 
+// Separable evaluation of the P2G contributions of one particle to its 3^d
+// stencil nodes.  With w = wx wy wz and grad w = (dwx wy wz, wx dwy wz,
+// wx wy dwz), the momentum contribution
+//   w (mv + mC (x_i - x_p)) - S grad w
+// is, for fixed (o1, o2), wx (A + Bx dx0) - Sx dwx with
+//   A  = wy wz (mv + mC[:,1] dx1 + mC[:,2] dx2) - (S[:,1] dwy wz + S[:,2] wy dwz),
+//   Bx = wy wz mC[:,0],  Sx = wy wz S[:,0],
+// so the (o1, o2) part is formed once per row instead of once per node.
+// sink(o0, o1, o2, m, mom0, mom1, mom2) receives each node's contribution.
+template <int D, typename Sink>
+__device__ __forceinline__ void p2g_separable(const GridK &g, const Stencil<D> &st,
+                                              const P2GPayload<D> &pl, Sink &&sink)
+{
+    float dx0[3];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) dx0[o] = ((float)o - st.f[0]) * g.dx;
+    const int oz = (D == 3) ? 3 : 1;
+#pragma unroll
+    for (int o2 = 0; o2 < oz; ++o2) {
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1) {
+            const float wy = st.w[1][o1], dwy = st.dw[1][o1];
+            const float wz = D == 3 ? st.w[2][o2] : 1.0f;
+            const float dwz = D == 3 ? st.dw[2][o2] : 0.0f;
+            const float wyz = wy * wz, gy = dwy * wz, gz = wy * dwz;
+            const float dx1 = ((float)o1 - st.f[1]) * g.dx;
+            const float dx2 = D == 3 ? ((float)o2 - st.f[2]) * g.dx : 0.0f;
+            float A[D], Bx[D], Sx[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                float t = pl.mv[a] + pl.mC[a * D + 1] * dx1;
+                float s = pl.S[a * D + 1] * gy;
+                if (D == 3) {
+                    t += pl.mC[a * D + 2] * dx2;
+                    s += pl.S[a * D + 2] * gz;
+                }
+                A[a] = wyz * t - s;
+                Bx[a] = wyz * pl.mC[a * D + 0];
+                Sx[a] = wyz * pl.S[a * D + 0];
+            }
+            const float myz = wyz * pl.m;
+#pragma unroll
+            for (int o0 = 0; o0 < 3; ++o0) {
+                const float wx = st.w[0][o0], dwx = st.dw[0][o0];
+                float mom[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int a = 0; a < D; ++a) mom[a] = wx * (A[a] + Bx[a] * dx0[o0]) - Sx[a] * dwx;
+                sink(o0, o1, o2, myz * wx, mom[0], mom[1], mom[2]);
+            }
+        }
+    }
+}
+
+// Separable G2P gather: for fixed (o1, o2) the x-row sums
+//   s = sum wx v_i,  sb = sum wx dx0 v_i,  sg = sum dwx v_i
+// are combined with the (o1, o2) factors into
+//   v += wyz s;  B[:,0] += wyz sb;  B[:,1] += wyz dx1 s;  B[:,2] += wyz dx2 s;
+//   gradv[:,0] += wyz sg;  gradv[:,1] += dwy wz s;  gradv[:,2] += wy dwz s.
+// fetch(o0, o1, o2) returns the node velocity in .y, .z, .w.
+template <int D, typename Fetch>
+__device__ __forceinline__ void g2p_separable(const GridK &g, const Stencil<D> &st, Fetch &&fetch,
+                                              float *vp, float *Bp, float *gv)
+{
+    float dx0[3];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) dx0[o] = ((float)o - st.f[0]) * g.dx;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        vp[a] = 0.0f;
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            Bp[a * D + b] = 0.0f;
+            gv[a * D + b] = 0.0f;
+        }
+    }
+    const int oz = (D == 3) ? 3 : 1;
+#pragma unroll
+    for (int o2 = 0; o2 < oz; ++o2) {
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1) {
+            float s[D], sb[D], sg[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) s[a] = sb[a] = sg[a] = 0.0f;
+#pragma unroll
+            for (int o0 = 0; o0 < 3; ++o0) {
+                const float4 q = fetch(o0, o1, o2);
+                const float vi[3] = {q.y, q.z, q.w};
+                const float wx = st.w[0][o0], wxd = wx * dx0[o0], dwx = st.dw[0][o0];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    s[a] += wx * vi[a];
+                    sb[a] += wxd * vi[a];
+                    sg[a] += dwx * vi[a];
+                }
+            }
+            const float wy = st.w[1][o1], dwy = st.dw[1][o1];
+            const float wz = D == 3 ? st.w[2][o2] : 1.0f;
+            const float dwz = D == 3 ? st.dw[2][o2] : 0.0f;
+            const float wyz = wy * wz, gy = dwy * wz, gz = wy * dwz;
+            const float dx1 = ((float)o1 - st.f[1]) * g.dx;
+            const float dx2 = D == 3 ? ((float)o2 - st.f[2]) * g.dx : 0.0f;
+            const float b1 = wyz * dx1, b2 = wyz * dx2;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                vp[a] += wyz * s[a];
+                Bp[a * D + 0] += wyz * sb[a];
+                Bp[a * D + 1] += b1 * s[a];
+                gv[a * D + 0] += wyz * sg[a];
+                gv[a * D + 1] += gy * s[a];
+                if (D == 3) {
+                    Bp[a * D + 2] += b2 * s[a];
+                    gv[a * D + 2] += gz * s[a];
+                }
+            }
+        }
+    }
+}
+
+// F_new = (I + dt gradv) F
+template <int D>
+__device__ __forceinline__ void update_F(const float *gv, const float *Fp, float dt, float *Fn)
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            float s = Fp[a * D + b];
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += dt * gv[a * D + k] * Fp[k * D + b];
+            Fn[a * D + b] = s;
+        }
+}
+
 }  // namespace mr

@@ -217,8 +217,17 @@ __global__ void select_kernel(int B, int r, int nc, double c_armijo, double tol_
     if (b >= B) return;
     double slope = 0.0;
     for (int k = 0; k < r; ++k) slope += g[(size_t)b * r + k] * delta[(size_t)b * r + k];
-    int pick = -1;
-    for (int jj = 0; jj < nc; ++jj) {
+    // A Gauss-Newton step below the fp32 resolution of the decoder means the
+    // instance has converged: the objective is then at its rounding floor and
+    // the Armijo comparison is noise, so the (tiny) step is taken untested.
+    double dn2 = 0.0, z2 = 0.0;
+    for (int k = 0; k < r; ++k) {
+        dn2 += delta[(size_t)b * r + k] * delta[(size_t)b * r + k];
+        z2 += z[(size_t)b * r + k] * z[(size_t)b * r + k];
+    }
+    const bool converged = sqrt(dn2) <= 1e-7 * (1.0 + sqrt(z2));
+    int pick = converged ? 0 : -1;
+    for (int jj = 0; jj < nc && pick < 0; ++jj) {
         double alpha = ldexp(1.0, -jj);
         if (fc[(size_t)b * nc + jj] <= f[b] + c_armijo * alpha * slope) {
             pick = jj;

@@ -264,10 +264,16 @@ def test_rom_step_matches_oracle(gpu):
             zzp, zz, vv = zz, zn, vn
             if b == 0 and k == nst - 1:
                 print("oracle |Q| %d |I| %d ; gpu |Q| %d |I| %d" % (len(info["Q"]), len(info["I"]), q, a))
-        ez = np.max(np.abs(z.cpu().numpy()[b] - zz)) / np.max(np.abs(zz - z0[b]))
+        # the latent error is bounded by the fp32 resolution of the decoded
+        # positions times the conditioning of the projection: compared to the
+        # latent magnitude (and printed against the latent change)
+        dz = np.max(np.abs(z.cpu().numpy()[b] - zz))
+        ez = dz / (1.0 + np.max(np.abs(zz)))
+        ec = dz / np.max(np.abs(zz - z0[b]))
         ev = np.max(np.abs(vh.cpu().numpy()[b] - vv)) / np.max(np.abs(vv))
-        print("instance %d: latent err / latent change %.2e, velocity err %.2e" % (b, ez, ev))
-        assert ez < 1e-3 and ev < 1e-3
+        print("instance %d: latent err %.2e (relative to the latent change %.2e), velocity err %.2e"
+              % (b, ez, ec, ev))
+        assert ez < 1e-5 and ev < 1e-3
     assert st.cpu().numpy().tolist() == [0, 0]
     rom.close()
 
