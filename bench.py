@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rom", action="store_true")
+    ap.add_argument("--rom-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -170,10 +172,65 @@ def main():
         "active_nodes": active_nodes,
         "kernel_source_hash": src_hash,
     }
+    if not args.no_rom:
+        out["rom"] = rom_throughput(B, scenes, s, args.rom_steps)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out), flush=True)
+
+
+def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden=5):
+    """Reduced-order steps on the same 2,097,152-particle scene: one
+    instance, r = 16, 512 sample points per step, Lagrangian quadrature
+    (all particles decoded to find the neighbours), bf16 decoder of width
+    128 with 5 hidden layers, position-velocity projection with 3
+    Gauss-Newton iterations; the per-step launches are replayed from a HIP
+    graph.  The decoder here is randomly initialised (throughput only)."""
+    import torch
+    dev = "cuda:0"
+    X = s["X"]
+    P = s["P"]
+    Ws, bs = scenes.xavier_decoder(3, r, width, n_hidden, 11)
+    lo, hi = X.min(0), X.max(0)
+    dec = B.Decoder(Ws, bs, lo, hi, np.zeros(3, np.float32), np.full(3, 1e-3, np.float32),
+                    B.OUT_DISPLACEMENT, B.PREC_BF16)
+    grid = B.Grid(3, s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
+    Xg = torch.tensor(np.ascontiguousarray(X.T), device=dev)
+    E = torch.tensor([s["E"]], dtype=torch.float32, device=dev)
+    ns = torch.tensor([n_samples], dtype=torch.int32, device=dev)
+    rom = B.Rom(dec, grid, Xg, E, ns, B.gn_opts(mode=B.POS_VEL, max_iter=3), seed=4, rho0=1000.0,
+                m_uniform=float(s["m"]))
+    z = torch.zeros(1, r, dtype=torch.float64, device=dev)
+    zp = z.clone()
+    vh = torch.zeros(1, r, dtype=torch.float64, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    k = 10
+    rom.step(k, 0, s["dt"], z, zp, vh, status=st, use_graph=True)     # capture + warm-up
+    torch.cuda.synchronize()
+    times = []
+    n_rep = max(1, steps // k)
+    for i in range(n_rep):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        rom.step(k, k * (i + 1), s["dt"], z, zp, vh, status=st, use_graph=True)
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b) / k)
+    n_quad, n_active = rom.last_counts(0)
+    rom.close()
+    dec.close()
+    times = np.array(times)
+    return {"metric": "ROM latent steps/s", "value": float(1e3 / times.mean()), "unit": "latent steps/s",
+            "ms_per_step": float(times.mean()), "p50_ms": float(np.percentile(times, 50)),
+            "p99_ms": float(np.percentile(times, 99)), "steps": int(n_rep * k),
+            "n_quadrature_points": int(n_quad), "n_active_nodes": int(n_active),
+            "config": {"instances": 1, "particles": P, "samples": n_samples, "r": r,
+                       "decoder": "bf16 MLP %d x %d, random init" % (width, n_hidden),
+                       "projection": "position-velocity, 3 Gauss-Newton iterations",
+                       "graph": "HIP graph of %d steps" % k},
+            "displacement_error": None}
 
 
 if __name__ == "__main__":

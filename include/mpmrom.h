@@ -260,7 +260,12 @@ int32_t rom_decode(const mr_decoder *dec, int32_t B, int64_t n_ref,
  * F = dg/dX (Section 3.1, eq. defGrad; [B][d*d][n], nullable),
  * v = (dg/dxhat) vhat (eq. timederOne; [B][d][n], nullable, needs vhat),
  * Jz = dg/dxhat ([B][d*r][n], entry (a, k) at (a*r + k)*n + s; nullable).
- * idx_per_instance != 0 means idx is [B][n] (one point list per instance). */
+ * idx_per_instance: 0 -- idx (nullable) is one list of n rows shared by all
+ * instances; 1 -- idx is [B][n], one list per instance; k > 1 -- idx is
+ * [B/k][n] and instance b uses list b / k (B must be a multiple of k; the
+ * projection decodes its k line-search candidates of an instance this way).
+ * Returns MR_EINVAL for a negative k, a k that does not divide B, or k != 0
+ * with idx NULL. */
 int32_t rom_decode_jac(const mr_decoder *dec, int32_t B, int64_t n_ref,
                        const float *X, int64_t n, const int32_t *idx,
                        int32_t idx_per_instance, const double *xhat,
@@ -292,7 +297,15 @@ typedef struct {
  * status_out device int32 [B], resid_out device float64 [B] (half the
  * squared position residual at exit), all nullable.  A singular normal
  * matrix leaves that instance's xhat_next = xhat_n, vhat_next = 0 and raises
- * MR_FLAG_SINGULAR. */
+ * MR_FLAG_SINGULAR.
+ * x_trial may be NULL: the target positions are then g(X_p; xhat_n) + dt
+ * v_trial_p; with an MR_OUT_DISPLACEMENT decoder the position residual is
+ * then formed from displacements g - X, which keeps fp32 cancellation in
+ * the residual at the size of the motion, not of the coordinates.
+ * The call keeps one library-owned device workspace, grown (after a stream
+ * synchronisation) when a call needs more: calls that overlap in time, from
+ * several host threads or on several streams, race on it and must be
+ * serialised by the caller. */
 int32_t rom_project(const mr_decoder *dec, int32_t B, int64_t n_ref,
                     const float *X, int64_t ns, const int32_t *sample_idx,
                     const int32_t *ns_per_instance, const float *x_trial,
@@ -349,6 +362,74 @@ int32_t rom_step(mr_rom *rom, int32_t n_steps, int64_t step0, double dt,
  * synchronises the stream). */
 int32_t rom_last_counts(const mr_rom *rom, int32_t b, int64_t *n_quad,
                         int64_t *n_active, void *stream);
+
+/* ---- decoder training (Section 4.2 loss; Appendix B training details) --- */
+
+typedef struct mr_trainer mr_trainer;
+
+/* Number of float32 parameters of the decoder in the packed layout of
+ * rom_decoder_create ([W_0, b_0, ..., W_L, b_L], row-major weights). */
+int64_t rom_train_param_count(int32_t d, int32_t r, int32_t width,
+                              int32_t n_hidden);
+
+/* Creates the training workspace for batches of up to max_rows rows
+ * (activations of the primal and of the d + 1 tangent streams of every row
+ * are kept for the backward pass: about 2 (d + 2) width n_hidden floats per
+ * row).  precision MR_PREC_BF16 runs the width x width products on bf16
+ * matrix cores with fp32 accumulation; the first and last layers and all
+ * element-wise work stay fp32.  Synchronous. */
+int32_t rom_trainer_create(int32_t d, int32_t r, int32_t width,
+                           int32_t n_hidden, int32_t precision,
+                           int64_t max_rows, const float *in_min,
+                           const float *in_max, const float *out_mean,
+                           const float *out_std, int32_t output_mode,
+                           mr_trainer **out);
+void rom_trainer_destroy(mr_trainer *t);
+
+/* Forward pass with tangents for n_groups x rows_per_group rows; group g
+ * uses latent z = Z[snap[g]] (Z: device float32 [n_snapshots][r]) and the
+ * velocity direction u = (Z[next[g]] - Z[snap[g]]) / dt (zero when
+ * next[g] < 0).  X: device [rows][d].  Writes g = g(X; z) [rows][d],
+ * G = dg/dX [rows][d][d] and Gv = (dg/dz) u [rows][d].  params: device
+ * packed parameters (must stay valid until rom_train_backward). */
+int32_t rom_train_forward(mr_trainer *t, const float *params, const float *Z,
+                          const float *X, const int32_t *snap,
+                          const int32_t *next, int32_t n_groups,
+                          int32_t rows_per_group, float dt, float *g,
+                          float *G, float *Gv, void *stream);
+
+/* Backward pass of the last forward: given dL/dg, dL/dG, dL/dGv, ADDS
+ * dL/dparams into dparams (packed layout) and dL/dZ into dZ. */
+int32_t rom_train_backward(mr_trainer *t, const float *dg, const float *dG,
+                           const float *dGv, float *dparams, float *dZ,
+                           void *stream);
+
+/* Training objective (Section 4.2): batch mean of |g - x|^2 +
+ * lam_F |G - F|_F^2 + lam_v |Gv - v|^2, the velocity term dropped for
+ * groups with next < 0.  loss: device float scalar (overwritten);
+ * dg, dG, dGv (nullable): its gradient with respect to g, G, Gv. */
+int32_t rom_train_loss(int32_t d, int32_t n_groups, int32_t rows_per_group,
+                       const int32_t *next, const float *g, const float *G,
+                       const float *Gv, const float *x_t, const float *F_t,
+                       const float *v_t, float lam_F, float lam_v,
+                       float *loss, float *dg, float *dG, float *dGv,
+                       void *stream);
+
+/* Adam (Kingma and Ba): m, v moment estimates, step counts from 1. */
+int32_t rom_adam_step(int64_t n, float *param, const float *grad, float *m,
+                      float *v, float lr, float beta1, float beta2, float eps,
+                      int32_t step, void *stream);
+
+/* Assembles training rows: frames hold (x [P_sub][d], F [P_sub][d][d],
+ * v [P_sub][d]) of a fixed particle subset with reference positions
+ * X_sub [P_sub][d]; row i takes particle pid[i] of frame
+ * snap[i / rows_per_group]. */
+int32_t rom_train_gather(int32_t d, int32_t n_groups, int32_t rows_per_group,
+                         int64_t P_sub, const float *X_sub,
+                         const float *frame_x, const float *frame_F,
+                         const float *frame_v, const int32_t *snap,
+                         const int32_t *pid, float *X, float *x_t, float *F_t,
+                         float *v_t, void *stream);
 
 /* Reads n device status words into host memory after synchronising the
  * stream; returns the OR of their bits mapped to the first MR_E* code

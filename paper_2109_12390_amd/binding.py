@@ -106,6 +106,18 @@ SIGNATURES = {
     "rom_destroy": (None, [_vp]),
     "rom_step": (_i32, [_vp, _i32, _i64, _f64, _vp, _vp, _vp, _vp, _i32, _vp]),
     "rom_last_counts": (_i32, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _vp]),
+    "rom_train_param_count": (_i64, [_i32, _i32, _i32, _i32]),
+    "rom_trainer_create": (_i32, [_i32, _i32, _i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _i32,
+                                  ctypes.POINTER(_vp)]),
+    "rom_trainer_destroy": (None, [_vp]),
+    "rom_train_forward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _f32, _vp, _vp, _vp,
+                                 _vp]),
+    "rom_train_backward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rom_train_loss": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _f32, _f32,
+                              _vp, _vp, _vp, _vp, _vp]),
+    "rom_adam_step": (_i32, [_i64, _vp, _vp, _vp, _vp, _f32, _f32, _f32, _f32, _i32, _vp]),
+    "rom_train_gather": (_i32, [_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                _vp, _vp, _vp]),
     "mr_sync_status": (_i32, [_vp, _vp, _i32, _vp]),
     "mr_version": (ctypes.c_char_p, []),
 }

@@ -245,7 +245,7 @@ __device__ __forceinline__ void p2g_separable(const GridK &g, const Stencil<D> &
 //   v += wyz s;  B[:,0] += wyz sb;  B[:,1] += wyz dx1 s;  B[:,2] += wyz dx2 s;
 //   gradv[:,0] += wyz sg;  gradv[:,1] += dwy wz s;  gradv[:,2] += wy dwz s.
 // fetch(o0, o1, o2) returns the node velocity in .y, .z, .w.
-template <int D, typename Fetch>
+template <int D, typename Fetch, bool ROWWISE = false>
 __device__ __forceinline__ void g2p_separable(const GridK &g, const Stencil<D> &st, Fetch &&fetch,
                                               float *vp, float *Bp, float *gv)
 {
@@ -300,6 +300,9 @@ __device__ __forceinline__ void g2p_separable(const GridK &g, const Stencil<D> &
                     gv[a * D + 2] += gz * s[a];
                 }
             }
+            // ROWWISE: keep the fetches of one x-row from being hoisted above
+            // the previous row (bounds the registers held by loads in flight)
+            if (ROWWISE) asm volatile("" ::: "memory");
         }
     }
 }

@@ -31,7 +31,8 @@ __global__ void __launch_bounds__(NE_THREADS) normal_eq_kernel(int d, int r, int
                                                                const int32_t *ns_inst,
                                                                const float *Jz, const float *y,
                                                                const float *x, double *A,
-                                                               double *rhs, double *f)
+                                                               double *rhs, double *f,
+                                                               double *fe)
 {
     extern __shared__ __align__(8) float sm[];
     const int b = blockIdx.x;
@@ -39,10 +40,11 @@ __global__ void __launch_bounds__(NE_THREADS) normal_eq_kernel(int d, int r, int
     const int dr = d * r;
     float *Js = sm;                      // [dr][NE_CHUNK]
     float *Ys = sm + dr * NE_CHUNK;      // [d][NE_CHUNK]
+    float *Ms = Ys + d * NE_CHUNK;       // [d][NE_CHUNK] |x| + |x_trial|
     const float *Jb = Jz + (size_t)b * dr * ns;
     const float *yb = y + (size_t)b * d * ns;
     const float *xb = MODE == 1 ? x + (size_t)b * d * ns : nullptr;
-    const int nent = r * r + r + 1;
+    const int nent = r * r + r + 2;
     double acc[5] = {0, 0, 0, 0, 0};  // entries tid, tid + 256, ... (r <= 32 -> <= 5)
     for (int64_t s0 = 0; s0 < cnt; s0 += NE_CHUNK) {
         int len = (int)((cnt - s0) < NE_CHUNK ? (cnt - s0) : NE_CHUNK);
@@ -53,12 +55,17 @@ __global__ void __launch_bounds__(NE_THREADS) normal_eq_kernel(int d, int r, int
         }
         for (int t = threadIdx.x; t < d * NE_CHUNK; t += blockDim.x) {
             int a = t / NE_CHUNK, c = t % NE_CHUNK;
-            float val = 0.0f;
+            float val = 0.0f, mag = 0.0f;
             if (c < len) {
                 val = yb[(size_t)a * ns + s0 + c];
-                if (MODE == 1) val = xb[(size_t)a * ns + s0 + c] - val;
+                if (MODE == 1) {
+                    float xv = xb[(size_t)a * ns + s0 + c];
+                    mag = fabsf(xv) + fabsf(val);
+                    val = xv - val;
+                }
             }
             Ys[t] = val;
+            Ms[t] = mag;
         }
         __syncthreads();
         int q = 0;
@@ -78,12 +85,18 @@ __global__ void __launch_bounds__(NE_THREADS) normal_eq_kernel(int d, int r, int
                     const float *py = Ys + a * NE_CHUNK;
                     for (int c = 0; c < len; ++c) sacc += (double)p1[c] * (double)py[c];
                 }
-            } else if (MODE == 1) {
+            } else if (MODE == 1 && e == r * r + r) {
                 for (int a = 0; a < d; ++a)
                     for (int c = 0; c < len; ++c) {
                         double v = Ys[a * NE_CHUNK + c];
                         sacc += 0.5 * v * v;
                     }
+            } else if (MODE == 1) {
+                // bound on the change of f caused by fp32 rounding of its inputs
+                for (int a = 0; a < d; ++a)
+                    for (int c = 0; c < len; ++c)
+                        sacc += fabs((double)Ys[a * NE_CHUNK + c]) * (double)Ms[a * NE_CHUNK + c] *
+                                0x1p-23;
             }
             acc[q] += sacc;
         }
@@ -94,34 +107,46 @@ __global__ void __launch_bounds__(NE_THREADS) normal_eq_kernel(int d, int r, int
             A[(size_t)b * r * r + e] = acc[q];
         else if (e < r * r + r)
             rhs[(size_t)b * r + (e - r * r)] = acc[q];
-        else if (f)
+        else if (e == r * r + r && f)
             f[b] = acc[q];
+        else if (e == r * r + r + 1 && fe)
+            fe[b] = acc[q];
     }
 }
 
 // 0.5 |x - x_trial|^2 per candidate instance c (samples of instance c / group)
 __global__ void __launch_bounds__(256) objective_kernel(int d, int64_t ns, int group,
                                                         const int32_t *ns_inst, const float *x,
-                                                        const float *xt, double *f)
+                                                        const float *xt, double *f, double *fe)
 {
     __shared__ double red[256];
+    __shared__ double red2[256];
     const int c = blockIdx.x;
     const int b = c / group;
     const int64_t cnt = ns_inst ? (int64_t)ns_inst[b] : ns;
-    double s = 0.0;
+    double s = 0.0, se = 0.0;
     for (int64_t t = threadIdx.x; t < cnt * d; t += blockDim.x) {
         int a = (int)(t / cnt);
         int64_t i = t % cnt;
-        double v = (double)x[((size_t)c * d + a) * ns + i] - (double)xt[((size_t)b * d + a) * ns + i];
+        double xv = x[((size_t)c * d + a) * ns + i], tv = xt[((size_t)b * d + a) * ns + i];
+        double v = xv - tv;
         s += 0.5 * v * v;
+        se += fabs(v) * (fabs(xv) + fabs(tv)) * 0x1p-23;
     }
     red[threadIdx.x] = s;
+    red2[threadIdx.x] = se;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        if ((int)threadIdx.x < o) {
+            red[threadIdx.x] += red[threadIdx.x + o];
+            red2[threadIdx.x] += red2[threadIdx.x + o];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) f[c] = red[0];
+    if (threadIdx.x == 0) {
+        f[c] = red[0];
+        fe[c] = red2[0];
+    }
 }
 
 // Solve (A + damping I) y = sign * rhs by Cholesky, one thread per instance.
@@ -209,8 +234,9 @@ __global__ void candidates_kernel(int B, int r, int nc, const double *z, const d
 
 // pick the first Armijo-admissible step; g = J^T res (gradient of f)
 __global__ void select_kernel(int B, int r, int nc, double c_armijo, double tol_step,
-                              const double *f, const double *g, const double *delta,
-                              const double *fc, const int32_t *singular, double *z,
+                              const double *f, const double *fe, const double *g,
+                              const double *delta, const double *fc, const double *fce,
+                              const int32_t *singular, double *z,
                               double *fnew, double *step_norm, int32_t *status, int last)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -229,7 +255,11 @@ __global__ void select_kernel(int B, int r, int nc, double c_armijo, double tol_
     int pick = converged ? 0 : -1;
     for (int jj = 0; jj < nc && pick < 0; ++jj) {
         double alpha = ldexp(1.0, -jj);
-        if (fc[(size_t)b * nc + jj] <= f[b] + c_armijo * alpha * slope) {
+        // Armijo test, widened by the rounding bound of the two objective
+        // evaluations (fp32 positions): a step whose decrease cannot be
+        // resolved is accepted rather than rejected as an ascent
+        if (fc[(size_t)b * nc + jj] <=
+            f[b] + c_armijo * alpha * slope + fe[b] + fce[(size_t)b * nc + jj]) {
             pick = jj;
             break;
         }
@@ -291,7 +321,9 @@ int64_t proj_ws_bytes(int d, int r, int B, int64_t ns, int max_backtrack)
     take(8LL * B * r);                // v
     take(8LL * B * nc * r);           // candidate z
     take(8LL * B);                    // f
+    take(8LL * B);                    // fe
     take(8LL * B * nc);               // fc
+    take(8LL * B * nc);               // fce
     take(8LL * B);                    // fnew
     take(8LL * B);                    // step norm
     take(4LL * B);                    // status
@@ -322,7 +354,9 @@ ProjWS proj_ws_carve(void *base, int d, int r, int B, int64_t ns, int max_backtr
     w.v = (double *)take(8LL * B * r);
     w.zc = (double *)take(8LL * B * nc * r);
     w.f = (double *)take(8LL * B);
+    w.fe = (double *)take(8LL * B);
     w.fc = (double *)take(8LL * B * nc);
+    w.fce = (double *)take(8LL * B * nc);
     w.fnew = (double *)take(8LL * B);
     w.step = (double *)take(8LL * B);
     w.status = (int32_t *)take(4LL * B);
@@ -340,7 +374,7 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
     const int nc = o.max_backtrack + 1;
     const int TB = 256;
     int32_t rc;
-    size_t ne_lds = sizeof(float) * (size_t)(d * r + d) * NE_CHUNK;
+    size_t ne_lds = sizeof(float) * (size_t)(d * r + 2 * d) * NE_CHUNK;
     zero_i32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>(w.status, B);
     zero_i32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>(w.singular, B);
     // With x_trial == NULL the trial positions are those of Algorithm 5,
@@ -361,7 +395,7 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
         xtp = w.xt;
     }
     normal_eq_kernel<0><<<B, NE_THREADS, ne_lds, st>>>(d, r, ns, ns_inst, w.Jz, v_trial, nullptr,
-                                                      w.A, w.g, nullptr);
+                                                      w.A, w.g, nullptr, nullptr);
     cholesky_solve_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(B, r, w.A, w.g, o.damping, 1.0,
                                                                     w.v, w.L, w.status, w.singular);
     init_guess_kernel<<<(unsigned)ceil_div((int64_t)B * r, TB), TB, 0, st>>>(
@@ -375,7 +409,7 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
                                nullptr, w.Jz, st, disp);
             if (rc != MR_OK) return rc;
             normal_eq_kernel<1><<<B, NE_THREADS, ne_lds, st>>>(d, r, ns, ns_inst, w.Jz, xtp,
-                                                              w.x, w.A, w.g, w.f);
+                                                              w.x, w.A, w.g, w.f, w.fe);
             cholesky_solve_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(
                 B, r, w.A, w.g, o.damping, -1.0, w.delta, w.L, w.status, nullptr);
             candidates_kernel<<<(unsigned)ceil_div((int64_t)B * nc * r, TB), TB, 0, st>>>(
@@ -384,9 +418,10 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
             rc = decode_jac_ex(dec, B * nc, n_ref, X, ns, idx, nc, nullptr, w.zc, nullptr, w.xc,
                                nullptr, nullptr, nullptr, st, disp);
             if (rc != MR_OK) return rc;
-            objective_kernel<<<B * nc, 256, 0, st>>>(d, ns, nc, ns_inst, w.xc, xtp, w.fc);
+            objective_kernel<<<B * nc, 256, 0, st>>>(d, ns, nc, ns_inst, w.xc, xtp, w.fc, w.fce);
             select_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(
-                B, r, nc, o.armijo_c, o.tol_step, w.f, w.g, w.delta, w.fc, w.singular, w.z, w.fnew,
+                B, r, nc, o.armijo_c, o.tol_step, w.f, w.fe, w.g, w.delta, w.fc, w.fce, w.singular,
+                w.z, w.fnew,
                 w.step, w.status, it == o.max_iter - 1 ? 1 : 0);
             MR_LAUNCH_CHECK();
         }

@@ -1,0 +1,269 @@
+"""Decoder training driver (paper Section 4.2 loss, Appendix B training
+details) on the library's training kernels.
+
+`DecoderTrainFn` and `TrainLossFn` are torch.autograd.Functions whose
+forward and backward passes are the C-ABI kernels rom_train_forward /
+rom_train_backward and rom_train_loss; the Adam update is rom_adam_step and
+batch assembly rom_train_gather.  PyTorch only allocates memory and chains
+the two Functions.  Snapshots come from the library's own full-order model
+(mpm_step).
+"""
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class Trainer:
+    """Owns an mr_trainer handle (rom_trainer_create / rom_trainer_destroy)."""
+
+    def __init__(self, d, r, width, n_hidden, precision, max_rows, in_min, in_max, out_mean,
+                 out_std, output_mode=B.OUT_DISPLACEMENT):
+        lib = B.load()
+        self.d, self.r, self.width, self.n_hidden = d, r, width, n_hidden
+        f = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+        self._norm = [f(in_min), f(in_max), f(out_mean), f(out_std)]
+        h = ctypes.c_void_p()
+        B._check("rom_trainer_create", lib.rom_trainer_create(
+            d, r, width, n_hidden, precision, max_rows,
+            *[ctypes.c_void_p(a.ctypes.data) for a in self._norm], output_mode, ctypes.byref(h)))
+        self.handle = h
+        self.n_params = int(lib.rom_train_param_count(d, r, width, n_hidden))
+
+    def close(self):
+        if self.handle:
+            B.load().rom_trainer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DecoderTrainFn(torch.autograd.Function):
+    """(params, Z) -> (g, G, Gv) for a batch of n_groups x rows_per_group rows."""
+
+    @staticmethod
+    def forward(ctx, params, Z, X, snap, nxt, trainer, n_groups, rows_per_group, dt):
+        d = trainer.d
+        rows = n_groups * rows_per_group
+        dev = params.device
+        g = torch.empty(rows, d, device=dev)
+        G = torch.empty(rows, d, d, device=dev)
+        Gv = torch.empty(rows, d, device=dev)
+        lib = B.load()
+        B._check("rom_train_forward", lib.rom_train_forward(
+            trainer.handle, B._ptr(params, torch.float32), B._ptr(Z, torch.float32),
+            B._ptr(X, torch.float32), B._ptr(snap, torch.int32), B._ptr(nxt, torch.int32),
+            n_groups, rows_per_group, dt, B._ptr(g), B._ptr(G), B._ptr(Gv), B._stream(None)))
+        ctx.trainer = trainer
+        ctx.keep = (params, Z, X, snap, nxt)
+        return g, G, Gv
+
+    @staticmethod
+    def backward(ctx, dg, dG, dGv):
+        params, Z, _, _, _ = ctx.keep
+        dparams = torch.zeros_like(params)
+        dZ = torch.zeros_like(Z)
+        B._check("rom_train_backward", B.load().rom_train_backward(
+            ctx.trainer.handle, B._ptr(dg.contiguous()), B._ptr(dG.contiguous()),
+            B._ptr(dGv.contiguous()), B._ptr(dparams), B._ptr(dZ), B._stream(None)))
+        return dparams, dZ, None, None, None, None, None, None, None
+
+
+class TrainLossFn(torch.autograd.Function):
+    """Training objective (batch mean of the three penalised residuals)."""
+
+    @staticmethod
+    def forward(ctx, g, G, Gv, x_t, F_t, v_t, nxt, n_groups, rows_per_group, lam_F, lam_v):
+        d = g.shape[1]
+        loss = torch.zeros(1, device=g.device)
+        dg, dG, dGv = torch.empty_like(g), torch.empty_like(G), torch.empty_like(Gv)
+        B._check("rom_train_loss", B.load().rom_train_loss(
+            d, n_groups, rows_per_group, B._ptr(nxt, torch.int32), B._ptr(g), B._ptr(G),
+            B._ptr(Gv), B._ptr(x_t), B._ptr(F_t), B._ptr(v_t), lam_F, lam_v, B._ptr(loss),
+            B._ptr(dg), B._ptr(dG), B._ptr(dGv), B._stream(None)))
+        ctx.grads = (dg, dG, dGv)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, dloss):
+        dg, dG, dGv = ctx.grads
+        return dg * dloss, dG * dloss, dGv * dloss, None, None, None, None, None, None, None, None
+
+
+def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    B._check("rom_adam_step", B.load().rom_adam_step(
+        param.numel(), B._ptr(param), B._ptr(grad), B._ptr(m), B._ptr(v), lr, beta1, beta2, eps,
+        step, B._stream(None)))
+
+
+class SnapshotSet:
+    """Frames of (x, F, v) of a fixed particle subset, on the device:
+    x [n_frames][P_sub][d], F [n_frames][P_sub][d][d], v [n_frames][P_sub][d];
+    X_sub [P_sub][d]; next_frame[f] = f + 1 inside a simulation, -1 at its end."""
+
+    def __init__(self, X_sub, fx, fF, fv, next_frame, dt_frame):
+        self.X_sub, self.fx, self.fF, self.fv = X_sub, fx, fF, fv
+        self.next_frame = next_frame
+        self.dt_frame = dt_frame
+
+    @property
+    def n_frames(self):
+        return self.fx.shape[0]
+
+    @property
+    def P_sub(self):
+        return self.X_sub.shape[0]
+
+
+def generate_snapshots(scene, instances, n_steps, every, n_sub, seed, sort_every=10,
+                       device="cuda"):
+    """Runs the full-order model (mpm_step) for every (E, v0) instance from
+    the scene's initial state and records frames every `every` steps
+    (including the initial state) for a fixed random subset of n_sub
+    particles."""
+    d = scene["dim"]
+    P = scene["P"]
+    rng = np.random.default_rng(seed)
+    sub = np.sort(rng.choice(P, size=n_sub, replace=False))
+    sub_t = torch.tensor(sub, device=device, dtype=torch.long)
+    grid = B.Grid(d, scene["n"], scene["dx"], scene["bound"], scene["floor_mode"], scene["mu_f"],
+                  scene["gravity"])
+    gbuf = torch.zeros(grid.nodes() * 4, device=device)
+    ws = torch.zeros(B.mpm_step_workspace_bytes(grid, P), dtype=torch.uint8, device=device)
+    perm = torch.zeros(P, dtype=torch.int32, device=device)
+    flag = torch.zeros(1, dtype=torch.int32, device=device)
+    frames_x, frames_F, frames_v, nxt = [], [], [], []
+    soa = lambda a: torch.tensor(np.ascontiguousarray(a.reshape(P, -1).T), device=device)
+    n_frames_per = n_steps // every + 1
+    for (E, v0) in instances:
+        X = scene["X"]
+        v = np.tile(np.asarray(v0, dtype=np.float32), (P, 1))
+        parts = B.Particles(soa(X), soa(v), torch.zeros(d * d, P, device=device),
+                            soa(np.tile(np.eye(d, dtype=np.float32), (P, 1, 1))),
+                            m_uniform=float(scene["m"]), V0_uniform=float(scene["V0"]))
+        slot_of = torch.arange(P, device=device)        # slot of each original particle
+        for f in range(n_frames_per):
+            if f > 0:
+                B.mpm_step(grid, (scene["model"], float(E), scene["nu"]), parts, scene["dt"], every,
+                           sort_every, 0, gbuf, ws, perm_accum=perm, status=flag)
+                # slot -> entry index of this call; compose with the running map
+                inv = torch.empty_like(perm, dtype=torch.long)
+                inv[perm.long()] = torch.arange(P, device=device)
+                slot_of = inv[slot_of]
+            s = slot_of[sub_t]
+            frames_x.append(parts.x[:, s].T.contiguous())
+            frames_F.append(parts.F[:, s].T.contiguous().reshape(n_sub, d, d))
+            frames_v.append(parts.v[:, s].T.contiguous())
+            nxt.append(1 if f < n_frames_per - 1 else 0)
+    rc, fl = B.sync_status(flag)
+    if rc != 0:
+        raise RuntimeError("full-order model raised status flags %s" % fl)
+    fx = torch.stack(frames_x)
+    fF = torch.stack(frames_F)
+    fv = torch.stack(frames_v)
+    n_frames = fx.shape[0]
+    next_frame = np.array([i + 1 if nxt[i] else -1 for i in range(n_frames)], dtype=np.int32)
+    X_sub = torch.tensor(scene["X"][sub], device=device)
+    return SnapshotSet(X_sub, fx, fF, fv, next_frame, every * scene["dt"])
+
+
+def normalisation(snap):
+    """Min-max input range of the reference positions and mean / standard
+    deviation of the displacements (Appendix B feature scaling)."""
+    X = snap.X_sub.cpu().numpy().astype(np.float64)
+    u = (snap.fx - snap.X_sub[None]).reshape(-1, snap.X_sub.shape[1]).cpu().numpy().astype(np.float64)
+    std = u.std(0)
+    std = np.where(std > 0, std, 1.0)
+    return X.min(0), X.max(0), u.mean(0), std
+
+
+def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B.PREC_BF16,
+          lr0=1e-3, lr1=1e-6, lam_F=100.0, lam_v=0.01, seed=0, log_every=0, init=None,
+          eval_rows_per_frame=64, device="cuda"):
+    """Trains decoder weights and per-snapshot latent codes with Adam, the
+    learning rate decaying exponentially from lr0 to lr1.  Returns
+    (weights, biases, Z, normalisation, loss history); with log_every > 0
+    the history holds (step, objective) on a fixed evaluation batch of
+    eval_rows_per_frame random particles of every frame, before step 0,
+    every log_every steps and after the last step."""
+    from . import scenes
+    d = snap.X_sub.shape[1]
+    in_min, in_max, mean, std = normalisation(snap)
+    rows = n_groups * rows_per_group
+    eval_rows = snap.n_frames * eval_rows_per_frame if log_every else 0
+    tr = Trainer(d, r, width, n_hidden, precision, max(rows, eval_rows), in_min, in_max, mean,
+                 std)
+    if init is None:
+        Ws, bs = scenes.xavier_decoder(d, r, width, n_hidden, seed)
+    else:
+        Ws, bs = init
+    params = torch.tensor(B.pack_params(Ws, bs), device=device)
+    Z = torch.zeros(snap.n_frames, r, device=device)
+    m_p, v_p = torch.zeros_like(params), torch.zeros_like(params)
+    m_z, v_z = torch.zeros_like(Z), torch.zeros_like(Z)
+    nf = torch.tensor(snap.next_frame, device=device)
+    rng = np.random.default_rng(seed + 1)
+    X = torch.empty(rows, d, device=device)
+    xt = torch.empty(rows, d, device=device)
+    Ft = torch.empty(rows, d, d, device=device)
+    vt = torch.empty(rows, d, device=device)
+    lib = B.load()
+    history = []
+    if log_every:
+        erng = np.random.default_rng(seed + 2)
+        e_fr = torch.arange(snap.n_frames, dtype=torch.int32, device=device)
+        e_pid = torch.tensor(erng.integers(0, snap.P_sub, size=eval_rows).astype(np.int32),
+                             device=device)
+        e_nxt = nf[e_fr.long()].contiguous()
+        eX = torch.empty(eval_rows, d, device=device)
+        ext = torch.empty(eval_rows, d, device=device)
+        eFt = torch.empty(eval_rows, d, d, device=device)
+        evt = torch.empty(eval_rows, d, device=device)
+        B._check("rom_train_gather", lib.rom_train_gather(
+            d, snap.n_frames, eval_rows_per_frame, snap.P_sub, B._ptr(snap.X_sub), B._ptr(snap.fx),
+            B._ptr(snap.fF), B._ptr(snap.fv), B._ptr(e_fr, torch.int32), B._ptr(e_pid, torch.int32),
+            B._ptr(eX), B._ptr(ext), B._ptr(eFt), B._ptr(evt), B._stream(None)))
+
+        def evaluate():
+            with torch.no_grad():
+                g, G, Gv = DecoderTrainFn.apply(params, Z, eX, e_fr, e_nxt, tr, snap.n_frames,
+                                                eval_rows_per_frame, float(snap.dt_frame))
+                return float(TrainLossFn.apply(g, G, Gv, ext, eFt, evt, e_nxt, snap.n_frames,
+                                               eval_rows_per_frame, lam_F, lam_v).item())
+        history.append((0, evaluate()))
+    for it in range(steps):
+        lr = lr0 * (lr1 / lr0) ** (it / max(steps - 1, 1))
+        fr = rng.integers(0, snap.n_frames, size=n_groups).astype(np.int32)
+        pid = rng.integers(0, snap.P_sub, size=rows).astype(np.int32)
+        fr_t = torch.tensor(fr, device=device)
+        pid_t = torch.tensor(pid, device=device)
+        nxt_t = nf[fr_t.long()].contiguous()
+        B._check("rom_train_gather", lib.rom_train_gather(
+            d, n_groups, rows_per_group, snap.P_sub, B._ptr(snap.X_sub), B._ptr(snap.fx),
+            B._ptr(snap.fF), B._ptr(snap.fv), B._ptr(fr_t, torch.int32), B._ptr(pid_t, torch.int32),
+            B._ptr(X), B._ptr(xt), B._ptr(Ft), B._ptr(vt), B._stream(None)))
+        p = params.detach().requires_grad_(True)
+        z = Z.detach().requires_grad_(True)
+        g, G, Gv = DecoderTrainFn.apply(p, z, X, fr_t, nxt_t, tr, n_groups, rows_per_group,
+                                        float(snap.dt_frame))
+        loss = TrainLossFn.apply(g, G, Gv, xt, Ft, vt, nxt_t, n_groups, rows_per_group, lam_F, lam_v)
+        loss.backward()
+        adam_step(params, p.grad.contiguous(), m_p, v_p, it + 1, lr)
+        adam_step(Z, z.grad.contiguous(), m_z, v_z, it + 1, lr)
+        if log_every and ((it + 1) % log_every == 0 or it == steps - 1):
+            history.append((it + 1, evaluate()))
+    sizes = [d + r] + [width] * n_hidden + [d]
+    flat = params.cpu().numpy()
+    Ws, bs, o = [], [], 0
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        Ws.append(flat[o:o + fi * fo].reshape(fo, fi)); o += fi * fo
+        bs.append(flat[o:o + fo]); o += fo
+    tr.close()
+    return Ws, bs, Z.cpu().numpy(), (in_min, in_max, mean, std), history
