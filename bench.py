@@ -85,6 +85,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rom", action="store_true")
     ap.add_argument("--rom-steps", type=int, default=100)
+    ap.add_argument("--rom-instances", type=int, default=256)
+    ap.add_argument("--rom-batched-steps", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 256 MiB ten times (the reference "
+                         "kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -95,6 +100,15 @@ def main():
     from paper_2109_12390_amd import binding as B
     from paper_2109_12390_amd import scenes
 
+    if args.copy_calibration:
+        a = torch.ones(64 << 20, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
+                          "launches": 10}), flush=True)
+        return
     B.load()
     dev = "cuda:0"
     s = scenes.scene_3d()
@@ -174,6 +188,9 @@ def main():
     }
     if not args.no_rom:
         out["rom"] = rom_throughput(B, scenes, s, args.rom_steps)
+        if args.rom_instances > 0:
+            out["rom_batched"] = rom_batched_throughput(B, scenes, s, args.rom_instances,
+                                                        args.rom_batched_steps)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(s)
@@ -231,6 +248,62 @@ def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden
                        "projection": "position-velocity, 3 Gauss-Newton iterations",
                        "graph": "HIP graph of %d steps" % k},
             "displacement_error": None}
+
+
+def rom_batched_throughput(B, scenes, s, n_inst, steps, r=16, width=128, n_hidden=5):
+    """Reduced-order steps of n_inst parameter instances of the same scene
+    advanced together: Young's moduli log-uniform in [1e3, 1e5] and initial
+    latent velocities from seeded draws, 256 to 1024 sample points per
+    instance, the same bf16 decoder (random initialisation, throughput only),
+    position-velocity projection with 3 Gauss-Newton iterations, every step
+    of all instances replayed from one HIP graph.  Aggregate latent steps/s
+    = instances x steps / time."""
+    import torch
+    dev = "cuda:0"
+    X = s["X"]
+    P = s["P"]
+    Ws, bs = scenes.xavier_decoder(3, r, width, n_hidden, 11)
+    lo, hi = X.min(0), X.max(0)
+    dec = B.Decoder(Ws, bs, lo, hi, np.zeros(3, np.float32), np.full(3, 1e-3, np.float32),
+                    B.OUT_DISPLACEMENT, B.PREC_BF16)
+    grid = B.Grid(3, s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
+    Xg = torch.tensor(np.ascontiguousarray(X.T), device=dev)
+    Es, _ = scenes.parameter_instances(n_inst, 21)
+    rng = np.random.default_rng(22)
+    ns = rng.integers(256, 1025, size=n_inst).astype(np.int32)
+    E = torch.tensor(Es.astype(np.float32), device=dev)
+    nst = torch.tensor(ns, device=dev)
+    rom = B.Rom(dec, grid, Xg, E, nst, B.gn_opts(mode=B.POS_VEL, max_iter=3), seed=5, rho0=1000.0,
+                m_uniform=float(s["m"]))
+    z = torch.zeros(n_inst, r, dtype=torch.float64, device=dev)
+    zp = z.clone()
+    vh = torch.tensor(1e-2 * rng.standard_normal((n_inst, r)), device=dev)
+    st = torch.zeros(n_inst, dtype=torch.int32, device=dev)
+    rom.step(1, 0, s["dt"], z, zp, vh, status=st, use_graph=True)      # capture + warm-up
+    torch.cuda.synchronize()
+    times = []
+    for i in range(steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        rom.step(1, i + 1, s["dt"], z, zp, vh, status=st, use_graph=True)
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    q = [rom.last_counts(b)[0] for b in (0, n_inst // 2, n_inst - 1)]
+    rom.close()
+    dec.close()
+    times = np.array(times)
+    return {"metric": "ROM latent steps/s (all instances)", "value": float(n_inst * 1e3 / times.mean()),
+            "unit": "latent steps/s", "ms_per_batched_step": float(times.mean()),
+            "p50_ms": float(np.percentile(times, 50)), "p99_ms": float(np.percentile(times, 99)),
+            "steps": int(steps), "quadrature_points_sampled_instances": [int(v) for v in q],
+            "config": {"instances": n_inst, "particles": P, "samples": "256-1024 per instance",
+                       "r": r, "decoder": "bf16 MLP %d x %d, random init" % (width, n_hidden),
+                       "E": "log-uniform [1e3, 1e5]",
+                       "projection": "position-velocity, 3 Gauss-Newton iterations",
+                       "graph": "HIP graph of one step of all instances"},
+            "error_vs_full_order": None}
 
 
 if __name__ == "__main__":

@@ -71,6 +71,17 @@ struct DecIO {
 __device__ __forceinline__ float elu(float z) { return z > 0.0f ? z : expm1f(z); }
 __device__ __forceinline__ float elu_d(float z) { return z > 0.0f ? 1.0f : expf(z); }
 
+// ELU and its derivative from one hardware exponential, for activations that
+// are stored in bf16: e^z - 1 is formed by subtraction, whose absolute error
+// (a few 1e-8) is far below the bf16 rounding of the unit-sized activations
+// it is summed with in the next layer.
+__device__ __forceinline__ void elu_fast(float z, float &h, float &e)
+{
+    const float ex = __expf(fminf(z, 0.0f));
+    h = z > 0.0f ? z : ex - 1.0f;
+    e = z > 0.0f ? 1.0f : ex;
+}
+
 // round-to-nearest-even fp32 -> bf16 bit pattern (finite inputs)
 __host__ __device__ __forceinline__ uint16_t bf16_bits(float f)
 {
@@ -83,24 +94,36 @@ __host__ __device__ __forceinline__ uint16_t bf16_bits(float f)
 
 template <typename T>
 struct Elem;
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// Panel element type: fp32 (accurate ELU, libm exponentials) or bf16 (fast
+// ELU, hardware round-to-nearest-even conversion).  store4 writes four
+// consecutive units of one column (16 or 8 bytes, aligned: the panel row
+// stride and the unit offset 4 (lane / 16) are multiples of 4 elements).
 template <>
 struct Elem<float> {
     static constexpr int KS = 4;    // k per MFMA
     static constexpr int PAD = 4;   // row padding (elements)
-    __device__ static float make(float f) { return f; }
-    __device__ static float load_f(const float *p) { return *p; }
+    __device__ static void act(float z, float &h, float &e)
+    {
+        h = elu(z);
+        e = elu_d(z);
+    }
+    __device__ static void store4(float *p, f32x4 v) { *reinterpret_cast<f32x4 *>(p) = v; }
+    __device__ static f32x4 load4(const float *p) { return *reinterpret_cast<const f32x4 *>(p); }
 };
 template <>
 struct Elem<uint16_t> {
     static constexpr int KS = 32;
     static constexpr int PAD = 8;
-    __device__ static uint16_t make(float f) { return bf16_bits(f); }
-    __device__ static float load_f(const uint16_t *p)
+    __device__ static void act(float z, float &h, float &e) { elu_fast(z, h, e); }
+    __device__ static void store4(uint16_t *p, f32x4 v)
     {
-        uint32_t u = ((uint32_t)*p) << 16;
-        float f;
-        memcpy(&f, &u, 4);
-        return f;
+        *reinterpret_cast<bf16x4 *>(p) = __builtin_convertvector(v, bf16x4);
+    }
+    __device__ static f32x4 load4(const uint16_t *p)
+    {
+        return __builtin_convertvector(*reinterpret_cast<const bf16x4 *>(p), f32x4);
     }
 };
 
@@ -124,19 +147,52 @@ __device__ __forceinline__ f32x4 mfma_step(const uint16_t *Arow, const uint16_t 
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
 }
 
-template <typename T, int W, int S, int NP, bool DB>
-__global__ void __launch_bounds__(256) decoder_kernel(DecK P, StreamSpec ss, DecIO io)
+// launch shapes: point tiles per wave of the primal-only evaluation, and
+// whether the primal-only / five-stream evaluations keep one row tile of
+// accumulators (double-buffered panel) instead of the whole layer
+#ifndef MR_DEC_PRIMAL_NP
+#define MR_DEC_PRIMAL_NP 1
+#endif
+#ifndef MR_DEC_PRIMAL_DB
+#define MR_DEC_PRIMAL_DB false
+#endif
+#ifndef MR_DEC_TANGENT_DB
+#define MR_DEC_TANGENT_DB false
+#endif
+#ifndef MR_DEC_PRIMAL_WPB
+#define MR_DEC_PRIMAL_WPB 16
+#endif
+#ifndef MR_DEC_TANGENT_WPB
+#define MR_DEC_TANGENT_WPB 4
+#endif
+
+// Shared memory of a block: the per-instance vectors c0 and u (2 W floats),
+// in bf16 mode the current hidden layer's weights (W rows, padded stride),
+// then one activation panel per wave (two in the double-buffered shape).
+// Staging the weights once per block and layer turns the MFMA A-operand
+// fetches into LDS reads; from global memory every k-step waited on a
+// cache round trip.
+template <typename T, int W>
+struct DecSmem {
+    static constexpr bool WLDS = sizeof(T) == 2;
+    static constexpr int LD = W + Elem<T>::PAD;
+    static constexpr size_t fixed = 2 * W * sizeof(float) + (WLDS ? (size_t)W * LD * sizeof(T) : 0);
+};
+
+template <typename T, int W, int S, int NP, bool DB, int WPB>
+__global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss, DecIO io)
 {
     using E = Elem<T>;
+    using SM = DecSmem<T, W>;
     constexpr int NCT = NP * S;          // column tiles per wave
     constexpr int COLS = NCT * 16;       // columns per wave
-    constexpr int LD = W + E::PAD;       // panel row stride
+    constexpr int LD = W + E::PAD;       // panel and staged-weight row stride
     constexpr int NRT = W / 16;          // row tiles
     constexpr int NKS = W / E::KS;       // k-steps per row tile
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int nwaves = blockDim.x >> 6;
+    constexpr int nwaves = WPB;
     const int b = blockIdx.y;
     const int64_t n_b = io.n_inst ? (int64_t)io.n_inst[b] : io.n;
     // a block entirely past this instance's points leaves before any barrier
@@ -144,8 +200,8 @@ __global__ void __launch_bounds__(256) decoder_kernel(DecK P, StreamSpec ss, Dec
     // per-instance vectors: c0 = W_z xhat + b0, u = W_z vhat
     float *c0 = reinterpret_cast<float *>(smem);
     float *u = c0 + W;
-    T *panel = reinterpret_cast<T *>(smem + 2 * W * sizeof(float)) +
-               (size_t)wave * (DB ? 2 : 1) * COLS * LD;
+    T *wsh = reinterpret_cast<T *>(smem + 2 * W * sizeof(float));
+    T *panel = reinterpret_cast<T *>(smem + SM::fixed) + (size_t)wave * (DB ? 2 : 1) * COLS * LD;
     T *pin = panel;
     T *pout = DB ? panel + COLS * LD : panel;
     const double *xh = io.xhat + (size_t)b * P.r;
@@ -163,10 +219,12 @@ __global__ void __launch_bounds__(256) decoder_kernel(DecK P, StreamSpec ss, Dec
     __syncthreads();
 
     // ---- first layer: lane handles point column j = lane % 16 of each point
-    // tile, units i = lane/16 + 4 m
+    // tile and units 16 m + 4 (lane / 16) + q, q = 0..3 (the layout of an MFMA
+    // output tile), stored four units at a time
     const int64_t wbase = ((int64_t)blockIdx.x * nwaves + wave) * (NP * 16);
     const int j = lane & 15;
     const int g = lane >> 4;
+    const int in0 = P.d + P.r;
 #pragma unroll
     for (int pt = 0; pt < NP; ++pt) {
         int64_t s = wbase + pt * 16 + j;
@@ -175,21 +233,33 @@ __global__ void __launch_bounds__(256) decoder_kernel(DecK P, StreamSpec ss, Dec
             int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * io.n : 0) + s] : s;
             for (int a = 0; a < P.d; ++a) Xn[a] = io.X[a * io.n_ref + row] * P.scale[a] + P.shift[a];
         }
-        for (int i = g; i < W; i += 4) {
-            const float *w0 = P.W0 + (size_t)i * (P.d + P.r);
-            float z = c0[i];
-            for (int a = 0; a < P.d; ++a) z += w0[a] * Xn[a];
-            float h = elu(z), e = elu_d(z);
+        for (int m = 0; m < NRT; ++m) {
+            const int i0 = 16 * m + 4 * g;
+            f32x4 h4, e4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float *w0 = P.W0 + (size_t)(i0 + q) * in0;
+                float z = c0[i0 + q];
+                for (int a = 0; a < P.d; ++a) z += w0[a] * Xn[a];
+                float h, e;
+                E::act(z, h, e);
+                h4[q] = h;
+                e4[q] = e;
+            }
 #pragma unroll
             for (int st = 0; st < S; ++st) {
-                float val;
-                int kind = ss.kind[st], arg = ss.arg[st];
-                if (kind == SK_PRIMAL) val = h;
-                else if (kind == SK_SPATIAL) val = e * w0[arg] * P.scale[arg];
-                else if (kind == SK_VELOCITY) val = e * u[i];
-                else if (kind == SK_LATENT) val = e * w0[P.d + arg];
-                else val = 0.0f;
-                pin[((pt * S + st) * 16 + j) * LD + i] = E::make(val);
+                const int kind = ss.kind[st], arg = ss.arg[st];
+                f32x4 val;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float *w0 = P.W0 + (size_t)(i0 + q) * in0;
+                    if (kind == SK_PRIMAL) val[q] = h4[q];
+                    else if (kind == SK_SPATIAL) val[q] = e4[q] * w0[arg] * P.scale[arg];
+                    else if (kind == SK_VELOCITY) val[q] = e4[q] * u[i0 + q];
+                    else if (kind == SK_LATENT) val[q] = e4[q] * w0[P.d + arg];
+                    else val[q] = 0.0f;
+                }
+                E::store4(pin + ((pt * S + st) * 16 + j) * LD + i0, val);
             }
         }
     }
@@ -198,10 +268,22 @@ __global__ void __launch_bounds__(256) decoder_kernel(DecK P, StreamSpec ss, Dec
     // ---- hidden layers on matrix cores
     for (int l = 0; l < P.nh - 1; ++l) {
         const T *Wl;
-        if constexpr (sizeof(T) == 2)
-            Wl = reinterpret_cast<const T *>(P.Whb) + (size_t)l * W * W;
-        else
+        int lda = W;
+        if constexpr (SM::WLDS) {
+            const T *src = reinterpret_cast<const T *>(P.Whb) + (size_t)l * W * W;
+            __syncthreads();   // every wave is done with the previous layer's weights
+            constexpr int V = W / 8;   // 16-byte vectors per row
+            for (int t = threadIdx.x; t < W * V; t += 64 * WPB) {
+                const int row = t / V, c8 = t % V;
+                *reinterpret_cast<uint4 *>(wsh + row * LD + 8 * c8) =
+                    reinterpret_cast<const uint4 *>(src)[t];
+            }
+            __syncthreads();
+            Wl = wsh;
+            lda = LD;
+        } else {
             Wl = reinterpret_cast<const T *>(P.Wh) + (size_t)l * W * W;
+        }
         const float *bl = P.bh + (size_t)l * W;
         if constexpr (!DB) {
             f32x4 acc[NRT][NCT];
@@ -211,7 +293,7 @@ __global__ void __launch_bounds__(256) decoder_kernel(DecK P, StreamSpec ss, Dec
                 for (int ct = 0; ct < NCT; ++ct) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt) {
-                const T *Arow = Wl + (size_t)(rt * 16 + j) * W;
+                const T *Arow = Wl + (size_t)(rt * 16 + j) * lda;
 #pragma unroll
                 for (int ks = 0; ks < NKS; ++ks)
 #pragma unroll
@@ -220,57 +302,68 @@ __global__ void __launch_bounds__(256) decoder_kernel(DecK P, StreamSpec ss, Dec
                                                 pin + (ct * 16 + j) * LD + ks * E::KS, acc[rt][ct],
                                                 lane);
             }
-            __syncthreads();  // every wave finished reading its panel
+            // the panel is this wave's own: its reads above precede the
+            // in-place writes below in the wave's in-order LDS stream
 #pragma unroll
-            for (int rt = 0; rt < NRT; ++rt)
+            for (int rt = 0; rt < NRT; ++rt) {
+                const int i0 = rt * 16 + 4 * g;
+                f32x4 b4;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    int i = rt * 16 + 4 * g + q;
-                    float bi = bl[i];
+                for (int q = 0; q < 4; ++q) b4[q] = bl[i0 + q];
 #pragma unroll
-                    for (int pt = 0; pt < NP; ++pt) {
-                        float z = acc[rt][pt * S][q] + bi;
-                        float e = elu_d(z);
-                        pout[((pt * S) * 16 + j) * LD + i] = E::make(elu(z));
+                for (int pt = 0; pt < NP; ++pt) {
+                    f32x4 h4, e4;
 #pragma unroll
-                        for (int st = 1; st < S; ++st)
-                            pout[((pt * S + st) * 16 + j) * LD + i] =
-                                E::make(e * acc[rt][pt * S + st][q]);
+                    for (int q = 0; q < 4; ++q) {
+                        float h, e;
+                        E::act(acc[rt][pt * S][q] + b4[q], h, e);
+                        h4[q] = h;
+                        e4[q] = e;
                     }
+                    E::store4(pout + ((pt * S) * 16 + j) * LD + i0, h4);
+#pragma unroll
+                    for (int st = 1; st < S; ++st)
+                        E::store4(pout + ((pt * S + st) * 16 + j) * LD + i0,
+                                  e4 * acc[rt][pt * S + st]);
                 }
+            }
         } else {
 #pragma unroll 1
             for (int rt = 0; rt < NRT; ++rt) {
                 f32x4 acc[NCT];
 #pragma unroll
                 for (int ct = 0; ct < NCT; ++ct) acc[ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-                const T *Arow = Wl + (size_t)(rt * 16 + j) * W;
+                const T *Arow = Wl + (size_t)(rt * 16 + j) * lda;
 #pragma unroll
                 for (int ks = 0; ks < NKS; ++ks)
 #pragma unroll
                     for (int ct = 0; ct < NCT; ++ct)
                         acc[ct] = mfma_step(Arow + ks * E::KS,
                                             pin + (ct * 16 + j) * LD + ks * E::KS, acc[ct], lane);
+                const int i0 = rt * 16 + 4 * g;
+                f32x4 b4;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    int i = rt * 16 + 4 * g + q;
-                    float bi = bl[i];
+                for (int q = 0; q < 4; ++q) b4[q] = bl[i0 + q];
 #pragma unroll
-                    for (int pt = 0; pt < NP; ++pt) {
-                        float z = acc[pt * S][q] + bi;
-                        float e = elu_d(z);
-                        pout[((pt * S) * 16 + j) * LD + i] = E::make(elu(z));
+                for (int pt = 0; pt < NP; ++pt) {
+                    f32x4 h4, e4;
 #pragma unroll
-                        for (int st = 1; st < S; ++st)
-                            pout[((pt * S + st) * 16 + j) * LD + i] = E::make(e * acc[pt * S + st][q]);
+                    for (int q = 0; q < 4; ++q) {
+                        float h, e;
+                        E::act(acc[pt * S][q] + b4[q], h, e);
+                        h4[q] = h;
+                        e4[q] = e;
                     }
+                    E::store4(pout + ((pt * S) * 16 + j) * LD + i0, h4);
+#pragma unroll
+                    for (int st = 1; st < S; ++st)
+                        E::store4(pout + ((pt * S + st) * 16 + j) * LD + i0, e4 * acc[pt * S + st]);
                 }
             }
             T *tmp = pin;
             pin = pout;
             pout = tmp;
         }
-        __syncthreads();
     }
 
     // ---- output layer (fp32): y_a = WL[a] . h (+ bL[a] for the primal)
@@ -285,7 +378,10 @@ __global__ void __launch_bounds__(256) decoder_kernel(DecK P, StreamSpec ss, Dec
         const T *h = pin + (size_t)col * LD;
         const float *wl = P.WL + (size_t)a * W;
         float y = 0.0f;
-        for (int i = 0; i < W; ++i) y += wl[i] * E::load_f(h + i);
+        for (int i = 0; i < W; i += 4) {
+            const f32x4 h4 = E::load4(h + i);
+            y += wl[i] * h4[0] + wl[i + 1] * h4[1] + wl[i + 2] * h4[2] + wl[i + 3] * h4[3];
+        }
         int kind = ss.kind[st], arg = ss.arg[st];
         const int64_t n = io.n;
         const size_t bo = (size_t)b;
@@ -311,38 +407,49 @@ __global__ void __launch_bounds__(256) decoder_kernel(DecK P, StreamSpec ss, Dec
     }
 }
 
-template <typename T, int W, int S, int NP, bool DB>
+template <typename T, int W, int S, int NP, bool DB, int WPB>
 int32_t launch_one(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStream_t st)
 {
     using E = Elem<T>;
     constexpr int COLS = NP * S * 16;
-    size_t per_wave = (size_t)(DB ? 2 : 1) * COLS * (W + E::PAD) * sizeof(T);
-    size_t fixed = 2 * W * sizeof(float);
-    const size_t budget = 150 * 1024;
-    int wpb = (int)((budget - fixed) / per_wave);
-    if (wpb > 4) wpb = 4;
-    if (wpb < 1) return MR_EINVAL;
-    size_t lds = fixed + (size_t)wpb * per_wave;
-    int64_t pts_per_block = (int64_t)wpb * NP * 16;
+    constexpr size_t per_wave = (size_t)(DB ? 2 : 1) * COLS * (W + E::PAD) * sizeof(T);
+    constexpr size_t lds = DecSmem<T, W>::fixed + (size_t)WPB * per_wave;
+    static_assert(WPB >= 1 && lds <= 160 * 1024, "decoder block does not fit the LDS of a compute unit");
+    const int64_t pts_per_block = (int64_t)WPB * NP * 16;
     dim3 grid((unsigned)ceil_div(io.n, pts_per_block), (unsigned)io.B);
-    auto kern = decoder_kernel<T, W, S, NP, DB>;
+    auto kern = decoder_kernel<T, W, S, NP, DB, WPB>;
     static bool attr_set = false;  // the LDS size of an instantiation is fixed
     if (!attr_set) {
         MR_CHECK_HIP(hipFuncSetAttribute((const void *)kern,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
-    kern<<<grid, 64 * wpb, lds, st>>>(P, ss, io);
+    kern<<<grid, 64 * WPB, lds, st>>>(P, ss, io);
     MR_LAUNCH_CHECK();
     return MR_OK;
+}
+
+// waves per block of a shape: as many as fit 150 KB of LDS, at most `cap`
+template <typename T, int W, int S, int NP, bool DB>
+constexpr int dec_wpb(int cap)
+{
+    constexpr size_t per_wave = (size_t)(DB ? 2 : 1) * NP * S * 16 * (W + Elem<T>::PAD) * sizeof(T);
+    constexpr size_t fixed = DecSmem<T, W>::fixed;
+    int w = (int)((150 * 1024 - fixed) / per_wave);
+    return w < cap ? w : cap;
 }
 
 template <typename T, int W>
 int32_t launch_w(int cfg, const DecK &P, const StreamSpec &ss, const DecIO &io, hipStream_t st)
 {
-    if (cfg == 1) return launch_one<T, W, 1, 4, false>(P, ss, io, st);
-    if (cfg == 5) return launch_one<T, W, 5, 1, false>(P, ss, io, st);
-    return launch_one<T, W, 9, 1, true>(P, ss, io, st);
+    constexpr int NP1 = MR_DEC_PRIMAL_NP;
+    constexpr bool DB1 = MR_DEC_PRIMAL_DB, DB5 = MR_DEC_TANGENT_DB;
+    if (cfg == 1)
+        return launch_one<T, W, 1, NP1, DB1, dec_wpb<T, W, 1, NP1, DB1>(MR_DEC_PRIMAL_WPB)>(P, ss, io,
+                                                                                          st);
+    if (cfg == 5)
+        return launch_one<T, W, 5, 1, DB5, dec_wpb<T, W, 5, 1, DB5>(MR_DEC_TANGENT_WPB)>(P, ss, io, st);
+    return launch_one<T, W, 9, 1, true, dec_wpb<T, W, 9, 1, true>(4)>(P, ss, io, st);
 }
 
 // Decoder without hidden layers (the linear manifold): y = W0 [Xn, xhat] + b0.

@@ -350,8 +350,13 @@ struct CellTile {
 
 __device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
 
+// waves per SIMD the tile kernels are compiled for (bounds their registers)
+#ifndef MR_TILE_MIN_WAVES
+#define MR_TILE_MIN_WAVES 1
+#endif
+
 template <int D, bool FUSED>
-__global__ void __launch_bounds__(256) tile_scatter_kernel(
+__global__ void __launch_bounds__(256, MR_TILE_MIN_WAVES) tile_scatter_kernel(
     GridK g, TileGeom tg, float *x, float *v, float *C, float *F, const float *m, const float *V0,
     float m_u, float V0_u, int64_t n, const int32_t *offsets, const int32_t *counts, int apic,
     int model, float mu, float la, float dt, const float *grid_in, float *grid_out, float *v_out,

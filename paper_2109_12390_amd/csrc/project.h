@@ -15,7 +15,7 @@ int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const flo
 
 struct ProjWS {
     float *Jz, *x, *xc, *xt;
-    double *A, *L, *g, *delta, *z, *v, *zc, *f, *fe, *fc, *fce, *fnew, *step;
+    double *A, *part, *g, *delta, *z, *v, *zc, *f, *fe, *fc, *fce, *fnew, *step;
     int32_t *status, *singular;
 };
 

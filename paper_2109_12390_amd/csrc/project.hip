@@ -2,11 +2,12 @@
 // velocity least squares and Gauss-Newton position projection over the
 // sample points, batched over B instances.
 //
-//  * normal equations: one workgroup per instance stages chunks of the
-//    latent Jacobian (fp32, from the decoder kernels) in LDS and accumulates
-//    J^T J, J^T y and 0.5 |y|^2 in fp64 (products of fp32 values are exact in
-//    fp64, so only the summation rounds);
-//  * the r x r solve is an fp64 Cholesky factorisation, one thread per
+//  * normal equations: one workgroup per (instance, chunk of 64 samples)
+//    stages the chunk's latent Jacobian (fp32, from the decoder kernels) in
+//    LDS as fp64 and forms partial J^T J, J^T y and 0.5 |y|^2 (products of
+//    fp32 values are exact in fp64, so only the summation rounds); a second
+//    kernel adds the partials in chunk order;
+//  * the r x r solve is an fp64 Cholesky factorisation, one wave per
 //    instance;
 //  * backtracking: the max_backtrack + 1 trial step lengths 1, 1/2, 1/4, ...
 //    are decoded together in one launch (B (max_backtrack + 1) instances)
@@ -23,95 +24,122 @@ __global__ void zero_i32_kernel(int32_t *a, int64_t n)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = 0;
 }
-constexpr int NE_CHUNK = 32;  // samples staged per pass
+constexpr int NE_CH = 64;             // samples per partial-sum workgroup
+constexpr int NE_LD = NE_CH + 1;      // LDS row stride (doubles), off the bank period
 
-// mode 0: rhs = J^T v (velocity);  mode 1: rhs = J^T (x - x_trial), f = 0.5|x - x_trial|^2
+__host__ __device__ inline int ne_chunks(int64_t ns) { return (int)((ns + NE_CH - 1) / NE_CH); }
+__host__ __device__ inline int ne_entries(int r) { return r * r + r + 2; }
+
+// Partial sums of the normal equations over one chunk of NE_CH samples of
+// one instance (grid: chunks x B).  Entry e of the chunk's record:
+//   e < r^2        (J^T J)[k1][k2]       = sum_a,s J[a k1][s] J[a k2][s]
+//   e < r^2 + r    (J^T y)[k]            = sum_a,s J[a k][s] y[a][s]
+//   e = r^2 + r    0.5 |y|^2                       (MODE 1)
+//   e = r^2 + r + 1  sum |y| (|x| + |x_trial|) 2^-23 (MODE 1): a bound on
+//                  the change of the objective caused by fp32 rounding
+// with y = v_trial (MODE 0) or y = x - x_trial (MODE 1).  The fp32 inputs
+// are widened to fp64 once when staged; their products are exact in fp64,
+// so only the summation rounds.
 template <int MODE>
-__global__ void __launch_bounds__(NE_THREADS) normal_eq_kernel(int d, int r, int64_t ns,
-                                                               const int32_t *ns_inst,
-                                                               const float *Jz, const float *y,
-                                                               const float *x, double *A,
-                                                               double *rhs, double *f,
-                                                               double *fe)
+__global__ void __launch_bounds__(NE_THREADS) normal_eq_partial_kernel(
+    int d, int r, int64_t ns, const int32_t *ns_inst, const float *Jz, const float *y,
+    const float *x, double *part)
 {
-    extern __shared__ __align__(8) float sm[];
-    const int b = blockIdx.x;
+    extern __shared__ __align__(8) double smd[];
+    const int ch = blockIdx.x, nch = gridDim.x, b = blockIdx.y;
     const int64_t cnt = ns_inst ? (int64_t)ns_inst[b] : ns;
+    const int64_t s0 = (int64_t)ch * NE_CH;
+    const int len = s0 >= cnt ? 0 : (int)((cnt - s0) < NE_CH ? (cnt - s0) : NE_CH);
     const int dr = d * r;
-    float *Js = sm;                      // [dr][NE_CHUNK]
-    float *Ys = sm + dr * NE_CHUNK;      // [d][NE_CHUNK]
-    float *Ms = Ys + d * NE_CHUNK;       // [d][NE_CHUNK] |x| + |x_trial|
+    double *Js = smd;                   // [dr][NE_LD]
+    double *Ys = Js + dr * NE_LD;       // [d][NE_LD]
+    double *Ms = Ys + d * NE_LD;        // [d][NE_LD]
     const float *Jb = Jz + (size_t)b * dr * ns;
     const float *yb = y + (size_t)b * d * ns;
     const float *xb = MODE == 1 ? x + (size_t)b * d * ns : nullptr;
-    const int nent = r * r + r + 2;
-    double acc[5] = {0, 0, 0, 0, 0};  // entries tid, tid + 256, ... (r <= 32 -> <= 5)
-    for (int64_t s0 = 0; s0 < cnt; s0 += NE_CHUNK) {
-        int len = (int)((cnt - s0) < NE_CHUNK ? (cnt - s0) : NE_CHUNK);
-        __syncthreads();
-        for (int t = threadIdx.x; t < dr * NE_CHUNK; t += blockDim.x) {
-            int row = t / NE_CHUNK, c = t % NE_CHUNK;
-            Js[t] = c < len ? Jb[(size_t)row * ns + s0 + c] : 0.0f;
-        }
-        for (int t = threadIdx.x; t < d * NE_CHUNK; t += blockDim.x) {
-            int a = t / NE_CHUNK, c = t % NE_CHUNK;
-            float val = 0.0f, mag = 0.0f;
-            if (c < len) {
-                val = yb[(size_t)a * ns + s0 + c];
-                if (MODE == 1) {
-                    float xv = xb[(size_t)a * ns + s0 + c];
-                    mag = fabsf(xv) + fabsf(val);
-                    val = xv - val;
-                }
-            }
-            Ys[t] = val;
-            Ms[t] = mag;
-        }
-        __syncthreads();
-        int q = 0;
-        for (int e = threadIdx.x; e < nent; e += blockDim.x, ++q) {
-            double sacc = 0.0;
-            if (e < r * r) {
-                int k1 = e / r, k2 = e % r;
-                for (int a = 0; a < d; ++a) {
-                    const float *p1 = Js + (a * r + k1) * NE_CHUNK;
-                    const float *p2 = Js + (a * r + k2) * NE_CHUNK;
-                    for (int c = 0; c < len; ++c) sacc += (double)p1[c] * (double)p2[c];
-                }
-            } else if (e < r * r + r) {
-                int k = e - r * r;
-                for (int a = 0; a < d; ++a) {
-                    const float *p1 = Js + (a * r + k) * NE_CHUNK;
-                    const float *py = Ys + a * NE_CHUNK;
-                    for (int c = 0; c < len; ++c) sacc += (double)p1[c] * (double)py[c];
-                }
-            } else if (MODE == 1 && e == r * r + r) {
-                for (int a = 0; a < d; ++a)
-                    for (int c = 0; c < len; ++c) {
-                        double v = Ys[a * NE_CHUNK + c];
-                        sacc += 0.5 * v * v;
-                    }
-            } else if (MODE == 1) {
-                // bound on the change of f caused by fp32 rounding of its inputs
-                for (int a = 0; a < d; ++a)
-                    for (int c = 0; c < len; ++c)
-                        sacc += fabs((double)Ys[a * NE_CHUNK + c]) * (double)Ms[a * NE_CHUNK + c] *
-                                0x1p-23;
-            }
-            acc[q] += sacc;
-        }
+    for (int t = threadIdx.x; t < dr * NE_CH; t += NE_THREADS) {
+        const int row = t / NE_CH, c = t % NE_CH;
+        Js[row * NE_LD + c] = c < len ? (double)Jb[(size_t)row * ns + s0 + c] : 0.0;
     }
-    int q = 0;
-    for (int e = threadIdx.x; e < nent; e += blockDim.x, ++q) {
+    for (int t = threadIdx.x; t < d * NE_CH; t += NE_THREADS) {
+        const int a = t / NE_CH, c = t % NE_CH;
+        double val = 0.0, mag = 0.0;
+        if (c < len) {
+            const float yv = yb[(size_t)a * ns + s0 + c];
+            if (MODE == 1) {
+                const float xv = xb[(size_t)a * ns + s0 + c];
+                mag = (double)fabsf(xv) + (double)fabsf(yv);
+                val = (double)(xv - yv);
+            } else {
+                val = (double)yv;
+            }
+        }
+        Ys[a * NE_LD + c] = val;
+        Ms[a * NE_LD + c] = mag;
+    }
+    __syncthreads();
+    const int nent = ne_entries(r);
+    double *pb = part + ((size_t)b * nch + ch) * nent;
+    for (int e = threadIdx.x; e < nent; e += NE_THREADS) {
+        double s = 0.0;
+        if (e < r * r) {
+            const int k1 = e / r, k2 = e % r;
+            for (int a = 0; a < d; ++a) {
+                const double *p1 = Js + (a * r + k1) * NE_LD;
+                const double *p2 = Js + (a * r + k2) * NE_LD;
+                for (int c = 0; c < len; ++c) s += p1[c] * p2[c];
+            }
+        } else if (e < r * r + r) {
+            const int k = e - r * r;
+            for (int a = 0; a < d; ++a) {
+                const double *p1 = Js + (a * r + k) * NE_LD;
+                const double *py = Ys + a * NE_LD;
+                for (int c = 0; c < len; ++c) s += p1[c] * py[c];
+            }
+        } else if (MODE == 1 && e == r * r + r) {
+            for (int a = 0; a < d; ++a)
+                for (int c = 0; c < len; ++c) s += 0.5 * Ys[a * NE_LD + c] * Ys[a * NE_LD + c];
+        } else if (MODE == 1) {
+            for (int a = 0; a < d; ++a)
+                for (int c = 0; c < len; ++c)
+                    s += fabs(Ys[a * NE_LD + c]) * Ms[a * NE_LD + c] * 0x1p-23;
+        }
+        pb[e] = s;
+    }
+}
+
+// Sum of the chunk records in chunk order (deterministic) into A, rhs, f, fe.
+__global__ void __launch_bounds__(NE_THREADS) normal_eq_reduce_kernel(int r, int nch,
+                                                                      const double *part,
+                                                                      double *A, double *rhs,
+                                                                      double *f, double *fe)
+{
+    const int b = blockIdx.x;
+    const int nent = ne_entries(r);
+    for (int e = threadIdx.x; e < nent; e += NE_THREADS) {
+        double s = 0.0;
+        for (int ch = 0; ch < nch; ++ch) s += part[((size_t)b * nch + ch) * nent + e];
         if (e < r * r)
-            A[(size_t)b * r * r + e] = acc[q];
+            A[(size_t)b * r * r + e] = s;
         else if (e < r * r + r)
-            rhs[(size_t)b * r + (e - r * r)] = acc[q];
+            rhs[(size_t)b * r + (e - r * r)] = s;
         else if (e == r * r + r && f)
-            f[b] = acc[q];
+            f[b] = s;
         else if (e == r * r + r + 1 && fe)
-            fe[b] = acc[q];
+            fe[b] = s;
     }
+}
+
+template <int MODE>
+void normal_eq(int d, int r, int B, int64_t ns, const int32_t *ns_inst, const float *Jz,
+               const float *y, const float *x, double *part, double *A, double *rhs, double *f,
+               double *fe, hipStream_t st)
+{
+    const int nch = ne_chunks(ns);
+    const size_t lds = sizeof(double) * (size_t)(d * r + 2 * d) * NE_LD;
+    normal_eq_partial_kernel<MODE><<<dim3((unsigned)nch, (unsigned)B), NE_THREADS, lds, st>>>(
+        d, r, ns, ns_inst, Jz, y, x, part);
+    normal_eq_reduce_kernel<<<(unsigned)B, NE_THREADS, 0, st>>>(r, nch, part, A, rhs, f, fe);
 }
 
 // 0.5 |x - x_trial|^2 per candidate instance c (samples of instance c / group)
@@ -149,50 +177,68 @@ __global__ void __launch_bounds__(256) objective_kernel(int d, int64_t ns, int g
     }
 }
 
-// Solve (A + damping I) y = sign * rhs by Cholesky, one thread per instance.
-__global__ void cholesky_solve_kernel(int B, int r, const double *A, const double *rhs,
-                                      double damping, double sign, double *y, double *L_ws,
-                                      int32_t *status, int32_t *singular)
+// Solve (A + damping I) y = sign * rhs by Cholesky, one wave per instance
+// (r <= 32): the matrix sits in LDS; column j of L is formed by lanes i >= j
+// in parallel (left-looking), and the two triangular solves keep y_i in lane
+// i, updating the remaining lanes after each pivot.  A pivot below 1e-12 of
+// its original diagonal (or not positive) marks the instance singular:
+// y = 0 and MR_FLAG_SINGULAR.
+__global__ void __launch_bounds__(64) cholesky_solve_kernel(int B, int r, const double *A,
+                                                            const double *rhs, double damping,
+                                                            double sign, double *y,
+                                                            int32_t *status, int32_t *singular)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    __shared__ double Ls[32][33];
+    __shared__ double dg[32];
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (b >= B) return;                                   // block-uniform
     const double *Ab = A + (size_t)b * r * r;
-    double *L = L_ws + (size_t)b * r * r;
-    double *yb = y + (size_t)b * r;
-    bool ok = true;
-    for (int i = 0; i < r && ok; ++i) {
-        for (int j2 = 0; j2 <= i; ++j2) {
-            double s = Ab[i * r + j2] + (i == j2 ? damping : 0.0);
-            for (int k = 0; k < j2; ++k) s -= L[i * r + k] * L[j2 * r + k];
-            if (i == j2) {
-                // a pivot that lost all but ~1e-12 of the diagonal is singular
-                if (!(s > 1e-12 * (Ab[i * r + i] + damping)) || !(s > 0.0)) {
-                    ok = false;
-                    break;
-                }
-                L[i * r + i] = sqrt(s);
-            } else {
-                L[i * r + j2] = s / L[j2 * r + j2];
-            }
-        }
+    for (int t = lane; t < r * r; t += 64) {
+        const int i = t / r, k = t % r;
+        Ls[i][k] = Ab[t] + (i == k ? damping : 0.0);
     }
+    if (lane < r) dg[lane] = Ab[lane * r + lane] + damping;
+    __syncthreads();
+    bool ok = true;
+    for (int j = 0; j < r; ++j) {
+        const bool act = lane >= j && lane < r;
+        double s = 0.0;
+        if (act) {
+            s = Ls[lane][j];
+            for (int k = 0; k < j; ++k) s -= Ls[lane][k] * Ls[j][k];
+        }
+        const double piv = __shfl(s, j);
+        if (!(piv > 1e-12 * dg[j]) || !(piv > 0.0)) {   // wave-uniform
+            ok = false;
+            break;
+        }
+        const double ljj = sqrt(piv);
+        if (act) Ls[lane][j] = lane == j ? ljj : s / ljj;
+        __syncthreads();
+    }
+    double* yb = y + (size_t)b * r;
     if (!ok) {
-        for (int i = 0; i < r; ++i) yb[i] = 0.0;
-        if (status) status[b] |= MR_FLAG_SINGULAR;
-        if (singular) singular[b] = 1;
+        if (lane < r) yb[lane] = 0.0;
+        if (lane == 0) {
+            if (status) status[b] |= MR_FLAG_SINGULAR;
+            if (singular) singular[b] = 1;
+        }
         return;
     }
     // forward: L w = sign rhs ; backward: L^T y = w
+    double yk = lane < r ? sign * rhs[(size_t)b * r + lane] : 0.0;
     for (int i = 0; i < r; ++i) {
-        double s = sign * rhs[(size_t)b * r + i];
-        for (int k = 0; k < i; ++k) s -= L[i * r + k] * yb[k];
-        yb[i] = s / L[i * r + i];
+        const double wi = __shfl(yk, i) / Ls[i][i];
+        if (lane == i) yk = wi;
+        else if (lane > i && lane < r) yk -= Ls[lane][i] * wi;
     }
     for (int i = r - 1; i >= 0; --i) {
-        double s = yb[i];
-        for (int k = i + 1; k < r; ++k) s -= L[k * r + i] * yb[k];
-        yb[i] = s / L[i * r + i];
+        const double yi = __shfl(yk, i) / Ls[i][i];
+        if (lane == i) yk = yi;
+        else if (lane < i) yk -= Ls[i][lane] * yi;
     }
+    if (lane < r) yb[lane] = yk;
 }
 
 // trial point of Algorithm 5 from the decoded current point: x_n + dt v_trial
@@ -314,7 +360,7 @@ int64_t proj_ws_bytes(int d, int r, int B, int64_t ns, int max_backtrack)
     take(4LL * B * nc * d * ns);      // candidate x
     take(4LL * B * d * ns);           // trial positions / displacements
     take(8LL * B * r * r);            // A
-    take(8LL * B * r * r);            // L
+    take(8LL * B * ne_chunks(ns) * ne_entries(r));   // normal-equation partial sums
     take(8LL * B * r);                // rhs / g
     take(8LL * B * r);                // delta
     take(8LL * B * r);                // z
@@ -347,7 +393,7 @@ ProjWS proj_ws_carve(void *base, int d, int r, int B, int64_t ns, int max_backtr
     w.xc = (float *)take(4LL * B * nc * d * ns);
     w.xt = (float *)take(4LL * B * d * ns);
     w.A = (double *)take(8LL * B * r * r);
-    w.L = (double *)take(8LL * B * r * r);
+    w.part = (double *)take(8LL * B * ne_chunks(ns) * ne_entries(r));
     w.g = (double *)take(8LL * B * r);
     w.delta = (double *)take(8LL * B * r);
     w.z = (double *)take(8LL * B * r);
@@ -374,7 +420,6 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
     const int nc = o.max_backtrack + 1;
     const int TB = 256;
     int32_t rc;
-    size_t ne_lds = sizeof(float) * (size_t)(d * r + 2 * d) * NE_CHUNK;
     zero_i32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>(w.status, B);
     zero_i32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>(w.singular, B);
     // With x_trial == NULL the trial positions are those of Algorithm 5,
@@ -394,10 +439,10 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
                                                                                 w.xt);
         xtp = w.xt;
     }
-    normal_eq_kernel<0><<<B, NE_THREADS, ne_lds, st>>>(d, r, ns, ns_inst, w.Jz, v_trial, nullptr,
-                                                      w.A, w.g, nullptr, nullptr);
-    cholesky_solve_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(B, r, w.A, w.g, o.damping, 1.0,
-                                                                    w.v, w.L, w.status, w.singular);
+    normal_eq<0>(d, r, B, ns, ns_inst, w.Jz, v_trial, nullptr, w.part, w.A, w.g, nullptr, nullptr,
+                 st);
+    cholesky_solve_kernel<<<(unsigned)B, 64, 0, st>>>(B, r, w.A, w.g, o.damping, 1.0, w.v,
+                                                      w.status, w.singular);
     init_guess_kernel<<<(unsigned)ceil_div((int64_t)B * r, TB), TB, 0, st>>>(
         B, r, o.mode, dt, zn, zp, w.v, w.singular, w.z, w.v);
     MR_LAUNCH_CHECK();
@@ -408,10 +453,9 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
             rc = decode_jac_ex(dec, B, n_ref, X, ns, idx, 1, ns_inst, w.z, nullptr, w.x, nullptr,
                                nullptr, w.Jz, st, disp);
             if (rc != MR_OK) return rc;
-            normal_eq_kernel<1><<<B, NE_THREADS, ne_lds, st>>>(d, r, ns, ns_inst, w.Jz, xtp,
-                                                              w.x, w.A, w.g, w.f, w.fe);
-            cholesky_solve_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(
-                B, r, w.A, w.g, o.damping, -1.0, w.delta, w.L, w.status, nullptr);
+            normal_eq<1>(d, r, B, ns, ns_inst, w.Jz, xtp, w.x, w.part, w.A, w.g, w.f, w.fe, st);
+            cholesky_solve_kernel<<<(unsigned)B, 64, 0, st>>>(B, r, w.A, w.g, o.damping, -1.0,
+                                                              w.delta, w.status, nullptr);
             candidates_kernel<<<(unsigned)ceil_div((int64_t)B * nc * r, TB), TB, 0, st>>>(
                 B, r, nc, w.z, w.delta, w.zc);
             MR_LAUNCH_CHECK();

@@ -1,0 +1,138 @@
+"""Reduced-order model against the full-order model on the same parameters
+(paper Section 5: the full-order solution judges the reduced one).
+
+`fom_positions` runs mpm_step and records particle positions (in reference
+order); `rom_positions` initialises the latent state by the least-squares
+initial conditions (Section 3.1, eq. essentialSpecInt, by point quadrature
+over a particle subset: rom_project with x_trial = X, then the velocity
+problem at that latent), runs rom_step and decodes every particle at the
+recorded steps (rom_decode); `displacement_error` accumulates
+sqrt(sum |x_rom - x_fom|^2) / sqrt(sum |x_fom - X|^2) over steps and
+particles, and the paper's position error in percent.
+"""
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def _grid(scene):
+    return B.Grid(scene["dim"], scene["n"], scene["dx"], scene["bound"], scene["floor_mode"],
+                  scene["mu_f"], scene["gravity"])
+
+
+def fom_positions(scene, E, v0, n_steps, record_every, sort_every=10, affine=True,
+                  device="cuda"):
+    """Full-order positions at steps 0, record_every, ... (reference order),
+    as a list of (d, P) float32 device tensors.  affine=False runs the
+    transfers without the APIC affine term (the PIC scheme of Algorithm 1,
+    which the reduced-order substep of Algorithm 5 also uses)."""
+    d, P = scene["dim"], scene["P"]
+    soa = lambda a: torch.tensor(np.ascontiguousarray(a.reshape(P, -1).T), device=device)
+    v = np.tile(np.asarray(v0, dtype=np.float32), (P, 1))
+    parts = B.Particles(soa(scene["X"]), soa(v), torch.zeros(d * d, P, device=device),
+                        soa(np.tile(np.eye(d, dtype=np.float32), (P, 1, 1))),
+                        m_uniform=float(scene["m"]), V0_uniform=float(scene["V0"]))
+    grid = _grid(scene)
+    gbuf = torch.zeros(grid.nodes() * 4, device=device)
+    ws = torch.zeros(B.mpm_step_workspace_bytes(grid, P), dtype=torch.uint8, device=device)
+    perm = torch.zeros(P, dtype=torch.int32, device=device)
+    flag = torch.zeros(1, dtype=torch.int32, device=device)
+    slot_of = torch.arange(P, device=device)
+    out = [parts.x.clone()]
+    done = 0
+    while done < n_steps:
+        k = min(record_every, n_steps - done)
+        B.mpm_step(grid, (scene["model"], float(E), scene["nu"]), parts, scene["dt"], k,
+                   sort_every, 0 if affine else B.NO_AFFINE, gbuf, ws, perm_accum=perm,
+                   status=flag)
+        inv = torch.empty(P, dtype=torch.long, device=device)
+        inv[perm.long()] = torch.arange(P, device=device)
+        slot_of = inv[slot_of]
+        done += k
+        out.append(parts.x[:, slot_of].contiguous())
+    rc, fl = B.sync_status(flag)
+    if rc != 0:
+        raise RuntimeError("full-order model raised %s" % fl)
+    return out
+
+
+def rom_initial_state(dec, scene, v0, z_guess=None, n_quad=65536, seed=0, iters=8,
+                      device="cuda"):
+    """Least-squares initial latent position and velocity over a random
+    subset of n_quad particles (point quadrature of the two integrals).  The
+    Gauss-Newton iteration starts at z_guess (default 0): the latent codes a
+    decoder was trained with for the initial frame of its simulations (all
+    of which start from the reference configuration) are the natural start,
+    since a network can map several codes to the same configuration and the
+    dynamics are only trained along the codes it has seen."""
+    P, d, r = scene["P"], scene["dim"], dec.r
+    rng = np.random.default_rng(seed)
+    q = np.sort(rng.choice(P, size=min(n_quad, P), replace=False)).astype(np.int32)
+    X = torch.tensor(np.ascontiguousarray(scene["X"].T), device=device)
+    idx = torch.tensor(q[None, :], device=device)
+    x_trial = X[:, idx[0].long()].contiguous()[None]
+    v_trial = torch.tensor(np.tile(np.asarray(v0, np.float32)[:, None], (1, len(q))), device=device)[None]
+    z0 = torch.zeros(1, r, dtype=torch.float64, device=device)
+    if z_guess is not None:
+        z0[0] = torch.as_tensor(np.asarray(z_guess, dtype=np.float64), device=device)
+    z = torch.zeros_like(z0)
+    vh = torch.zeros_like(z0)
+    B.rom_project(dec, X, idx, x_trial.contiguous(), v_trial.contiguous(), z0, z0, 1.0,
+                  B.gn_opts(mode=B.POS_VEL, max_iter=iters), z, vh)
+    vh2 = torch.zeros_like(z0)
+    zz = torch.zeros_like(z0)
+    B.rom_project(dec, X, idx, x_trial.contiguous(), v_trial.contiguous(), z, z, 0.0,
+                  B.gn_opts(mode=B.VEL_ONLY, max_iter=0), zz, vh2)
+    return z, vh2
+
+
+def rom_positions(dec, scene, E, v0, n_steps, record_every, n_samples, opts, seed=7,
+                  use_graph=True, z_guess=None, device="cuda"):
+    """Reduced-order positions of every particle at the recorded steps and
+    the step statistics."""
+    P, d = scene["P"], scene["dim"]
+    X = torch.tensor(np.ascontiguousarray(scene["X"].T), device=device)
+    grid = _grid(scene)
+    rom = B.Rom(dec, grid, X, torch.tensor([float(E)], device=device),
+                torch.tensor([n_samples], dtype=torch.int32, device=device), opts, seed=seed,
+                rho0=float(scene["rho"]), m_uniform=float(scene["m"]),
+                model=scene["model"], nu=scene["nu"])
+    z, vh = rom_initial_state(dec, scene, v0, z_guess=z_guess, device=device)
+    zp = z.clone()
+    st = torch.zeros(1, dtype=torch.int32, device=device)
+    xbuf = torch.zeros(1, d, P, device=device)
+    B.rom_decode(dec, X, z, xbuf)
+    out = [xbuf[0].clone()]
+    done = 0
+    times = []
+    while done < n_steps:
+        k = min(record_every, n_steps - done)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        rom.step(k, done, scene["dt"], z, zp, vh, status=st, use_graph=use_graph)
+        b.record()
+        B.rom_decode(dec, X, z, xbuf)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b) / k)
+        done += k
+        out.append(xbuf[0].clone())
+    nq, na = rom.last_counts(0)
+    rom.close()
+    return out, {"status": int(st.item()), "ms_per_step": float(np.mean(times[1:] if len(times) > 1 else times)),
+                 "n_quadrature_points": nq, "n_active_nodes": na}
+
+
+def displacement_error(x_rom, x_fom, X):
+    """(displacement-relative error, position error in percent) accumulated
+    over the recorded steps and all particles."""
+    num = den_d = den_p = 0.0
+    Xt = torch.as_tensor(np.ascontiguousarray(X.T), device=x_fom[0].device).double()
+    for a, b in zip(x_rom, x_fom):
+        a = a.double()
+        b = b.double()
+        num += float(((a - b) ** 2).sum())
+        den_d += float(((b - Xt) ** 2).sum())
+        den_p += float((b ** 2).sum())
+    return (num / den_d) ** 0.5, 100.0 * (num / den_p) ** 0.5

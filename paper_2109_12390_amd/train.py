@@ -123,11 +123,11 @@ class SnapshotSet:
 
 
 def generate_snapshots(scene, instances, n_steps, every, n_sub, seed, sort_every=10,
-                       device="cuda"):
+                       affine=True, device="cuda"):
     """Runs the full-order model (mpm_step) for every (E, v0) instance from
     the scene's initial state and records frames every `every` steps
     (including the initial state) for a fixed random subset of n_sub
-    particles."""
+    particles.  affine=False drops the APIC affine term (PIC transfers)."""
     d = scene["dim"]
     P = scene["P"]
     rng = np.random.default_rng(seed)
@@ -152,7 +152,8 @@ def generate_snapshots(scene, instances, n_steps, every, n_sub, seed, sort_every
         for f in range(n_frames_per):
             if f > 0:
                 B.mpm_step(grid, (scene["model"], float(E), scene["nu"]), parts, scene["dt"], every,
-                           sort_every, 0, gbuf, ws, perm_accum=perm, status=flag)
+                           sort_every, 0 if affine else B.NO_AFFINE, gbuf, ws, perm_accum=perm,
+                           status=flag)
                 # slot -> entry index of this call; compose with the running map
                 inv = torch.empty_like(perm, dtype=torch.long)
                 inv[perm.long()] = torch.arange(P, device=device)

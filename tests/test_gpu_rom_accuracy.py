@@ -1,0 +1,89 @@
+"""The learned part end to end: the full-order model generates snapshots,
+the decoder is trained on them with the library's training kernels, the
+reduced-order model (Lagrangian quadrature, 256 sample points, position-
+velocity projection) runs from the least-squares initial state, and the
+full-order model judges it (displacement-relative error over the recorded
+frames).  The same reduced-order run with the untrained network (the
+initialisation the training starts from, same normalisation) is the method
+without the learned part.
+
+The reduced substep (Algorithm 5) transfers momentum without an affine
+term, so its reference is the full-order model with the same transfers
+(Algorithm 1 as printed: MR_NO_AFFINE); on this scene that model and the
+APIC one differ by about 15% of the displacement, which no reduced model
+of the former can close.  The error against the APIC model is printed.
+
+Scene: a 3D Neo-Hookean cube (8^3 cells, 4,096 particles) on a 32^3 grid,
+released just above the Coulomb floor with a downward and sideways
+velocity, so that contact compresses and shears it within the run.
+Penalty weights: the position term of this scene is ~7e-4 per particle
+(rms displacement 2.7e-2), the velocity one ~2.3 (rms velocity 1.5) and
+the gradient one ~6e-3; lam_F = 1 and lam_v = 1e-4 put the three on one
+scale (the paper's 100 and 0.01 were chosen for its own scenes' units)."""
+import numpy as np
+import pytest
+
+from paper_2109_12390_amd import binding as B
+from paper_2109_12390_amd import evaluate as EV
+from paper_2109_12390_amd import scenes
+from paper_2109_12390_amd import train as TR
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N_STEPS, RECORD = 300, 10
+
+
+def _scene():
+    n = 32
+    dx = 1.0 / n
+    return scenes.make_scene(3, n, (8, 8, 8), (0.375, 3.4 * dx, 0.375), 2, 1000.0, 5.0e4, 0.3,
+                             scenes.MODEL_NEO_HOOKEAN, (0.0, -9.8, 0.0), scenes.FLOOR_COULOMB,
+                             0.3, 3, 1.0e-4, 5)
+
+
+@pytest.fixture(scope="module")
+def fom_and_training(gpu):
+    s = _scene()
+    E, v0 = 5.0e4, (0.4, -1.5, 0.0)
+    fom = EV.fom_positions(s, E, v0, N_STEPS, RECORD, affine=False)
+    fom_apic = EV.fom_positions(s, E, v0, N_STEPS, RECORD, affine=True)
+    snap = TR.generate_snapshots(s, [(E, v0)], n_steps=N_STEPS, every=5, n_sub=s["P"], seed=1,
+                                 affine=False)
+    r, width, nh = 8, 64, 3
+    Ws, bs, Z, norm, hist = TR.train(snap, width=width, n_hidden=nh, r=r, steps=4000, n_groups=16,
+                                     rows_per_group=64, lr0=1e-2, lr1=1e-4, lam_F=1.0, lam_v=1e-4,
+                                     log_every=1000)
+    print("training objective on the evaluation batch", hist)
+    init = scenes.xavier_decoder(3, r, width, nh, 0)     # what train() starts from
+    # initial latent: projection of the rest configuration, started from the
+    # code the training gave the first frame (zero for the untrained network)
+    return s, E, v0, (fom, fom_apic), (Ws, bs, Z[0]), init + (None,), norm
+
+
+def _rom_error(s, E, v0, foms, weights, norm, prec):
+    Ws, bs, z_guess = weights
+    lo, hi, mean, std = norm
+    dec = B.Decoder(Ws, bs, lo, hi, mean, std, B.OUT_DISPLACEMENT, prec)
+    x_rom, st = EV.rom_positions(dec, s, E, v0, N_STEPS, RECORD, n_samples=256,
+                                 opts=B.gn_opts(mode=B.POS_VEL, max_iter=3), z_guess=z_guess)
+    dec.close()
+    return [EV.displacement_error(x_rom, f, s["X"]) for f in foms], st
+
+
+@pytest.mark.parametrize("prec", [B.PREC_FP32, B.PREC_BF16])
+def test_trained_decoder_beats_the_untrained_one(fom_and_training, prec):
+    s, E, v0, foms, trained, init, norm = fom_and_training
+    ((e_tr, p_tr), (e_tr_apic, _)), st_tr = _rom_error(s, E, v0, foms, trained, norm, prec)
+    ((e_un, p_un), _), st_un = _rom_error(s, E, v0, foms, init, norm, prec)
+    print("prec %d: displacement error trained %.3e (position %.4f%%), untrained %.3e "
+          "(position %.4f%%); trained vs the APIC full-order model %.3e; quadrature points %d, "
+          "active nodes %d" % (prec, e_tr, p_tr, e_un, p_un, e_tr_apic,
+                               st_tr["n_quadrature_points"], st_tr["n_active_nodes"]))
+    # measured: trained ~0.20 in fp32 and bf16; untrained ~1.06 (fp32) and
+    # 0.55-0.72 (bf16, whose rounding perturbs the random network); training
+    # on this small set is not deterministic (atomic gradient sums), so the
+    # bounds leave room for its spread
+    assert np.isfinite(e_tr) and np.isfinite(e_un)
+    assert e_tr < 0.5 * e_un
+    assert e_tr < 0.3
