@@ -336,6 +336,19 @@ __global__ void gather_plane_kernel(const float *src, float *dst, const int32_t 
 // padded region layout (row stride 12 / 24 float4) keeps the 16 lanes of a
 // LDS cycle on distinct banks.
 
+// tiles (one wave each) per workgroup of the tile kernels
+#ifndef MR_TILE_WPB
+#define MR_TILE_WPB 1
+#endif
+#ifndef MR_TILE_PREFETCH
+#define MR_TILE_PREFETCH 0
+#endif
+// per-node ordering of the scatter arithmetic and row-wise G2P gathering:
+// fewer live registers in exchange for less instruction-level overlap
+#ifndef MR_TILE_ORDERED
+#define MR_TILE_ORDERED 0
+#endif
+
 template <int D>
 struct CellTile {
     static constexpr int TS = Tiling<D>::TS;        // cells per tile edge
@@ -345,7 +358,7 @@ struct CellTile {
     static constexpr int SZ = (D == 3) ? SY * R : 0;
     static constexpr int RNP = (D == 3) ? SZ * R : SY * R;
     static constexpr int RCN = (D == 3) ? RC * RC * RC : RC * RC;
-    static constexpr int WPB = 4;                   // waves (tiles) per workgroup
+    static constexpr int WPB = MR_TILE_WPB;         // waves (tiles) per workgroup
 };
 
 __device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
@@ -356,7 +369,7 @@ __device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
 #endif
 
 template <int D, bool FUSED>
-__global__ void __launch_bounds__(256, MR_TILE_MIN_WAVES) tile_scatter_kernel(
+__global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scatter_kernel(
     GridK g, TileGeom tg, float *x, float *v, float *C, float *F, const float *m, const float *V0,
     float m_u, float V0_u, int64_t n, const int32_t *offsets, const int32_t *counts, int apic,
     int model, float mu, float la, float dt, const float *grid_in, float *grid_out, float *v_out,
@@ -388,12 +401,42 @@ __global__ void __launch_bounds__(256, MR_TILE_MIN_WAVES) tile_scatter_kernel(
     const float4 *gin4 = reinterpret_cast<const float4 *>(grid_in);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int64_t base = c0;
+    // fused: the next slot's x and F are loaded while the current slot is
+    // processed (slot k + 1 of a lane exists iff k + 1 < cnt, so its index is
+    // known one slot ahead)
+    float pre_x[FUSED && MR_TILE_PREFETCH ? D : 1], pre_F[FUSED && MR_TILE_PREFETCH ? D * D : 1];
+    if (FUSED && MR_TILE_PREFETCH) {
+        const uint64_t m0k = __ballot(0 < cnt);
+        if (0 < cnt) {
+            const int64_t p0 = base + __popcll(m0k & below);
+#pragma unroll
+            for (int a = 0; a < D; ++a) pre_x[a] = x[a * n + p0];
+#pragma unroll
+            for (int q = 0; q < D * D; ++q) pre_F[q] = F[q * n + p0];
+        }
+    }
     for (int k = 0;; ++k) {
         const bool act = k < cnt;
         const uint64_t mask = __ballot(act);
         if (mask == 0) break;
         const int64_t p = base + __popcll(mask & below);
         base += __popcll(mask);
+        float cur_x[FUSED && MR_TILE_PREFETCH ? D : 1], cur_F[FUSED && MR_TILE_PREFETCH ? D * D : 1];
+        if (FUSED && MR_TILE_PREFETCH) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) cur_x[a] = pre_x[a];
+#pragma unroll
+            for (int q = 0; q < D * D; ++q) cur_F[q] = pre_F[q];
+            const bool act1 = k + 1 < cnt;
+            const uint64_t mask1 = __ballot(act1);
+            if (act1) {
+                const int64_t p1 = base + __popcll(mask1 & below);
+#pragma unroll
+                for (int a = 0; a < D; ++a) pre_x[a] = x[a * n + p1];
+#pragma unroll
+                for (int q = 0; q < D * D; ++q) pre_F[q] = F[q * n + p1];
+            }
+        }
         bool scat = false, inreg = false;
         Stencil<D> sn;
         P2GPayload<D> pl;
@@ -403,18 +446,27 @@ __global__ void __launch_bounds__(256, MR_TILE_MIN_WAVES) tile_scatter_kernel(
             bool ok = true;
             if (FUSED) {
                 float xp[D], Fp[D * D];
+                if (MR_TILE_PREFETCH) {
 #pragma unroll
-                for (int a = 0; a < D; ++a) xp[a] = x[a * n + p];
+                    for (int a = 0; a < D; ++a) xp[a] = cur_x[a];
 #pragma unroll
-                for (int q = 0; q < D * D; ++q) Fp[q] = F[q * n + p];
+                    for (int q = 0; q < D * D; ++q) Fp[q] = cur_F[q];
+                } else {
+#pragma unroll
+                    for (int a = 0; a < D; ++a) xp[a] = x[a * n + p];
+#pragma unroll
+                    for (int q = 0; q < D * D; ++q) Fp[q] = F[q * n + p];
+                }
                 Stencil<D> so;
                 ok = make_stencil<D>(g, xp, so);
                 if (ok) {
                     float Bp[D * D], gv[D * D];
-                    g2p_separable<D>(g, so, [&](int o0, int o1, int o2) {
+                    auto fetch = [&](int o0, int o1, int o2) {
                         return gin4[node_lin(g, so.base[0] + o0, so.base[1] + o1,
                                              D == 3 ? so.base[2] + o2 : 0)];
-                    }, vp, Bp, gv);
+                    };
+                    g2p_separable<D, decltype(fetch) &, MR_TILE_ORDERED != 0>(g, so, fetch, vp, Bp,
+                                                                             gv);
                     mr::update_F<D>(gv, Fp, dt, Fn);
 #pragma unroll
                     for (int q = 0; q < D * D; ++q) Cp[q] = cscale * Bp[q];
@@ -484,8 +536,7 @@ __global__ void __launch_bounds__(256, MR_TILE_MIN_WAVES) tile_scatter_kernel(
                 lds_order();
             }
             if (go) {
-                p2g_separable<D>(g, sn, pl, [&](int o0, int o1, int o2, float mw, float q0,
-                                                 float q1, float q2) {
+                auto rmw = [&](int o0, int o1, int o2, float mw, float q0, float q1, float q2) {
                     float4 *a4 = acc + nb + o0 + CT::SY * o1 + (D == 3 ? CT::SZ * o2 : 0);
                     float4 q = *a4;
                     q.x += mw;
@@ -494,7 +545,8 @@ __global__ void __launch_bounds__(256, MR_TILE_MIN_WAVES) tile_scatter_kernel(
                     q.w += q2;
                     *a4 = q;
                     lds_order();
-                });
+                };
+                p2g_separable<D, decltype(rmw) &, MR_TILE_ORDERED != 0>(g, sn, pl, rmw);
                 pending = false;
             }
         }
@@ -714,7 +766,7 @@ int32_t p2g_impl(const GridK &g, const mr_material *mat, const mr_particles *par
         sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
         TileGeom tg = tile_geom<D>(g);
         if (tg.ntiles > 0)
-            tile_scatter_kernel<D, false><<<(unsigned)ceil_div(tg.ntiles, CellTile<D>::WPB), 256, 0, st>>>(
+            tile_scatter_kernel<D, false><<<(unsigned)ceil_div(tg.ntiles, CellTile<D>::WPB), 64 * CellTile<D>::WPB, 0, st>>>(
                 g, tg, parts->x, parts->v, parts->C, parts->F, parts->m, parts->V0, parts->m_uniform,
                 parts->V0_uniform, parts->n, ws.offsets, ws.counts, apic, mat->model, lm.mu, lm.la, dt,
                 nullptr, grid, nullptr, nullptr, flag);
@@ -894,7 +946,7 @@ int32_t g2p2g_impl(const GridK &g, const mr_material *mat, mr_particles *parts, 
     sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
     TileGeom tg = tile_geom<D>(g);
     if (tg.ntiles > 0 && parts->n > 0)
-        tile_scatter_kernel<D, true><<<(unsigned)ceil_div(tg.ntiles, CellTile<D>::WPB), 256, 0, st>>>(
+        tile_scatter_kernel<D, true><<<(unsigned)ceil_div(tg.ntiles, CellTile<D>::WPB), 64 * CellTile<D>::WPB, 0, st>>>(
             g, tg, parts->x, parts->v, parts->C, parts->F, parts->m, parts->V0, parts->m_uniform,
             parts->V0_uniform, parts->n, ws.offsets, ws.counts, apic, mat->model, lm.mu, lm.la, dt,
             grid_in, grid_out, v_out, C_out, flag);

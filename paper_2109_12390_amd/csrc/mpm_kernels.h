@@ -195,7 +195,11 @@ __device__ __forceinline__ float p2g_node(const GridK &g, const Stencil<D> &st,
 //   Bx = wy wz mC[:,0],  Sx = wy wz S[:,0],
 // so the (o1, o2) part is formed once per row instead of once per node.
 // sink(o0, o1, o2, m, mom0, mom1, mom2) receives each node's contribution.
-template <int D, typename Sink>
+// ORDERED: each node's arithmetic is pinned after the previous node's sink
+// (an empty asm that claims to modify the row factors), so that a sink with
+// ordered memory side effects does not make the compiler precompute all 3^d
+// contributions into registers ahead of them.
+template <int D, typename Sink, bool ORDERED = false>
 __device__ __forceinline__ void p2g_separable(const GridK &g, const Stencil<D> &st,
                                               const P2GPayload<D> &pl, Sink &&sink)
 {
@@ -234,6 +238,13 @@ __device__ __forceinline__ void p2g_separable(const GridK &g, const Stencil<D> &
 #pragma unroll
                 for (int a = 0; a < D; ++a) mom[a] = wx * (A[a] + Bx[a] * dx0[o0]) - Sx[a] * dwx;
                 sink(o0, o1, o2, myz * wx, mom[0], mom[1], mom[2]);
+                if (ORDERED) {
+                    if (D == 3)
+                        asm volatile("" : "+v"(A[0]), "+v"(A[D - 2]), "+v"(A[D - 1]),
+                                          "+v"(Bx[0]), "+v"(Bx[D - 2]), "+v"(Bx[D - 1]));
+                    else
+                        asm volatile("" : "+v"(A[0]), "+v"(A[D - 1]), "+v"(Bx[0]), "+v"(Bx[D - 1]));
+                }
             }
         }
     }
