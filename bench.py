@@ -217,7 +217,8 @@ def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden
     E = torch.tensor([s["E"]], dtype=torch.float32, device=dev)
     ns = torch.tensor([n_samples], dtype=torch.int32, device=dev)
     rom = B.Rom(dec, grid, Xg, E, ns, B.gn_opts(mode=B.POS_VEL, max_iter=3), seed=4, rho0=1000.0,
-                m_uniform=float(s["m"]))
+                m_uniform=float(s["m"]), autotune=True)
+    shapes = decoder_shapes(dec, 1, P, n_samples)
     z = torch.zeros(1, r, dtype=torch.float64, device=dev)
     zp = z.clone()
     vh = torch.zeros(1, r, dtype=torch.float64, device=dev)
@@ -240,6 +241,7 @@ def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden
     dec.close()
     times = np.array(times)
     return {"metric": "ROM latent steps/s", "value": float(1e3 / times.mean()), "unit": "latent steps/s",
+            "decoder_shapes": shapes,
             "ms_per_step": float(times.mean()), "p50_ms": float(np.percentile(times, 50)),
             "p99_ms": float(np.percentile(times, 99)), "steps": int(n_rep * k),
             "n_quadrature_points": int(n_quad), "n_active_nodes": int(n_active),
@@ -248,6 +250,17 @@ def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden
                        "projection": "position-velocity, 3 Gauss-Newton iterations",
                        "graph": "HIP graph of %d steps" % k},
             "displacement_error": None}
+
+
+SHAPE_NAMES = ["1 point tile per wave", "2 point tiles per wave", "4 point tiles per wave",
+               "units split over a block"]
+
+
+def decoder_shapes(dec, n_inst, P, n_samples):
+    """Autotuned decoder launch shapes of a reduced-order step's launches."""
+    return {"all particles (positions)": SHAPE_NAMES[dec.shape(1, n_inst, P)],
+            "samples (latent Jacobian)": SHAPE_NAMES[dec.shape(9, n_inst, n_samples)],
+            "line-search candidates": SHAPE_NAMES[dec.shape(1, n_inst * 9, n_samples)]}
 
 
 def rom_batched_throughput(B, scenes, s, n_inst, steps, r=16, width=128, n_hidden=5):
@@ -274,7 +287,8 @@ def rom_batched_throughput(B, scenes, s, n_inst, steps, r=16, width=128, n_hidde
     E = torch.tensor(Es.astype(np.float32), device=dev)
     nst = torch.tensor(ns, device=dev)
     rom = B.Rom(dec, grid, Xg, E, nst, B.gn_opts(mode=B.POS_VEL, max_iter=3), seed=5, rho0=1000.0,
-                m_uniform=float(s["m"]))
+                m_uniform=float(s["m"]), autotune=True)
+    shapes = decoder_shapes(dec, n_inst, P, int(ns.max()))
     z = torch.zeros(n_inst, r, dtype=torch.float64, device=dev)
     zp = z.clone()
     vh = torch.tensor(1e-2 * rng.standard_normal((n_inst, r)), device=dev)
@@ -295,6 +309,7 @@ def rom_batched_throughput(B, scenes, s, n_inst, steps, r=16, width=128, n_hidde
     dec.close()
     times = np.array(times)
     return {"metric": "ROM latent steps/s (all instances)", "value": float(n_inst * 1e3 / times.mean()),
+            "decoder_shapes": shapes,
             "unit": "latent steps/s", "ms_per_batched_step": float(times.mean()),
             "p50_ms": float(np.percentile(times, 50)), "p99_ms": float(np.percentile(times, 99)),
             "steps": int(steps), "quadrature_points_sampled_instances": [int(v) for v in q],

@@ -242,6 +242,28 @@ int32_t rom_decoder_create(int32_t d, int32_t r, int32_t width,
                            mr_decoder **out);
 void rom_decoder_destroy(mr_decoder *dec);
 
+/* Launch-shape autotuner.  The decoder kernels have several shapes per
+ * stream configuration (cfg 1: positions only; 5: positions, F and v;
+ * 9: positions and eight latent-Jacobian columns): waves splitting the
+ * points (one, two or four 16-point tiles per wave) or the waves of a block
+ * splitting a layer's units for a shared tile of 16 points (small point
+ * sets).  rom_decoder_autotune times each shape of every configuration in
+ * cfg_mask (bit 0: cfg 1, bit 1: cfg 5, bit 2: cfg 9) on B instances of n
+ * points (capped at 2^22 points, 2^20 for cfg 9, with one instance), `reps`
+ * launches each, and records the fastest for that size class
+ * (floor(log2(B n))) in the decoder.  Untuned size classes use the nearest
+ * tuned class within a factor of 4, else row splitting up to 8192 points.
+ * Every shape computes identical results.  Synchronous on `stream`;
+ * allocates and frees scratch.  Returns MR_EINVAL for B < 1, n < 1,
+ * reps < 1 or unknown mask bits. */
+int32_t rom_decoder_autotune(mr_decoder *dec, int32_t B, int64_t n,
+                             int32_t cfg_mask, int32_t reps, void *stream);
+
+/* Shape a launch of configuration cfg (1, 5 or 9) on B instances of n
+ * points would use: 0 points split one tile per wave, 1 two tiles, 2 four
+ * tiles, 3 units split across the waves of a block; negative on error. */
+int32_t rom_decoder_shape(const mr_decoder *dec, int32_t cfg, int32_t B, int64_t n);
+
 /* Replaces the parameters of an existing decoder (same shapes); params is a
  * device or host pointer as flagged by `params_on_device`.  Stream-ordered
  * when on device. */
@@ -328,14 +350,20 @@ typedef struct {
     float m_uniform;         /* particle mass when m_all is NULL             */
     int32_t model;           /* constitutive model                           */
     float nu;                /* Poisson ratio (shared)                       */
-    int32_t sort_quadrature; /* non-zero: cell-sort the quadrature points    */
+    int32_t autotune;        /* non-zero: rom_create times the decoder's
+                                launch shapes at this runner's sizes
+                                (rom_decoder_autotune) before returning   */
 } mr_rom_config;
 
 /* Creates the reduced-order model runner.  X_all: device SoA [d][P] reference
  * positions; m_all (nullable) device masses; E: device float32 [B] Young's
  * moduli; n_samples: device int32 [B] sample counts (r/d <= count <=
- * n_samples_max).  The decoder, grid and option structs are copied.
- * Allocates all workspace up front (synchronous). */
+ * n_samples_max).  The grid and option structs are copied; the decoder is
+ * referenced and must outlive the runner.  Allocates all workspace up front
+ * (synchronous).  With cfg->autotune set, the decoder's launch shapes are
+ * tuned for the runner's four decoder launches (all particles, the
+ * quadrature list, the samples, the line-search candidates), which updates
+ * the decoder's shape table. */
 int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
                    const mr_rom_config *cfg, const float *X_all,
                    const float *m_all, const float *E,

@@ -62,7 +62,7 @@ class MrRomConfig(ctypes.Structure):
                 ("n_samples_max", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("rho0", ctypes.c_float), ("m_uniform", ctypes.c_float),
                 ("model", ctypes.c_int32), ("nu", ctypes.c_float),
-                ("sort_quadrature", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -96,6 +96,8 @@ SIGNATURES = {
                                   ctypes.POINTER(_vp)]),
     "rom_decoder_destroy": (None, [_vp]),
     "rom_decoder_set_params": (_i32, [_vp, _vp, _i32, _vp]),
+    "rom_decoder_autotune": (_i32, [_vp, _i32, _i64, _i32, _i32, _vp]),
+    "rom_decoder_shape": (_i32, [_vp, _i32, _i32, _i64]),
     "rom_decode": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _vp, _vp, _vp]),
     "rom_decode_jac": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                               _vp, _vp]),
@@ -369,6 +371,16 @@ class Decoder:
         _check("rom_decoder_set_params", load().rom_decoder_set_params(
             self.handle, _ptr(params, torch.float32), 1, _stream(stream)))
 
+    def autotune(self, B, n, cfg_mask=7, reps=3, stream=None):
+        """Times the decoder's launch shapes at B instances of n points
+        (rom_decoder_autotune) and records the fastest in the decoder."""
+        _check("rom_decoder_autotune", load().rom_decoder_autotune(self.handle, B, n, cfg_mask, reps,
+                                                                   _stream(stream)))
+
+    def shape(self, cfg, B, n):
+        """Launch shape a configuration (1, 5 or 9) uses at B x n points."""
+        return int(load().rom_decoder_shape(self.handle, cfg, B, n))
+
     def close(self):
         if self.handle:
             load().rom_decoder_destroy(self.handle)
@@ -423,12 +435,12 @@ class Rom:
     """Owns an mr_rom handle (rom_create / rom_destroy)."""
 
     def __init__(self, dec, grid, X_all, E, n_samples, opts, seed, rho0, m_uniform=0.0,
-                 m_all=None, model=NEO_HOOKEAN, nu=0.3):
+                 m_all=None, model=NEO_HOOKEAN, nu=0.3, autotune=False):
         lib = load()
         self.dec = dec
         self.B = E.numel()
         cfg = MrRomConfig(self.B, X_all.shape[1], int(n_samples.max().item()), seed, rho0,
-                          m_uniform, model, nu, 0)
+                          m_uniform, model, nu, 1 if autotune else 0)
         self.opts = opts
         h = ctypes.c_void_p()
         _check("rom_create", lib.rom_create(dec.handle, ctypes.byref(grid.c()), ctypes.byref(cfg),

@@ -25,8 +25,15 @@
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// launch shapes of the decoder kernels (see launch_w)
+enum DecVariant { DEC_COL = 0, DEC_COL_NP2 = 1, DEC_COL_NP4 = 2, DEC_ROWS = 3, DEC_NVARIANT = 4 };
+constexpr int DEC_BUCKETS = 32;   // size classes: floor(log2(instances x points))
+
 struct mr_decoder {
     int d, r, width, W, nh, mode, prec;
+    // autotuned shape per stream configuration (1, 5, 9) and size class;
+    // -1: not tuned (a size rule applies)
+    mutable int8_t tuned[3][DEC_BUCKETS];
     float *dev;          // padded fp32 parameters (one allocation)
     uint16_t *hid_bf16;  // hidden weights in bf16, (nh - 1) x W x W
     size_t n_params;     // unpadded parameter count
@@ -145,6 +152,38 @@ __device__ __forceinline__ f32x4 mfma_step(const uint16_t *Arow, const uint16_t 
     bf16x8 a = *reinterpret_cast<const bf16x8 *>(Arow + 8 * g);
     bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bcol + 8 * g);
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+}
+
+// Output of one (point s, stream st, component a) of instance b, from the
+// last layer's dot product y = W_L[a] . h: the position (plus b_L, the
+// output scaling and, in displacement mode, X), a column of F = dg/dX, the
+// velocity, or a latent-Jacobian entry.
+__device__ __forceinline__ void emit_output(const DecK &P, const StreamSpec &ss, const DecIO &io,
+                                            int b, int64_t s, int st, int a, float y)
+{
+    const int D = P.d;
+    const int kind = ss.kind[st], arg = ss.arg[st];
+    const int64_t n = io.n;
+    const size_t bo = (size_t)b;
+    if (kind == SK_PRIMAL) {
+        if (io.x) {
+            float val = P.mean[a] + P.stdv[a] * (y + P.bL[a]);
+            if (P.mode == MR_OUT_DISPLACEMENT && !io.disp_only) {
+                int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * n : 0) + s] : s;
+                val += io.X[a * io.n_ref + row];
+            }
+            io.x[(bo * D + a) * n + s] = val;
+        }
+    } else if (kind == SK_SPATIAL) {
+        if (io.F) {
+            float val = P.stdv[a] * y + ((P.mode == MR_OUT_DISPLACEMENT && a == arg) ? 1.0f : 0.0f);
+            io.F[(bo * D * D + a * D + arg) * n + s] = val;
+        }
+    } else if (kind == SK_VELOCITY) {
+        if (io.v) io.v[(bo * D + a) * n + s] = P.stdv[a] * y;
+    } else if (kind == SK_LATENT) {
+        if (io.Jz) io.Jz[(bo * D * P.r + (size_t)a * P.r + arg) * n + s] = P.stdv[a] * y;
+    }
 }
 
 // launch shapes: point tiles per wave of the primal-only evaluation, and
@@ -382,28 +421,154 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
             const f32x4 h4 = E::load4(h + i);
             y += wl[i] * h4[0] + wl[i + 1] * h4[1] + wl[i + 2] * h4[2] + wl[i + 3] * h4[3];
         }
-        int kind = ss.kind[st], arg = ss.arg[st];
-        const int64_t n = io.n;
-        const size_t bo = (size_t)b;
-        if (kind == SK_PRIMAL) {
-            if (io.x) {
-                float val = P.mean[a] + P.stdv[a] * (y + P.bL[a]);
-                if (P.mode == MR_OUT_DISPLACEMENT && !io.disp_only) {
-                    int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * n : 0) + s] : s;
-                    val += io.X[a * io.n_ref + row];
-                }
-                io.x[(bo * D + a) * n + s] = val;
-            }
-        } else if (kind == SK_SPATIAL) {
-            if (io.F) {
-                float val = P.stdv[a] * y + ((P.mode == MR_OUT_DISPLACEMENT && a == arg) ? 1.0f : 0.0f);
-                io.F[(bo * D * D + a * D + arg) * n + s] = val;
-            }
-        } else if (kind == SK_VELOCITY) {
-            if (io.v) io.v[(bo * D + a) * n + s] = P.stdv[a] * y;
-        } else if (kind == SK_LATENT) {
-            if (io.Jz) io.Jz[(bo * D * P.r + (size_t)a * P.r + arg) * n + s] = P.stdv[a] * y;
+        emit_output(P, ss, io, b, s, st, a, y);
+    }
+}
+
+
+// Row-split shape, for small point sets: a block of W/16 waves evaluates one
+// tile of 16 points with all S streams; wave w owns output units
+// 16 w .. 16 w + 15 of every layer, the activation panel is shared by the
+// block (double-buffered) and the layer's weights are staged once per block.
+// The per-element arithmetic and its order are those of decoder_kernel, so
+// both shapes give identical results.
+template <typename T, int W, int S>
+__global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, StreamSpec ss,
+                                                                     DecIO io)
+{
+    using E = Elem<T>;
+    using SM = DecSmem<T, W>;
+    constexpr int NW = W / 16;           // waves = row tiles
+    constexpr int COLS = S * 16;
+    constexpr int LD = W + E::PAD;
+    constexpr int NKS = W / E::KS;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    const int b = blockIdx.y;
+    const int64_t n_b = io.n_inst ? (int64_t)io.n_inst[b] : io.n;
+    const int64_t s0 = (int64_t)blockIdx.x * 16;
+    if (s0 >= n_b) return;                                  // block-uniform
+    float *c0 = reinterpret_cast<float *>(smem);
+    float *u = c0 + W;
+    T *wsh = reinterpret_cast<T *>(smem + 2 * W * sizeof(float));
+    T *pin = reinterpret_cast<T *>(smem + SM::fixed);
+    T *pout = pin + COLS * LD;
+    const double *xh = io.xhat + (size_t)b * P.r;
+    const double *vh = io.vhat ? io.vhat + (size_t)b * P.r : nullptr;
+    for (int i = threadIdx.x; i < W; i += 64 * NW) {
+        double a0 = P.b0[i], a1 = 0.0;
+        for (int k = 0; k < P.r; ++k) {
+            double w = P.W0[(size_t)i * (P.d + P.r) + P.d + k];
+            a0 += w * xh[k];
+            if (vh) a1 += w * vh[k];
         }
+        c0[i] = (float)a0;
+        u[i] = (float)a1;
+    }
+    __syncthreads();
+    // first layer: this wave's 16 units for the tile's 16 points
+    const int in0 = P.d + P.r;
+    const int i0 = 16 * wave + 4 * g;
+    {
+        const int64_t s = s0 + j;
+        float Xn[3] = {0.0f, 0.0f, 0.0f};
+        if (s < n_b) {
+            int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * io.n : 0) + s] : s;
+            for (int a = 0; a < P.d; ++a) Xn[a] = io.X[a * io.n_ref + row] * P.scale[a] + P.shift[a];
+        }
+        f32x4 h4, e4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float *w0 = P.W0 + (size_t)(i0 + q) * in0;
+            float z = c0[i0 + q];
+            for (int a = 0; a < P.d; ++a) z += w0[a] * Xn[a];
+            float h, e;
+            E::act(z, h, e);
+            h4[q] = h;
+            e4[q] = e;
+        }
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+            const int kind = ss.kind[st], arg = ss.arg[st];
+            f32x4 val;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float *w0 = P.W0 + (size_t)(i0 + q) * in0;
+                if (kind == SK_PRIMAL) val[q] = h4[q];
+                else if (kind == SK_SPATIAL) val[q] = e4[q] * w0[arg] * P.scale[arg];
+                else if (kind == SK_VELOCITY) val[q] = e4[q] * u[i0 + q];
+                else if (kind == SK_LATENT) val[q] = e4[q] * w0[P.d + arg];
+                else val[q] = 0.0f;
+            }
+            E::store4(pin + (st * 16 + j) * LD + i0, val);
+        }
+    }
+    __syncthreads();
+    // hidden layers
+    for (int l = 0; l < P.nh - 1; ++l) {
+        const T *Wl;
+        int lda = W;
+        if constexpr (SM::WLDS) {
+            const T *src = reinterpret_cast<const T *>(P.Whb) + (size_t)l * W * W;
+            constexpr int V = W / 8;
+            for (int t = threadIdx.x; t < W * V; t += 64 * NW) {
+                const int row = t / V, c8 = t % V;
+                *reinterpret_cast<uint4 *>(wsh + row * LD + 8 * c8) =
+                    reinterpret_cast<const uint4 *>(src)[t];
+            }
+            __syncthreads();
+            Wl = wsh;
+            lda = LD;
+        } else {
+            Wl = reinterpret_cast<const T *>(P.Wh) + (size_t)l * W * W;
+        }
+        const float *bl = P.bh + (size_t)l * W;
+        f32x4 acc[S];
+#pragma unroll
+        for (int ct = 0; ct < S; ++ct) acc[ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        const T *Arow = Wl + (size_t)(16 * wave + j) * lda;
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+            for (int ct = 0; ct < S; ++ct)
+                acc[ct] = mfma_step(Arow + ks * E::KS, pin + (ct * 16 + j) * LD + ks * E::KS,
+                                    acc[ct], lane);
+        f32x4 b4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b4[q] = bl[i0 + q];
+        f32x4 h4, e4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float h, e;
+            E::act(acc[0][q] + b4[q], h, e);
+            h4[q] = h;
+            e4[q] = e;
+        }
+        E::store4(pout + j * LD + i0, h4);
+#pragma unroll
+        for (int st = 1; st < S; ++st) E::store4(pout + (st * 16 + j) * LD + i0, e4 * acc[st]);
+        __syncthreads();   // the new panel is complete; the old one and the weights are free
+        T *tmp = pin;
+        pin = pout;
+        pout = tmp;
+    }
+    // output layer
+    const int D = P.d;
+    for (int it = threadIdx.x; it < COLS * D; it += 64 * NW) {
+        const int col = it / D, a = it % D;
+        const int st = col >> 4, jj = col & 15;
+        const int64_t s = s0 + jj;
+        if (s >= n_b) continue;
+        const T *h = pin + (size_t)col * LD;
+        const float *wl = P.WL + (size_t)a * W;
+        float y = 0.0f;
+        for (int i = 0; i < W; i += 4) {
+            const f32x4 h4 = E::load4(h + i);
+            y += wl[i] * h4[0] + wl[i + 1] * h4[1] + wl[i + 2] * h4[2] + wl[i + 3] * h4[3];
+        }
+        emit_output(P, ss, io, b, s, st, a, y);
     }
 }
 
@@ -439,16 +604,50 @@ constexpr int dec_wpb(int cap)
     return w < cap ? w : cap;
 }
 
+template <typename T, int W, int S>
+int32_t launch_rows(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStream_t st)
+{
+    constexpr size_t lds = DecSmem<T, W>::fixed + 2 * (size_t)S * 16 * (W + Elem<T>::PAD) * sizeof(T);
+    static_assert(lds <= 160 * 1024, "decoder block does not fit the LDS of a compute unit");
+    dim3 grid((unsigned)ceil_div(io.n, 16), (unsigned)io.B);
+    auto kern = decoder_rows_kernel<T, W, S>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        MR_CHECK_HIP(hipFuncSetAttribute((const void *)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    kern<<<grid, 64 * (W / 16), lds, st>>>(P, ss, io);
+    MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
+// Launch shapes per stream configuration (1: primal only, 5: x, F, v;
+// 9: x and 8 latent-Jacobian columns):
+//   DEC_COL      one or more point tiles per wave, waves split the points
+//   DEC_COL_NP2  two point tiles per wave (primal only)
+//   DEC_COL_NP4  four point tiles per wave (primal only)
+//   DEC_ROWS     waves of a block split a layer's units (small point sets)
 template <typename T, int W>
-int32_t launch_w(int cfg, const DecK &P, const StreamSpec &ss, const DecIO &io, hipStream_t st)
+int32_t launch_w(int cfg, int variant, const DecK &P, const StreamSpec &ss, const DecIO &io,
+                 hipStream_t st)
 {
     constexpr int NP1 = MR_DEC_PRIMAL_NP;
     constexpr bool DB1 = MR_DEC_PRIMAL_DB, DB5 = MR_DEC_TANGENT_DB;
-    if (cfg == 1)
+    if (cfg == 1) {
+        if (variant == DEC_ROWS) return launch_rows<T, W, 1>(P, ss, io, st);
+        if (variant == DEC_COL_NP2)
+            return launch_one<T, W, 1, 2, false, dec_wpb<T, W, 1, 2, false>(12)>(P, ss, io, st);
+        if (variant == DEC_COL_NP4)
+            return launch_one<T, W, 1, 4, false, dec_wpb<T, W, 1, 4, false>(6)>(P, ss, io, st);
         return launch_one<T, W, 1, NP1, DB1, dec_wpb<T, W, 1, NP1, DB1>(MR_DEC_PRIMAL_WPB)>(P, ss, io,
                                                                                           st);
-    if (cfg == 5)
+    }
+    if (cfg == 5) {
+        if (variant == DEC_ROWS) return launch_rows<T, W, 5>(P, ss, io, st);
         return launch_one<T, W, 5, 1, DB5, dec_wpb<T, W, 5, 1, DB5>(MR_DEC_TANGENT_WPB)>(P, ss, io, st);
+    }
+    if (variant == DEC_ROWS) return launch_rows<T, W, 9>(P, ss, io, st);
     return launch_one<T, W, 9, 1, true, dec_wpb<T, W, 9, 1, true>(4)>(P, ss, io, st);
 }
 
@@ -496,8 +695,31 @@ __global__ void linear_decoder_kernel(DecK P, DecIO io)
     }
 }
 
+inline int cfg_index(int cfg) { return cfg == 1 ? 0 : (cfg == 5 ? 1 : 2); }
+
+// size class of a launch: floor(log2(instances x points))
+inline int size_bucket(int64_t pts)
+{
+    int b = 0;
+    while (b < DEC_BUCKETS - 1 && ((int64_t)2 << b) <= pts) ++b;
+    return b;
+}
+
+// Shape for a launch: the autotuned choice of the nearest tuned size class
+// (within a factor 4), else the size rule (row split below 8192 points).
+int dec_variant(const mr_decoder *dec, int cfg, int64_t pts)
+{
+    const int ci = cfg_index(cfg), bk = size_bucket(pts);
+    for (int dist = 0; dist <= 2; ++dist)
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const int q = bk + sgn * dist;
+            if (q >= 0 && q < DEC_BUCKETS && dec->tuned[ci][q] >= 0) return dec->tuned[ci][q];
+        }
+    return pts <= 8192 ? DEC_ROWS : DEC_COL;
+}
+
 int32_t launch_cfg(const mr_decoder *dec, int cfg, const StreamSpec &ss, const DecIO &io,
-                   hipStream_t st)
+                   hipStream_t st, int variant_override = -1)
 {
     DecK P;
     P.d = dec->d;
@@ -524,12 +746,14 @@ int32_t launch_cfg(const mr_decoder *dec, int cfg, const StreamSpec &ss, const D
         MR_LAUNCH_CHECK();
         return MR_OK;
     }
-    bool bf = dec->prec == MR_PREC_BF16;
+    const int variant = variant_override >= 0 ? variant_override
+                                              : dec_variant(dec, cfg, (int64_t)io.B * io.n);
+    const bool bf = dec->prec == MR_PREC_BF16;
     switch (dec->W) {
-    case 16: return bf ? launch_w<uint16_t, 16>(cfg, P, ss, io, st) : launch_w<float, 16>(cfg, P, ss, io, st);
-    case 32: return bf ? launch_w<uint16_t, 32>(cfg, P, ss, io, st) : launch_w<float, 32>(cfg, P, ss, io, st);
-    case 64: return bf ? launch_w<uint16_t, 64>(cfg, P, ss, io, st) : launch_w<float, 64>(cfg, P, ss, io, st);
-    case 128: return bf ? launch_w<uint16_t, 128>(cfg, P, ss, io, st) : launch_w<float, 128>(cfg, P, ss, io, st);
+    case 16: return bf ? launch_w<uint16_t, 16>(cfg, variant, P, ss, io, st) : launch_w<float, 16>(cfg, variant, P, ss, io, st);
+    case 32: return bf ? launch_w<uint16_t, 32>(cfg, variant, P, ss, io, st) : launch_w<float, 32>(cfg, variant, P, ss, io, st);
+    case 64: return bf ? launch_w<uint16_t, 64>(cfg, variant, P, ss, io, st) : launch_w<float, 64>(cfg, variant, P, ss, io, st);
+    case 128: return bf ? launch_w<uint16_t, 128>(cfg, variant, P, ss, io, st) : launch_w<float, 128>(cfg, variant, P, ss, io, st);
     default: return MR_EINVAL;
     }
 }
@@ -632,6 +856,127 @@ extern "C" int32_t rom_decoder_set_params(mr_decoder *dec, const float *params,
     return MR_OK;
 }
 
+namespace mr {
+
+// stream specification of a configuration as decode_jac_ex builds it
+static StreamSpec spec_of(int cfg, int d)
+{
+    StreamSpec ss{};
+    ss.kind[0] = SK_PRIMAL;
+    if (cfg == 5) {
+        for (int a = 0; a < 3; ++a) {
+            ss.kind[1 + a] = a < d ? SK_SPATIAL : SK_ZERO;
+            ss.arg[1 + a] = a;
+        }
+        ss.kind[4] = SK_VELOCITY;
+    } else if (cfg == 9) {
+        for (int q = 0; q < 8; ++q) {
+            ss.kind[1 + q] = SK_LATENT;
+            ss.arg[1 + q] = q;
+        }
+    }
+    return ss;
+}
+
+int32_t decoder_autotune(const mr_decoder *dec, int32_t B, int64_t n, int32_t cfg_mask,
+                         int32_t reps, hipStream_t st)
+{
+    if (!dec || B < 1 || n < 1 || reps < 1 || (cfg_mask & ~7)) return MR_EINVAL;
+    if (dec->nh == 0) return MR_OK;   // the linear decoder has one shape
+    const int d = dec->d, r = dec->r;
+    const int64_t pts = (int64_t)B * n;
+    int32_t rc = MR_OK;
+    for (int ci = 0; ci < 3 && rc == MR_OK; ++ci) {
+        if (!(cfg_mask & (1 << ci))) continue;
+        const int cfg = ci == 0 ? 1 : (ci == 1 ? 5 : 9);
+        // representative size: the same instances and points when affordable,
+        // else one instance with a capped point count
+        const int64_t cap = ci == 2 ? ((int64_t)1 << 20) : ((int64_t)1 << 22);
+        int32_t Bt = B;
+        int64_t nt = n;
+        if (pts > cap) {
+            Bt = 1;
+            nt = cap;
+        }
+        const int64_t rj = ci == 2 ? (int64_t)d * (r > 8 ? r : 8) : 0;
+        const int64_t out_floats = (int64_t)Bt * nt * (ci == 0 ? d : (ci == 1 ? d + d * d + d : d + rj));
+        float *X = nullptr, *out = nullptr;
+        double *lat = nullptr;
+        if (hipMalloc(&X, sizeof(float) * d * nt) != hipSuccess ||
+            hipMalloc(&out, sizeof(float) * out_floats) != hipSuccess ||
+            hipMalloc(&lat, sizeof(double) * 2 * Bt * r) != hipSuccess) {
+            (void)hipFree(X);
+            (void)hipFree(out);
+            (void)hipFree(lat);
+            return MR_ENOMEM;
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipMemsetAsync(X, 0, sizeof(float) * d * nt, st) != hipSuccess ||
+            hipMemsetAsync(lat, 0, sizeof(double) * 2 * Bt * r, st) != hipSuccess ||
+            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            rc = MR_EDEVICE;
+        DecIO io{};
+        io.B = Bt;
+        io.n_ref = nt;
+        io.n = nt;
+        io.X = X;
+        io.idx_div = 1;
+        io.xhat = lat;
+        io.vhat = lat + (size_t)Bt * r;
+        io.x = out;
+        if (ci == 1) {
+            io.F = out + (size_t)Bt * d * nt;
+            io.v = io.F + (size_t)Bt * d * d * nt;
+        } else if (ci == 2) {
+            io.Jz = out + (size_t)Bt * d * nt;
+        }
+        const StreamSpec ss = spec_of(cfg, d);
+        const int cand[4] = {DEC_COL, DEC_COL_NP2, DEC_COL_NP4, DEC_ROWS};
+        float best = 0.0f;
+        int best_v = DEC_COL;
+        for (int k = 0; k < 4 && rc == MR_OK; ++k) {
+            const int v = cand[k];
+            if (cfg != 1 && (v == DEC_COL_NP2 || v == DEC_COL_NP4)) continue;
+            rc = launch_cfg(dec, cfg, ss, io, st, v);   // warm-up (and LDS attribute)
+            if (rc != MR_OK) break;
+            if (hipEventRecord(e0, st) != hipSuccess) rc = MR_EDEVICE;
+            for (int q = 0; q < reps && rc == MR_OK; ++q) rc = launch_cfg(dec, cfg, ss, io, st, v);
+            if (rc == MR_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                                hipEventSynchronize(e1) != hipSuccess))
+                rc = MR_EDEVICE;
+            float ms = 0.0f;
+            if (rc == MR_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MR_EDEVICE;
+            if (rc == MR_OK && (k == 0 || ms < best)) {
+                best = ms;
+                best_v = v;
+            }
+        }
+        if (rc == MR_OK) dec->tuned[ci][size_bucket(pts)] = (int8_t)best_v;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(X);
+        (void)hipFree(out);
+        (void)hipFree(lat);
+    }
+    return rc;
+}
+
+}  // namespace mr
+
+extern "C" int32_t rom_decoder_autotune(mr_decoder *dec, int32_t B, int64_t n, int32_t cfg_mask,
+                                        int32_t reps, void *stream)
+{
+    return decoder_autotune(dec, B, n, cfg_mask, reps, as_stream(stream));
+}
+
+extern "C" int32_t rom_decoder_shape(const mr_decoder *dec, int32_t cfg, int32_t B, int64_t n)
+{
+    if (!dec || B < 1 || n < 0 || (cfg != 1 && cfg != 5 && cfg != 9)) return MR_EINVAL;
+    if (dec->nh == 0) return DEC_COL;
+    return dec_variant(dec, cfg, (int64_t)B * n);
+}
+
 extern "C" int32_t rom_decoder_create(int32_t d, int32_t r, int32_t width, int32_t n_hidden,
                                       const float *params, const float *in_min,
                                       const float *in_max, const float *out_mean,
@@ -653,6 +998,7 @@ extern "C" int32_t rom_decoder_create(int32_t d, int32_t r, int32_t width, int32
     while (W < width) W *= 2;
     mr_decoder *dec = (mr_decoder *)calloc(1, sizeof(mr_decoder));
     if (!dec) return MR_ENOMEM;
+    memset(dec->tuned, 0xff, sizeof(dec->tuned));   // nothing tuned yet
     dec->d = d;
     dec->r = r;
     dec->width = width;

@@ -477,6 +477,20 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
         rom_destroy(R);
         return MR_EDEVICE;
     }
+    if (cfg->autotune) {
+        // the four decoder launches of a step: every particle (positions),
+        // the quadrature list (x, F, v), the samples (latent Jacobian) and
+        // the line-search candidates (positions)
+        const int32_t nc = opts->max_backtrack + 1;
+        int32_t rc = decoder_autotune(dec, (int32_t)B, P, 1, 3, R->cap_stream);
+        if (rc == MR_OK) rc = decoder_autotune(dec, (int32_t)B, R->q_cap, 2, 3, R->cap_stream);
+        if (rc == MR_OK) rc = decoder_autotune(dec, (int32_t)B, R->ns_max, 4, 3, R->cap_stream);
+        if (rc == MR_OK) rc = decoder_autotune(dec, (int32_t)B * nc, R->ns_max, 1, 3, R->cap_stream);
+        if (rc != MR_OK) {
+            rom_destroy(R);
+            return rc;
+        }
+    }
     *out = R;
     return MR_OK;
 }

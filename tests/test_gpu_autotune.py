@@ -1,0 +1,74 @@
+"""Decoder launch shapes and their autotuner (rom_decoder_autotune,
+rom_decoder_shape): every shape evaluates the same arithmetic in the same
+order per output, so a decode that runs with the point-splitting shape (large
+point count) and the same points decoded through the unit-splitting shape
+(small point count, or a forced choice after tuning) agree to fp32 rounding
+of differently contracted sums."""
+import numpy as np
+import pytest
+
+from paper_2109_12390_amd import binding as B
+from paper_2109_12390_amd import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+dev = "cuda"
+
+
+def _dec(prec, width=128, nh=5, r=16, seed=3):
+    Ws, bs = scenes.random_decoder(3, r, width, nh, seed, scale=1.0, bias_scale=0.1)
+    return B.Decoder(Ws, bs, np.zeros(3, np.float32), np.ones(3, np.float32),
+                     np.zeros(3, np.float32), np.full(3, 0.05, np.float32), B.OUT_DISPLACEMENT, prec)
+
+
+def _decode_all(dec, X, z, vh, idx=None):
+    n = X.shape[1] if idx is None else idx.numel()
+    out = dict(x=torch.zeros(1, 3, n, device=dev), F=torch.zeros(1, 9, n, device=dev),
+               v=torch.zeros(1, 3, n, device=dev), Jz=torch.zeros(1, 48, n, device=dev))
+    B.rom_decode_jac(dec, X, z, idx=idx, vhat=vh, **out)
+    xo = torch.zeros(1, 3, n, device=dev)
+    B.rom_decode(dec, X, z, xo, idx=idx)
+    out["x_only"] = xo
+    return out
+
+
+@pytest.mark.parametrize("prec", [B.PREC_FP32, B.PREC_BF16])
+def test_shapes_agree_and_autotune(gpu, prec):
+    rng = np.random.default_rng(7)
+    n = 40000
+    X = torch.tensor(rng.uniform(0, 1, size=(3, n)).astype(np.float32), device=dev)
+    z = torch.tensor(0.3 * rng.standard_normal((1, 16)), device=dev)
+    vh = torch.tensor(0.3 * rng.standard_normal((1, 16)), device=dev)
+    dec = _dec(prec)
+    # untuned size rule: points split for 40,000 points, units split for 2,000
+    assert dec.shape(1, 1, n) == 0 and dec.shape(1, 1, 2000) == 3
+    big = _decode_all(dec, X, z, vh)
+    idx = torch.arange(0, n, 20, dtype=torch.int32, device=dev)
+    small = _decode_all(dec, X, z, vh, idx=idx)
+    worst = 0.0
+    for k in big:
+        a = big[k][:, :, idx.long()]
+        b = small[k]
+        e = float((a - b).abs().max() / (a.abs().max() + 1e-30))
+        worst = max(worst, e)
+    print("prec %d: point-split vs unit-split shapes, worst relative difference %.2e" % (prec, worst))
+    assert worst < 1e-5
+    dec.autotune(1, n, cfg_mask=7, reps=2)
+    tuned = [dec.shape(c, 1, n) for c in (1, 5, 9)]
+    print("tuned shapes at %d points (cfg 1, 5, 9):" % n, tuned)
+    assert all(0 <= t <= 3 for t in tuned)
+    again = _decode_all(dec, X, z, vh)
+    for k in big:
+        e = float((again[k] - big[k]).abs().max() / (big[k].abs().max() + 1e-30))
+        assert e < 1e-5, k
+    dec.close()
+
+
+def test_autotune_rejects_bad_arguments(gpu):
+    dec = _dec(B.PREC_BF16, width=32, nh=2, r=4)
+    lib = B.load()
+    assert lib.rom_decoder_autotune(dec.handle, 0, 100, 1, 1, None) == B.MR_EINVAL
+    assert lib.rom_decoder_autotune(dec.handle, 1, 100, 8, 1, None) == B.MR_EINVAL
+    assert lib.rom_decoder_autotune(dec.handle, 1, 100, 1, 0, None) == B.MR_EINVAL
+    assert lib.rom_decoder_shape(dec.handle, 2, 1, 100) == B.MR_EINVAL
+    dec.close()
