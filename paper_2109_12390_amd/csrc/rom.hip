@@ -24,6 +24,11 @@
 #include "mpm_kernels.h"
 #include "project.h"
 
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
 #include <stdlib.h>
 
 #include <vector>
@@ -36,7 +41,8 @@ struct mr_rom {
     mr_gn_opts opts;
     int B;
     int64_t P, ns_max, q_cap, nodes, words;
-    float *X, *m, *E;
+    float *X, *m, *E;      // X and m in the runner's particle order
+    int32_t *internal_of;  // [P] caller's particle index -> runner's index
     int32_t *n_samples;
     int32_t *samples;   // [B][ns_max]
     float *x_all;       // [B][d][P]
@@ -70,7 +76,8 @@ __device__ __forceinline__ uint64_t mix64(uint64_t c)
 }
 
 __global__ void sample_kernel(uint64_t seed, const int64_t *counter, int64_t P, int ns_max,
-                              const int32_t *n_samples, int32_t *samples)
+                              const int32_t *n_samples, const int32_t *internal_of,
+                              int32_t *samples)
 {
     const int b = blockIdx.y;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,7 +92,9 @@ __global__ void sample_kernel(uint64_t seed, const int64_t *counter, int64_t P, 
     } else {
         idx = 0;  // padding entry, masked by the per-instance count
     }
-    samples[(int64_t)b * ns_max + k] = idx;
+    // draws are particle indices of the caller's order; the runner stores the
+    // particles in its own (cell-coherent) order
+    samples[(int64_t)b * ns_max + k] = internal_of[idx];
 }
 
 template <int D>
@@ -182,6 +191,12 @@ __global__ void clamp_count_kernel(int B, int32_t *q_count, int64_t q_cap)
     if (b < B && q_count[b] > q_cap) q_count[b] = (int32_t)q_cap;
 }
 
+// P2G of Algorithm 5 over the quadrature list (C = 0, m = m_p, V0 = m_p / rho0),
+// restricted to the marked nodes I.  Consecutive entries of the list
+// (ascending particle index) mostly share a base cell and so the same 3^d
+// nodes; the lanes of a wave first sum their contributions over each run of
+// equal base cells (segmented suffix sums by shifts of 1, 2, 4, ... within the
+// run) and only the run's first lane issues the HBM atomics.
 template <int D>
 __global__ void __launch_bounds__(256) p2g_quad_kernel(GridK g, int64_t q_cap, int64_t words,
                                                        const int32_t *q_count, const int32_t *Q,
@@ -192,53 +207,95 @@ __global__ void __launch_bounds__(256) p2g_quad_kernel(GridK g, int64_t q_cap, i
                                                        float dt, const uint32_t *bitmap,
                                                        float *grid, int64_t nodes, int32_t *status)
 {
+    constexpr int NS = (D == 3) ? 27 : 9;
     const int b = blockIdx.y;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= q_count[b]) return;
-    float xp[D], vp[D], Fp[D * D], tau[D * D];
+    const int lane = threadIdx.x & 63;
+    const bool act = s < q_count[b];
+    float val[NS][D + 1];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-        xp[a] = xQ[((int64_t)b * D + a) * q_cap + s];
-        vp[a] = vQ[((int64_t)b * D + a) * q_cap + s];
-    }
+    for (int i = 0; i < NS; ++i)
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) Fp[k] = FQ[((int64_t)b * D * D + k) * q_cap + s];
-    Lame lm = lame_of(E[b], nu);
+        for (int c = 0; c <= D; ++c) val[i][c] = 0.0f;
+    int key = -2 - lane;            // distinct for lanes without a contribution
     Stencil<D> st;
-    bool ok = make_stencil<D>(g, xp, st);
-    ok = kirchhoff<D>(model, lm.mu, lm.la, Fp, tau) && ok;
-    if (!ok) {
-        atomicOr(status + b, MR_FLAG_DOMAIN);
-        return;
-    }
-    const int32_t q = Q[(int64_t)b * q_cap + s];
-    float m = m_all ? m_all[q] : m_uniform;
-    P2GPayload<D> pl;
-    pl.m = m;
-    float sc = dt * m * inv_rho0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) pl.mv[a] = m * vp[a];
-#pragma unroll
-    for (int k = 0; k < D * D; ++k) {
-        pl.mC[k] = 0.0f;
-        pl.S[k] = sc * tau[k];
-    }
     const uint32_t *bm = bitmap + (int64_t)b * words;
+    if (act) {
+        float xp[D], vp[D], Fp[D * D], tau[D * D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            xp[a] = xQ[((int64_t)b * D + a) * q_cap + s];
+            vp[a] = vQ[((int64_t)b * D + a) * q_cap + s];
+        }
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) Fp[k] = FQ[((int64_t)b * D * D + k) * q_cap + s];
+        Lame lm = lame_of(E[b], nu);
+        bool ok = make_stencil<D>(g, xp, st);
+        ok = kirchhoff<D>(model, lm.mu, lm.la, Fp, tau) && ok;
+        if (!ok) {
+            atomicOr(status + b, MR_FLAG_DOMAIN);
+        } else {
+            const int32_t q = Q[(int64_t)b * q_cap + s];
+            const float m = m_all ? m_all[q] : m_uniform;
+            P2GPayload<D> pl;
+            pl.m = m;
+            const float sc = dt * m * inv_rho0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) pl.mv[a] = m * vp[a];
+#pragma unroll
+            for (int k = 0; k < D * D; ++k) {
+                pl.mC[k] = 0.0f;
+                pl.S[k] = sc * tau[k];
+            }
+            key = (int)node_lin(g, st.base[0], st.base[1], D == 3 ? st.base[2] : 0);
+#pragma unroll
+            for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2)
+#pragma unroll
+                for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+                    for (int o0 = 0; o0 < 3; ++o0) {
+                        const int i = o0 + 3 * (o1 + 3 * o2);
+                        float mom[D];
+                        val[i][0] = p2g_node<D>(g, st, pl, o0, o1, o2, mom);
+#pragma unroll
+                        for (int a = 0; a < D; ++a) val[i][1 + a] = mom[a];
+                    }
+        }
+    }
+    // runs of equal keys among consecutive lanes: run_end = last lane of mine
+    const int key_next = __shfl_down(key, 1);
+    const bool last = lane == 63 || key_next != key;
+    const uint64_t lastmask = __ballot(last);
+    const int run_end = __ffsll((long long)(lastmask & (~0ull << lane))) - 1;
+    const int key_prev = __shfl_up(key, 1);
+    const bool head = lane == 0 || key_prev != key;
+    for (int dist = 1; dist < 64; dist <<= 1) {
+        const bool take = lane + dist <= run_end;
+        if (__ballot(take) == 0) break;
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+            for (int c = 0; c <= D; ++c) {
+                const float o = __shfl_down(val[i][c], dist);
+                if (take) val[i][c] += o;
+            }
+    }
+    if (!head || key < 0) return;
     float *gb = grid + (int64_t)b * nodes * 4;
-    const int oz = (D == 3) ? 3 : 1;
-    for (int o2 = 0; o2 < oz; ++o2)
+#pragma unroll
+    for (int o2 = 0; o2 < (D == 3 ? 3 : 1); ++o2)
 #pragma unroll
         for (int o1 = 0; o1 < 3; ++o1)
 #pragma unroll
             for (int o0 = 0; o0 < 3; ++o0) {
-                int64_t i = node_lin(g, st.base[0] + o0, st.base[1] + o1, D == 3 ? st.base[2] + o2 : 0);
+                const int64_t i = node_lin(g, st.base[0] + o0, st.base[1] + o1,
+                                           D == 3 ? st.base[2] + o2 : 0);
                 if (!bit_set(bm, i)) continue;
-                float mom[D];
-                float mw = p2g_node<D>(g, st, pl, o0, o1, o2, mom);
+                const int k = o0 + 3 * (o1 + 3 * o2);
                 float *gp = gb + 4 * i;
-                atomicAdd(gp, mw);
+                atomicAdd(gp, val[k][0]);
 #pragma unroll
-                for (int a = 0; a < D; ++a) atomicAdd(gp + 1 + a, mom[a]);
+                for (int a = 0; a < D; ++a) atomicAdd(gp + 1 + a, val[k][1 + a]);
             }
 }
 
@@ -323,7 +380,7 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
     fill_u32_kernel<<<2048, TB, 0, st>>>(R->bitmap, (int64_t)B * R->words);
     fill_f4_kernel<<<4096, TB, 0, st>>>(reinterpret_cast<float4 *>(R->grid), (int64_t)B * R->nodes);
     sample_kernel<<<gs, TB, 0, st>>>(R->cfg.seed, R->counter, R->P, (int)R->ns_max, R->n_samples,
-                                      R->samples);
+                                      R->internal_of, R->samples);
     MR_LAUNCH_CHECK();
     // Algorithm 3: decode every particle, mark I, collect Q
     rc = rom_decode(R->dec, B, R->P, R->X, R->P, nullptr, xhat, R->x_all, st);
@@ -386,7 +443,8 @@ using namespace mr;
 extern "C" void rom_destroy(mr_rom *R)
 {
     if (!R) return;
-    void *bufs[] = {R->X, R->m, R->E, R->n_samples, R->samples, R->x_all, R->bitmap, R->Q,
+    void *bufs[] = {R->X, R->m, R->E, R->internal_of, R->n_samples, R->samples, R->x_all,
+                    R->bitmap, R->Q,
                     R->q_count, R->n_active, R->xQ, R->FQ, R->vQ, R->grid, R->xs, R->xt, R->vt,
                     R->z_next, R->v_next, R->status_step, R->counter, R->proj_ws};
     for (void *p : bufs)
@@ -435,6 +493,7 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
         if (ok && hipMalloc(p, bytes > 0 ? bytes : 4) != hipSuccess) ok = false;
     };
     alloc((void **)&R->X, 4 * d * P);
+    alloc((void **)&R->internal_of, 4 * P);
     if (m_all) alloc((void **)&R->m, 4 * P);
     alloc((void **)&R->E, 4 * B);
     alloc((void **)&R->n_samples, 4 * B);
@@ -469,10 +528,44 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
             rom_destroy(R);
             return MR_EINVAL;
         }
-    bool cp = hipMemcpy(R->X, X_all, 4 * d * P, hipMemcpyDeviceToDevice) == hipSuccess &&
-              hipMemcpy(R->E, E, 4 * B, hipMemcpyDeviceToDevice) == hipSuccess &&
-              hipMemcpy(R->n_samples, n_samples, 4 * B, hipMemcpyDeviceToDevice) == hipSuccess &&
-              (!m_all || hipMemcpy(R->m, m_all, 4 * P, hipMemcpyDeviceToDevice) == hipSuccess);
+    // The runner keeps the particles sorted by the base cell of their
+    // reference position (stable): the quadrature list, collected in this
+    // order, then holds runs of particles sharing a stencil, which the
+    // quadrature P2G sums within a wave before its atomics.
+    std::vector<float> Xh((size_t)d * P), Xs((size_t)d * P), mh, ms;
+    std::vector<int64_t> key(P);
+    std::vector<int32_t> order(P), inv(P);
+    bool cp = hipMemcpy(Xh.data(), X_all, 4 * d * P, hipMemcpyDeviceToHost) == hipSuccess;
+    if (cp && m_all) {
+        mh.resize(P);
+        ms.resize(P);
+        cp = hipMemcpy(mh.data(), m_all, 4 * P, hipMemcpyDeviceToHost) == hipSuccess;
+    }
+    if (cp) {
+        const int nn[3] = {g.n0, g.n1, g.n2};
+        for (int64_t p = 0; p < P; ++p) {
+            int64_t kk = 0;
+            for (int a = d - 1; a >= 0; --a) {
+                float bf = floorf(Xh[(size_t)a * P + p] * g.inv_dx - 0.5f);
+                int64_t bi = bf < 0.0f ? 0 : (bf > (float)(nn[a] - 1) ? nn[a] - 1 : (int64_t)bf);
+                kk = kk * nn[a] + bi;
+            }
+            key[p] = kk;
+            order[p] = (int32_t)p;
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+        for (int64_t i = 0; i < P; ++i) {
+            inv[order[i]] = (int32_t)i;
+            for (int a = 0; a < d; ++a) Xs[(size_t)a * P + i] = Xh[(size_t)a * P + order[i]];
+            if (m_all) ms[i] = mh[order[i]];
+        }
+        cp = hipMemcpy(R->X, Xs.data(), 4 * d * P, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(R->internal_of, inv.data(), 4 * P, hipMemcpyHostToDevice) == hipSuccess &&
+             (!m_all || hipMemcpy(R->m, ms.data(), 4 * P, hipMemcpyHostToDevice) == hipSuccess);
+    }
+    cp = cp && hipMemcpy(R->E, E, 4 * B, hipMemcpyDeviceToDevice) == hipSuccess &&
+         hipMemcpy(R->n_samples, n_samples, 4 * B, hipMemcpyDeviceToDevice) == hipSuccess;
     if (!cp || hipStreamCreateWithFlags(&R->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         rom_destroy(R);
         return MR_EDEVICE;
