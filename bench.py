@@ -9,9 +9,13 @@ fused gather-of-step-n / scatter-of-step-n+1 kernel, each followed by the
 grid update.  HIP events bracket the whole region; the library's launch
 timer records an event pair around every launch inside it on the same
 stream, which gives the per-kernel average durations of the roofline entry.
+The JSON line also carries the reduced-order step on the same scene: its
+throughput with one instance and with 256 instances in one graph (random
+decoder of the benchmarked shape), and a trained decoder's reduced model
+judged against the full-order model over 500 steps.
 Prints one JSON line on stdout.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-rom]
 """
 import argparse
 import hashlib
@@ -86,6 +90,10 @@ def main():
     ap.add_argument("--no-rom", action="store_true")
     ap.add_argument("--rom-steps", type=int, default=100)
     ap.add_argument("--rom-instances", type=int, default=256)
+    ap.add_argument("--rom-accuracy-steps", type=int, default=500,
+                    help="steps of the trained reduced model judged against the full-order "
+                         "model (0: skip)")
+    ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--rom-batched-steps", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB ten times (the reference "
@@ -191,6 +199,10 @@ def main():
         if args.rom_instances > 0:
             out["rom_batched"] = rom_batched_throughput(B, scenes, s, args.rom_instances,
                                                         args.rom_batched_steps)
+        if args.rom_accuracy_steps > 0:
+            log("training a decoder on full-order snapshots and judging the reduced model ...")
+            out["rom_trained"] = rom_trained_accuracy(B, scenes, s, args.rom_accuracy_steps,
+                                                      args.train_steps)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(s)
@@ -202,8 +214,9 @@ def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden
     instance, r = 16, 512 sample points per step, Lagrangian quadrature
     (all particles decoded to find the neighbours), bf16 decoder of width
     128 with 5 hidden layers, position-velocity projection with 3
-    Gauss-Newton iterations; the per-step launches are replayed from a HIP
-    graph.  The decoder here is randomly initialised (throughput only)."""
+    Gauss-Newton iterations (damping 1e-4); the per-step launches are
+    replayed from a HIP graph.  The decoder here is randomly initialised
+    (throughput only; the trained leg measures accuracy)."""
     import torch
     dev = "cuda:0"
     X = s["X"]
@@ -216,7 +229,8 @@ def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden
     Xg = torch.tensor(np.ascontiguousarray(X.T), device=dev)
     E = torch.tensor([s["E"]], dtype=torch.float32, device=dev)
     ns = torch.tensor([n_samples], dtype=torch.int32, device=dev)
-    rom = B.Rom(dec, grid, Xg, E, ns, B.gn_opts(mode=B.POS_VEL, max_iter=3), seed=4, rho0=1000.0,
+    rom = B.Rom(dec, grid, Xg, E, ns, B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4), seed=4,
+                rho0=1000.0,
                 m_uniform=float(s["m"]), autotune=True)
     shapes = decoder_shapes(dec, 1, P, n_samples)
     z = torch.zeros(1, r, dtype=torch.float64, device=dev)
@@ -250,6 +264,54 @@ def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden
                        "projection": "position-velocity, 3 Gauss-Newton iterations",
                        "graph": "HIP graph of %d steps" % k},
             "displacement_error": None}
+
+
+def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_hidden=5,
+                         n_samples=512):
+    """The reduced model with a trained decoder on the same 2,097,152-particle
+    scene and parameters (E = 5e4, v0 = (0, -1, 0)): full-order snapshots
+    (every 5th step of n_steps, 65,536 particles), GPU training (bf16
+    kernels, Adam with the learning rate decaying exponentially 1e-2 -> 1e-4
+    over train_steps batches of 16,384 rows, penalty weights balanced to the
+    data scale), then n_steps reduced steps (512 samples, position-velocity
+    projection, 3 Gauss-Newton iterations, normal equations damped by 1e-4)
+    judged every 10 steps against the full-order model with the transfers of
+    the reduced substep (no affine term)."""
+    import torch
+    from paper_2109_12390_amd import evaluate as EV
+    from paper_2109_12390_amd import train as TR
+    E, v0 = float(s["E"]), (0.0, -1.0, 0.0)
+    t0 = time.perf_counter()
+    fom = EV.fom_positions(s, E, v0, n_steps, 10, affine=False)
+    snap = TR.generate_snapshots(s, [(E, v0)], n_steps=n_steps, every=5, n_sub=65536, seed=4,
+                                 affine=False)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    lam_F, lam_v = TR.balanced_penalties(snap)
+    t0 = time.perf_counter()
+    Ws, bs, Z, norm, hist = TR.train(snap, width=width, n_hidden=n_hidden, r=r, steps=train_steps,
+                                     n_groups=64, rows_per_group=256, lr0=1e-2, lr1=1e-4,
+                                     lam_F=lam_F, lam_v=lam_v, log_every=train_steps)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    lo, hi, mean, std = norm
+    dec = B.Decoder(Ws, bs, lo, hi, mean, std, B.OUT_DISPLACEMENT, B.PREC_BF16)
+    x_rom, st = EV.rom_positions(dec, s, E, v0, n_steps, 10, n_samples=n_samples,
+                                 opts=B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4),
+                                 z_guess=Z[0])
+    dec.close()
+    err, pos = EV.displacement_error(x_rom, fom, s["X"])
+    return {"metric": "ROM latent steps/s at the measured displacement error",
+            "value": float(1e3 / st["ms_per_step"]), "unit": "latent steps/s",
+            "ms_per_step": st["ms_per_step"], "displacement_error": err,
+            "position_error_percent": pos, "status": st["status"], "steps": n_steps,
+            "train": {"steps": train_steps, "rows_per_step": 64 * 256, "objective": hist,
+                      "lam_F": lam_F, "lam_v": lam_v, "seconds": t_train,
+                      "snapshot_seconds": t_data, "frames": snap.n_frames, "particles": 65536},
+            "config": {"instances": 1, "particles": s["P"], "samples": n_samples, "r": r,
+                       "decoder": "bf16 MLP %d x %d, trained" % (width, n_hidden),
+                       "projection": "position-velocity, 3 Gauss-Newton iterations, damping 1e-4",
+                       "reference": "full-order model without the affine transfer term"}}
 
 
 SHAPE_NAMES = ["1 point tile per wave", "2 point tiles per wave", "4 point tiles per wave",
@@ -286,7 +348,8 @@ def rom_batched_throughput(B, scenes, s, n_inst, steps, r=16, width=128, n_hidde
     ns = rng.integers(256, 1025, size=n_inst).astype(np.int32)
     E = torch.tensor(Es.astype(np.float32), device=dev)
     nst = torch.tensor(ns, device=dev)
-    rom = B.Rom(dec, grid, Xg, E, nst, B.gn_opts(mode=B.POS_VEL, max_iter=3), seed=5, rho0=1000.0,
+    rom = B.Rom(dec, grid, Xg, E, nst, B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4), seed=5,
+                rho0=1000.0,
                 m_uniform=float(s["m"]), autotune=True)
     shapes = decoder_shapes(dec, n_inst, P, int(ns.max()))
     z = torch.zeros(n_inst, r, dtype=torch.float64, device=dev)

@@ -325,11 +325,17 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
         }
         const float *bl = P.bh + (size_t)l * W;
         if constexpr (!DB) {
+            // primal columns start from the bias, tangent columns from zero
             f32x4 acc[NRT][NCT];
 #pragma unroll
-            for (int rt = 0; rt < NRT; ++rt)
+            for (int rt = 0; rt < NRT; ++rt) {
+                f32x4 b4;
 #pragma unroll
-                for (int ct = 0; ct < NCT; ++ct) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int q = 0; q < 4; ++q) b4[q] = bl[rt * 16 + 4 * g + q];
+#pragma unroll
+                for (int ct = 0; ct < NCT; ++ct)
+                    acc[rt][ct] = (ct % S == 0) ? b4 : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt) {
                 const T *Arow = Wl + (size_t)(rt * 16 + j) * lda;
@@ -346,16 +352,13 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt) {
                 const int i0 = rt * 16 + 4 * g;
-                f32x4 b4;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) b4[q] = bl[i0 + q];
 #pragma unroll
                 for (int pt = 0; pt < NP; ++pt) {
                     f32x4 h4, e4;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         float h, e;
-                        E::act(acc[rt][pt * S][q] + b4[q], h, e);
+                        E::act(acc[rt][pt * S][q], h, e);
                         h4[q] = h;
                         e4[q] = e;
                     }
@@ -370,8 +373,12 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
 #pragma unroll 1
             for (int rt = 0; rt < NRT; ++rt) {
                 f32x4 acc[NCT];
+                f32x4 b4;
 #pragma unroll
-                for (int ct = 0; ct < NCT; ++ct) acc[ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int q = 0; q < 4; ++q) b4[q] = bl[rt * 16 + 4 * g + q];
+#pragma unroll
+                for (int ct = 0; ct < NCT; ++ct)
+                    acc[ct] = (ct % S == 0) ? b4 : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
                 const T *Arow = Wl + (size_t)(rt * 16 + j) * lda;
 #pragma unroll
                 for (int ks = 0; ks < NKS; ++ks)
@@ -380,16 +387,13 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
                         acc[ct] = mfma_step(Arow + ks * E::KS,
                                             pin + (ct * 16 + j) * LD + ks * E::KS, acc[ct], lane);
                 const int i0 = rt * 16 + 4 * g;
-                f32x4 b4;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) b4[q] = bl[i0 + q];
 #pragma unroll
                 for (int pt = 0; pt < NP; ++pt) {
                     f32x4 h4, e4;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         float h, e;
-                        E::act(acc[pt * S][q] + b4[q], h, e);
+                        E::act(acc[pt * S][q], h, e);
                         h4[q] = h;
                         e4[q] = e;
                     }
@@ -526,8 +530,12 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
         }
         const float *bl = P.bh + (size_t)l * W;
         f32x4 acc[S];
+        f32x4 b4;
 #pragma unroll
-        for (int ct = 0; ct < S; ++ct) acc[ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int q = 0; q < 4; ++q) b4[q] = bl[i0 + q];
+        acc[0] = b4;
+#pragma unroll
+        for (int ct = 1; ct < S; ++ct) acc[ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         const T *Arow = Wl + (size_t)(16 * wave + j) * lda;
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks)
@@ -535,14 +543,11 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
             for (int ct = 0; ct < S; ++ct)
                 acc[ct] = mfma_step(Arow + ks * E::KS, pin + (ct * 16 + j) * LD + ks * E::KS,
                                     acc[ct], lane);
-        f32x4 b4;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) b4[q] = bl[i0 + q];
         f32x4 h4, e4;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             float h, e;
-            E::act(acc[0][q] + b4[q], h, e);
+            E::act(acc[0][q], h, e);
             h4[q] = h;
             e4[q] = e;
         }

@@ -175,6 +175,18 @@ def generate_snapshots(scene, instances, n_steps, every, n_sub, seed, sort_every
     return SnapshotSet(X_sub, fx, fF, fv, next_frame, every * scene["dt"])
 
 
+def balanced_penalties(snap):
+    """Penalty weights that put the three terms of the objective on the
+    scale of the position term for this data: lam_F = E|u|^2 / E|F - I|^2 and
+    lam_v = E|u|^2 / E|v|^2 over the snapshot rows (u the displacement).
+    The paper's lam_F = 100, lam_v = 0.01 are tied to its scenes' units."""
+    d = snap.X_sub.shape[1]
+    u2 = float(((snap.fx - snap.X_sub[None]) ** 2).sum(-1).mean())
+    f2 = float(((snap.fF - torch.eye(d, device=snap.fF.device)) ** 2).sum((-1, -2)).mean())
+    v2 = float((snap.fv ** 2).sum(-1).mean())
+    return (u2 / f2 if f2 > 0 else 1.0), (u2 / v2 if v2 > 0 else 1.0)
+
+
 def normalisation(snap):
     """Min-max input range of the reference positions and mean / standard
     deviation of the displacements (Appendix B feature scaling)."""
