@@ -160,7 +160,7 @@ def main():
         "g2p2g": 96 * P + 2 * grid_bytes,           # read and write x, F; read and flush the touched nodes
         "p2g": 96 * P + grid_bytes,                 # read x, v, C, F; flush the touched nodes
         "g2p": 48 * P + grid_bytes + 96 * P,        # read x, F and the grid; write x, v, C, F
-        "grid_update": 32 * grid.nodes(),           # read and write every node
+        "grid_update": 48 * grid.nodes(),           # read and write every node, clear the other grid
         "zero_grid": 16 * grid.nodes(),             # clear the second grid
         "cell_sort": (2 * 96 + 16) * P,             # gather-permute the state, keys and indices
     }

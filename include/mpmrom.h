@@ -78,7 +78,8 @@ extern "C" {
 #define MR_KC_GRID 2     /* grid update                                      */
 #define MR_KC_G2P 3      /* grid-to-particle gather                          */
 #define MR_KC_G2P2G 4    /* fused gather of step n and scatter of step n + 1 */
-#define MR_KC_ZERO 5     /* zeroing of the second grid of the fused path     */
+#define MR_KC_ZERO 5     /* separate grid clears (mpm_step clears the second
+                            grid inside the grid update: no launches here) */
 #define MR_KC_COUNT 6
 
 /* decoder enums */
@@ -207,7 +208,9 @@ int32_t mpm_g2p2g(const mr_grid *grid_desc, const mr_material *mat,
  * mpm_step_workspace_bytes(grid, n) bytes.  perm_accum (nullable, n int32)
  * receives, for every array slot on return, the index that particle had on
  * entry.  timing (nullable) records every launch.  Particles end with x, v,
- * C, F of the last step. */
+ * C, F of the last step.  Between sorts the state may live in the
+ * workspace (each sort gathers from one copy into the other); it is in the
+ * caller's arrays again when the call's work completes on the stream. */
 int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
                  mr_particles *parts, float dt, int32_t n_steps,
                  int32_t sort_every, int32_t flags, float *grid,

@@ -271,31 +271,30 @@ __global__ void cell_segment_sort_kernel(const int32_t *offsets, const int32_t *
 }
 
 // slot-major order inside a tile: the particle of rank k in local cell c goes
-// to tile_start + sum_c' min(cnt[c'], k) + #{c' < c : cnt[c'] > k}
+// to tile_start + sum_c' min(cnt[c'], k) + #{c' < c : cnt[c'] > k}.  One wave
+// per tile, lane = local cell: for each rank k the cells holding a k-th
+// particle are one ballot, whose population count is that slot's length and
+// whose count below the lane is the cell's place in it.
 template <int D>
 __global__ void __launch_bounds__(64) tile_slot_kernel(const int32_t *offsets,
                                                        const int32_t *counts,
                                                        const int32_t *cell_sorted,
                                                        int32_t *perm, int64_t ntiles)
 {
-    constexpr int NC = Tiling<D>::CELLS;
-    __shared__ int cnt[NC];
-    int64_t t = blockIdx.x;
+    static_assert(Tiling<D>::CELLS == 64, "one lane per local cell");
+    const int64_t t = blockIdx.x;
     if (t >= ntiles) return;
-    int c = threadIdx.x;
-    int64_t cell = t * NC + c;
-    cnt[c] = counts[cell];
-    __syncthreads();
-    int tile_start = offsets[t * NC];
-    int my_cnt = cnt[c];
-    int my_off = offsets[cell];
-    for (int k = 0; k < my_cnt; ++k) {
-        int pos = tile_start;
-        for (int q = 0; q < NC; ++q) {
-            int cq = cnt[q];
-            pos += (cq < k ? cq : k) + ((q < c && cq > k) ? 1 : 0);
-        }
-        perm[pos] = cell_sorted[my_off + k];
+    const int c = threadIdx.x;
+    const int64_t cell = t * 64 + c;
+    const int my_cnt = counts[cell];
+    const int my_off = offsets[cell];
+    int64_t pos0 = offsets[t * 64];                 // start of the tile's particles
+    const uint64_t below = c == 0 ? 0ull : (~0ull >> (64 - c));
+    for (int k = 0;; ++k) {
+        const uint64_t has = __ballot(k < my_cnt);
+        if (has == 0) break;
+        if (k < my_cnt) perm[pos0 + __popcll(has & below)] = cell_sorted[my_off + k];
+        pos0 += __popcll(has);
     }
 }
 
@@ -573,11 +572,14 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
 
 template <int D>
 __global__ void grid_update_kernel(GridK g, float dt, float *grid, const int32_t *active,
-                                   int64_t count)
+                                   int64_t count, float *clear = nullptr)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= count) return;
     int64_t i = active ? (int64_t)active[s] : s;
+    // the time loop clears the other grid buffer (the next scatter target)
+    // in the same pass
+    if (clear) reinterpret_cast<float4 *>(clear)[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float4 *gp = reinterpret_cast<float4 *>(grid) + i;
     float4 q = *gp;
     if (!(q.x > 0.0f)) {
@@ -673,7 +675,7 @@ int64_t sort_ws_bytes(const GridK &g, int64_t n, SortWorkspace *ws, char *basep)
     int64_t o_keys = take(4 * n), o_counts = take(4 * (ncells + 1)),
             o_offsets = take(4 * (ncells + 1)), o_fill = take(4 * (ncells + 1)),
             o_cs = take(4 * n), o_perm = take(4 * n), o_bs = take(4 * nb), o_tot = take(4),
-            o_copy = take(4 * n * (2 * D + 2 * D * D + 2));
+            o_copy = take(4 * n * (2 * D + 2 * D * D + 3));
     if (ws) {
         ws->keys = (int32_t *)(basep + o_keys);
         ws->counts = (int32_t *)(basep + o_counts);
@@ -691,7 +693,8 @@ int64_t sort_ws_bytes(const GridK &g, int64_t n, SortWorkspace *ws, char *basep)
 
 template <int D>
 int32_t cell_sort_impl(const GridK &g, mr_particles *parts, int32_t *perm_out, void *workspace,
-                       int32_t *flag, hipStream_t st, int32_t *carry = nullptr)
+                       int32_t *flag, hipStream_t st, int32_t *carry = nullptr,
+                       const mr_particles *dst = nullptr, int32_t *carry_dst = nullptr)
 {
     const int64_t n = parts->n;
     SortWorkspace ws;
@@ -717,17 +720,26 @@ int32_t cell_sort_impl(const GridK &g, mr_particles *parts, int32_t *perm_out, v
     tail_copy_kernel<<<gb, TB, 0, st>>>(ws.cell_sorted, ws.perm,
                                         ws.offsets + tg.ntiles * Tiling<D>::CELLS, n);
     MR_LAUNCH_CHECK();
-    // gather every particle array through the permutation
+    // gather every particle array through the permutation: in place (through
+    // a copy) or, when a destination set is given, straight into it
     struct Arr {
-        float *p;
+        float *p, *q;
         int planes;
-    } arrs[7] = {{parts->x, D}, {parts->v, D}, {parts->C, D * D}, {parts->F, D * D},
-                 {const_cast<float *>(parts->m), 1}, {const_cast<float *>(parts->V0), 1},
-                 {reinterpret_cast<float *>(carry), 1}};
+    } arrs[7] = {{parts->x, dst ? dst->x : nullptr, D},
+                 {parts->v, dst ? dst->v : nullptr, D},
+                 {parts->C, dst ? dst->C : nullptr, D * D},
+                 {parts->F, dst ? dst->F : nullptr, D * D},
+                 {const_cast<float *>(parts->m), dst ? const_cast<float *>(dst->m) : nullptr, 1},
+                 {const_cast<float *>(parts->V0), dst ? const_cast<float *>(dst->V0) : nullptr, 1},
+                 {reinterpret_cast<float *>(carry), reinterpret_cast<float *>(carry_dst), 1}};
     for (auto &a : arrs) {
         if (!a.p) continue;
-        MR_CHECK_HIP(hipMemcpyAsync(ws.copy, a.p, 4 * n * a.planes, hipMemcpyDeviceToDevice, st));
-        gather_plane_kernel<<<gb, TB, 0, st>>>(ws.copy, a.p, ws.perm, n, a.planes);
+        if (dst) {
+            gather_plane_kernel<<<gb, TB, 0, st>>>(a.p, a.q, ws.perm, n, a.planes);
+        } else {
+            MR_CHECK_HIP(hipMemcpyAsync(ws.copy, a.p, 4 * n * a.planes, hipMemcpyDeviceToDevice, st));
+            gather_plane_kernel<<<gb, TB, 0, st>>>(ws.copy, a.p, ws.perm, n, a.planes);
+        }
     }
     MR_LAUNCH_CHECK();
     if (perm_out)
@@ -1111,23 +1123,90 @@ extern "C" int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
     float *gA = grid;
     float *gB = (float *)((char *)workspace + ((mpm_workspace_bytes(grid_desc, parts->n) + 255) &
                                                ~(int64_t)255));
+    // The state alternates between the caller's arrays and a copy in the
+    // sort workspace: each sort gathers from one set into the other, and the
+    // last state is copied back at the end if it lives in the workspace.
+    const int64_t n = parts->n;
+    SortWorkspace sws;
+    if (dim == 2)
+        sort_ws_bytes<2>(g, n, &sws, (char *)workspace);
+    else
+        sort_ws_bytes<3>(g, n, &sws, (char *)workspace);
+    mr_particles shadow = *parts;
+    int32_t *shadow_carry = nullptr;
+    {
+        float *cp = sws.copy;
+        auto carve = [&](const float *src, int planes) -> float * {
+            if (!src) return nullptr;
+            float *q = cp;
+            cp += (int64_t)planes * n;
+            return q;
+        };
+        shadow.x = carve(parts->x, dim);
+        shadow.v = carve(parts->v, dim);
+        shadow.C = carve(parts->C, dim * dim);
+        shadow.F = carve(parts->F, dim * dim);
+        shadow.m = carve(parts->m, 1);
+        shadow.V0 = carve(parts->V0, 1);
+        shadow_carry = perm_accum ? reinterpret_cast<int32_t *>(cp) : nullptr;
+    }
+    mr_particles *cur = parts, *other = &shadow;
+    int32_t *carry_cur = perm_accum, *carry_other = shadow_carry;
     auto do_sort = [&]() -> int32_t {
         TimedLaunch tl(timing, MR_KC_SORT, st);
-        return dim == 2 ? cell_sort_impl<2>(g, parts, nullptr, workspace, status_flag, st, perm_accum)
-                        : cell_sort_impl<3>(g, parts, nullptr, workspace, status_flag, st, perm_accum);
+        int32_t r = dim == 2 ? cell_sort_impl<2>(g, cur, nullptr, workspace, status_flag, st,
+                                                 carry_cur, other, carry_other)
+                             : cell_sort_impl<3>(g, cur, nullptr, workspace, status_flag, st,
+                                                 carry_cur, other, carry_other);
+        mr_particles *tp = cur;
+        cur = other;
+        other = tp;
+        int32_t *tc = carry_cur;
+        carry_cur = carry_other;
+        carry_other = tc;
+        return r;
+    };
+    auto copy_back = [&]() -> int32_t {
+        if (cur == parts) return MR_OK;
+        struct {
+            const float *src;
+            float *dst;
+            int planes;
+        } planes[7] = {{shadow.x, parts->x, dim},
+                       {shadow.v, parts->v, dim},
+                       {shadow.C, parts->C, dim * dim},
+                       {shadow.F, parts->F, dim * dim},
+                       {shadow.m, const_cast<float *>(parts->m), 1},
+                       {shadow.V0, const_cast<float *>(parts->V0), 1},
+                       {reinterpret_cast<const float *>(shadow_carry),
+                        reinterpret_cast<float *>(perm_accum), 1}};
+        for (auto &c : planes)
+            if (c.src && c.dst)
+                MR_CHECK_HIP(hipMemcpyAsync(c.dst, c.src, 4 * n * c.planes, hipMemcpyDeviceToDevice,
+                                            st));
+        return MR_OK;
     };
     auto do_p2g = [&]() -> int32_t {
         TimedLaunch tl(timing, MR_KC_P2G, st);
-        return mpm_p2g(grid_desc, mat, parts, nullptr, 0, dt, gA, naff | (sorted ? MR_SORTED : 0),
+        return mpm_p2g(grid_desc, mat, cur, nullptr, 0, dt, gA, naff | (sorted ? MR_SORTED : 0),
                        workspace, status_flag, stream);
     };
+    const int64_t nodes = grid_nodes(g);
     auto do_update = [&]() -> int32_t {
+        // after every grid update the other buffer is free: it is cleared in
+        // the same pass for the next fused step
         TimedLaunch tl(timing, MR_KC_GRID, st);
-        return mpm_grid_update(grid_desc, dt, gA, nullptr, 0, stream);
+        const unsigned gbn = (unsigned)ceil_div(nodes, 256);
+        if (dim == 2)
+            grid_update_kernel<2><<<gbn, 256, 0, st>>>(g, dt, gA, nullptr, nodes, gB);
+        else
+            grid_update_kernel<3><<<gbn, 256, 0, st>>>(g, dt, gA, nullptr, nodes, gB);
+        MR_LAUNCH_CHECK();
+        return MR_OK;
     };
     auto do_g2p = [&]() -> int32_t {
         TimedLaunch tl(timing, MR_KC_G2P, st);
-        return mpm_g2p(grid_desc, parts, nullptr, 0, dt, gA, naff, nullptr, nullptr, status_flag,
+        return mpm_g2p(grid_desc, cur, nullptr, 0, dt, gA, naff, nullptr, nullptr, status_flag,
                        stream);
     };
     if (sorted && (rc = do_sort()) != MR_OK) return rc;
@@ -1140,13 +1219,8 @@ extern "C" int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
             if ((rc = do_p2g()) != MR_OK) return rc;
         } else {
             {
-                TimedLaunch tl(timing, MR_KC_ZERO, st);
-                if (hipMemsetAsync(gB, 0, sizeof(float) * 4 * grid_nodes(g), st) != hipSuccess)
-                    return MR_EDEVICE;
-            }
-            {
                 TimedLaunch tl(timing, MR_KC_G2P2G, st);
-                rc = mpm_g2p2g(grid_desc, mat, parts, dt, gA, gB,
+                rc = mpm_g2p2g(grid_desc, mat, cur, dt, gA, gB,
                                naff | MR_NO_VC_OUT | MR_ACCUMULATE, workspace, status_flag, stream);
             }
             if (rc != MR_OK) return rc;
@@ -1156,5 +1230,6 @@ extern "C" int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
         }
         if ((rc = do_update()) != MR_OK) return rc;
     }
-    return do_g2p();
+    if ((rc = do_g2p()) != MR_OK) return rc;
+    return copy_back();
 }
