@@ -81,10 +81,11 @@ __device__ __forceinline__ float elu_d(float z) { return z > 0.0f ? 1.0f : expf(
 // ELU and its derivative from one hardware exponential, for activations that
 // are stored in bf16: e^z - 1 is formed by subtraction, whose absolute error
 // (a few 1e-8) is far below the bf16 rounding of the unit-sized activations
-// it is summed with in the next layer.
+// it is summed with in the next layer.  For z > 0 the exponential (possibly
+// +inf) is discarded by the selects, so it needs no clamp.
 __device__ __forceinline__ void elu_fast(float z, float &h, float &e)
 {
-    const float ex = __expf(fminf(z, 0.0f));
+    const float ex = __expf(z);
     h = z > 0.0f ? z : ex - 1.0f;
     e = z > 0.0f ? 1.0f : ex;
 }
