@@ -11,8 +11,8 @@
 //    ones, ...), so that the lanes of a wave sit in distinct cells.  The
 //    workgroup accumulates its particles into an LDS copy of the tile's node
 //    region (tile plus stencil reach plus one cell of drift margin on each
-//    side) with LDS float atomics, then flushes the region to HBM with one
-//    global atomic per non-zero node channel.  Particles that drifted beyond
+//    side) with plain LDS read-modify-write, then flushes the region to HBM
+//    with one global atomic per non-zero node channel.  Particles that drifted beyond
 //    the margin since the sort fall back to global atomics.
 #include "mpm_kernels.h"
 
@@ -362,6 +362,23 @@ struct CellTile {
 
 __device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
 
+// an empty asm that claims to modify the stencil and payload values (stops
+// the compiler from hoisting what is computed from them out of a loop)
+template <int D>
+__device__ __forceinline__ void opaque_payload(Stencil<D> &st, P2GPayload<D> &pl)
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        asm volatile("" : "+v"(st.f[a]));
+#pragma unroll
+        for (int o = 0; o < 3; ++o) asm volatile("" : "+v"(st.w[a][o]), "+v"(st.dw[a][o]));
+        asm volatile("" : "+v"(pl.mv[a]));
+    }
+    asm volatile("" : "+v"(pl.m));
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) asm volatile("" : "+v"(pl.mC[q]), "+v"(pl.S[q]));
+}
+
 // waves per SIMD the tile kernels are compiled for (bounds their registers)
 #ifndef MR_TILE_MIN_WAVES
 #define MR_TILE_MIN_WAVES 1
@@ -535,6 +552,11 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
                 lds_order();
             }
             if (go) {
+                // sorted P2G: keep the node contributions inside the round
+                // (computed node by node next to their updates) rather than
+                // hoisted out of the retry loop and held in registers
+                // (measured: faster there, no gain in the fused kernel)
+                if (!FUSED) opaque_payload<D>(sn, pl);
                 auto rmw = [&](int o0, int o1, int o2, float mw, float q0, float q1, float q2) {
                     float4 *a4 = acc + nb + o0 + CT::SY * o1 + (D == 3 ? CT::SZ * o2 : 0);
                     float4 q = *a4;

@@ -160,10 +160,15 @@ def test_cell_sort_permutation_is_bit_exact(gpu, dim, P):
     assert flag.item() & B.FLAG_DOMAIN
 
 
-@pytest.mark.parametrize("dim,P", [(3, 20000), (2, 6000)])
-def test_sorted_tiled_p2g_matches_oracle(gpu, dim, P):
-    """Cell-sort, move the particles by up to 1.4 cells (beyond the drift
-    margin for some, exercising the global fallback), then the tiled P2G."""
+@pytest.mark.parametrize("dim,P,move", [(3, 20000, "random"), (2, 6000, "random"),
+                                        (3, 20000, "none"), (2, 6000, "none"),
+                                        (3, 20000, "rigid"), (2, 6000, "rigid")])
+def test_sorted_tiled_p2g_matches_oracle(gpu, dim, P, move):
+    """Cell-sort, then the tiled P2G with the particles moved since the sort:
+    random: by up to 1.4 cells each (mixed drifts, some beyond the drift
+    margin: base-cell claims and the global fallback); none: every particle
+    in its sort-time cell (no claims); rigid: all translated by one cell
+    diagonally (every lane drifted, distinct base cells)."""
     rng = np.random.default_rng(50 + dim)
     n = [40] * dim
     dx = 1 / 40
@@ -174,7 +179,12 @@ def test_sorted_tiled_p2g_matches_oracle(gpu, dim, P):
     perm = torch.zeros(P, dtype=torch.int32, device=dev)
     B.mpm_cell_sort(grid, parts, ws, perm_out=perm)
     p = perm.cpu().numpy()
-    xs = x[p] + (rng.uniform(-1.4, 1.4, size=(P, dim)) * dx).astype(np.float32)
+    if move == "random":
+        xs = x[p] + (rng.uniform(-1.4, 1.4, size=(P, dim)) * dx).astype(np.float32)
+    elif move == "rigid":
+        xs = x[p] + np.float32(dx) * np.array([1.0, -1.0, 1.0][:dim], dtype=np.float32)
+    else:
+        xs = x[p].copy()
     parts.x.copy_(T(soa(xs)))
     model = 0 if dim == 2 else 1
     mu, la = OM.lame(1e4, 0.3)
