@@ -182,6 +182,12 @@ typedef struct mr_timing mr_timing;
 int32_t mr_timing_create(int32_t capacity, mr_timing **out);
 void mr_timing_destroy(mr_timing *t);
 int32_t mr_timing_reset(mr_timing *t);
+/* Restricts recording to the classes whose bit is set in class_mask
+ * (bit MR_KC_*) and, per class, to every `every`-th launch counted from
+ * this call (every >= 1, else MR_EINVAL).  Each recorded launch costs a few
+ * microseconds of stream time for its event pair, so sampling keeps a timed
+ * run close to an untimed one.  Default: all classes, every launch. */
+int32_t mr_timing_sample(mr_timing *t, uint32_t class_mask, int32_t every);
 /* Synchronises on the recorded events; per class c < n_classes returns the
  * number of launches and their summed duration in milliseconds. */
 int32_t mr_timing_read(mr_timing *t, int32_t n_classes, int64_t *launches,
@@ -200,10 +206,10 @@ int32_t mpm_g2p2g(const mr_grid *grid_desc, const mr_material *mat,
                   int32_t *status_flag, void *stream);
 
 /* n_steps full-order steps (Algorithm 1 with the affine transfer unless
- * MR_NO_AFFINE in flags).  With sort_every > 0 the particles are
- * cell-sorted before step 0 and every sort_every steps, P2G uses the sorted
- * tiled scatter, and in between the gather of one step and the scatter of
- * the next run as one fused kernel (mpm_g2p2g).  grid: device scratch of
+ * MR_NO_AFFINE in flags): per step the scatter into one of two grid
+ * buffers, the grid update (which clears the other buffer) and the gather.
+ * With sort_every > 0 the particles are cell-sorted before step 0 and every
+ * sort_every steps and P2G uses the sorted tiled scatter.  grid: device scratch of
  * 4 * nodes floats (contents on return unspecified); workspace:
  * mpm_step_workspace_bytes(grid, n) bytes.  perm_accum (nullable, n int32)
  * receives, for every array slot on return, the index that particle had on

@@ -90,6 +90,7 @@ SIGNATURES = {
     "mr_timing_create": (_i32, [_i32, ctypes.POINTER(_vp)]),
     "mr_timing_destroy": (None, [_vp]),
     "mr_timing_reset": (_i32, [_vp]),
+    "mr_timing_sample": (_i32, [_vp, ctypes.c_uint32, _i32]),
     "mr_timing_read": (_i32, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_f64)]),
     "mpm_step_workspace_bytes": (_i64, [ctypes.POINTER(MrGrid), _i64]),
     "rom_decoder_create": (_i32, [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _i32,
@@ -279,6 +280,15 @@ class Timing:
 
     def reset(self):
         _check("mr_timing_reset", load().mr_timing_reset(self.handle))
+
+    def sample(self, every, classes=None):
+        """Record only every `every`-th launch of each class in `classes`
+        (names from KC_NAMES; default all)."""
+        names = KC_NAMES if classes is None else classes
+        mask = 0
+        for nm in names:
+            mask |= 1 << KC_NAMES.index(nm)
+        _check("mr_timing_sample", load().mr_timing_sample(self.handle, mask, every))
 
     def read(self):
         n = len(KC_NAMES)

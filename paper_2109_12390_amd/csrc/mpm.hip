@@ -1019,6 +1019,9 @@ struct mr_timing {
     int32_t cap, count;
     hipEvent_t *ev;  // 2 per record
     int32_t *cls;
+    uint32_t mask;        // classes recorded
+    int32_t every;        // record every `every`-th launch of a class
+    int64_t seen[32];     // launches of each class since the last reset
 };
 
 extern "C" int32_t mr_timing_create(int32_t capacity, mr_timing **out)
@@ -1027,6 +1030,8 @@ extern "C" int32_t mr_timing_create(int32_t capacity, mr_timing **out)
     mr_timing *t = (mr_timing *)calloc(1, sizeof(mr_timing));
     if (!t) return MR_ENOMEM;
     t->cap = capacity;
+    t->mask = ~0u;
+    t->every = 1;
     t->ev = (hipEvent_t *)calloc(2 * (size_t)capacity, sizeof(hipEvent_t));
     t->cls = (int32_t *)calloc((size_t)capacity, sizeof(int32_t));
     if (!t->ev || !t->cls) {
@@ -1060,6 +1065,16 @@ extern "C" int32_t mr_timing_reset(mr_timing *t)
 {
     if (!t) return MR_EINVAL;
     t->count = 0;
+    for (int64_t &c : t->seen) c = 0;
+    return MR_OK;
+}
+
+extern "C" int32_t mr_timing_sample(mr_timing *t, uint32_t class_mask, int32_t every)
+{
+    if (!t || every < 1) return MR_EINVAL;
+    t->mask = class_mask;
+    t->every = every;
+    for (int64_t &c : t->seen) c = 0;
     return MR_OK;
 }
 
@@ -1091,7 +1106,8 @@ struct TimedLaunch {
     hipStream_t st;
     TimedLaunch(mr_timing *tm, int cls, hipStream_t s) : t(tm), idx(-1), st(s)
     {
-        if (t && t->count < t->cap) {
+        if (t && cls >= 0 && cls < 32 && ((t->mask >> cls) & 1u) &&
+            t->seen[cls]++ % t->every == 0 && t->count < t->cap) {
             idx = t->count++;
             t->cls[idx] = cls;
             (void)hipEventRecord(t->ev[2 * idx], st);
@@ -1112,7 +1128,7 @@ extern "C" int64_t mpm_step_workspace_bytes(const mr_grid *grid_desc, int64_t n)
     GridK g;
     if (!grid_from_desc(grid_desc, g) || n < 0) return -1;
     int64_t sort_bytes = mpm_workspace_bytes(grid_desc, n);
-    return sort_bytes + 16 * grid_nodes(g) + 256;  // + second grid for the fused path
+    return sort_bytes + 16 * grid_nodes(g) + 256;  // + the second grid buffer
 }
 
 __global__ void iota_kernel(int32_t *a, int64_t n)
@@ -1208,15 +1224,16 @@ extern "C" int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
                                             st));
         return MR_OK;
     };
-    auto do_p2g = [&]() -> int32_t {
+    auto do_p2g = [&](float *target, bool cleared) -> int32_t {
         TimedLaunch tl(timing, MR_KC_P2G, st);
-        return mpm_p2g(grid_desc, mat, cur, nullptr, 0, dt, gA, naff | (sorted ? MR_SORTED : 0),
-                       workspace, status_flag, stream);
+        return mpm_p2g(grid_desc, mat, cur, nullptr, 0, dt, target,
+                       naff | (sorted ? MR_SORTED : 0) | (cleared ? MR_ACCUMULATE : 0), workspace,
+                       status_flag, stream);
     };
     const int64_t nodes = grid_nodes(g);
     auto do_update = [&]() -> int32_t {
         // after every grid update the other buffer is free: it is cleared in
-        // the same pass for the next fused step
+        // the same pass for the next scatter
         TimedLaunch tl(timing, MR_KC_GRID, st);
         const unsigned gbn = (unsigned)ceil_div(nodes, 256);
         if (dim == 2)
@@ -1231,25 +1248,22 @@ extern "C" int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
         return mpm_g2p(grid_desc, cur, nullptr, 0, dt, gA, naff, nullptr, nullptr, status_flag,
                        stream);
     };
+    // Every step: G2P from the updated grid, the cell sort when due, the
+    // sorted P2G into the other grid buffer (cleared by the previous grid
+    // update), then the grid update of that buffer, which clears the first.
+    // The separate gather and sorted scatter outrun the fused kernel
+    // (mpm_g2p2g) on this part despite re-reading v and C: the gather runs at
+    // high occupancy and the scatter alone fits three waves per SIMD.
     if (sorted && (rc = do_sort()) != MR_OK) return rc;
-    if ((rc = do_p2g()) != MR_OK) return rc;
+    if ((rc = do_p2g(gA, false)) != MR_OK) return rc;
     if ((rc = do_update()) != MR_OK) return rc;
     for (int32_t s = 1; s < n_steps; ++s) {
-        if (!sorted || s % sort_every == 0) {
-            if ((rc = do_g2p()) != MR_OK) return rc;
-            if (sorted && (rc = do_sort()) != MR_OK) return rc;
-            if ((rc = do_p2g()) != MR_OK) return rc;
-        } else {
-            {
-                TimedLaunch tl(timing, MR_KC_G2P2G, st);
-                rc = mpm_g2p2g(grid_desc, mat, cur, dt, gA, gB,
-                               naff | MR_NO_VC_OUT | MR_ACCUMULATE, workspace, status_flag, stream);
-            }
-            if (rc != MR_OK) return rc;
-            float *tmp = gA;
-            gA = gB;
-            gB = tmp;
-        }
+        if ((rc = do_g2p()) != MR_OK) return rc;
+        if (sorted && s % sort_every == 0 && (rc = do_sort()) != MR_OK) return rc;
+        if ((rc = do_p2g(gB, true)) != MR_OK) return rc;
+        float *tmp = gA;
+        gA = gB;
+        gB = tmp;
         if ((rc = do_update()) != MR_OK) return rc;
     }
     if ((rc = do_g2p()) != MR_OK) return rc;

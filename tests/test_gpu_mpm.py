@@ -263,6 +263,40 @@ def test_three_dimensional_scene_small(gpu):
     assert ex <= 1e-3 and ev <= 1e-2 and ed <= 1e-2
 
 
+def test_launch_timer_sampling(gpu):
+    """mr_timing_sample: only the chosen classes, every k-th launch of each;
+    the timed run's state matches an untimed run's (up to the order of the
+    grid's float atomics)."""
+    s = scenes.scene_3d(n=32, cube_cells=8, seed=5, v0=(0.3, -2.0, 0.1))
+    st0 = scenes.initial_state(s)
+    grid = _gpu_scene(B, s)
+    steps, every = 25, 3
+    xs = []
+    for timed in (False, True):
+        parts = make_parts(B, st0["x"], st0["v"], st0["C"], st0["F"], m_u=float(s["m"]),
+                           V0_u=float(s["V0"]))
+        gbuf = torch.zeros(grid.nodes() * 4, device=dev)
+        ws = torch.zeros(B.mpm_step_workspace_bytes(grid, s["P"]), dtype=torch.uint8, device=dev)
+        tm = None
+        if timed:
+            tm = B.Timing(256)
+            tm.sample(every, ["p2g", "cell_sort"])
+        B.mpm_step(grid, (s["model"], s["E"], s["nu"]), parts, s["dt"], steps, 10, 0, gbuf, ws,
+                   timing=tm)
+        xs.append(parts.x.cpu().numpy())
+        if timed:
+            r = tm.read()
+            tm.close()
+    # launches: one scatter per step; sorts before steps 0, 10 and 20
+    assert set(r) == {"p2g", "cell_sort"}
+    assert r["p2g"][0] == -(-steps // every)
+    assert r["cell_sort"][0] == 1
+    assert all(ms > 0 for _, ms in r.values())
+    assert rel_l2(xs[1], xs[0]) < 1e-6
+    with pytest.raises(B.MrError):
+        B.Timing(4).sample(0)
+
+
 def test_three_dimensional_full_size_one_step(gpu):
     """The 2,097,152-particle scene in the benchmark's launch configuration
     (mpm_step with cell sorting), one step against the oracle on every
