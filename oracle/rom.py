@@ -1,8 +1,9 @@
 """FP64 oracle of one reduced-order-model time step (Section 3.2,
-Algorithm 2) with Lagrangian-quadrature kinematics (Algorithm 3), the
-sample-point full-space dynamics (Algorithm 5) and the projection
-(Algorithm 6 or 7); plus the least-squares initial latents (Section 3.1,
-eq. essentialSpecInt) and the error metrics of Section 5.
+Algorithm 2) with Lagrangian-quadrature kinematics (Algorithm 3) or
+Eulerian-quadrature kinematics (Algorithm 4), the sample-point full-space
+dynamics (Algorithm 5) and the projection (Algorithm 6 or 7); plus the
+least-squares initial latents (Section 3.1, eq. essentialSpecInt) and the
+error metrics of Section 5.
 
 TEST INFRASTRUCTURE ONLY.
 
@@ -15,6 +16,19 @@ Readings:
     V0_p = m_p / rho0 (Algorithm 3, last step) and no affine velocity
     (Algorithm 5 uses the plain transfer).
   - The grid boundary band of the full-order model applies to the substep.
+  Eulerian quadrature (Algorithm 4):
+  - Points sit at (m + 1/2) dx / ell along each axis (ell per cell and
+    dimension, evenly spaced, volume (dx / ell)^d); the quadrature points of
+    a step are those whose stencil touches an active node (the nodes of the
+    samples' stencils), the same test as for the Lagrangian neighbours.
+  - The map is inverted by Newton's method on g(X; xhat) = x^Q with the
+    Jacobian F = dg/dX, started at X = x^Q, for a fixed number of
+    iterations; a point is kept when the final residual max-norm is within
+    a tolerance, det F > 0 and X lies in the reference body.  The reference
+    body is the set of grid cells (cell c = floor(X / dx)) holding at least
+    one reference particle.
+  - Mass m^Q = rho0 (dx / ell)^d / J and reference volume V0 = m^Q / rho0;
+    sample points are not quadrature points.
 """
 import numpy as np
 
@@ -101,21 +115,113 @@ def substep(scene, x_Q, F_Q, v_Q, m_Q, V0_Q, x_samples, dt):
                     apic=False, trial=True)
 
 
+def active_nodes(dim, n, dx, x_samples):
+    """The nodes of the samples' stencils (Algorithm 3 / 4, step 2), sorted."""
+    base = stencil_bases(dx, x_samples)
+    n_arr = np.asarray(n)
+    if np.any(base < 0) or np.any(base + 2 > n_arr - 1):
+        raise _mpm.OracleDomainError("decoded sample outside the lattice")
+    nodes = [_linear(n, base + o) for o in _offsets(dim)]
+    return np.unique(np.concatenate(nodes)) if len(base) else np.zeros(0, dtype=np.int64)
+
+
+def reference_occupancy(dim, n, dx, X_all):
+    """Reference body at grid resolution: flags over node-indexed cells
+    (cell c covers [c dx, (c + 1) dx)) holding a reference particle."""
+    c = np.floor(np.asarray(X_all, dtype=np.float64) / dx).astype(np.int64)
+    occ = np.zeros(int(np.prod(n)), dtype=bool)
+    ok = np.all((c >= 0) & (c <= np.asarray(n) - 2), axis=1)
+    occ[_linear(n, c[ok])] = True
+    return occ
+
+
+def quadrature_lattice(dim, n, dx, ell):
+    """Every Eulerian quadrature point of the domain, (m + 1/2) dx / ell per
+    axis over the n - 1 cells per axis; returns (points (M, d), base (M, d))."""
+    axes = [(np.arange((n[a] - 1) * ell) + 0.5) * (dx / ell) for a in range(dim)]
+    grids = np.meshgrid(*axes, indexing="ij")
+    pts = np.stack([g.reshape(-1) for g in grids], axis=1)
+    return pts, stencil_bases(dx, pts)
+
+
+def eulerian_points(dim, n, dx, ell, I):
+    """Algorithm 4, step 3: the quadrature points whose stencil lies in the
+    lattice and touches a node of I."""
+    pts, base = quadrature_lattice(dim, n, dx, ell)
+    n_arr = np.asarray(n)
+    inside = np.all((base >= 0) & (base + 2 <= n_arr - 1), axis=1)
+    pts, base = pts[inside], base[inside]
+    marked = np.zeros(int(np.prod(n)), dtype=bool)
+    marked[np.asarray(I, dtype=np.int64)] = True
+    touch = np.zeros(len(pts), dtype=bool)
+    for o in _offsets(dim):
+        touch |= marked[_linear(n, base + o)]
+    return pts[touch]
+
+
+def invert_map(jac_fn, x_target, iters):
+    """Newton's method for g(X) = x_target from X = x_target: X <- X -
+    F(X)^{-1} (g(X) - x_target), `iters` times.  jac_fn(X) returns (g, F)."""
+    X = np.array(x_target, dtype=np.float64)
+    for _ in range(iters):
+        g, F = jac_fn(X)
+        X = X - np.linalg.solve(F, (g - x_target)[..., None])[..., 0]
+    return X
+
+
+def eulerian_quadrature(dec, dim, n, dx, x_samples, zhat, vhat, ell, iters, tol, rho0,
+                        occupied):
+    """Algorithm 4: quadrature points, their reference positions (inverse
+    map), F, v and masses.  Returns a dict with the kept points' xQ, FQ, vQ,
+    mQ, V0Q, their reference positions XQ, and I and the candidate count."""
+    I = active_nodes(dim, n, dx, x_samples)
+    xq = eulerian_points(dim, n, dx, ell, I)
+    jac = lambda X: _dec.decode_jac(dec, X, zhat)[:2]
+    X = invert_map(jac, xq, iters)
+    x, F, _, v = _dec.decode_jac(dec, X, zhat, vhat)
+    det = np.linalg.det(F) if len(F) else np.zeros(0)
+    conv = np.max(np.abs(x - xq), axis=1) <= tol if len(x) else np.zeros(0, dtype=bool)
+    c = np.floor(X / dx).astype(np.int64)
+    in_lat = np.all((c >= 0) & (c <= np.asarray(n) - 2), axis=1)
+    inside = np.zeros(len(X), dtype=bool)
+    inside[in_lat] = occupied[_linear(n, c[in_lat])]
+    keep = conv & (det > 0.0) & inside
+    Vq = (dx / ell) ** dim
+    m = rho0 * Vq / det[keep]
+    return {"xQ": xq[keep], "XQ": X[keep], "FQ": F[keep], "vQ": v[keep], "mQ": m,
+            "V0Q": m / rho0, "I": I, "n_candidates": len(xq), "keep": keep,
+            "X_all": X, "x_candidates": xq}
+
+
 def rom_step(dec, scene, X_all, m_all, V0_all, zhat, zhat_prev, vhat, dt,
-             samples, opts):
-    """One ROM step (Algorithm 2).  Returns (zhat_next, vhat_next, info)."""
+             samples, opts, quadrature="lagrangian", ell=2, newton_iters=4, newton_tol=None,
+             rho0=None, occupied=None):
+    """One ROM step (Algorithm 2) with Lagrangian (Algorithm 3) or Eulerian
+    (Algorithm 4) quadrature kinematics.  Returns (zhat_next, vhat_next,
+    info).  Eulerian: rho0 and the reference occupancy are required;
+    newton_tol defaults to 1e-3 dx."""
     dim, n, dx = scene["dim"], scene["n"], scene["dx"]
     samples = np.asarray(samples, dtype=np.int64)
-    x_all = _dec.decode(dec, X_all, zhat)
-    I, Q, N = neighbour_set(dim, n, dx, x_all, samples)
-    xQ, FQ, JQ, vQ = _dec.decode_jac(dec, X_all[Q], zhat, vhat)
-    pos = np.searchsorted(Q, samples)
-    x_trial, v_trial = substep(scene, xQ, FQ, vQ, np.asarray(m_all)[Q],
-                               np.asarray(V0_all)[Q], xQ[pos], dt)
+    if quadrature == "eulerian":
+        x_s = _dec.decode(dec, X_all[samples], zhat)
+        tol = 1e-3 * dx if newton_tol is None else newton_tol
+        eq = eulerian_quadrature(dec, dim, n, dx, x_s, zhat, vhat, ell, newton_iters, tol, rho0,
+                                 occupied)
+        x_trial, v_trial = substep(scene, eq["xQ"], eq["FQ"], eq["vQ"], eq["mQ"], eq["V0Q"], x_s,
+                                   dt)
+        info = {"I": eq["I"], "eulerian": eq}
+    else:
+        x_all = _dec.decode(dec, X_all, zhat)
+        I, Q, N = neighbour_set(dim, n, dx, x_all, samples)
+        xQ, FQ, JQ, vQ = _dec.decode_jac(dec, X_all[Q], zhat, vhat)
+        pos = np.searchsorted(Q, samples)
+        x_trial, v_trial = substep(scene, xQ, FQ, vQ, np.asarray(m_all)[Q],
+                                   np.asarray(V0_all)[Q], xQ[pos], dt)
+        info = {"I": I, "Q": Q, "N": N}
     z, vh, it, f, status = _proj.project(dec, X_all[samples], x_trial, v_trial,
                                          zhat, zhat_prev, dt, opts)
-    info = {"I": I, "Q": Q, "N": N, "x_trial": x_trial, "v_trial": v_trial,
-            "iters": it, "objective": f, "status": status}
+    info.update({"x_trial": x_trial, "v_trial": v_trial, "iters": it, "objective": f,
+                 "status": status})
     return z, vh, info
 
 

@@ -1,0 +1,173 @@
+"""Pins of the Eulerian-quadrature oracle (Algorithm 4): point counts in
+closed form, the point set against a pure-Python enumeration, the Newton
+inversion against the exact inverse of an affine map and against an
+independent root finder, masses and reference positions under a
+translation, and the translation-manifold ROM with Eulerian quadrature
+against the symplectic-Euler closed form."""
+import itertools
+
+import numpy as np
+import pytest
+from scipy import optimize
+
+from oracle import decoder as D
+from oracle import mpm
+from oracle import project as PR
+from oracle import rom
+
+
+def translation_decoder(d):
+    W = np.concatenate([np.zeros((d, d)), np.eye(d)], axis=1)
+    return D.Decoder([W], [np.zeros(d)], np.zeros(d), np.ones(d), np.zeros(d), np.ones(d))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("ell", [2, 4])
+def test_one_interior_sample_point_count(dim, ell):
+    """One sample: I is its 3^d stencil; a point touches I iff its base is
+    within -2..2 of the sample's base per axis, and ell points per axis have
+    a given base, so |points| = (5 ell)^d."""
+    n = [16] * dim
+    dx = 1 / 16
+    xs = np.full((1, dim), 0.5 + 0.3 * dx)
+    I = rom.active_nodes(dim, n, dx, xs)
+    assert len(I) == 3 ** dim
+    pts = rom.eulerian_points(dim, n, dx, ell, I)
+    assert len(pts) == (5 * ell) ** dim
+    # evenly spaced at dx / ell, volume (dx / ell)^d each
+    frac = pts / (dx / ell) - 0.5
+    np.testing.assert_allclose(frac, np.round(frac), atol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_points_match_python_enumeration(dim):
+    rng = np.random.default_rng(4)
+    n = [8] * dim
+    dx = 1 / 8
+    ell = 2
+    xs = rng.uniform(0.3, 0.7, size=(3, dim))
+    I = rom.active_nodes(dim, n, dx, xs)
+    pts = rom.eulerian_points(dim, n, dx, ell, I)
+    # enumerate every lattice point in plain Python
+    Iset = set()
+    for x in xs:
+        b = [int(np.floor(x[a] / dx - 0.5)) for a in range(dim)]
+        for o in itertools.product(range(3), repeat=dim):
+            Iset.add(tuple(b[a] + o[a] for a in range(dim)))
+    want = []
+    for m in itertools.product(range((n[0] - 1) * ell), repeat=dim):
+        p = [(mi + 0.5) * dx / ell for mi in m]
+        b = [int(np.floor(p[a] / dx - 0.5)) for a in range(dim)]
+        if any(bi < 0 or bi + 2 > n[0] - 1 for bi in b):
+            continue
+        st = {tuple(b[a] + o[a] for a in range(dim)) for o in itertools.product(range(3), repeat=dim)}
+        if st & Iset:
+            want.append(p)
+    got = sorted(map(tuple, np.round(pts, 12)))
+    assert got == sorted(map(tuple, np.round(np.array(want), 12)))
+
+
+def test_newton_inverts_an_affine_map_in_one_iteration():
+    """W = [S | 0]: g(X) = X + S (2X - 1) + c, so X = (I + 2S)^{-1} (x + S 1 - c);
+    Newton is exact after one step on an affine map."""
+    rng = np.random.default_rng(5)
+    d, r = 3, 2
+    S = 0.1 * rng.standard_normal((d, d))
+    c = 0.05 * rng.standard_normal(d)
+    W = np.concatenate([S, np.zeros((d, r))], axis=1)
+    dec = D.Decoder([W], [c], np.zeros(d), np.ones(d), np.zeros(d), np.ones(d))
+    x = rng.uniform(0.2, 0.8, size=(40, d))
+    z = rng.standard_normal(r)
+    X1 = rom.invert_map(lambda X: D.decode_jac(dec, X, z)[:2], x, 1)
+    exact = np.linalg.solve(np.eye(d) + 2 * S, (x + S.sum(1) - c).T).T
+    np.testing.assert_allclose(X1, exact, atol=1e-13)
+    X3 = rom.invert_map(lambda X: D.decode_jac(dec, X, z)[:2], x, 3)
+    np.testing.assert_allclose(X3, exact, atol=1e-13)
+
+
+def test_newton_matches_an_independent_root_finder():
+    rng = np.random.default_rng(6)
+    d, r, w = 3, 2, 8
+    Ws = [0.3 * rng.standard_normal((w, d + r)), 0.3 * rng.standard_normal((w, w)),
+          0.3 * rng.standard_normal((d, w))]
+    bs = [0.1 * rng.standard_normal(w), 0.1 * rng.standard_normal(w), 0.05 * rng.standard_normal(d)]
+    dec = D.Decoder(Ws, bs, np.zeros(d), np.ones(d), np.zeros(d), 0.05 * np.ones(d))
+    z = rng.standard_normal(r)
+    x = rng.uniform(0.3, 0.7, size=(12, d))
+    X = rom.invert_map(lambda Y: D.decode_jac(dec, Y, z)[:2], x, 8)
+    for k in range(len(x)):
+        sol = optimize.root(lambda Y: D.decode(dec, Y[None], z)[0] - x[k], x[k], tol=1e-14)
+        assert sol.success
+        np.testing.assert_allclose(X[k], sol.x, atol=1e-11)
+    np.testing.assert_allclose(D.decode(dec, X, z), x, atol=1e-12)
+
+
+def _box_particles(dim, n, lo, hi, ppc=2):
+    """Particles at (c + (j + 1/2) / ppc) dx in every cell of [lo, hi)^d."""
+    dx = 1 / n
+    c0, c1 = int(round(lo * n)), int(round(hi * n))
+    ax = (np.arange(c0 * ppc, c1 * ppc) + 0.5) * dx / ppc
+    g = np.meshgrid(*([ax] * dim), indexing="ij")
+    return np.stack([a.reshape(-1) for a in g], axis=1)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_translation_positions_masses_and_body(dim):
+    """g = X + t with t a whole number of cells: X^Q = x^Q - t exactly,
+    J = 1, m = rho0 (dx / ell)^d; a point is kept iff X^Q lies in the box
+    of reference cells [4, 12)^d."""
+    n, ell, rho0 = 16, 2, 1000.0
+    dx = 1 / n
+    X_all = _box_particles(dim, n, 0.25, 0.75)
+    occ = rom.reference_occupancy(dim, [n] * dim, dx, X_all)
+    t = np.array([2 * dx, -1 * dx, dx][:dim])
+    dec = translation_decoder(dim)
+    xs = np.array([[0.7, 0.45, 0.5][:dim], [0.3, 0.6, 0.4][:dim]])
+    eq = rom.eulerian_quadrature(dec, dim, [n] * dim, dx, xs, t, np.zeros(dim), ell, 3,
+                                 1e-3 * dx, rho0, occ)
+    np.testing.assert_allclose(eq["X_all"], eq["x_candidates"] - t, atol=1e-15)
+    np.testing.assert_allclose(np.linalg.det(eq["FQ"]), 1.0, atol=1e-15)
+    np.testing.assert_allclose(eq["mQ"], rho0 * (dx / ell) ** dim, rtol=1e-15)
+    Xc = eq["x_candidates"] - t
+    want = np.all((Xc >= 0.25) & (Xc < 0.75), axis=1)
+    np.testing.assert_array_equal(eq["keep"], want)
+    assert 0 < want.sum() < len(want)        # the box edge cuts the point set
+
+
+@pytest.mark.parametrize("mode", [PR.MODE_POS_VEL, PR.MODE_VEL_ONLY])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_translation_manifold_eulerian_rom_equals_symplectic_euler(mode, dim):
+    """Free fall of a filled box under g = X + xhat: every quadrature point
+    has F = I and the instance velocity, every node near the samples has
+    mass, so the ROM with Eulerian quadrature reproduces symplectic Euler."""
+    n = 32
+    dx = 1 / n
+    X_all = _box_particles(dim, n, 0.25, 0.75)
+    P = len(X_all)
+    occ = rom.reference_occupancy(dim, [n] * dim, dx, X_all)
+    dec = translation_decoder(dim)
+    mu, la = mpm.lame(1e4, 0.3)
+    grav = [0.0] * dim
+    grav[1] = -9.8
+    sc = dict(dim=dim, n=[n] * dim, dx=dx, bound=0, floor_mode=0, mu_f=0.0, gravity=grav,
+              model=1, mu=mu, la=la)
+    interior = np.nonzero(np.all((X_all > 0.25 + 4 * dx) & (X_all < 0.75 - 4 * dx), axis=1))[0]
+    rng = np.random.default_rng(7)
+    z = np.zeros(dim)
+    zp = z.copy()
+    vh = np.array([0.3, -0.2, 0.1][:dim])
+    z0, v0 = z.copy(), vh.copy()
+    dt = 1e-3
+    opts = PR.GNOptions(mode=mode, max_iter=3, fixed_iters=True)
+    nst = 4
+    for k in range(nst):
+        samples = np.sort(rng.choice(interior, size=3, replace=False))
+        zn, vn, info = rom.rom_step(dec, sc, X_all, None, None, z, zp, vh, dt, samples, opts,
+                                    quadrature="eulerian", ell=2, newton_iters=2, rho0=1000.0,
+                                    occupied=occ)
+        assert info["eulerian"]["keep"].all()
+        zp, z, vh = z, zn, vn
+    g = np.array(grav)
+    np.testing.assert_allclose(vh, v0 + nst * dt * g, atol=1e-12)
+    np.testing.assert_allclose(z, z0 + nst * dt * v0 + dt * dt * g * nst * (nst + 1) / 2,
+                               atol=1e-13)
