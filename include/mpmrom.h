@@ -362,7 +362,29 @@ typedef struct {
     int32_t autotune;        /* non-zero: rom_create times the decoder's
                                 launch shapes at this runner's sizes
                                 (rom_decoder_autotune) before returning   */
+    int32_t quadrature;      /* MR_QUAD_LAGRANGIAN (Algorithm 3) or
+                                MR_QUAD_EULERIAN (Algorithm 4)            */
+    int32_t quad_per_dim;    /* Eulerian: points per cell and dimension,
+                                2 or 4 (0 selects 2)                      */
+    int32_t newton_iters;    /* Eulerian: Newton iterations inverting the
+                                decoder, 1..16 (0 selects 4)              */
+    float newton_tol;        /* Eulerian: largest residual max-norm of an
+                                accepted point, in cells (0 selects 1e-3) */
 } mr_rom_config;
+
+/* quadrature kinematics of the reduced step (mr_rom_config.quadrature).
+ * Lagrangian (Algorithm 3): every reference particle is decoded each step
+ * and those whose stencil touches the samples' nodes are the quadrature
+ * points (particle mass, V0 = m / rho0).  Eulerian (Algorithm 4): only the
+ * samples are decoded; the quadrature points are the lattice points
+ * (m + 1/2) dx / l per axis (l = quad_per_dim) whose stencil touches the
+ * samples' nodes, their reference positions X solve g(X; xhat) = x by
+ * Newton's method from X = x (newton_iters iterations with F = dg/dX), and
+ * a point is kept when the residual is within newton_tol cells, det F > 0
+ * and X lies in the reference body (the grid cells holding a reference
+ * particle); its mass is rho0 (dx / l)^d / det F. */
+#define MR_QUAD_LAGRANGIAN 0
+#define MR_QUAD_EULERIAN 1
 
 /* Creates the reduced-order model runner.  X_all: device SoA [d][P] reference
  * positions; m_all (nullable) device masses; E: device float32 [B] Young's
@@ -382,9 +404,11 @@ void rom_destroy(mr_rom *rom);
 
 /* Advances every instance n_steps reduced-order steps of size dt, starting
  * at step counter `step0` (the sampler's stream index): for each step, draw
- * the sample points, decode every particle, mark the active nodes of the
- * samples' stencils, collect the neighbour particles touching them
- * (Algorithm 3), evaluate x, F, v at the quadrature points, run the
+ * the sample points, form the quadrature points (Lagrangian: decode every
+ * particle, mark the active nodes of the samples' stencils, collect the
+ * neighbour particles touching them, Algorithm 3; Eulerian: decode the
+ * samples, mark their nodes, generate and invert the lattice points,
+ * Algorithm 4), evaluate x, F, v at the quadrature points, run the
  * sample-point MPM substep (Algorithm 5) and project (Algorithm 6 or 7).
  * xhat, xhat_prev, vhat: device float64 [B][r], updated in place.
  * status_out: device int32 [B] (nullable), OR of MR_FLAG_* over the steps.

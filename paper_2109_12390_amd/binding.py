@@ -62,7 +62,13 @@ class MrRomConfig(ctypes.Structure):
                 ("n_samples_max", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("rho0", ctypes.c_float), ("m_uniform", ctypes.c_float),
                 ("model", ctypes.c_int32), ("nu", ctypes.c_float),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("quadrature", ctypes.c_int32),
+                ("quad_per_dim", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
+                ("newton_tol", ctypes.c_float)]
+
+
+QUAD_LAGRANGIAN = 0
+QUAD_EULERIAN = 1
 
 
 _vp = ctypes.c_void_p
@@ -445,12 +451,14 @@ class Rom:
     """Owns an mr_rom handle (rom_create / rom_destroy)."""
 
     def __init__(self, dec, grid, X_all, E, n_samples, opts, seed, rho0, m_uniform=0.0,
-                 m_all=None, model=NEO_HOOKEAN, nu=0.3, autotune=False):
+                 m_all=None, model=NEO_HOOKEAN, nu=0.3, autotune=False,
+                 quadrature=QUAD_LAGRANGIAN, quad_per_dim=0, newton_iters=0, newton_tol=0.0):
         lib = load()
         self.dec = dec
         self.B = E.numel()
         cfg = MrRomConfig(self.B, X_all.shape[1], int(n_samples.max().item()), seed, rho0,
-                          m_uniform, model, nu, 1 if autotune else 0)
+                          m_uniform, model, nu, 1 if autotune else 0, quadrature, quad_per_dim,
+                          newton_iters, newton_tol)
         self.opts = opts
         h = ctypes.c_void_p()
         _check("rom_create", lib.rom_create(dec.handle, ctypes.byref(grid.c()), ctypes.byref(cfg),

@@ -69,6 +69,7 @@ struct DecIO {
     int idx_per_inst;
     int idx_div;  // idx row of instance b is b / idx_div (when idx_per_inst)
     const int32_t *n_inst;  // nullable: points s >= n_inst[b] are skipped
+    int64_t x_stride;       // instance b reads its inputs at X + b * x_stride (0: shared)
     int disp_only;          // displacement mode: write g - X instead of g
     const double *xhat, *vhat;
     float *x, *F, *v, *Jz;
@@ -171,7 +172,7 @@ __device__ __forceinline__ void emit_output(const DecK &P, const StreamSpec &ss,
             float val = P.mean[a] + P.stdv[a] * (y + P.bL[a]);
             if (P.mode == MR_OUT_DISPLACEMENT && !io.disp_only) {
                 int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * n : 0) + s] : s;
-                val += io.X[a * io.n_ref + row];
+                val += io.X[(int64_t)b * io.x_stride + a * io.n_ref + row];
             }
             io.x[(bo * D + a) * n + s] = val;
         }
@@ -271,7 +272,7 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
         float Xn[3] = {0.0f, 0.0f, 0.0f};
         if (s < n_b) {
             int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * io.n : 0) + s] : s;
-            for (int a = 0; a < P.d; ++a) Xn[a] = io.X[a * io.n_ref + row] * P.scale[a] + P.shift[a];
+            for (int a = 0; a < P.d; ++a) Xn[a] = io.X[(int64_t)b * io.x_stride + a * io.n_ref + row] * P.scale[a] + P.shift[a];
         }
         for (int m = 0; m < NRT; ++m) {
             const int i0 = 16 * m + 4 * g;
@@ -481,7 +482,7 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
         float Xn[3] = {0.0f, 0.0f, 0.0f};
         if (s < n_b) {
             int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * io.n : 0) + s] : s;
-            for (int a = 0; a < P.d; ++a) Xn[a] = io.X[a * io.n_ref + row] * P.scale[a] + P.shift[a];
+            for (int a = 0; a < P.d; ++a) Xn[a] = io.X[(int64_t)b * io.x_stride + a * io.n_ref + row] * P.scale[a] + P.shift[a];
         }
         f32x4 h4, e4;
 #pragma unroll
@@ -672,7 +673,7 @@ __global__ void linear_decoder_kernel(DecK P, DecIO io)
     const double *vh = io.vhat ? io.vhat + (size_t)b * P.r : nullptr;
     float Xr[3], Xn[3];
     for (int a = 0; a < D; ++a) {
-        Xr[a] = io.X[a * io.n_ref + row];
+        Xr[a] = io.X[(int64_t)b * io.x_stride + a * io.n_ref + row];
         Xn[a] = Xr[a] * P.scale[a] + P.shift[a];
     }
     const size_t bo = (size_t)b;
@@ -1098,10 +1099,11 @@ namespace mr {
 int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X, int64_t n,
                       const int32_t *idx, int32_t idx_per_instance, const int32_t *n_inst,
                       const double *xhat, const double *vhat, float *x, float *F, float *v,
-                      float *Jz, hipStream_t st, int disp_only)
+                      float *Jz, hipStream_t st, int disp_only, int64_t x_stride)
 {
     if (n == 0) return MR_OK;
     DecIO io{};
+    io.x_stride = x_stride;
     io.n_inst = n_inst;
     io.disp_only = disp_only;
     io.B = B;

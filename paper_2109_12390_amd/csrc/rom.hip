@@ -21,6 +21,15 @@
 //   7. for every sample, the grid update of its 3^d nodes (v = p/m + dt g,
 //      boundary band) fused into the trial G2P: v_trial, x_trial = x + dt v;
 //   8. projection of (x_trial, v_trial) onto the manifold.
+// With Eulerian quadrature (Algorithm 4) steps 2-5 become: decode the
+// samples only; mark their stencil nodes I and, dilated by two cells, the
+// stencil bases whose lattice points touch I (each base once, appended to a
+// per-instance list); expand every base into its l^d lattice points; invert
+// the decoder at them by Newton's method (decoder launches with the spatial
+// tangents, then a per-point d x d solve); decode x, F, v at the result and
+// keep a point (mass rho0 (dx / l)^d / det F) when the residual is small,
+// det F > 0 and its reference position lies in a reference cell holding a
+// particle.
 #include "mpm_kernels.h"
 #include "project.h"
 
@@ -63,6 +72,16 @@ struct mr_rom {
     double graph_dt;
     double *graph_ptrs[3];
     int32_t *graph_status;
+    // Eulerian quadrature
+    int quad, ell, newton_iters;
+    float newton_tol;
+    int64_t qb_cap;        // stencil bases per instance
+    uint32_t *qb_bitmap;   // [B][words]
+    int32_t *qbase;        // [B][qb_cap] node index of each base
+    int32_t *qb_count;     // [B]
+    float *XQ;             // [B][d][q_cap] reference positions (Newton iterate)
+    float *mQ;             // [B][q_cap] point masses (0: discarded)
+    uint32_t *occ;         // [words] reference cells holding a particle
 };
 
 namespace mr {
@@ -202,6 +221,7 @@ __global__ void __launch_bounds__(256) p2g_quad_kernel(GridK g, int64_t q_cap, i
                                                        const int32_t *q_count, const int32_t *Q,
                                                        const float *xQ, const float *FQ,
                                                        const float *vQ, const float *m_all,
+                                                       const float *m_q,
                                                        float m_uniform, float inv_rho0,
                                                        const float *E, float nu, int model,
                                                        float dt, const uint32_t *bitmap,
@@ -220,7 +240,18 @@ __global__ void __launch_bounds__(256) p2g_quad_kernel(GridK g, int64_t q_cap, i
     int key = -2 - lane;            // distinct for lanes without a contribution
     Stencil<D> st;
     const uint32_t *bm = bitmap + (int64_t)b * words;
+    // point mass: per point (Eulerian quadrature; 0 marks a discarded point)
+    // or the particle's
+    float m = 0.0f;
     if (act) {
+        if (m_q) {
+            m = m_q[(int64_t)b * q_cap + s];
+        } else {
+            const int32_t q = Q[(int64_t)b * q_cap + s];
+            m = m_all ? m_all[q] : m_uniform;
+        }
+    }
+    if (act && m > 0.0f) {
         float xp[D], vp[D], Fp[D * D], tau[D * D];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -235,8 +266,6 @@ __global__ void __launch_bounds__(256) p2g_quad_kernel(GridK g, int64_t q_cap, i
         if (!ok) {
             atomicOr(status + b, MR_FLAG_DOMAIN);
         } else {
-            const int32_t q = Q[(int64_t)b * q_cap + s];
-            const float m = m_all ? m_all[q] : m_uniform;
             P2GPayload<D> pl;
             pl.m = m;
             const float sc = dt * m * inv_rho0;
@@ -337,6 +366,193 @@ __global__ void g2p_trial_kernel(GridK g, int ns_max, const int32_t *n_samples, 
     }
 }
 
+// --- Eulerian quadrature (Algorithm 4) -------------------------------------
+
+// lattice point `sub` (0 .. l^d - 1) of the stencil base with node index
+// base_lin: per axis the l points (m + 1/2) dx / l, m = l b + l/2 + j, whose
+// stencil base is b (they lie in ((b + 1/2) dx, (b + 3/2) dx))
+template <int D>
+__device__ __forceinline__ void eul_point(const GridK &g, int32_t base_lin, int sub, int L,
+                                          float *xq)
+{
+    int bc[3];
+    bc[0] = base_lin % g.n0;
+    bc[1] = (base_lin / g.n0) % g.n1;
+    bc[2] = base_lin / (g.n0 * g.n1);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int j = sub % L;
+        sub /= L;
+        const int m = L * bc[a] + L / 2 + j;
+        xq[a] = ((float)m + 0.5f) * (g.dx / (float)L);
+    }
+}
+
+// one thread per (sample, offset in -2..2 per axis): marks the sample's
+// stencil nodes in I (offsets 0..2) and the stencil bases within two cells
+// (their lattice points touch I), appending each newly marked base once
+template <int D>
+__global__ void eul_mark_kernel(GridK g, int ns_max, const int32_t *n_samples, const float *xs,
+                                uint32_t *bitmap, uint32_t *qb_bitmap, int64_t words,
+                                int32_t *qbase, int64_t qb_cap, int32_t *qb_count,
+                                int32_t *status)
+{
+    constexpr int NO = (D == 3) ? 125 : 25;
+    const int b = blockIdx.y;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = (int)(t / NO), o = (int)(t % NO);
+    if (k >= ns_max || k >= n_samples[b]) return;
+    float xp[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) xp[a] = xs[((int64_t)b * D + a) * ns_max + k];
+    Stencil<D> st;
+    if (!make_stencil<D>(g, xp, st)) {
+        if (o == 0) atomicOr(status + b, MR_FLAG_DOMAIN);
+        return;
+    }
+    const int n[3] = {g.n0, g.n1, g.n2};
+    int off[3] = {o % 5 - 2, (o / 5) % 5 - 2, D == 3 ? o / 25 - 2 : 0};
+    int q[3] = {0, 0, 0};
+    bool node = true, valid = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        q[a] = st.base[a] + off[a];
+        node = node && off[a] >= 0;
+        valid = valid && q[a] >= 0 && q[a] + 2 <= n[a] - 1;
+    }
+    const int64_t i = node_lin(g, q[0], q[1], q[2]);
+    if (node) atomicOr(bitmap + (int64_t)b * words + (i >> 5), 1u << (i & 31));
+    if (!valid) return;
+    const uint32_t bit = 1u << (i & 31);
+    const uint32_t old = atomicOr(qb_bitmap + (int64_t)b * words + (i >> 5), bit);
+    if (old & bit) return;
+    const int32_t pos = atomicAdd(qb_count + b, 1);
+    if (pos < qb_cap)
+        qbase[(int64_t)b * qb_cap + pos] = (int32_t)i;
+    else
+        atomicOr(status + b, MR_FLAG_DOMAIN);  // capacity exceeded
+}
+
+__global__ void eul_count_kernel(int B, const int32_t *qb_count, int64_t qb_cap, int LD,
+                                 int32_t *q_count)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int64_t nb = qb_count[b] < qb_cap ? qb_count[b] : qb_cap;
+    q_count[b] = (int32_t)(nb * LD);
+}
+
+// Newton's starting point X = x^Q
+template <int D>
+__global__ void eul_init_kernel(GridK g, int64_t q_cap, const int32_t *q_count,
+                                const int32_t *qbase, int64_t qb_cap, int L, int LD, float *XQ)
+{
+    const int b = blockIdx.y;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= q_count[b]) return;
+    float xq[D];
+    eul_point<D>(g, qbase[(int64_t)b * qb_cap + s / LD], (int)(s % LD), L, xq);
+#pragma unroll
+    for (int a = 0; a < D; ++a) XQ[((int64_t)b * D + a) * q_cap + s] = xq[a];
+}
+
+// determinant and solution of F y = r (Cramer's rule, d <= 3)
+template <int D>
+__device__ __forceinline__ float solve_small(const float *F, const float *r, float *y)
+{
+    if (D == 2) {
+        const float det = F[0] * F[3] - F[1] * F[2];
+        const float inv = 1.0f / det;
+        y[0] = (F[3] * r[0] - F[1] * r[1]) * inv;
+        y[1] = (F[0] * r[1] - F[2] * r[0]) * inv;
+        return det;
+    }
+    const float c00 = F[4] * F[8] - F[5] * F[7];
+    const float c01 = F[5] * F[6] - F[3] * F[8];
+    const float c02 = F[3] * F[7] - F[4] * F[6];
+    const float det = F[0] * c00 + F[1] * c01 + F[2] * c02;
+    const float inv = 1.0f / det;
+    // y = adj(F) r / det, adj(F) = cofactor matrix transposed
+    const float c10 = F[2] * F[7] - F[1] * F[8];
+    const float c11 = F[0] * F[8] - F[2] * F[6];
+    const float c12 = F[1] * F[6] - F[0] * F[7];
+    const float c20 = F[1] * F[5] - F[2] * F[4];
+    const float c21 = F[2] * F[3] - F[0] * F[5];
+    const float c22 = F[0] * F[4] - F[1] * F[3];
+    y[0] = (c00 * r[0] + c10 * r[1] + c20 * r[2]) * inv;
+    y[1] = (c01 * r[0] + c11 * r[1] + c21 * r[2]) * inv;
+    y[2] = (c02 * r[0] + c12 * r[1] + c22 * r[2]) * inv;
+    return det;
+}
+
+template <int D>
+__device__ __forceinline__ float det_small(const float *F)
+{
+    if (D == 2) return F[0] * F[3] - F[1] * F[2];
+    return F[0] * (F[4] * F[8] - F[5] * F[7]) + F[1] * (F[5] * F[6] - F[3] * F[8]) +
+           F[2] * (F[3] * F[7] - F[4] * F[6]);
+}
+
+// one Newton step X <- X - F^{-1} (g(X) - x^Q) from the decoded g and F
+template <int D>
+__global__ void eul_newton_kernel(GridK g, int64_t q_cap, const int32_t *q_count,
+                                  const int32_t *qbase, int64_t qb_cap, int L, int LD,
+                                  const float *xg, const float *FQ, float *XQ)
+{
+    const int b = blockIdx.y;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= q_count[b]) return;
+    float xq[D], r[D], F[D * D], y[D];
+    eul_point<D>(g, qbase[(int64_t)b * qb_cap + s / LD], (int)(s % LD), L, xq);
+#pragma unroll
+    for (int a = 0; a < D; ++a) r[a] = xg[((int64_t)b * D + a) * q_cap + s] - xq[a];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) F[k] = FQ[((int64_t)b * D * D + k) * q_cap + s];
+    const float det = solve_small<D>(F, r, y);
+    if (!(det != 0.0f) || !isfinite(det)) return;   // left as is; rejected at the end
+#pragma unroll
+    for (int a = 0; a < D; ++a) XQ[((int64_t)b * D + a) * q_cap + s] -= y[a];
+}
+
+// acceptance and mass; the point's position becomes the exact lattice point
+template <int D>
+__global__ void eul_finish_kernel(GridK g, int64_t q_cap, const int32_t *q_count,
+                                  const int32_t *qbase, int64_t qb_cap, int L, int LD,
+                                  const float *XQ, float *xQ, const float *FQ,
+                                  const uint32_t *occ, float rho0_vq, float tol, float *mQ)
+{
+    const int b = blockIdx.y;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= q_count[b]) return;
+    float xq[D], F[D * D];
+    eul_point<D>(g, qbase[(int64_t)b * qb_cap + s / LD], (int)(s % LD), L, xq);
+    float res = 0.0f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int64_t o = ((int64_t)b * D + a) * q_cap + s;
+        res = fmaxf(res, fabsf(xQ[o] - xq[a]));
+        xQ[o] = xq[a];
+    }
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) F[k] = FQ[((int64_t)b * D * D + k) * q_cap + s];
+    const float J = det_small<D>(F);
+    const int n[3] = {g.n0, g.n1, g.n2};
+    int c[3] = {0, 0, 0};
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const float cf = floorf(XQ[((int64_t)b * D + a) * q_cap + s] * g.inv_dx);
+        inside = inside && cf >= 0.0f && cf <= (float)(n[a] - 2);
+        c[a] = inside ? (int)cf : 0;
+    }
+    if (inside) {
+        const int64_t i = node_lin(g, c[0], c[1], c[2]);
+        inside = (occ[i >> 5] >> (i & 31)) & 1u;
+    }
+    const bool keep = res <= tol && J > 0.0f && inside;
+    mQ[(int64_t)b * q_cap + s] = keep ? rho0_vq / J : 0.0f;
+}
+
 __global__ void fill_u32_kernel(uint32_t *a, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -382,6 +598,64 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
     sample_kernel<<<gs, TB, 0, st>>>(R->cfg.seed, R->counter, R->P, (int)R->ns_max, R->n_samples,
                                       R->internal_of, R->samples);
     MR_LAUNCH_CHECK();
+    dim3 gq((unsigned)ceil_div(R->q_cap, TB), (unsigned)B);
+    float inv_rho0 = 1.0f / R->cfg.rho0;
+    if (R->quad == MR_QUAD_EULERIAN) {
+        // Algorithm 4
+        const int L = R->ell;
+        const int LD = d == 3 ? L * L * L : L * L;
+        fill_u32_kernel<<<2048, TB, 0, st>>>(R->qb_bitmap, (int64_t)B * R->words);
+        fill_u32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>((uint32_t *)R->qb_count, B);
+        rc = decode_jac_ex(R->dec, B, R->P, R->X, R->ns_max, R->samples, 1, R->n_samples, xhat,
+                           nullptr, R->xs, nullptr, nullptr, nullptr, st);
+        if (rc != MR_OK) return rc;
+        const int no = d == 3 ? 125 : 25;
+        dim3 gm((unsigned)ceil_div(R->ns_max * no, TB), (unsigned)B);
+        if (d == 2)
+            eul_mark_kernel<2><<<gm, TB, 0, st>>>(g, (int)R->ns_max, R->n_samples, R->xs, R->bitmap,
+                                                  R->qb_bitmap, R->words, R->qbase, R->qb_cap,
+                                                  R->qb_count, R->status_step);
+        else
+            eul_mark_kernel<3><<<gm, TB, 0, st>>>(g, (int)R->ns_max, R->n_samples, R->xs, R->bitmap,
+                                                  R->qb_bitmap, R->words, R->qbase, R->qb_cap,
+                                                  R->qb_count, R->status_step);
+        eul_count_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>(B, R->qb_count, R->qb_cap, LD,
+                                                                   R->q_count);
+        if (d == 2)
+            eul_init_kernel<2><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap, L,
+                                                  LD, R->XQ);
+        else
+            eul_init_kernel<3><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap, L,
+                                                  LD, R->XQ);
+        MR_LAUNCH_CHECK();
+        const int64_t xstr = (int64_t)d * R->q_cap;
+        for (int it = 0; it < R->newton_iters; ++it) {
+            rc = decode_jac_ex(R->dec, B, R->q_cap, R->XQ, R->q_cap, nullptr, 0, R->q_count, xhat,
+                               nullptr, R->xQ, R->FQ, nullptr, nullptr, st, 0, xstr);
+            if (rc != MR_OK) return rc;
+            if (d == 2)
+                eul_newton_kernel<2><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap,
+                                                        L, LD, R->xQ, R->FQ, R->XQ);
+            else
+                eul_newton_kernel<3><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap,
+                                                        L, LD, R->xQ, R->FQ, R->XQ);
+            MR_LAUNCH_CHECK();
+        }
+        rc = decode_jac_ex(R->dec, B, R->q_cap, R->XQ, R->q_cap, nullptr, 0, R->q_count, xhat,
+                           vhat, R->xQ, R->FQ, R->vQ, nullptr, st, 0, xstr);
+        if (rc != MR_OK) return rc;
+        const float vq = d == 3 ? (g.dx / L) * (g.dx / L) * (g.dx / L) : (g.dx / L) * (g.dx / L);
+        const float tol = R->newton_tol * g.dx;
+        if (d == 2)
+            eul_finish_kernel<2><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap, L,
+                                                    LD, R->XQ, R->xQ, R->FQ, R->occ,
+                                                    R->cfg.rho0 * vq, tol, R->mQ);
+        else
+            eul_finish_kernel<3><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap, L,
+                                                    LD, R->XQ, R->xQ, R->FQ, R->occ,
+                                                    R->cfg.rho0 * vq, tol, R->mQ);
+        MR_LAUNCH_CHECK();
+    } else {
     // Algorithm 3: decode every particle, mark I, collect Q
     rc = rom_decode(R->dec, B, R->P, R->X, R->P, nullptr, xhat, R->x_all, st);
     if (rc != MR_OK) return rc;
@@ -404,19 +678,19 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
     rc = decode_jac_ex(R->dec, B, R->P, R->X, R->q_cap, R->Q, 1, R->q_count, xhat, vhat, R->xQ,
                        R->FQ, R->vQ, nullptr, st);
     if (rc != MR_OK) return rc;
+    }
     // Algorithm 5
-    dim3 gq((unsigned)ceil_div(R->q_cap, TB), (unsigned)B);
-    float inv_rho0 = 1.0f / R->cfg.rho0;
+    const bool eul = R->quad == MR_QUAD_EULERIAN;
     if (d == 2)
         p2g_quad_kernel<2><<<gq, TB, 0, st>>>(g, R->q_cap, R->words, R->q_count, R->Q, R->xQ, R->FQ,
-                                              R->vQ, R->m, R->cfg.m_uniform, inv_rho0, R->E,
-                                              R->cfg.nu, R->cfg.model, (float)dt, R->bitmap,
-                                              R->grid, R->nodes, R->status_step);
+                                              R->vQ, R->m, eul ? R->mQ : nullptr, R->cfg.m_uniform,
+                                              inv_rho0, R->E, R->cfg.nu, R->cfg.model, (float)dt,
+                                              R->bitmap, R->grid, R->nodes, R->status_step);
     else
         p2g_quad_kernel<3><<<gq, TB, 0, st>>>(g, R->q_cap, R->words, R->q_count, R->Q, R->xQ, R->FQ,
-                                              R->vQ, R->m, R->cfg.m_uniform, inv_rho0, R->E,
-                                              R->cfg.nu, R->cfg.model, (float)dt, R->bitmap,
-                                              R->grid, R->nodes, R->status_step);
+                                              R->vQ, R->m, eul ? R->mQ : nullptr, R->cfg.m_uniform,
+                                              inv_rho0, R->E, R->cfg.nu, R->cfg.model, (float)dt,
+                                              R->bitmap, R->grid, R->nodes, R->status_step);
     if (d == 2)
         g2p_trial_kernel<2><<<gs, TB, 0, st>>>(g, (int)R->ns_max, R->n_samples, R->xs, R->grid,
                                                R->nodes, (float)dt, R->xt, R->vt);
@@ -446,7 +720,8 @@ extern "C" void rom_destroy(mr_rom *R)
     void *bufs[] = {R->X, R->m, R->E, R->internal_of, R->n_samples, R->samples, R->x_all,
                     R->bitmap, R->Q,
                     R->q_count, R->n_active, R->xQ, R->FQ, R->vQ, R->grid, R->xs, R->xt, R->vt,
-                    R->z_next, R->v_next, R->status_step, R->counter, R->proj_ws};
+                    R->z_next, R->v_next, R->status_step, R->counter, R->proj_ws,
+                    R->qb_bitmap, R->qbase, R->qb_count, R->XQ, R->mQ, R->occ};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     if (R->graph) (void)hipGraphExecDestroy(R->graph);
@@ -470,6 +745,15 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
         return MR_EINVAL;
     if (cfg->model == MR_FIXED_COROTATED && d != 2) return MR_EINVAL;
     if ((int64_t)cfg->B * (opts->max_backtrack + 1) > 65535) return MR_EINVAL;
+    if (cfg->quadrature != MR_QUAD_LAGRANGIAN && cfg->quadrature != MR_QUAD_EULERIAN)
+        return MR_EINVAL;
+    const int ell = cfg->quad_per_dim == 0 ? 2 : cfg->quad_per_dim;
+    const int newton_iters = cfg->newton_iters == 0 ? 4 : cfg->newton_iters;
+    const float newton_tol = cfg->newton_tol == 0.0f ? 1e-3f : cfg->newton_tol;
+    if (cfg->quadrature == MR_QUAD_EULERIAN &&
+        ((ell != 2 && ell != 4) || newton_iters < 1 || newton_iters > 16 ||
+         !(newton_tol > 0.0f) || !(newton_tol < 1.0f)))
+        return MR_EINVAL;
     mr_rom *R = (mr_rom *)calloc(1, sizeof(mr_rom));
     if (!R) return MR_ENOMEM;
     R->dec = dec;
@@ -483,10 +767,26 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
     R->ns_max = cfg->n_samples_max;
     R->nodes = grid_nodes(g);
     R->words = ceil_div(R->nodes, 32);
+    R->quad = cfg->quadrature;
+    R->ell = ell;
+    R->newton_iters = newton_iters;
+    R->newton_tol = newton_tol;
+    const bool eul = R->quad == MR_QUAD_EULERIAN;
     // quadrature capacity: every sample's 3^d nodes are reached from a
-    // (5 cells)^d box; allow 16 particles per cell
-    int64_t per = (d == 3) ? 125 * 16 : 25 * 16;
-    R->q_cap = R->ns_max * per < R->P ? R->ns_max * per : R->P;
+    // (5 cells)^d box of stencil bases; Lagrangian: allow 16 particles per
+    // cell; Eulerian: every base of the box, l^d points each
+    const int64_t box = (d == 3) ? 125 : 25;
+    if (eul) {
+        R->qb_cap = R->ns_max * box < R->nodes ? R->ns_max * box : R->nodes;
+        R->q_cap = R->qb_cap * (d == 3 ? ell * ell * ell : ell * ell);
+    } else {
+        const int64_t per = box * 16;
+        R->q_cap = R->ns_max * per < R->P ? R->ns_max * per : R->P;
+    }
+    if (R->q_cap > INT32_MAX) {
+        free(R);
+        return MR_EINVAL;
+    }
     const int64_t B = R->B, P = R->P;
     bool ok = true;
     auto alloc = [&](void **p, int64_t bytes) {
@@ -498,9 +798,18 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
     alloc((void **)&R->E, 4 * B);
     alloc((void **)&R->n_samples, 4 * B);
     alloc((void **)&R->samples, 4 * B * R->ns_max);
-    alloc((void **)&R->x_all, 4 * B * d * P);
+    if (!eul) {
+        alloc((void **)&R->x_all, 4 * B * d * P);
+        alloc((void **)&R->Q, 4 * B * R->q_cap);
+    } else {
+        alloc((void **)&R->qb_bitmap, 4 * B * R->words);
+        alloc((void **)&R->qbase, 4 * B * R->qb_cap);
+        alloc((void **)&R->qb_count, 4 * B);
+        alloc((void **)&R->XQ, 4 * B * d * R->q_cap);
+        alloc((void **)&R->mQ, 4 * B * R->q_cap);
+        alloc((void **)&R->occ, 4 * R->words);
+    }
     alloc((void **)&R->bitmap, 4 * B * R->words);
-    alloc((void **)&R->Q, 4 * B * R->q_cap);
     alloc((void **)&R->q_count, 4 * B);
     alloc((void **)&R->xQ, 4 * B * d * R->q_cap);
     alloc((void **)&R->FQ, 4 * B * d * d * R->q_cap);
@@ -563,6 +872,23 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
         cp = hipMemcpy(R->X, Xs.data(), 4 * d * P, hipMemcpyHostToDevice) == hipSuccess &&
              hipMemcpy(R->internal_of, inv.data(), 4 * P, hipMemcpyHostToDevice) == hipSuccess &&
              (!m_all || hipMemcpy(R->m, ms.data(), 4 * P, hipMemcpyHostToDevice) == hipSuccess);
+        if (cp && eul) {
+            // reference body: cells c = floor(X / dx) holding a particle
+            std::vector<uint32_t> occ(R->words, 0u);
+            for (int64_t p = 0; p < P; ++p) {
+                int64_t c[3] = {0, 0, 0};
+                bool in = true;
+                for (int a = 0; a < d; ++a) {
+                    const float cf = floorf(Xh[(size_t)a * P + p] * g.inv_dx);
+                    in = in && cf >= 0.0f && cf <= (float)(nn[a] - 2);
+                    c[a] = in ? (int64_t)cf : 0;
+                }
+                if (!in) continue;
+                const int64_t i = c[0] + (int64_t)g.n0 * (c[1] + (int64_t)g.n1 * c[2]);
+                occ[i >> 5] |= 1u << (i & 31);
+            }
+            cp = hipMemcpy(R->occ, occ.data(), 4 * R->words, hipMemcpyHostToDevice) == hipSuccess;
+        }
     }
     cp = cp && hipMemcpy(R->E, E, 4 * B, hipMemcpyDeviceToDevice) == hipSuccess &&
          hipMemcpy(R->n_samples, n_samples, 4 * B, hipMemcpyDeviceToDevice) == hipSuccess;
@@ -574,8 +900,10 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
         // the four decoder launches of a step: every particle (positions),
         // the quadrature list (x, F, v), the samples (latent Jacobian) and
         // the line-search candidates (positions)
+        // (Eulerian: the samples (positions) and the lattice points (x, F, v)
+        // instead of every particle)
         const int32_t nc = opts->max_backtrack + 1;
-        int32_t rc = decoder_autotune(dec, (int32_t)B, P, 1, 3, R->cap_stream);
+        int32_t rc = decoder_autotune(dec, (int32_t)B, eul ? R->ns_max : P, 1, 3, R->cap_stream);
         if (rc == MR_OK) rc = decoder_autotune(dec, (int32_t)B, R->q_cap, 2, 3, R->cap_stream);
         if (rc == MR_OK) rc = decoder_autotune(dec, (int32_t)B, R->ns_max, 4, 3, R->cap_stream);
         if (rc == MR_OK) rc = decoder_autotune(dec, (int32_t)B * nc, R->ns_max, 1, 3, R->cap_stream);

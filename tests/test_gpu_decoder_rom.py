@@ -278,6 +278,129 @@ def test_rom_step_matches_oracle(gpu):
     rom.close()
 
 
+def test_rom_step_eulerian_translation_closed_form(gpu):
+    """Eulerian quadrature (Algorithm 4) with g = X + xhat: every lattice
+    point inverts exactly, carries F = I and the instance velocity, and every
+    stencil node of a sample gets mass from points inside the body, so the
+    ROM reproduces the free-fall closed form."""
+    s = _rom_inputs(cube=16)
+    d = 3
+    W = np.concatenate([np.zeros((d, d)), np.eye(d)], axis=1).astype(np.float32)
+    X = s["X"]
+    lo, hi = X.min(0), X.max(0)
+    gdec = B.Decoder([W], [np.zeros(d, np.float32)], lo, hi, np.zeros(d), np.ones(d))
+    grid = B.Grid(3, s["n"], s["dx"], 0, B.FLOOR_STICKY, 0.0, s["gravity"])
+    E = T(np.array([5e4, 1e4], np.float32))
+    ns = T(np.array([16, 8], np.int32), torch.int32)
+    for use_graph in (False, True):
+        for mode in (B.POS_VEL, B.VEL_ONLY):
+            rom = B.Rom(gdec, grid, T(soa(X)), E, ns, B.gn_opts(mode=mode, max_iter=2), seed=3,
+                        rho0=1000.0, m_uniform=float(s["m"]), quadrature=B.QUAD_EULERIAN)
+            z = torch.zeros(2, 3, dtype=torch.float64, device=dev)
+            zp = z.clone()
+            v0 = np.array([[0.1, -0.5, 0.2], [0.0, 0.3, -0.1]])
+            vh = T(v0, torch.float64)
+            st = torch.zeros(2, dtype=torch.int32, device=dev)
+            nst = 6
+            rom.step(nst, 0, s["dt"], z, zp, vh, status=st, use_graph=use_graph)
+            g = np.array(s["gravity"])
+            dt = s["dt"]
+            vexp = v0 + nst * dt * g
+            zexp = nst * dt * v0 + dt * dt * g * nst * (nst + 1) / 2
+            ev = np.max(np.abs(vh.cpu().numpy() - vexp))
+            ez = np.max(np.abs(z.cpu().numpy() - zexp))
+            q, a = rom.last_counts(0)
+            print("eulerian graph %d mode %d: |v - closed form| %.2e |z - closed form| %.2e; "
+                  "lattice points %d, active nodes %d" % (use_graph, mode, ev, ez, q, a))
+            assert st.cpu().numpy().tolist() == [0, 0]
+            assert ev < 1e-5 and ez < 1e-8
+            assert q % 8 == 0 and q > 0
+            rom.close()
+
+
+def eulerian_oracle_run(s, odec, Es, nss, z0, v0, nst, seed, ell=2, iters=4):
+    """The oracle's ROM steps with Eulerian quadrature for each instance, and
+    the smallest distance (in cells) of a kept-or-dropped point's reference
+    position to a cell face across which the reference body changes (where
+    a rounding difference could flip the body test)."""
+    from oracle import mpm as OM
+    sc = oracle_scene(s)
+    P = s["P"]
+    Xd = s["X"].astype(np.float32).astype(np.float64)
+    n, dx = sc["n"], sc["dx"]
+    occ = OR.reference_occupancy(3, n, dx, Xd)
+    out, margin = [], np.inf
+    for b in range(len(Es)):
+        sc_b = dict(sc)
+        sc_b["mu"], sc_b["la"] = OM.lame(float(Es[b]), s["nu"])
+        zz, zzp, vv = z0[b].copy(), z0[b].copy(), v0[b].copy()
+        oopts = OP.GNOptions(mode=OP.MODE_POS_VEL, max_iter=3, fixed_iters=True)
+        for k in range(nst):
+            samples = OR.sample_indices(seed, b, k, int(nss[b]), P)
+            zn, vn, info = OR.rom_step(odec, sc_b, Xd, None, None, zz, zzp, vv, s["dt"], samples,
+                                       oopts, quadrature="eulerian", ell=ell, newton_iters=iters,
+                                       rho0=1000.0, occupied=occ)
+            Xa = info["eulerian"]["X_all"] / dx
+            c = np.floor(Xa).astype(np.int64)
+            for a in range(3):
+                for side in (0, 1):
+                    nb = c.copy()
+                    nb[:, a] += 1 if side else -1
+                    ok = np.all((nb >= 0) & (nb <= np.asarray(n) - 2), axis=1) & \
+                        np.all((c >= 0) & (c <= np.asarray(n) - 2), axis=1)
+                    lin = lambda t: t[:, 0] + n[0] * (t[:, 1] + n[1] * t[:, 2])
+                    diff = np.zeros(len(c), dtype=bool)
+                    diff[ok] = occ[lin(c[ok])] != occ[lin(nb[ok])]
+                    dist = (Xa[:, a] - c[:, a]) if side == 0 else (c[:, a] + 1 - Xa[:, a])
+                    if diff.any():
+                        margin = min(margin, float(dist[diff].min()))
+            zzp, zz, vv = zz, zn, vn
+        out.append((zz, vv, info))
+    return out, margin
+
+
+def test_rom_step_eulerian_matches_oracle(gpu):
+    """Random fp32 decoder, 3D scene on a 32^3 grid, two instances, 3 steps
+    with Eulerian quadrature (l = 2, 4 Newton iterations) against the
+    oracle.  The decoder seed is one where no reference position lies
+    within 3e-5 cells of a face across which the reference body changes
+    (fp32 Newton and decoding move it by about 2e-6 cells), so both sides
+    take the same body decisions."""
+    s = _rom_inputs(seed=6)
+    d, r = 3, 8
+    X = s["X"]
+    odec, gdec = make_decoder(d, r, 32, 3, 52, X, out_std=0.01)
+    grid = B.Grid(3, s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
+    Es = np.array([5e4, 2e4], np.float32)
+    nss = np.array([24, 12], np.int32)
+    opts = B.gn_opts(mode=B.POS_VEL, max_iter=3)
+    rom = B.Rom(gdec, grid, T(soa(X)), T(Es), T(nss, torch.int32), opts, seed=99, rho0=1000.0,
+                m_uniform=float(s["m"]), quadrature=B.QUAD_EULERIAN)
+    rng = np.random.default_rng(52)
+    z0 = 0.2 * rng.standard_normal((2, r))
+    v0 = 0.5 * rng.standard_normal((2, r))
+    z = T(z0, torch.float64)
+    zp = T(z0, torch.float64)
+    vh = T(v0, torch.float64)
+    st = torch.zeros(2, dtype=torch.int32, device=dev)
+    nst = 3
+    rom.step(nst, 0, s["dt"], z, zp, vh, status=st)
+    q, a = rom.last_counts(0)
+    ref, margin = eulerian_oracle_run(s, odec, Es, nss, z0, v0, nst, 99)
+    print("oracle lattice points %d |I| %d ; gpu %d %d; body-face margin %.2e cells"
+          % (ref[0][2]["eulerian"]["n_candidates"], len(ref[0][2]["I"]), q, a, margin))
+    assert margin > 3e-5
+    for b in range(2):
+        zz, vv, _ = ref[b]
+        dz = np.max(np.abs(z.cpu().numpy()[b] - zz))
+        ez = dz / (1.0 + np.max(np.abs(zz)))
+        ev = np.max(np.abs(vh.cpu().numpy()[b] - vv)) / np.max(np.abs(vv))
+        print("instance %d: latent err %.2e, velocity err %.2e" % (b, ez, ev))
+        assert ez < 1e-5 and ev < 1e-3
+    assert st.cpu().numpy().tolist() == [0, 0]
+    rom.close()
+
+
 def test_linear_decoder_matches_oracle(gpu):
     """Decoder without hidden layers (the linear-manifold baseline)."""
     d, r = 3, 6
