@@ -96,6 +96,8 @@ def main():
                          "model (0: skip)")
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--rom-batched-steps", type=int, default=4)
+    ap.add_argument("--rom-pareto-steps", type=int, default=30,
+                    help="steps per point of the quadrature / samples / projection sweep (0: off)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB ten times (the reference "
                          "kernel that scales the HBM byte counters)")
@@ -210,6 +212,8 @@ def main():
     }
     if not args.no_rom:
         out["rom"] = rom_throughput(B, scenes, s, args.rom_steps)
+        if args.rom_pareto_steps > 0:
+            out["rom_pareto"] = rom_pareto(B, scenes, s, args.rom_pareto_steps)
         if args.rom_instances > 0:
             out["rom_batched"] = rom_batched_throughput(B, scenes, s, args.rom_instances,
                                                         args.rom_batched_steps)
@@ -223,16 +227,20 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden=5):
+def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden=5,
+                   quadrature=None, mode=None):
     """Reduced-order steps on the same 2,097,152-particle scene: one
     instance, r = 16, 512 sample points per step, Lagrangian quadrature
     (all particles decoded to find the neighbours), bf16 decoder of width
     128 with 5 hidden layers, position-velocity projection with 3
     Gauss-Newton iterations (damping 1e-4); the per-step launches are
     replayed from a HIP graph.  The decoder here is randomly initialised
-    (throughput only; the trained leg measures accuracy)."""
+    (throughput only; the trained leg measures accuracy).  quadrature and
+    mode select the Eulerian quadrature and the velocity-only projection."""
     import torch
     dev = "cuda:0"
+    quadrature = B.QUAD_LAGRANGIAN if quadrature is None else quadrature
+    mode = B.POS_VEL if mode is None else mode
     X = s["X"]
     P = s["P"]
     Ws, bs = scenes.xavier_decoder(3, r, width, n_hidden, 11)
@@ -243,9 +251,8 @@ def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden
     Xg = torch.tensor(np.ascontiguousarray(X.T), device=dev)
     E = torch.tensor([s["E"]], dtype=torch.float32, device=dev)
     ns = torch.tensor([n_samples], dtype=torch.int32, device=dev)
-    rom = B.Rom(dec, grid, Xg, E, ns, B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4), seed=4,
-                rho0=1000.0,
-                m_uniform=float(s["m"]), autotune=True)
+    rom = B.Rom(dec, grid, Xg, E, ns, B.gn_opts(mode=mode, max_iter=3, damping=1e-4), seed=4,
+                rho0=1000.0, m_uniform=float(s["m"]), autotune=True, quadrature=quadrature)
     shapes = decoder_shapes(dec, 1, P, n_samples)
     z = torch.zeros(1, r, dtype=torch.float64, device=dev)
     zp = z.clone()
@@ -275,9 +282,31 @@ def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden
             "n_quadrature_points": int(n_quad), "n_active_nodes": int(n_active),
             "config": {"instances": 1, "particles": P, "samples": n_samples, "r": r,
                        "decoder": "bf16 MLP %d x %d, random init" % (width, n_hidden),
-                       "projection": "position-velocity, 3 Gauss-Newton iterations",
+                       "quadrature": "Eulerian (l = 2, 4 Newton iterations)"
+                       if quadrature == B.QUAD_EULERIAN else "Lagrangian",
+                       "projection": "position-velocity, 3 Gauss-Newton iterations"
+                       if mode == B.POS_VEL else "velocity only",
                        "graph": "HIP graph of %d steps" % k},
             "displacement_error": None}
+
+
+def rom_pareto(B, scenes, s, steps):
+    """Latent steps/s over the paper's axes of the reduced model's cost:
+    quadrature (Lagrangian: every particle decoded each step; Eulerian:
+    samples and lattice points only), sample count and projection scheme,
+    on the 2.1M-particle scene with the randomly initialised decoder."""
+    rows = []
+    for quad, qn in ((B.QUAD_LAGRANGIAN, "lagrangian"), (B.QUAD_EULERIAN, "eulerian")):
+        for ns in (50, 512):
+            for mode, mn in ((B.POS_VEL, "position-velocity"), (B.VEL_ONLY, "velocity-only")):
+                r = rom_throughput(B, scenes, s, steps, n_samples=ns, quadrature=quad, mode=mode)
+                rows.append({"quadrature": qn, "samples": ns, "projection": mn,
+                             "latent_steps_per_s": round(r["value"], 1),
+                             "ms_per_step": round(r["ms_per_step"], 4),
+                             "quadrature_points": r["n_quadrature_points"],
+                             "active_nodes": r["n_active_nodes"]})
+                log("pareto:", json.dumps(rows[-1]))
+    return rows
 
 
 def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_hidden=5,
@@ -313,8 +342,26 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
     x_rom, st = EV.rom_positions(dec, s, E, v0, n_steps, 10, n_samples=n_samples,
                                  opts=B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4),
                                  z_guess=Z[0])
-    dec.close()
     err, pos = EV.displacement_error(x_rom, fom, s["X"])
+    # the same decoder under the other quadrature and the paper's fast
+    # configuration (few samples, velocity-only projection)
+    variants = []
+    for qn, quad, ns, mode, mn in (("eulerian", B.QUAD_EULERIAN, n_samples, B.POS_VEL,
+                                    "position-velocity"),
+                                   ("lagrangian", B.QUAD_LAGRANGIAN, 50, B.VEL_ONLY,
+                                    "velocity-only"),
+                                   ("eulerian", B.QUAD_EULERIAN, 50, B.VEL_ONLY, "velocity-only")):
+        xr, sv = EV.rom_positions(dec, s, E, v0, n_steps, 10, n_samples=ns,
+                                  opts=B.gn_opts(mode=mode, max_iter=3, damping=1e-4),
+                                  z_guess=Z[0], quadrature=quad)
+        e2, p2 = EV.displacement_error(xr, fom, s["X"])
+        variants.append({"quadrature": qn, "samples": ns, "projection": mn,
+                         "latent_steps_per_s": round(1e3 / sv["ms_per_step"], 1),
+                         "ms_per_step": round(sv["ms_per_step"], 4),
+                         "displacement_error": round(e2, 4), "position_error_percent": round(p2, 4),
+                         "status": sv["status"]})
+        log("trained variant:", json.dumps(variants[-1]))
+    dec.close()
     return {"metric": "ROM latent steps/s at the measured displacement error",
             "value": float(1e3 / st["ms_per_step"]), "unit": "latent steps/s",
             "ms_per_step": st["ms_per_step"], "displacement_error": err,
@@ -325,7 +372,9 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
             "config": {"instances": 1, "particles": s["P"], "samples": n_samples, "r": r,
                        "decoder": "bf16 MLP %d x %d, trained" % (width, n_hidden),
                        "projection": "position-velocity, 3 Gauss-Newton iterations, damping 1e-4",
-                       "reference": "full-order model without the affine transfer term"}}
+                       "quadrature": "Lagrangian",
+                       "reference": "full-order model without the affine transfer term"},
+            "variants": variants}
 
 
 SHAPE_NAMES = ["1 point tile per wave", "2 point tiles per wave", "4 point tiles per wave",

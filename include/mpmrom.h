@@ -367,7 +367,7 @@ typedef struct {
     int32_t quad_per_dim;    /* Eulerian: points per cell and dimension,
                                 2 or 4 (0 selects 2)                      */
     int32_t newton_iters;    /* Eulerian: Newton iterations inverting the
-                                decoder, 1..16 (0 selects 4)              */
+                                decoder, 1..16 (0 selects 2)              */
     float newton_tol;        /* Eulerian: largest residual max-norm of an
                                 accepted point, in cells (0 selects 1e-3) */
 } mr_rom_config;
@@ -381,8 +381,12 @@ typedef struct {
  * samples' nodes, their reference positions X solve g(X; xhat) = x by
  * Newton's method from X = x (newton_iters iterations with F = dg/dX), and
  * a point is kept when the residual is within newton_tol cells, det F > 0
- * and X lies in the reference body (the grid cells holding a reference
- * particle); its mass is rho0 (dx / l)^d / det F. */
+ * and the reference density at X is positive; its mass is that density
+ * times (dx / l)^d / det F.  The reference density is the reference
+ * particles' mass spread with the quadratic B-spline on a lattice of
+ * spacing dx / l, read by multilinear interpolation (rho0 inside a body
+ * sampled at that spacing, tapering to 0 over one spacing at its surface);
+ * rom_create builds it on the host. */
 #define MR_QUAD_LAGRANGIAN 0
 #define MR_QUAD_EULERIAN 1
 

@@ -24,11 +24,15 @@ Readings:
   - The map is inverted by Newton's method on g(X; xhat) = x^Q with the
     Jacobian F = dg/dX, started at X = x^Q, for a fixed number of
     iterations; a point is kept when the final residual max-norm is within
-    a tolerance, det F > 0 and X lies in the reference body.  The reference
-    body is the set of grid cells (cell c = floor(X / dx)) holding at least
-    one reference particle.
-  - Mass m^Q = rho0 (dx / ell)^d / J and reference volume V0 = m^Q / rho0;
-    sample points are not quadrature points.
+    a tolerance, det F > 0 and X lies in the reference body.
+  - The reference body and its density come from the reference particles:
+    rho_ref is their mass spread with the quadratic B-spline on a lattice of
+    spacing h = dx / ell (nodes k h), read at X by multilinear
+    interpolation.  It equals rho0 inside a body sampled at spacing h
+    (partition of unity), tapers over about h at the surface and is 0
+    outside; m^Q = rho_ref(X) (dx / ell)^d / J (rho0 V / J in the interior)
+    and V0 = m^Q / rho0; a point with rho_ref(X) = 0 is discarded.
+    Sample points are not quadrature points.
 """
 import numpy as np
 
@@ -125,14 +129,56 @@ def active_nodes(dim, n, dx, x_samples):
     return np.unique(np.concatenate(nodes)) if len(base) else np.zeros(0, dtype=np.int64)
 
 
-def reference_occupancy(dim, n, dx, X_all):
-    """Reference body at grid resolution: flags over node-indexed cells
-    (cell c covers [c dx, (c + 1) dx)) holding a reference particle."""
-    c = np.floor(np.asarray(X_all, dtype=np.float64) / dx).astype(np.int64)
-    occ = np.zeros(int(np.prod(n)), dtype=bool)
-    ok = np.all((c >= 0) & (c <= np.asarray(n) - 2), axis=1)
-    occ[_linear(n, c[ok])] = True
-    return occ
+def density_lattice_shape(n, ell):
+    """Nodes per axis of the reference-density lattice (spacing dx / ell)."""
+    return [(na - 1) * ell + 1 for na in n]
+
+
+def reference_density(dim, n, dx, ell, X_all, m_all):
+    """rho_ref on the lattice of spacing h = dx / ell: sum over reference
+    particles of m_p N((X_k - X_p) / h) / h^d with the tensor quadratic
+    B-spline N (stencil base floor(X / h - 1/2)); particles whose stencil
+    leaves the lattice are skipped.  Returns a flat array (x fastest)."""
+    h = dx / ell
+    shape = density_lattice_shape(n, ell)
+    rho = np.zeros(int(np.prod(shape)))
+    X = np.asarray(X_all, dtype=np.float64)
+    m = np.broadcast_to(np.asarray(m_all, dtype=np.float64), (X.shape[0],))
+    base = np.floor(X / h - 0.5).astype(np.int64)
+    ok = np.all((base >= 0) & (base + 2 <= np.asarray(shape) - 1), axis=1)
+    X, m, base = X[ok], m[ok], base[ok]
+    f = X / h - base
+    # quadratic B-spline weights of the three nodes base..base+2 (the MPM
+    # kernel of Section 2.2) at offset f in [1/2, 3/2)
+    w = [np.stack([0.5 * (1.5 - f[:, a]) ** 2, 0.75 - (f[:, a] - 1.0) ** 2,
+                   0.5 * (f[:, a] - 0.5) ** 2], axis=1) for a in range(dim)]
+    for o in _offsets(dim):
+        wt = np.ones(len(X))
+        for a in range(dim):
+            wt = wt * w[a][:, o[a]]
+        np.add.at(rho, _linear(shape, base + o), m * wt / h ** dim)
+    return rho
+
+
+def density_at(rho, dim, n, dx, ell, X):
+    """Multilinear interpolation of the lattice density at points X (0
+    outside the lattice)."""
+    h = dx / ell
+    shape = np.asarray(density_lattice_shape(n, ell))
+    t = np.asarray(X, dtype=np.float64) / h
+    i0 = np.floor(t).astype(np.int64)
+    fr = t - i0
+    ok = np.all((i0 >= 0) & (i0 + 1 <= shape - 1), axis=1)
+    out = np.zeros(len(t))
+    for c in _offsets(dim):
+        if np.any(c > 1):
+            continue
+        wt = np.ones(len(t))
+        for a in range(dim):
+            wt = wt * np.where(c[a] == 1, fr[:, a], 1.0 - fr[:, a])
+        idx = np.where(ok[:, None], i0 + c, 0)
+        out += np.where(ok, wt * rho[_linear(list(shape), idx)], 0.0)
+    return out
 
 
 def quadrature_lattice(dim, n, dx, ell):
@@ -170,10 +216,11 @@ def invert_map(jac_fn, x_target, iters):
 
 
 def eulerian_quadrature(dec, dim, n, dx, x_samples, zhat, vhat, ell, iters, tol, rho0,
-                        occupied):
+                        rho_ref):
     """Algorithm 4: quadrature points, their reference positions (inverse
-    map), F, v and masses.  Returns a dict with the kept points' xQ, FQ, vQ,
-    mQ, V0Q, their reference positions XQ, and I and the candidate count."""
+    map), F, v and masses (rho_ref: reference_density on the lattice of
+    spacing dx / ell).  Returns a dict with the kept points' xQ, FQ, vQ, mQ,
+    V0Q, their reference positions XQ, and I and the candidate count."""
     I = active_nodes(dim, n, dx, x_samples)
     xq = eulerian_points(dim, n, dx, ell, I)
     jac = lambda X: _dec.decode_jac(dec, X, zhat)[:2]
@@ -181,24 +228,21 @@ def eulerian_quadrature(dec, dim, n, dx, x_samples, zhat, vhat, ell, iters, tol,
     x, F, _, v = _dec.decode_jac(dec, X, zhat, vhat)
     det = np.linalg.det(F) if len(F) else np.zeros(0)
     conv = np.max(np.abs(x - xq), axis=1) <= tol if len(x) else np.zeros(0, dtype=bool)
-    c = np.floor(X / dx).astype(np.int64)
-    in_lat = np.all((c >= 0) & (c <= np.asarray(n) - 2), axis=1)
-    inside = np.zeros(len(X), dtype=bool)
-    inside[in_lat] = occupied[_linear(n, c[in_lat])]
-    keep = conv & (det > 0.0) & inside
+    rho = density_at(rho_ref, dim, n, dx, ell, X)
+    keep = conv & (det > 0.0) & (rho > 0.0)
     Vq = (dx / ell) ** dim
-    m = rho0 * Vq / det[keep]
+    m = rho[keep] * Vq / det[keep]
     return {"xQ": xq[keep], "XQ": X[keep], "FQ": F[keep], "vQ": v[keep], "mQ": m,
             "V0Q": m / rho0, "I": I, "n_candidates": len(xq), "keep": keep,
-            "X_all": X, "x_candidates": xq}
+            "X_all": X, "x_candidates": xq, "rho": rho}
 
 
 def rom_step(dec, scene, X_all, m_all, V0_all, zhat, zhat_prev, vhat, dt,
-             samples, opts, quadrature="lagrangian", ell=2, newton_iters=4, newton_tol=None,
-             rho0=None, occupied=None):
+             samples, opts, quadrature="lagrangian", ell=2, newton_iters=2, newton_tol=None,
+             rho0=None, rho_ref=None):
     """One ROM step (Algorithm 2) with Lagrangian (Algorithm 3) or Eulerian
     (Algorithm 4) quadrature kinematics.  Returns (zhat_next, vhat_next,
-    info).  Eulerian: rho0 and the reference occupancy are required;
+    info).  Eulerian: rho0 and the reference density lattice are required;
     newton_tol defaults to 1e-3 dx."""
     dim, n, dx = scene["dim"], scene["n"], scene["dx"]
     samples = np.asarray(samples, dtype=np.int64)
@@ -206,7 +250,7 @@ def rom_step(dec, scene, X_all, m_all, V0_all, zhat, zhat_prev, vhat, dt,
         x_s = _dec.decode(dec, X_all[samples], zhat)
         tol = 1e-3 * dx if newton_tol is None else newton_tol
         eq = eulerian_quadrature(dec, dim, n, dx, x_s, zhat, vhat, ell, newton_iters, tol, rho0,
-                                 occupied)
+                                 rho_ref)
         x_trial, v_trial = substep(scene, eq["xQ"], eq["FQ"], eq["vQ"], eq["mQ"], eq["V0Q"], x_s,
                                    dt)
         info = {"I": eq["I"], "eulerian": eq}

@@ -27,9 +27,12 @@
 // per-instance list); expand every base into its l^d lattice points; invert
 // the decoder at them by Newton's method (decoder launches with the spatial
 // tangents, then a per-point d x d solve); decode x, F, v at the result and
-// keep a point (mass rho0 (dx / l)^d / det F) when the residual is small,
-// det F > 0 and its reference position lies in a reference cell holding a
-// particle.
+// keep a point when the residual is small, det F > 0 and the reference
+// density at its reference position is positive; its mass is that density
+// times (dx / l)^d / det F.  The reference density is the particles' mass
+// spread with the quadratic B-spline on a lattice of spacing dx / l (rho0
+// inside a body sampled at that spacing, tapering over one spacing at the
+// surface), built once at creation.
 #include "mpm_kernels.h"
 #include "project.h"
 
@@ -81,7 +84,8 @@ struct mr_rom {
     int32_t *qb_count;     // [B]
     float *XQ;             // [B][d][q_cap] reference positions (Newton iterate)
     float *mQ;             // [B][q_cap] point masses (0: discarded)
-    uint32_t *occ;         // [words] reference cells holding a particle
+    float *rho;            // reference density on the lattice of spacing dx / l
+    int rn[3];             // its nodes per axis
 };
 
 namespace mr {
@@ -518,8 +522,8 @@ __global__ void eul_newton_kernel(GridK g, int64_t q_cap, const int32_t *q_count
 template <int D>
 __global__ void eul_finish_kernel(GridK g, int64_t q_cap, const int32_t *q_count,
                                   const int32_t *qbase, int64_t qb_cap, int L, int LD,
-                                  const float *XQ, float *xQ, const float *FQ,
-                                  const uint32_t *occ, float rho0_vq, float tol, float *mQ)
+                                  const float *XQ, float *xQ, const float *FQ, const float *rho,
+                                  int rn0, int rn1, int rn2, float vq, float tol, float *mQ)
 {
     const int b = blockIdx.y;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -536,21 +540,38 @@ __global__ void eul_finish_kernel(GridK g, int64_t q_cap, const int32_t *q_count
 #pragma unroll
     for (int k = 0; k < D * D; ++k) F[k] = FQ[((int64_t)b * D * D + k) * q_cap + s];
     const float J = det_small<D>(F);
-    const int n[3] = {g.n0, g.n1, g.n2};
-    int c[3] = {0, 0, 0};
-    bool inside = true;
+    // multilinear reading of the reference density at X (0 off the lattice)
+    const int rn[3] = {rn0, rn1, rn2};
+    const float inv_h = g.inv_dx * (float)L;
+    int i0[3] = {0, 0, 0};
+    float fr[3] = {0.0f, 0.0f, 0.0f};
+    bool on = true;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const float cf = floorf(XQ[((int64_t)b * D + a) * q_cap + s] * g.inv_dx);
-        inside = inside && cf >= 0.0f && cf <= (float)(n[a] - 2);
-        c[a] = inside ? (int)cf : 0;
+        const float t = XQ[((int64_t)b * D + a) * q_cap + s] * inv_h;
+        const float tf = floorf(t);
+        on = on && tf >= 0.0f && tf <= (float)(rn[a] - 2);
+        i0[a] = on ? (int)tf : 0;
+        fr[a] = t - tf;
     }
-    if (inside) {
-        const int64_t i = node_lin(g, c[0], c[1], c[2]);
-        inside = (occ[i >> 5] >> (i & 31)) & 1u;
+    float dens = 0.0f;
+    if (on) {
+#pragma unroll
+        for (int c = 0; c < (1 << D); ++c) {
+            float w = 1.0f;
+            int64_t idx = 0, stride = 1;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int bit = (c >> a) & 1;
+                w *= bit ? fr[a] : 1.0f - fr[a];
+                idx += (int64_t)(i0[a] + bit) * stride;
+                stride *= rn[a];
+            }
+            dens += w * rho[idx];
+        }
     }
-    const bool keep = res <= tol && J > 0.0f && inside;
-    mQ[(int64_t)b * q_cap + s] = keep ? rho0_vq / J : 0.0f;
+    const bool keep = res <= tol && J > 0.0f && dens > 0.0f;
+    mQ[(int64_t)b * q_cap + s] = keep ? dens * vq / J : 0.0f;
 }
 
 __global__ void fill_u32_kernel(uint32_t *a, int64_t n)
@@ -648,12 +669,12 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
         const float tol = R->newton_tol * g.dx;
         if (d == 2)
             eul_finish_kernel<2><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap, L,
-                                                    LD, R->XQ, R->xQ, R->FQ, R->occ,
-                                                    R->cfg.rho0 * vq, tol, R->mQ);
+                                                    LD, R->XQ, R->xQ, R->FQ, R->rho, R->rn[0],
+                                                    R->rn[1], R->rn[2], vq, tol, R->mQ);
         else
             eul_finish_kernel<3><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap, L,
-                                                    LD, R->XQ, R->xQ, R->FQ, R->occ,
-                                                    R->cfg.rho0 * vq, tol, R->mQ);
+                                                    LD, R->XQ, R->xQ, R->FQ, R->rho, R->rn[0],
+                                                    R->rn[1], R->rn[2], vq, tol, R->mQ);
         MR_LAUNCH_CHECK();
     } else {
     // Algorithm 3: decode every particle, mark I, collect Q
@@ -721,7 +742,7 @@ extern "C" void rom_destroy(mr_rom *R)
                     R->bitmap, R->Q,
                     R->q_count, R->n_active, R->xQ, R->FQ, R->vQ, R->grid, R->xs, R->xt, R->vt,
                     R->z_next, R->v_next, R->status_step, R->counter, R->proj_ws,
-                    R->qb_bitmap, R->qbase, R->qb_count, R->XQ, R->mQ, R->occ};
+                    R->qb_bitmap, R->qbase, R->qb_count, R->XQ, R->mQ, R->rho};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     if (R->graph) (void)hipGraphExecDestroy(R->graph);
@@ -748,7 +769,7 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
     if (cfg->quadrature != MR_QUAD_LAGRANGIAN && cfg->quadrature != MR_QUAD_EULERIAN)
         return MR_EINVAL;
     const int ell = cfg->quad_per_dim == 0 ? 2 : cfg->quad_per_dim;
-    const int newton_iters = cfg->newton_iters == 0 ? 4 : cfg->newton_iters;
+    const int newton_iters = cfg->newton_iters == 0 ? 2 : cfg->newton_iters;
     const float newton_tol = cfg->newton_tol == 0.0f ? 1e-3f : cfg->newton_tol;
     if (cfg->quadrature == MR_QUAD_EULERIAN &&
         ((ell != 2 && ell != 4) || newton_iters < 1 || newton_iters > 16 ||
@@ -807,7 +828,10 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
         alloc((void **)&R->qb_count, 4 * B);
         alloc((void **)&R->XQ, 4 * B * d * R->q_cap);
         alloc((void **)&R->mQ, 4 * B * R->q_cap);
-        alloc((void **)&R->occ, 4 * R->words);
+        R->rn[0] = (g.n0 - 1) * ell + 1;
+        R->rn[1] = (g.n1 - 1) * ell + 1;
+        R->rn[2] = d == 3 ? (g.n2 - 1) * ell + 1 : 1;
+        alloc((void **)&R->rho, 4 * (int64_t)R->rn[0] * R->rn[1] * R->rn[2]);
     }
     alloc((void **)&R->bitmap, 4 * B * R->words);
     alloc((void **)&R->q_count, 4 * B);
@@ -873,21 +897,40 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
              hipMemcpy(R->internal_of, inv.data(), 4 * P, hipMemcpyHostToDevice) == hipSuccess &&
              (!m_all || hipMemcpy(R->m, ms.data(), 4 * P, hipMemcpyHostToDevice) == hipSuccess);
         if (cp && eul) {
-            // reference body: cells c = floor(X / dx) holding a particle
-            std::vector<uint32_t> occ(R->words, 0u);
+            // reference density: every particle's mass spread with the
+            // quadratic B-spline over the 3^d lattice nodes of its stencil
+            // (spacing h = dx / l), divided by h^d
+            const double h = (double)g.dx / ell;
+            const int64_t nl = (int64_t)R->rn[0] * R->rn[1] * R->rn[2];
+            std::vector<double> rho(nl, 0.0);
+            const double inv_hd = d == 3 ? 1.0 / (h * h * h) : 1.0 / (h * h);
             for (int64_t p = 0; p < P; ++p) {
-                int64_t c[3] = {0, 0, 0};
+                int64_t bse[3] = {0, 0, 0};
+                double w[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
                 bool in = true;
                 for (int a = 0; a < d; ++a) {
-                    const float cf = floorf(Xh[(size_t)a * P + p] * g.inv_dx);
-                    in = in && cf >= 0.0f && cf <= (float)(nn[a] - 2);
-                    c[a] = in ? (int64_t)cf : 0;
+                    const double t = (double)Xh[(size_t)a * P + p] / h;
+                    const double bf = std::floor(t - 0.5);
+                    in = in && bf >= 0.0 && bf + 2.0 <= (double)(R->rn[a] - 1);
+                    bse[a] = (int64_t)bf;
+                    const double f = t - bf;
+                    w[a][0] = 0.5 * (1.5 - f) * (1.5 - f);
+                    w[a][1] = 0.75 - (f - 1.0) * (f - 1.0);
+                    w[a][2] = 0.5 * (f - 0.5) * (f - 0.5);
                 }
                 if (!in) continue;
-                const int64_t i = c[0] + (int64_t)g.n0 * (c[1] + (int64_t)g.n1 * c[2]);
-                occ[i >> 5] |= 1u << (i & 31);
+                const double mp = (m_all ? (double)mh[p] : (double)cfg->m_uniform) * inv_hd;
+                for (int o2 = 0; o2 < (d == 3 ? 3 : 1); ++o2)
+                    for (int o1 = 0; o1 < 3; ++o1)
+                        for (int o0 = 0; o0 < 3; ++o0) {
+                            const int64_t i = (bse[0] + o0) +
+                                              (int64_t)R->rn[0] * ((bse[1] + o1) +
+                                                                   (int64_t)R->rn[1] * (bse[2] + o2));
+                            rho[i] += mp * w[0][o0] * w[1][o1] * (d == 3 ? w[2][o2] : 1.0);
+                        }
             }
-            cp = hipMemcpy(R->occ, occ.data(), 4 * R->words, hipMemcpyHostToDevice) == hipSuccess;
+            std::vector<float> rhof(rho.begin(), rho.end());
+            cp = hipMemcpy(R->rho, rhof.data(), 4 * nl, hipMemcpyHostToDevice) == hipSuccess;
         }
     }
     cp = cp && hipMemcpy(R->E, E, 4 * B, hipMemcpyDeviceToDevice) == hipSuccess &&

@@ -88,16 +88,17 @@ def rom_initial_state(dec, scene, v0, z_guess=None, n_quad=65536, seed=0, iters=
 
 
 def rom_positions(dec, scene, E, v0, n_steps, record_every, n_samples, opts, seed=7,
-                  use_graph=True, z_guess=None, device="cuda"):
+                  use_graph=True, z_guess=None, device="cuda", **rom_kwargs):
     """Reduced-order positions of every particle at the recorded steps and
-    the step statistics."""
+    the step statistics.  rom_kwargs go to the runner (e.g. the Eulerian
+    quadrature options)."""
     P, d = scene["P"], scene["dim"]
     X = torch.tensor(np.ascontiguousarray(scene["X"].T), device=device)
     grid = _grid(scene)
     rom = B.Rom(dec, grid, X, torch.tensor([float(E)], device=device),
                 torch.tensor([n_samples], dtype=torch.int32, device=device), opts, seed=seed,
                 rho0=float(scene["rho"]), m_uniform=float(scene["m"]),
-                model=scene["model"], nu=scene["nu"])
+                model=scene["model"], nu=scene["nu"], **rom_kwargs)
     z, vh = rom_initial_state(dec, scene, v0, z_guess=z_guess, device=device)
     zp = z.clone()
     st = torch.zeros(1, dtype=torch.int32, device=device)

@@ -61,12 +61,13 @@ def fom_and_training(gpu):
     return s, E, v0, (fom, fom_apic), (Ws, bs, Z[0]), init + (None,), norm
 
 
-def _rom_error(s, E, v0, foms, weights, norm, prec):
+def _rom_error(s, E, v0, foms, weights, norm, prec, n_samples=256, mode=None, **rom_kwargs):
     Ws, bs, z_guess = weights
     lo, hi, mean, std = norm
     dec = B.Decoder(Ws, bs, lo, hi, mean, std, B.OUT_DISPLACEMENT, prec)
-    x_rom, st = EV.rom_positions(dec, s, E, v0, N_STEPS, RECORD, n_samples=256,
-                                 opts=B.gn_opts(mode=B.POS_VEL, max_iter=3), z_guess=z_guess)
+    x_rom, st = EV.rom_positions(dec, s, E, v0, N_STEPS, RECORD, n_samples=n_samples,
+                                 opts=B.gn_opts(mode=B.POS_VEL if mode is None else mode,
+                                                max_iter=3), z_guess=z_guess, **rom_kwargs)
     dec.close()
     return [EV.displacement_error(x_rom, f, s["X"]) for f in foms], st
 
@@ -87,6 +88,28 @@ def test_trained_decoder_beats_the_untrained_one(fom_and_training, prec):
     assert np.isfinite(e_tr) and np.isfinite(e_un)
     assert e_tr < 0.5 * e_un
     assert e_tr < 0.3
+
+
+@pytest.mark.parametrize("n_samples,mode", [(256, B.POS_VEL), (32, B.VEL_ONLY)])
+def test_eulerian_quadrature_accuracy(fom_and_training, n_samples, mode):
+    """The trained decoder with Eulerian quadrature (Algorithm 4: lattice
+    points inverted through the decoder instead of the neighbour particles)
+    against the same run with Lagrangian quadrature, both judged by the
+    full-order model."""
+    s, E, v0, foms, trained, init, norm = fom_and_training
+    ((e_eu, p_eu), _), st_eu = _rom_error(s, E, v0, foms, trained, norm, B.PREC_BF16,
+                                          n_samples=n_samples, mode=mode,
+                                          quadrature=B.QUAD_EULERIAN)
+    ((e_la, p_la), _), st_la = _rom_error(s, E, v0, foms, trained, norm, B.PREC_BF16,
+                                          n_samples=n_samples, mode=mode)
+    print("samples %d mode %d: displacement error Eulerian %.3e (%d lattice points), "
+          "Lagrangian %.3e (%d quadrature particles)"
+          % (n_samples, mode, e_eu, st_eu["n_quadrature_points"], e_la,
+             st_la["n_quadrature_points"]))
+    # measured on the 2.1M-particle scene: Eulerian 0.13 vs Lagrangian 0.14
+    # (512 samples), 0.18 vs 0.19 (50 samples, velocity-only)
+    assert np.isfinite(e_eu)
+    assert e_eu < 0.3 and e_eu < 1.5 * e_la + 0.02
 
 
 def test_batched_instances_error_distribution(gpu):

@@ -102,6 +102,12 @@ def test_newton_matches_an_independent_root_finder():
     np.testing.assert_allclose(D.decode(dec, X, z), x, atol=1e-12)
 
 
+def _lattice_nodes(shape, h):
+    """Node positions of a lattice in flat order, x fastest."""
+    idx = np.indices(tuple(shape[::-1])).reshape(len(shape), -1)[::-1].T
+    return idx * h
+
+
 def _box_particles(dim, n, lo, hi, ppc=2):
     """Particles at (c + (j + 1/2) / ppc) dx in every cell of [lo, hi)^d."""
     dx = 1 / n
@@ -112,26 +118,68 @@ def _box_particles(dim, n, lo, hi, ppc=2):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-def test_translation_positions_masses_and_body(dim):
-    """g = X + t with t a whole number of cells: X^Q = x^Q - t exactly,
-    J = 1, m = rho0 (dx / ell)^d; a point is kept iff X^Q lies in the box
-    of reference cells [4, 12)^d."""
+def test_reference_density_partition_of_unity_and_mass(dim):
+    """Particles on the lattice of spacing h = dx / ell with m = rho0 h^d:
+    rho_ref = rho0 at every node whose whole stencil neighbourhood is inside
+    the sampled box (B-spline partition of unity), 0 two spacings outside,
+    and the lattice holds the particles' total mass."""
     n, ell, rho0 = 16, 2, 1000.0
     dx = 1 / n
+    h = dx / ell
+    X_all = _box_particles(dim, n, 0.25, 0.75, ppc=ell)
+    X_all = X_all[X_all[:, 0] < 0.625]          # asymmetric: the box is [0.25, 0.625) in x
+    m = rho0 * h ** dim
+    rho = rom.reference_density(dim, [n] * dim, dx, ell, X_all, m)
+    shape = rom.density_lattice_shape([n] * dim, ell)
+    nodes = _lattice_nodes(shape, h)
+    hi = np.array([0.625, 0.75, 0.75][:dim])
+    inner = np.all((nodes >= 0.25 + h) & (nodes <= hi - h), axis=1)
+    outer = np.any((nodes <= 0.25 - 2 * h) | (nodes >= hi + 2 * h), axis=1)
+    np.testing.assert_allclose(rho[inner], rho0, rtol=1e-12)
+    assert np.all(rho[outer] == 0.0)
+    np.testing.assert_allclose(rho.sum() * h ** dim, m * len(X_all), rtol=1e-12)
+    # multilinear reading: exact at nodes, rho0 between inner nodes
+    np.testing.assert_allclose(rom.density_at(rho, dim, [n] * dim, dx, ell, nodes[inner]),
+                               rho0, rtol=1e-12)
+
+
+def test_density_reading_is_exact_for_linear_fields():
+    dim, n, ell = 3, 8, 2
+    dx = 1 / n
+    shape = rom.density_lattice_shape([n] * dim, ell)
+    nodes = _lattice_nodes(shape, dx / ell)
+    coef = np.array([1.0, -2.0, 0.5])
+    rho = 3.0 + nodes @ coef
+    X = np.random.default_rng(8).uniform(0.1, 0.8, size=(50, dim))
+    np.testing.assert_allclose(rom.density_at(rho, dim, [n] * dim, dx, ell, X), 3.0 + X @ coef,
+                               rtol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_translation_positions_and_masses(dim):
+    """g = X + t: X^Q = x^Q - t exactly, J = 1; the mass is rho_ref(X^Q)
+    (dx / ell)^d: rho0 (dx / ell)^d well inside the box, zero (point
+    dropped) well outside it."""
+    n, ell, rho0 = 16, 2, 1000.0
+    dx = 1 / n
+    h = dx / ell
     X_all = _box_particles(dim, n, 0.25, 0.75)
-    occ = rom.reference_occupancy(dim, [n] * dim, dx, X_all)
+    rho = rom.reference_density(dim, [n] * dim, dx, ell, X_all, rho0 * h ** dim)
     t = np.array([2 * dx, -1 * dx, dx][:dim])
     dec = translation_decoder(dim)
     xs = np.array([[0.7, 0.45, 0.5][:dim], [0.3, 0.6, 0.4][:dim]])
     eq = rom.eulerian_quadrature(dec, dim, [n] * dim, dx, xs, t, np.zeros(dim), ell, 3,
-                                 1e-3 * dx, rho0, occ)
-    np.testing.assert_allclose(eq["X_all"], eq["x_candidates"] - t, atol=1e-15)
-    np.testing.assert_allclose(np.linalg.det(eq["FQ"]), 1.0, atol=1e-15)
-    np.testing.assert_allclose(eq["mQ"], rho0 * (dx / ell) ** dim, rtol=1e-15)
+                                 1e-3 * dx, rho0, rho)
     Xc = eq["x_candidates"] - t
-    want = np.all((Xc >= 0.25) & (Xc < 0.75), axis=1)
-    np.testing.assert_array_equal(eq["keep"], want)
-    assert 0 < want.sum() < len(want)        # the box edge cuts the point set
+    np.testing.assert_allclose(eq["X_all"], Xc, atol=1e-15)
+    np.testing.assert_allclose(np.linalg.det(eq["FQ"]), 1.0, atol=1e-15)
+    inner = np.all((Xc >= 0.25 + 2 * h) & (Xc <= 0.75 - 2 * h), axis=1)
+    outer = np.any((Xc <= 0.25 - 2 * h) | (Xc >= 0.75 + 2 * h), axis=1)
+    assert inner.any() and outer.any()
+    np.testing.assert_allclose(eq["rho"][inner], rho0, rtol=1e-12)
+    assert np.all(eq["keep"][inner]) and not np.any(eq["keep"][outer])
+    kept_inner = inner[eq["keep"]]
+    np.testing.assert_allclose(eq["mQ"][kept_inner], rho0 * h ** dim, rtol=1e-12)
 
 
 @pytest.mark.parametrize("mode", [PR.MODE_POS_VEL, PR.MODE_VEL_ONLY])
@@ -144,7 +192,7 @@ def test_translation_manifold_eulerian_rom_equals_symplectic_euler(mode, dim):
     dx = 1 / n
     X_all = _box_particles(dim, n, 0.25, 0.75)
     P = len(X_all)
-    occ = rom.reference_occupancy(dim, [n] * dim, dx, X_all)
+    rho = rom.reference_density(dim, [n] * dim, dx, 2, X_all, 1000.0 * (dx / 2) ** dim)
     dec = translation_decoder(dim)
     mu, la = mpm.lame(1e4, 0.3)
     grav = [0.0] * dim
@@ -164,7 +212,7 @@ def test_translation_manifold_eulerian_rom_equals_symplectic_euler(mode, dim):
         samples = np.sort(rng.choice(interior, size=3, replace=False))
         zn, vn, info = rom.rom_step(dec, sc, X_all, None, None, z, zp, vh, dt, samples, opts,
                                     quadrature="eulerian", ell=2, newton_iters=2, rho0=1000.0,
-                                    occupied=occ)
+                                    rho_ref=rho)
         assert info["eulerian"]["keep"].all()
         zp, z, vh = z, zn, vn
     g = np.array(grav)
