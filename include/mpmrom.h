@@ -379,7 +379,8 @@ typedef struct {
  * samples are decoded; the quadrature points are the lattice points
  * (m + 1/2) dx / l per axis (l = quad_per_dim) whose stencil touches the
  * samples' nodes, their reference positions X solve g(X; xhat) = x by
- * Newton's method from X = x (newton_iters iterations with F = dg/dX), and
+ * newton_iters iterations from X = x: a displacement step X = x - u(x)
+ * (Jacobian replaced by I), then Newton steps with F = dg/dX, and
  * a point is kept when the residual is within newton_tol cells, det F > 0
  * and the reference density at X is positive; its mass is that density
  * times (dx / l)^d / det F.  The reference density is the reference

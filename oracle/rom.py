@@ -21,10 +21,12 @@ Readings:
     dimension, evenly spaced, volume (dx / ell)^d); the quadrature points of
     a step are those whose stencil touches an active node (the nodes of the
     samples' stencils), the same test as for the Lagrangian neighbours.
-  - The map is inverted by Newton's method on g(X; xhat) = x^Q with the
-    Jacobian F = dg/dX, started at X = x^Q, for a fixed number of
-    iterations; a point is kept when the final residual max-norm is within
-    a tolerance, det F > 0 and X lies in the reference body.
+  - The map is inverted from X = x^Q by a displacement step X <- x^Q -
+    (g(X) - X) (a Newton step with F replaced by I: the guess x - u(x))
+    followed by Newton steps with F = dg/dX at the current iterate, for a
+    fixed total number of iterations; a point is kept when the final
+    residual max-norm is within a tolerance, det F > 0 at the result and X
+    lies in the reference body.
   - The reference body and its density come from the reference particles:
     rho_ref is their mass spread with the quadratic B-spline on a lattice of
     spacing h = dx / ell (nodes k h), read at X by multilinear
@@ -206,12 +208,17 @@ def eulerian_points(dim, n, dx, ell, I):
 
 
 def invert_map(jac_fn, x_target, iters):
-    """Newton's method for g(X) = x_target from X = x_target: X <- X -
-    F(X)^{-1} (g(X) - x_target), `iters` times.  jac_fn(X) returns (g, F)."""
+    """Solves g(X) = x_target from X0 = x_target: the first iteration is
+    X <- X - (g(X) - x_target) (Jacobian replaced by I), every later one a
+    Newton step X <- X - F(X)^{-1} (g(X) - x_target); `iters` iterations in
+    all.  jac_fn(X) returns (g, F)."""
     X = np.array(x_target, dtype=np.float64)
-    for _ in range(iters):
+    for k in range(iters):
         g, F = jac_fn(X)
-        X = X - np.linalg.solve(F, (g - x_target)[..., None])[..., 0]
+        if k == 0:
+            X = X - (g - x_target)
+        else:
+            X = X - np.linalg.solve(F, (g - x_target)[..., None])[..., 0]
     return X
 
 

@@ -25,8 +25,9 @@
 // samples only; mark their stencil nodes I and, dilated by two cells, the
 // stencil bases whose lattice points touch I (each base once, appended to a
 // per-instance list); expand every base into its l^d lattice points; invert
-// the decoder at them by Newton's method (decoder launches with the spatial
-// tangents, then a per-point d x d solve); decode x, F, v at the result and
+// the decoder at them (a displacement step X = x - u(x) from a positions
+// decode, then Newton steps: decoder launches with the spatial tangents and
+// a per-point d x d solve); decode x, F, v at the result and
 // keep a point when the residual is small, det F > 0 and the reference
 // density at its reference position is positive; its mass is that density
 // times (dx / l)^d / det F.  The reference density is the particles' mass
@@ -497,7 +498,8 @@ __device__ __forceinline__ float det_small(const float *F)
            F[2] * (F[3] * F[7] - F[4] * F[6]);
 }
 
-// one Newton step X <- X - F^{-1} (g(X) - x^Q) from the decoded g and F
+// one step X <- X - F^{-1} (g(X) - x^Q) from the decoded g and F (F null:
+// the identity, i.e. X <- x^Q - u)
 template <int D>
 __global__ void eul_newton_kernel(GridK g, int64_t q_cap, const int32_t *q_count,
                                   const int32_t *qbase, int64_t qb_cap, int L, int LD,
@@ -510,10 +512,15 @@ __global__ void eul_newton_kernel(GridK g, int64_t q_cap, const int32_t *q_count
     eul_point<D>(g, qbase[(int64_t)b * qb_cap + s / LD], (int)(s % LD), L, xq);
 #pragma unroll
     for (int a = 0; a < D; ++a) r[a] = xg[((int64_t)b * D + a) * q_cap + s] - xq[a];
+    if (FQ) {
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) F[k] = FQ[((int64_t)b * D * D + k) * q_cap + s];
-    const float det = solve_small<D>(F, r, y);
-    if (!(det != 0.0f) || !isfinite(det)) return;   // left as is; rejected at the end
+        for (int k = 0; k < D * D; ++k) F[k] = FQ[((int64_t)b * D * D + k) * q_cap + s];
+        const float det = solve_small<D>(F, r, y);
+        if (!(det != 0.0f) || !isfinite(det)) return;   // left as is; rejected at the end
+    } else {
+#pragma unroll
+        for (int a = 0; a < D; ++a) y[a] = r[a];
+    }
 #pragma unroll
     for (int a = 0; a < D; ++a) XQ[((int64_t)b * D + a) * q_cap + s] -= y[a];
 }
@@ -650,16 +657,20 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
                                                   LD, R->XQ);
         MR_LAUNCH_CHECK();
         const int64_t xstr = (int64_t)d * R->q_cap;
+        // the first step takes the displacement guess X = x - u(x) (positions
+        // only, Jacobian replaced by I); later steps are Newton steps
         for (int it = 0; it < R->newton_iters; ++it) {
             rc = decode_jac_ex(R->dec, B, R->q_cap, R->XQ, R->q_cap, nullptr, 0, R->q_count, xhat,
-                               nullptr, R->xQ, R->FQ, nullptr, nullptr, st, 0, xstr);
+                               nullptr, R->xQ, it == 0 ? nullptr : R->FQ, nullptr, nullptr, st, 0,
+                               xstr);
             if (rc != MR_OK) return rc;
+            const float *Fit = it == 0 ? nullptr : R->FQ;
             if (d == 2)
                 eul_newton_kernel<2><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap,
-                                                        L, LD, R->xQ, R->FQ, R->XQ);
+                                                        L, LD, R->xQ, Fit, R->XQ);
             else
                 eul_newton_kernel<3><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap,
-                                                        L, LD, R->xQ, R->FQ, R->XQ);
+                                                        L, LD, R->xQ, Fit, R->XQ);
             MR_LAUNCH_CHECK();
         }
         rc = decode_jac_ex(R->dec, B, R->q_cap, R->XQ, R->q_cap, nullptr, 0, R->q_count, xhat,

@@ -69,7 +69,8 @@ def test_points_match_python_enumeration(dim):
 
 def test_newton_inverts_an_affine_map_in_one_iteration():
     """W = [S | 0]: g(X) = X + S (2X - 1) + c, so X = (I + 2S)^{-1} (x + S 1 - c);
-    Newton is exact after one step on an affine map."""
+    after the displacement step, one Newton step is exact on an affine map;
+    the displacement step alone is exact when the map is a translation."""
     rng = np.random.default_rng(5)
     d, r = 3, 2
     S = 0.1 * rng.standard_normal((d, d))
@@ -78,11 +79,18 @@ def test_newton_inverts_an_affine_map_in_one_iteration():
     dec = D.Decoder([W], [c], np.zeros(d), np.ones(d), np.zeros(d), np.ones(d))
     x = rng.uniform(0.2, 0.8, size=(40, d))
     z = rng.standard_normal(r)
-    X1 = rom.invert_map(lambda X: D.decode_jac(dec, X, z)[:2], x, 1)
     exact = np.linalg.solve(np.eye(d) + 2 * S, (x + S.sum(1) - c).T).T
-    np.testing.assert_allclose(X1, exact, atol=1e-13)
-    X3 = rom.invert_map(lambda X: D.decode_jac(dec, X, z)[:2], x, 3)
-    np.testing.assert_allclose(X3, exact, atol=1e-13)
+    X1 = rom.invert_map(lambda X: D.decode_jac(dec, X, z)[:2], x, 1)
+    np.testing.assert_allclose(X1, x - (D.decode(dec, x, z) - x), atol=1e-15)
+    X2 = rom.invert_map(lambda X: D.decode_jac(dec, X, z)[:2], x, 2)
+    np.testing.assert_allclose(X2, exact, atol=1e-13)
+    X4 = rom.invert_map(lambda X: D.decode_jac(dec, X, z)[:2], x, 4)
+    np.testing.assert_allclose(X4, exact, atol=1e-13)
+    t = np.array([0.02, -0.01, 0.03])
+    tdec = D.Decoder([np.zeros((d, d + r))], [t], np.zeros(d), np.ones(d), np.zeros(d),
+                     np.ones(d))
+    np.testing.assert_allclose(rom.invert_map(lambda X: D.decode_jac(tdec, X, z)[:2], x, 1),
+                               x - t, atol=1e-15)
 
 
 def test_newton_matches_an_independent_root_finder():
@@ -94,7 +102,7 @@ def test_newton_matches_an_independent_root_finder():
     dec = D.Decoder(Ws, bs, np.zeros(d), np.ones(d), np.zeros(d), 0.05 * np.ones(d))
     z = rng.standard_normal(r)
     x = rng.uniform(0.3, 0.7, size=(12, d))
-    X = rom.invert_map(lambda Y: D.decode_jac(dec, Y, z)[:2], x, 8)
+    X = rom.invert_map(lambda Y: D.decode_jac(dec, Y, z)[:2], x, 12)
     for k in range(len(x)):
         sol = optimize.root(lambda Y: D.decode(dec, Y[None], z)[0] - x[k], x[k], tol=1e-14)
         assert sol.success
