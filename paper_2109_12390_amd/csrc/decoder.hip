@@ -213,12 +213,42 @@ __device__ __forceinline__ void emit_output(const DecK &P, const StreamSpec &ss,
 // Staging the weights once per block and layer turns the MFMA A-operand
 // fetches into LDS reads; from global memory every k-step waited on a
 // cache round trip.
+// Fixed block LDS: c0 and u (W floats each), the first layer's spatial
+// weights W0[:, 0..d) and the output layer's weights (3 W floats each, d
+// padded to 3; read by every lane, so kept next to the compute instead of
+// behind a global load per use), then (bf16) a hidden layer's weights.
 template <typename T, int W>
 struct DecSmem {
     static constexpr bool WLDS = sizeof(T) == 2;
     static constexpr int LD = W + Elem<T>::PAD;
-    static constexpr size_t fixed = 2 * W * sizeof(float) + (WLDS ? (size_t)W * LD * sizeof(T) : 0);
+    static constexpr size_t vec = 8 * W * sizeof(float);
+    static constexpr size_t fixed = vec + (WLDS ? (size_t)W * LD * sizeof(T) : 0);
 };
+
+// c0 = W_z xhat + b0 and u = W_z vhat of instance b, the spatial columns of
+// W0 and the output weights into the block's fixed LDS
+template <int W>
+__device__ __forceinline__ void load_block_vectors(const DecK &P, const double *xh,
+                                                   const double *vh, float *c0, float *u,
+                                                   float *w0x, float *wls)
+{
+    const int in0 = P.d + P.r;
+    for (int i = threadIdx.x; i < W; i += blockDim.x) {
+        double s0 = P.b0[i], s1 = 0.0;
+        for (int k = 0; k < P.r; ++k) {
+            double w = P.W0[(size_t)i * in0 + P.d + k];
+            s0 += w * xh[k];
+            if (vh) s1 += w * vh[k];
+        }
+        c0[i] = (float)s0;
+        u[i] = (float)s1;
+    }
+    for (int i = threadIdx.x; i < 3 * W; i += blockDim.x) {
+        const int row = i / 3, a = i % 3;
+        w0x[i] = a < P.d ? P.W0[(size_t)row * in0 + a] : 0.0f;
+        wls[i] = i / W < P.d ? P.WL[i] : 0.0f;
+    }
+}
 
 template <typename T, int W, int S, int NP, bool DB, int WPB>
 __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss, DecIO io)
@@ -241,22 +271,15 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
     // per-instance vectors: c0 = W_z xhat + b0, u = W_z vhat
     float *c0 = reinterpret_cast<float *>(smem);
     float *u = c0 + W;
-    T *wsh = reinterpret_cast<T *>(smem + 2 * W * sizeof(float));
+    float *w0x = u + W;
+    float *wls = w0x + 3 * W;
+    T *wsh = reinterpret_cast<T *>(smem + SM::vec);
     T *panel = reinterpret_cast<T *>(smem + SM::fixed) + (size_t)wave * (DB ? 2 : 1) * COLS * LD;
     T *pin = panel;
     T *pout = DB ? panel + COLS * LD : panel;
     const double *xh = io.xhat + (size_t)b * P.r;
     const double *vh = io.vhat ? io.vhat + (size_t)b * P.r : nullptr;
-    for (int i = threadIdx.x; i < W; i += blockDim.x) {
-        double s0 = P.b0[i], s1 = 0.0;
-        for (int k = 0; k < P.r; ++k) {
-            double w = P.W0[(size_t)i * (P.d + P.r) + P.d + k];
-            s0 += w * xh[k];
-            if (vh) s1 += w * vh[k];
-        }
-        c0[i] = (float)s0;
-        u[i] = (float)s1;
-    }
+    load_block_vectors<W>(P, xh, vh, c0, u, w0x, wls);
     __syncthreads();
 
     // ---- first layer: lane handles point column j = lane % 16 of each point
@@ -279,7 +302,7 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
             f32x4 h4, e4;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float *w0 = P.W0 + (size_t)(i0 + q) * in0;
+                const float *w0 = w0x + (i0 + q) * 3;
                 float z = c0[i0 + q];
                 for (int a = 0; a < P.d; ++a) z += w0[a] * Xn[a];
                 float h, e;
@@ -293,11 +316,10 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
                 f32x4 val;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const float *w0 = P.W0 + (size_t)(i0 + q) * in0;
                     if (kind == SK_PRIMAL) val[q] = h4[q];
-                    else if (kind == SK_SPATIAL) val[q] = e4[q] * w0[arg] * P.scale[arg];
+                    else if (kind == SK_SPATIAL) val[q] = e4[q] * w0x[(i0 + q) * 3 + arg] * P.scale[arg];
                     else if (kind == SK_VELOCITY) val[q] = e4[q] * u[i0 + q];
-                    else if (kind == SK_LATENT) val[q] = e4[q] * w0[P.d + arg];
+                    else if (kind == SK_LATENT) val[q] = e4[q] * P.W0[(size_t)(i0 + q) * in0 + P.d + arg];
                     else val[q] = 0.0f;
                 }
                 E::store4(pin + ((pt * S + st) * 16 + j) * LD + i0, val);
@@ -421,7 +443,7 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
         int64_t s = wbase + pt * 16 + jj;
         if (s >= n_b) continue;
         const T *h = pin + (size_t)col * LD;
-        const float *wl = P.WL + (size_t)a * W;
+        const float *wl = wls + a * W;
         float y = 0.0f;
         for (int i = 0; i < W; i += 4) {
             const f32x4 h4 = E::load4(h + i);
@@ -458,21 +480,14 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
     if (s0 >= n_b) return;                                  // block-uniform
     float *c0 = reinterpret_cast<float *>(smem);
     float *u = c0 + W;
-    T *wsh = reinterpret_cast<T *>(smem + 2 * W * sizeof(float));
+    float *w0x = u + W;
+    float *wls = w0x + 3 * W;
+    T *wsh = reinterpret_cast<T *>(smem + SM::vec);
     T *pin = reinterpret_cast<T *>(smem + SM::fixed);
     T *pout = pin + COLS * LD;
     const double *xh = io.xhat + (size_t)b * P.r;
     const double *vh = io.vhat ? io.vhat + (size_t)b * P.r : nullptr;
-    for (int i = threadIdx.x; i < W; i += 64 * NW) {
-        double a0 = P.b0[i], a1 = 0.0;
-        for (int k = 0; k < P.r; ++k) {
-            double w = P.W0[(size_t)i * (P.d + P.r) + P.d + k];
-            a0 += w * xh[k];
-            if (vh) a1 += w * vh[k];
-        }
-        c0[i] = (float)a0;
-        u[i] = (float)a1;
-    }
+    load_block_vectors<W>(P, xh, vh, c0, u, w0x, wls);
     __syncthreads();
     // first layer: this wave's 16 units for the tile's 16 points
     const int in0 = P.d + P.r;
@@ -487,7 +502,7 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
         f32x4 h4, e4;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float *w0 = P.W0 + (size_t)(i0 + q) * in0;
+            const float *w0 = w0x + (i0 + q) * 3;
             float z = c0[i0 + q];
             for (int a = 0; a < P.d; ++a) z += w0[a] * Xn[a];
             float h, e;
@@ -501,11 +516,10 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
             f32x4 val;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float *w0 = P.W0 + (size_t)(i0 + q) * in0;
                 if (kind == SK_PRIMAL) val[q] = h4[q];
-                else if (kind == SK_SPATIAL) val[q] = e4[q] * w0[arg] * P.scale[arg];
+                else if (kind == SK_SPATIAL) val[q] = e4[q] * w0x[(i0 + q) * 3 + arg] * P.scale[arg];
                 else if (kind == SK_VELOCITY) val[q] = e4[q] * u[i0 + q];
-                else if (kind == SK_LATENT) val[q] = e4[q] * w0[P.d + arg];
+                else if (kind == SK_LATENT) val[q] = e4[q] * P.W0[(size_t)(i0 + q) * in0 + P.d + arg];
                 else val[q] = 0.0f;
             }
             E::store4(pin + (st * 16 + j) * LD + i0, val);
@@ -569,7 +583,7 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
         const int64_t s = s0 + jj;
         if (s >= n_b) continue;
         const T *h = pin + (size_t)col * LD;
-        const float *wl = P.WL + (size_t)a * W;
+        const float *wl = wls + a * W;
         float y = 0.0f;
         for (int i = 0; i < W; i += 4) {
             const f32x4 h4 = E::load4(h + i);
@@ -601,13 +615,13 @@ int32_t launch_one(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStre
     return MR_OK;
 }
 
-// waves per block of a shape: as many as fit 150 KB of LDS, at most `cap`
+// waves per block of a shape: as many as fit the 160 KB of LDS, at most `cap`
 template <typename T, int W, int S, int NP, bool DB>
 constexpr int dec_wpb(int cap)
 {
     constexpr size_t per_wave = (size_t)(DB ? 2 : 1) * NP * S * 16 * (W + Elem<T>::PAD) * sizeof(T);
     constexpr size_t fixed = DecSmem<T, W>::fixed;
-    int w = (int)((150 * 1024 - fixed) / per_wave);
+    int w = (int)((160 * 1024 - fixed) / per_wave);
     return w < cap ? w : cap;
 }
 
