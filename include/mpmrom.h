@@ -56,6 +56,9 @@ extern "C" {
 #define MR_FLAG_SINGULAR 2   /* Cholesky of a normal matrix failed          */
 #define MR_FLAG_NOCONV 4     /* Gauss-Newton step above tolerance at exit   */
 #define MR_FLAG_LINESEARCH 8 /* no step length passed the Armijo test       */
+#define MR_FLAG_DRIFT 16     /* deterministic P2G: a particle's stencil left
+                                its tile's region (moved more than a cell
+                                since the sort); it was not scattered      */
 
 /* ---- enums ------------------------------------------------------------- */
 #define MR_FLOOR_STICKY 0        /* every face of the boundary band sticky  */
@@ -71,6 +74,13 @@ extern "C" {
 #define MR_SORTED 16     /* p2g: particles are cell-sorted by mpm_cell_sort;
                             enables the LDS-tiled scatter                    */
 #define MR_NO_VC_OUT 32  /* g2p2g: do not store v_p and C_p                  */
+#define MR_DETERMINISTIC 64 /* p2g (with MR_SORTED), mpm_step, mpm_cell_sort_ex:
+                            bitwise-reproducible results, independent of the
+                            input order of the particles and of the runtime
+                            schedule: cells are ordered canonically (by
+                            position) by the sort, and each tile's region is
+                            staged and summed per node in a fixed tile order
+                            instead of flushed with float atomics          */
 
 /* kernel classes of the launch timer (mr_timing_read) */
 #define MR_KC_SORT 0     /* cell sort (all of its launches)                  */
@@ -132,7 +142,11 @@ typedef struct {
  * particles with this grid (any later motion is handled).  Particles whose
  * stencil leaves the lattice, or with J <= 0 under Neo-Hookean, are skipped
  * and raise MR_FLAG_DOMAIN.  `workspace` (nullable unless MR_SORTED) must
- * hold mpm_workspace_bytes(grid, n) bytes of device memory. */
+ * hold mpm_workspace_bytes(grid, n) bytes of device memory.
+ * MR_DETERMINISTIC (requires MR_SORTED and subset == NULL; the sort should
+ * be mpm_cell_sort_ex with MR_DETERMINISTIC): bitwise-reproducible grid
+ * values; every particle must still lie within a cell of its sort-time cell
+ * (else it is skipped and MR_FLAG_DRIFT raised). */
 int32_t mpm_p2g(const mr_grid *grid_desc, const mr_material *mat,
                 const mr_particles *parts, const int32_t *subset,
                 int64_t n_subset, float dt, float *grid, int32_t flags,
@@ -169,9 +183,18 @@ int32_t mpm_g2p(const mr_grid *grid_desc, mr_particles *parts,
 int32_t mpm_cell_sort(const mr_grid *grid_desc, mr_particles *parts,
                       int32_t *perm_out, void *workspace, int32_t *status_flag,
                       void *stream);
+/* mpm_cell_sort with flags: MR_DETERMINISTIC orders the particles of a cell
+ * by position (x, then y, then z; by previous order only between equal
+ * positions) instead of by previous order, so that the order -- and the
+ * deterministic P2G that relies on it -- does not depend on the input order.
+ * Other flag bits: MR_EINVAL. */
+int32_t mpm_cell_sort_ex(const mr_grid *grid_desc, mr_particles *parts,
+                         int32_t *perm_out, void *workspace, int32_t flags,
+                         int32_t *status_flag, void *stream);
 
 /* Device workspace bytes needed by mpm_cell_sort and the sorted P2G for a
- * grid and n particles. */
+ * grid and n particles (including the staging area of the deterministic
+ * P2G: 16 bytes per node of every tile's region). */
 int64_t mpm_workspace_bytes(const mr_grid *grid_desc, int64_t n);
 
 /* Launch timer: HIP events recorded on the launching stream around every
@@ -216,7 +239,11 @@ int32_t mpm_g2p2g(const mr_grid *grid_desc, const mr_material *mat,
  * entry.  timing (nullable) records every launch.  Particles end with x, v,
  * C, F of the last step.  Between sorts the state may live in the
  * workspace (each sort gathers from one copy into the other); it is in the
- * caller's arrays again when the call's work completes on the stream. */
+ * caller's arrays again when the call's work completes on the stream.
+ * MR_DETERMINISTIC (requires sort_every >= 1): canonical sorts and the
+ * deterministic P2G, so the final state does not depend on the input order
+ * of the particles (up to their relabelling, given by perm_accum) or on the
+ * run; particles must move less than a cell between sorts. */
 int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
                  mr_particles *parts, float dt, int32_t n_steps,
                  int32_t sort_every, int32_t flags, float *grid,

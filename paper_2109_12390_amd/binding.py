@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmpmrom.so")
 
 MR_OK = 0
 MR_EINVAL, MR_ENOMEM, MR_EDEVICE, MR_ESINGULAR, MR_ENOCONV, MR_EDOMAIN = -1, -2, -3, -4, -5, -6
-FLAG_DOMAIN, FLAG_SINGULAR, FLAG_NOCONV, FLAG_LINESEARCH = 1, 2, 4, 8
+FLAG_DOMAIN, FLAG_SINGULAR, FLAG_NOCONV, FLAG_LINESEARCH, FLAG_DRIFT = 1, 2, 4, 8, 16
 FLOOR_STICKY, FLOOR_COULOMB = 0, 1
 FIXED_COROTATED, NEO_HOOKEAN = 0, 1
 NO_AFFINE, ACCUMULATE, TRIAL, NO_F_UPDATE, SORTED = 1, 2, 4, 8, 16
@@ -86,6 +86,8 @@ SIGNATURES = {
                        _vp, _i32, _vp, _vp, _vp, _vp]),
     "mpm_cell_sort": (_i32, [ctypes.POINTER(MrGrid), ctypes.POINTER(MrParticles), _vp, _vp,
                              _vp, _vp]),
+    "mpm_cell_sort_ex": (_i32, [ctypes.POINTER(MrGrid), ctypes.POINTER(MrParticles), _vp, _vp,
+                                _i32, _vp, _vp]),
     "mpm_workspace_bytes": (_i64, [ctypes.POINTER(MrGrid), _i64]),
     "mpm_cell_keys": (_i32, [ctypes.POINTER(MrGrid), ctypes.POINTER(MrParticles), _vp, _vp]),
     "mpm_step": (_i32, [ctypes.POINTER(MrGrid), ctypes.POINTER(MrMaterial),
@@ -253,6 +255,15 @@ def mpm_g2p(grid, parts, dt, grid_buf, subset=None, flags=0, x_trial=None, v_tri
                                   _ptr(status, torch.int32), _stream(stream)))
 
 
+def mpm_cell_sort_ex(grid, parts, workspace, flags, perm_out=None, status=None, stream=None):
+    lib = load()
+    p = parts.c()
+    _check("mpm_cell_sort_ex", lib.mpm_cell_sort_ex(ctypes.byref(grid.c()), ctypes.byref(p),
+                                                    _ptr(perm_out, torch.int32), _ptr(workspace),
+                                                    flags, _ptr(status, torch.int32),
+                                                    _stream(stream)))
+
+
 def mpm_cell_sort(grid, parts, workspace, perm_out=None, status=None, stream=None):
     lib = load()
     p = parts.c()
@@ -273,6 +284,7 @@ def mpm_step_workspace_bytes(grid, n):
 
 
 NO_VC_OUT = 32
+DETERMINISTIC = 64
 KC_NAMES = ["cell_sort", "p2g", "grid_update", "g2p", "g2p2g", "zero_grid"]
 
 

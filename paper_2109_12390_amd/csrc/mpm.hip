@@ -247,10 +247,30 @@ __global__ void cell_scatter_kernel(const int32_t *keys, int64_t n, const int32_
     cell_sorted[slot] = (int32_t)p;
 }
 
-// insertion sort of each cell segment by particle index (restores the
-// previous order among particles of one cell: the sort is stable)
+// order of two particles inside a cell: by index (stable sort), or, in the
+// canonical order of the deterministic mode, by position (the bit patterns
+// of x, y, z, which order non-negative floats like their values) with the
+// index only between particles at the same position
+template <int D>
+__device__ __forceinline__ bool cell_before(int32_t a, int32_t b, const float *x, int64_t n,
+                                            bool canonical)
+{
+    if (canonical) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const uint32_t ua = __float_as_uint(x[k * n + a]), ub = __float_as_uint(x[k * n + b]);
+            if (ua != ub) return ua < ub;
+        }
+    }
+    return a < b;
+}
+
+// insertion sort of each cell segment (restores the previous order among
+// particles of one cell, or puts them in canonical order)
+template <int D>
 __global__ void cell_segment_sort_kernel(const int32_t *offsets, const int32_t *counts,
-                                         int64_t ncells, int32_t *cell_sorted)
+                                         int64_t ncells, int32_t *cell_sorted, const float *x,
+                                         int64_t n, int canonical)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
@@ -262,7 +282,7 @@ __global__ void cell_segment_sort_kernel(const int32_t *offsets, const int32_t *
     for (int i = 1; i < len; ++i) {
         int v = cell_sorted[s + i];
         int j = i - 1;
-        while (j >= 0 && cell_sorted[s + j] > v) {
+        while (j >= 0 && cell_before<D>(v, cell_sorted[s + j], x, n, canonical != 0)) {
             cell_sorted[s + j + 1] = cell_sorted[s + j];
             --j;
         }
@@ -384,12 +404,17 @@ __device__ __forceinline__ void opaque_payload(Stencil<D> &st, P2GPayload<D> &pl
 #define MR_TILE_MIN_WAVES 1
 #endif
 
-template <int D, bool FUSED>
+// DET (sorted P2G, deterministic mode): base cells are claimed by the lowest
+// lane (LDS atomic min), a particle whose stencil left the region raises
+// MR_FLAG_DRIFT instead of scattering with atomics, and the region is stored
+// whole to the tile's staging area (summed per node in tile order by
+// det_combine_kernel) instead of being flushed with atomics.
+template <int D, bool FUSED, bool DET = false>
 __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scatter_kernel(
     GridK g, TileGeom tg, float *x, float *v, float *C, float *F, const float *m, const float *V0,
     float m_u, float V0_u, int64_t n, const int32_t *offsets, const int32_t *counts, int apic,
     int model, float mu, float la, float dt, const float *grid_in, float *grid_out, float *v_out,
-    float *C_out, int32_t *flag)
+    float *C_out, int32_t *flag, float4 *stage = nullptr)
 {
     using CT = CellTile<D>;
     __shared__ float4 acc_all[CT::WPB][CT::RNP];
@@ -535,7 +560,12 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
                 m2 = D == 3 ? sn.base[2] - r2 : 0;
                 inreg = m0 >= 0 && m0 < CT::RC && m1 >= 0 && m1 < CT::RC &&
                         (D == 2 || (m2 >= 0 && m2 < CT::RC));
-                if (!inreg) scatter_global<D>(g, sn, pl, grid_out);
+                if (!inreg) {
+                    if (DET)
+                        raise_flag(flag, MR_FLAG_DRIFT);
+                    else
+                        scatter_global<D>(g, sn, pl, grid_out);
+                }
             }
         }
         bool pending = scat && inreg;
@@ -546,7 +576,13 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
         while (__ballot(pending) != 0) {
             bool go = pending;
             if (any_drift) {
-                if (pending) owner[key] = lane;
+                if (DET) {
+                    if (pending) owner[key] = 64;
+                    lds_order();
+                    if (pending) atomicMin(owner + key, lane);
+                } else if (pending) {
+                    owner[key] = lane;
+                }
                 lds_order();
                 go = pending && owner[key] == lane;
                 lds_order();
@@ -573,8 +609,17 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
         }
     }
     lds_order();
-    // flush the region: one global atomic per non-zero node channel
     constexpr int RN = (D == 3) ? CT::R * CT::R * CT::R : CT::R * CT::R;
+    if (DET) {
+        // the whole region, zeros included, in region order
+        float4 *dst = stage + t * RN;
+        for (int li = lane; li < RN; li += 64) {
+            const int i0 = li % CT::R, i1 = (li / CT::R) % CT::R, i2 = D == 3 ? li / (CT::R * CT::R) : 0;
+            dst[li] = acc[i0 + CT::SY * i1 + (D == 3 ? CT::SZ * i2 : 0)];
+        }
+        return;
+    }
+    // flush the region: one global atomic per non-zero node channel
     for (int li = lane; li < RN; li += 64) {
         const int i0 = li % CT::R, i1 = (li / CT::R) % CT::R, i2 = D == 3 ? li / (CT::R * CT::R) : 0;
         const float4 q = acc[i0 + CT::SY * i1 + (D == 3 ? CT::SZ * i2 : 0)];
@@ -587,6 +632,54 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
         atomicAdd(gp + 2, q.z);
         if (D == 3) atomicAdd(gp + 3, q.w);
     }
+}
+
+// Deterministic mode: node i of the grid sums the staged regions of the
+// tiles covering it (a tile's region spans nodes TS*tt - 1 .. TS*tt + TS + 2
+// per axis) in ascending tile order, skipping empty tiles, and writes (or
+// adds to) the grid.
+template <int D>
+__global__ void det_combine_kernel(GridK g, TileGeom tg, const int32_t *offsets,
+                                   const float4 *stage, float *grid, int accumulate)
+{
+    using CT = CellTile<D>;
+    constexpr int RN = (D == 3) ? CT::R * CT::R * CT::R : CT::R * CT::R;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nodes = (int64_t)g.n0 * g.n1 * (D == 3 ? g.n2 : 1);
+    if (i >= nodes) return;
+    const int c[3] = {(int)(i % g.n0), (int)((i / g.n0) % g.n1),
+                      D == 3 ? (int)(i / ((int64_t)g.n0 * g.n1)) : 0};
+    const int nt[3] = {tg.nt0, tg.nt1, tg.nt2};
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        // tiles tt with TS tt - 1 <= c <= TS tt + R - 2
+        int l = c[a] - (CT::R - 2);
+        l = l <= 0 ? 0 : (l + CT::TS - 1) / CT::TS;
+        int h = (c[a] + 1) / CT::TS;
+        hi[a] = h < nt[a] - 1 ? h : nt[a] - 1;
+        lo[a] = l;
+    }
+    float4 sum = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int t2 = lo[2]; t2 <= hi[2]; ++t2)
+        for (int t1 = lo[1]; t1 <= hi[1]; ++t1)
+            for (int t0 = lo[0]; t0 <= hi[0]; ++t0) {
+                const int64_t t = t0 + (int64_t)tg.nt0 * (t1 + (int64_t)tg.nt1 * t2);
+                if (offsets[t * Tiling<D>::CELLS] == offsets[(t + 1) * Tiling<D>::CELLS]) continue;
+                const int l0 = c[0] - (t0 * CT::TS - 1), l1 = c[1] - (t1 * CT::TS - 1);
+                const int l2 = D == 3 ? c[2] - (t2 * CT::TS - 1) : 0;
+                const float4 q = stage[t * RN + l0 + CT::R * (l1 + CT::R * l2)];
+                sum.x += q.x;
+                sum.y += q.y;
+                sum.z += q.z;
+                sum.w += q.w;
+            }
+    float4 *gp = reinterpret_cast<float4 *>(grid) + i;
+    if (accumulate) {
+        float4 o = *gp;
+        sum = make_float4(o.x + sum.x, o.y + sum.y, o.z + sum.z, o.w + sum.w);
+    }
+    *gp = sum;
 }
 
 // ---------------------------------------------------------------------------
@@ -679,6 +772,7 @@ __global__ void __launch_bounds__(256) g2p_kernel(GridK g, int64_t n, float *x, 
 struct SortWorkspace {
     int32_t *keys, *counts, *offsets, *fill, *cell_sorted, *perm, *block_sums, *total;
     float *copy;
+    float4 *stage;   // deterministic P2G: every tile's region, [tile][region node]
     int64_t ncells;
 };
 
@@ -697,7 +791,8 @@ int64_t sort_ws_bytes(const GridK &g, int64_t n, SortWorkspace *ws, char *basep)
     int64_t o_keys = take(4 * n), o_counts = take(4 * (ncells + 1)),
             o_offsets = take(4 * (ncells + 1)), o_fill = take(4 * (ncells + 1)),
             o_cs = take(4 * n), o_perm = take(4 * n), o_bs = take(4 * nb), o_tot = take(4),
-            o_copy = take(4 * n * (2 * D + 2 * D * D + 3));
+            o_copy = take(4 * n * (2 * D + 2 * D * D + 3)),
+            o_stage = take(16 * tg.ntiles * (int64_t)Tiling<D>::RN);
     if (ws) {
         ws->keys = (int32_t *)(basep + o_keys);
         ws->counts = (int32_t *)(basep + o_counts);
@@ -708,6 +803,7 @@ int64_t sort_ws_bytes(const GridK &g, int64_t n, SortWorkspace *ws, char *basep)
         ws->block_sums = (int32_t *)(basep + o_bs);
         ws->total = (int32_t *)(basep + o_tot);
         ws->copy = (float *)(basep + o_copy);
+        ws->stage = (float4 *)(basep + o_stage);
         ws->ncells = ncells;
     }
     return off;
@@ -716,7 +812,8 @@ int64_t sort_ws_bytes(const GridK &g, int64_t n, SortWorkspace *ws, char *basep)
 template <int D>
 int32_t cell_sort_impl(const GridK &g, mr_particles *parts, int32_t *perm_out, void *workspace,
                        int32_t *flag, hipStream_t st, int32_t *carry = nullptr,
-                       const mr_particles *dst = nullptr, int32_t *carry_dst = nullptr)
+                       const mr_particles *dst = nullptr, int32_t *carry_dst = nullptr,
+                       bool canonical = false)
 {
     const int64_t n = parts->n;
     SortWorkspace ws;
@@ -735,8 +832,8 @@ int32_t cell_sort_impl(const GridK &g, mr_particles *parts, int32_t *perm_out, v
     int32_t rc = exclusive_scan(ws.counts, ncells + 1, ws.offsets, ws.block_sums, ws.total, st);
     if (rc != MR_OK) return rc;
     cell_scatter_kernel<<<gb, TB, 0, st>>>(ws.keys, n, ws.offsets, ws.fill, ws.cell_sorted);
-    cell_segment_sort_kernel<<<(unsigned)ceil_div(ncells, TB), TB, 0, st>>>(
-        ws.offsets, ws.counts, ncells, ws.cell_sorted);
+    cell_segment_sort_kernel<D><<<(unsigned)ceil_div(ncells, TB), TB, 0, st>>>(
+        ws.offsets, ws.counts, ncells, ws.cell_sorted, parts->x, n, canonical ? 1 : 0);
     tile_slot_kernel<D><<<(unsigned)tg.ntiles, Tiling<D>::CELLS, 0, st>>>(
         ws.offsets, ws.counts, ws.cell_sorted, ws.perm, tg.ntiles);
     tail_copy_kernel<<<gb, TB, 0, st>>>(ws.cell_sorted, ws.perm,
@@ -792,9 +889,25 @@ int32_t p2g_impl(const GridK &g, const mr_material *mat, const mr_particles *par
 {
     Lame lm = lame_of(mat->E, mat->nu);
     int apic = (flags & MR_NO_AFFINE) ? 0 : 1;
+    PartPtrs<D> pp = part_ptrs<D>(parts);
+    if (flags & MR_DETERMINISTIC) {
+        // every node is written by the combine (added to with MR_ACCUMULATE)
+        SortWorkspace ws;
+        sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
+        TileGeom tg = tile_geom<D>(g);
+        if (tg.ntiles > 0)
+            tile_scatter_kernel<D, false, true><<<(unsigned)ceil_div(tg.ntiles, CellTile<D>::WPB), 64 * CellTile<D>::WPB, 0, st>>>(
+                g, tg, parts->x, parts->v, parts->C, parts->F, parts->m, parts->V0, parts->m_uniform,
+                parts->V0_uniform, parts->n, ws.offsets, ws.counts, apic, mat->model, lm.mu, lm.la, dt,
+                nullptr, grid, nullptr, nullptr, flag, ws.stage);
+        const int64_t nodes = grid_nodes(g);
+        det_combine_kernel<D><<<(unsigned)ceil_div(nodes, 256), 256, 0, st>>>(
+            g, tg, ws.offsets, ws.stage, grid, (flags & MR_ACCUMULATE) ? 1 : 0);
+        MR_LAUNCH_CHECK();
+        return MR_OK;
+    }
     if (!(flags & MR_ACCUMULATE))
         MR_CHECK_HIP(hipMemsetAsync(grid, 0, sizeof(float) * 4 * grid_nodes(g), st));
-    PartPtrs<D> pp = part_ptrs<D>(parts);
     if ((flags & MR_SORTED) && !subset) {
         SortWorkspace ws;
         sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
@@ -842,6 +955,7 @@ extern "C" int32_t mpm_p2g(const mr_grid *grid_desc, const mr_material *mat,
     if (mat->model == MR_FIXED_COROTATED && grid_desc->dim != 2) return MR_EINVAL;
     if (mat->model != MR_FIXED_COROTATED && mat->model != MR_NEO_HOOKEAN) return MR_EINVAL;
     if ((flags & MR_SORTED) && !workspace) return MR_EINVAL;
+    if ((flags & MR_DETERMINISTIC) && (!(flags & MR_SORTED) || subset)) return MR_EINVAL;
     int64_t ns = subset ? n_subset : parts->n;
     if (ns < 0) return MR_EINVAL;
     hipStream_t st = as_stream(stream);
@@ -906,16 +1020,27 @@ extern "C" int64_t mpm_workspace_bytes(const mr_grid *grid_desc, int64_t n)
                                : sort_ws_bytes<3>(g, n, nullptr, nullptr);
 }
 
-extern "C" int32_t mpm_cell_sort(const mr_grid *grid_desc, mr_particles *parts, int32_t *perm_out,
-                                 void *workspace, int32_t *status_flag, void *stream)
+extern "C" int32_t mpm_cell_sort_ex(const mr_grid *grid_desc, mr_particles *parts,
+                                    int32_t *perm_out, void *workspace, int32_t flags,
+                                    int32_t *status_flag, void *stream)
 {
     GridK g;
     if (!grid_from_desc(grid_desc, g) || !workspace || !check_parts(parts, grid_desc->dim, false))
         return MR_EINVAL;
-    if (parts->n > INT32_MAX) return MR_EINVAL;
+    if (parts->n > INT32_MAX || (flags & ~MR_DETERMINISTIC)) return MR_EINVAL;
     hipStream_t st = as_stream(stream);
-    return grid_desc->dim == 2 ? cell_sort_impl<2>(g, parts, perm_out, workspace, status_flag, st)
-                               : cell_sort_impl<3>(g, parts, perm_out, workspace, status_flag, st);
+    const bool canon = (flags & MR_DETERMINISTIC) != 0;
+    return grid_desc->dim == 2
+               ? cell_sort_impl<2>(g, parts, perm_out, workspace, status_flag, st, nullptr, nullptr,
+                                   nullptr, canon)
+               : cell_sort_impl<3>(g, parts, perm_out, workspace, status_flag, st, nullptr, nullptr,
+                                   nullptr, canon);
+}
+
+extern "C" int32_t mpm_cell_sort(const mr_grid *grid_desc, mr_particles *parts, int32_t *perm_out,
+                                 void *workspace, int32_t *status_flag, void *stream)
+{
+    return mpm_cell_sort_ex(grid_desc, parts, perm_out, workspace, 0, status_flag, stream);
 }
 
 extern "C" int32_t mpm_cell_keys(const mr_grid *grid_desc, const mr_particles *parts,
@@ -1148,6 +1273,8 @@ extern "C" int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
         return MR_EINVAL;
     if (!(flags & MR_NO_AFFINE) && !parts->C && parts->n > 0) return MR_EINVAL;
     if (sort_every > 0 && parts->n > INT32_MAX) return MR_EINVAL;
+    if ((flags & MR_DETERMINISTIC) && sort_every < 1) return MR_EINVAL;
+    const bool det = (flags & MR_DETERMINISTIC) != 0;
     const int dim = grid_desc->dim;
     int32_t rc = MR_OK;
     hipStream_t st = as_stream(stream);
@@ -1193,9 +1320,9 @@ extern "C" int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
     auto do_sort = [&]() -> int32_t {
         TimedLaunch tl(timing, MR_KC_SORT, st);
         int32_t r = dim == 2 ? cell_sort_impl<2>(g, cur, nullptr, workspace, status_flag, st,
-                                                 carry_cur, other, carry_other)
+                                                 carry_cur, other, carry_other, det)
                              : cell_sort_impl<3>(g, cur, nullptr, workspace, status_flag, st,
-                                                 carry_cur, other, carry_other);
+                                                 carry_cur, other, carry_other, det);
         mr_particles *tp = cur;
         cur = other;
         other = tp;
@@ -1227,7 +1354,8 @@ extern "C" int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
     auto do_p2g = [&](float *target, bool cleared) -> int32_t {
         TimedLaunch tl(timing, MR_KC_P2G, st);
         return mpm_p2g(grid_desc, mat, cur, nullptr, 0, dt, target,
-                       naff | (sorted ? MR_SORTED : 0) | (cleared ? MR_ACCUMULATE : 0), workspace,
+                       naff | (sorted ? MR_SORTED : 0) | (cleared ? MR_ACCUMULATE : 0) |
+                           (det ? MR_DETERMINISTIC : 0), workspace,
                        status_flag, stream);
     };
     const int64_t nodes = grid_nodes(g);

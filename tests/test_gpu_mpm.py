@@ -196,6 +196,84 @@ def test_sorted_tiled_p2g_matches_oracle(gpu, dim, P, move):
     close_channels(g[:, 1:1 + dim], gmv + 1e-4 * gf, name="momentum")
 
 
+@pytest.mark.parametrize("dim,P", [(3, 20000), (2, 6000)])
+def test_deterministic_p2g_is_bitwise_reproducible(gpu, dim, P):
+    """MR_DETERMINISTIC: after the canonical sort the grid is bitwise the
+    same for a shuffled input order and on a repeated run, every node is
+    written (no zeroing needed), and it matches the oracle; particles moved
+    beyond the drift margin raise MR_FLAG_DRIFT."""
+    rng = np.random.default_rng(60 + dim)
+    n = [40] * dim
+    dx = 1 / 40
+    x, v, C, F, m, V0 = random_state(rng, dim, P, lo=0.2, hi=0.8)
+    grid = B.Grid(dim, n, dx)
+    model = 0 if dim == 2 else 1
+    nodes = int(np.prod(n))
+    grids = []
+    for order in (np.arange(P), rng.permutation(P), np.arange(P)):
+        parts = make_parts(B, x[order], v[order], C[order], F[order], m[order], V0[order])
+        ws = B.new_workspace(grid, P)
+        flag = torch.zeros(1, dtype=torch.int32, device=dev)
+        B.mpm_cell_sort_ex(grid, parts, ws, B.DETERMINISTIC, status=flag)
+        gbuf = torch.full((nodes * 4,), 7.0, device=dev)
+        B.mpm_p2g(grid, (model, 1e4, 0.3), parts, gbuf, 1e-4, flags=B.SORTED | B.DETERMINISTIC,
+                  workspace=ws, status=flag)
+        assert flag.item() == 0
+        grids.append(gbuf.cpu().numpy())
+    assert np.array_equal(grids[0], grids[1]) and np.array_equal(grids[0], grids[2])
+    mu, la = OM.lame(1e4, 0.3)
+    gm, gmv, gf = OM.p2g(dim, n, dx, x, v, C, F, m, V0, model, mu, la)
+    g = grids[0].reshape(-1, 4)
+    close_channels(g[:, 0], gm, name="mass")
+    close_channels(g[:, 1:1 + dim], gmv + 1e-4 * gf, name="momentum")
+    # motion beyond the margin since the sort is reported, not scattered
+    parts = make_parts(B, x, v, C, F, m, V0)
+    ws = B.new_workspace(grid, P)
+    perm = torch.zeros(P, dtype=torch.int32, device=dev)
+    B.mpm_cell_sort_ex(grid, parts, ws, B.DETERMINISTIC, perm_out=perm)
+    p = perm.cpu().numpy()
+    xs = x[p] + (rng.uniform(-1.4, 1.4, size=(P, dim)) * dx).astype(np.float32)
+    parts.x.copy_(T(soa(xs)))
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    gbuf = torch.zeros(nodes * 4, device=dev)
+    B.mpm_p2g(grid, (model, 1e4, 0.3), parts, gbuf, 1e-4, flags=B.SORTED | B.DETERMINISTIC,
+              workspace=ws, status=flag)
+    assert flag.item() & B.FLAG_DRIFT
+
+
+def test_deterministic_steps_are_bitwise_reproducible(gpu):
+    """mpm_step with MR_DETERMINISTIC from the same state in two input
+    orders: after relabelling by perm_accum the final x, v, C, F agree bit
+    for bit (and with a repeated run), and stay within rounding of the
+    default schedule."""
+    s = scenes.scene_3d(n=32, cube_cells=8, seed=5, v0=(0.3, -2.0, 0.1))
+    st0 = scenes.initial_state(s)
+    P = s["P"]
+    grid = _gpu_scene(B, s)
+    rng = np.random.default_rng(61)
+    outs = []
+    for order, det in ((np.arange(P), True), (rng.permutation(P), True), (np.arange(P), True),
+                       (np.arange(P), False)):
+        parts = make_parts(B, st0["x"][order], st0["v"][order], st0["C"][order], st0["F"][order],
+                           m_u=float(s["m"]), V0_u=float(s["V0"]))
+        gbuf = torch.zeros(grid.nodes() * 4, device=dev)
+        ws = torch.zeros(B.mpm_step_workspace_bytes(grid, P), dtype=torch.uint8, device=dev)
+        perm = torch.zeros(P, dtype=torch.int32, device=dev)
+        flag = torch.zeros(1, dtype=torch.int32, device=dev)
+        B.mpm_step(grid, (s["model"], s["E"], s["nu"]), parts, s["dt"], 30, 10,
+                   B.DETERMINISTIC if det else 0, gbuf, ws, perm_accum=perm, status=flag)
+        assert flag.item() == 0
+        ident = order[perm.cpu().numpy()]           # original label of every slot
+        inv = np.empty(P, dtype=np.int64)
+        inv[ident] = np.arange(P)
+        outs.append({k: getattr(parts, k).cpu().numpy()[:, inv] for k in ("x", "v", "C", "F")})
+    for k in ("x", "v", "C", "F"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+        assert np.array_equal(outs[0][k], outs[2][k]), k
+    print("deterministic vs default schedule after 30 steps: x %.2e" % rel_l2(outs[0]["x"], outs[3]["x"]))
+    assert rel_l2(outs[0]["x"], outs[3]["x"]) < 1e-6
+
+
 def _run_oracle(sc, st, dt, steps):
     st = {k: np.asarray(v, dtype=np.float64) for k, v in st.items()}
     for _ in range(steps):
