@@ -276,6 +276,52 @@ def rom_step(dec, scene, X_all, m_all, V0_all, zhat, zhat_prev, vhat, dt,
     return z, vh, info
 
 
+# failures that hand the run over to the full-order model
+FALLBACK_STATUS = _proj.STATUS_SINGULAR | _proj.STATUS_NOCONV
+STATUS_DOMAIN = 1 << 8      # stress undefined (J <= 0), NaN, or a point off the lattice
+
+
+def full_state_from_latent(dec, X_all, zhat, vhat):
+    """The full-order state the reduced one stands for (Section 3.1:
+    x = g(X; xhat), F = dg/dX, v = (dg/dxhat) vhat), with C = 0 since the
+    reduced substep carries no affine term."""
+    x, F, _, v = _dec.decode_jac(dec, X_all, zhat, vhat)
+    return {"x": x, "v": v, "C": np.zeros_like(F), "F": F}
+
+
+def run_with_fallback(dec, scene, X_all, zhat, zhat_prev, vhat, dt, n_steps, sample_fn, opts,
+                      apic=False, **rom_kwargs):
+    """Reduced steps (rom_step with scene["m"], scene["V0"]) until one fails
+    (a singular normal matrix, Gauss-Newton above tolerance, or a domain
+    error); from the last good latent state the full-order state is
+    reconstructed and the remaining steps, the failed one included, run
+    with Algorithm 1.  sample_fn(step) gives the sample indices.
+    Returns (state, fallback step or None, failing status, full-order
+    status): state is the full-order state at the end (reconstructed from
+    the final latents when no step failed)."""
+    m_all, V0_all = scene["m"], scene["V0"]
+    for k in range(n_steps):
+        try:
+            zn, vn, info = rom_step(dec, scene, X_all, m_all, V0_all, zhat, zhat_prev, vhat, dt,
+                                    sample_fn(k), opts, **rom_kwargs)
+            bad = info["status"] & FALLBACK_STATUS
+            if not bad and not (np.all(np.isfinite(zn)) and np.all(np.isfinite(vn))):
+                bad = STATUS_DOMAIN
+        except _mpm.OracleDomainError:
+            bad = STATUS_DOMAIN
+        if bad:
+            state = full_state_from_latent(dec, X_all, zhat, vhat)
+            fom_status = 0
+            try:
+                for _ in range(k, n_steps):
+                    state = _mpm.step(scene, state, dt, apic=apic)
+            except _mpm.OracleDomainError:
+                fom_status = STATUS_DOMAIN
+            return state, k, bad, fom_status
+        zhat_prev, zhat, vhat = zhat, zn, vn
+    return full_state_from_latent(dec, X_all, zhat, vhat), None, 0, 0
+
+
 def rom_init(dec, X, V, opts, z0=None):
     """Least-squares initial latents (eq. essentialSpecInt by point
     quadrature): xhat_0 minimises sum ||X - g(X; z)||^2 by Gauss-Newton
