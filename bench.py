@@ -319,7 +319,9 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
     data scale), then n_steps reduced steps (512 samples, position-velocity
     projection, 3 Gauss-Newton iterations, normal equations damped by 1e-4)
     judged every 10 steps against the full-order model with the transfers of
-    the reduced substep (no affine term)."""
+    the reduced substep (no affine term).  The same decoder then runs on the
+    body sampled 2x finer per dimension (16,777,216 particles it never saw),
+    judged against the full-order model on that set."""
     import torch
     from paper_2109_12390_amd import evaluate as EV
     from paper_2109_12390_amd import train as TR
@@ -361,6 +363,28 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
                          "displacement_error": round(e2, 4), "position_error_percent": round(p2, 4),
                          "status": sv["status"]})
         log("trained variant:", json.dumps(variants[-1]))
+    # zero-shot super-resolution: the same body sampled 2x finer per
+    # dimension (4 particles per cell per dimension, a new jitter), which the
+    # decoder never saw, judged against the full-order model on that set
+    del x_rom, fom
+    fine = scenes.scene_3d(seed=3, sub=4)
+    fom_f = EV.fom_positions(fine, E, v0, n_steps, 10, affine=False)
+    super_res = []
+    for qn, quad in (("eulerian", B.QUAD_EULERIAN), ("lagrangian", B.QUAD_LAGRANGIAN)):
+        xr, sv = EV.rom_positions(dec, fine, E, v0, n_steps, 10, n_samples=n_samples,
+                                  opts=B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4),
+                                  z_guess=Z[0], quadrature=quad)
+        e2, p2 = EV.displacement_error(xr, fom_f, fine["X"])
+        del xr
+        super_res.append({"particles": fine["P"], "quadrature": qn, "samples": n_samples,
+                          "projection": "position-velocity",
+                          "latent_steps_per_s": round(1e3 / sv["ms_per_step"], 1),
+                          "ms_per_step": round(sv["ms_per_step"], 4),
+                          "quadrature_points": sv["n_quadrature_points"],
+                          "displacement_error": round(e2, 4), "position_error_percent": round(p2, 4),
+                          "status": sv["status"]})
+        log("super-resolution:", json.dumps(super_res[-1]))
+    del fom_f
     dec.close()
     return {"metric": "ROM latent steps/s at the measured displacement error",
             "value": float(1e3 / st["ms_per_step"]), "unit": "latent steps/s",
@@ -374,7 +398,7 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
                        "projection": "position-velocity, 3 Gauss-Newton iterations, damping 1e-4",
                        "quadrature": "Lagrangian",
                        "reference": "full-order model without the affine transfer term"},
-            "variants": variants}
+            "variants": variants, "super_resolution": super_res}
 
 
 SHAPE_NAMES = ["1 point tile per wave", "2 point tiles per wave", "4 point tiles per wave",

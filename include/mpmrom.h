@@ -423,7 +423,11 @@ typedef struct {
  * moduli; n_samples: device int32 [B] sample counts (r/d <= count <=
  * n_samples_max).  The grid and option structs are copied; the decoder is
  * referenced and must outlive the runner.  Allocates all workspace up front
- * (synchronous).  With cfg->autotune set, the decoder's launch shapes are
+ * (synchronous).  The quadrature list holds, per sample, the (5 cells)^d box
+ * of stencil bases around it: Lagrangian, twice the particles of the
+ * densest reference cell (at least 16) per base cell, at most P; Eulerian,
+ * l^d points per base.  A step that would exceed it keeps the first entries
+ * and raises MR_FLAG_DOMAIN.  With cfg->autotune set, the decoder's launch shapes are
  * tuned for the runner's four decoder launches (all particles, the
  * quadrature list, the samples, the line-search candidates), which updates
  * the decoder's shape table. */

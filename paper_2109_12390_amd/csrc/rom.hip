@@ -804,15 +804,42 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
     R->newton_iters = newton_iters;
     R->newton_tol = newton_tol;
     const bool eul = R->quad == MR_QUAD_EULERIAN;
+    // reference positions on the host: the stencil base cell of every
+    // particle orders the runner's particles (below) and gives the densest
+    // cell, which bounds the quadrature list
+    const int64_t Pn = cfg->n_particles;
+    std::vector<float> Xh((size_t)d * Pn);
+    std::vector<int64_t> key(Pn);
+    if (hipMemcpy(Xh.data(), X_all, 4 * d * Pn, hipMemcpyDeviceToHost) != hipSuccess) {
+        free(R);
+        return MR_EDEVICE;
+    }
+    int64_t ppc_max = 0;
+    {
+        const int nn[3] = {g.n0, g.n1, g.n2};
+        std::vector<int32_t> per_cell(R->nodes, 0);
+        for (int64_t p = 0; p < Pn; ++p) {
+            int64_t kk = 0;
+            for (int a = d - 1; a >= 0; --a) {
+                float bf = floorf(Xh[(size_t)a * Pn + p] * g.inv_dx - 0.5f);
+                int64_t bi = bf < 0.0f ? 0 : (bf > (float)(nn[a] - 1) ? nn[a] - 1 : (int64_t)bf);
+                kk = kk * nn[a] + bi;
+            }
+            key[p] = kk;
+            const int32_t c = ++per_cell[kk];
+            if (c > ppc_max) ppc_max = c;
+        }
+    }
     // quadrature capacity: every sample's 3^d nodes are reached from a
-    // (5 cells)^d box of stencil bases; Lagrangian: allow 16 particles per
-    // cell; Eulerian: every base of the box, l^d points each
+    // (5 cells)^d box of stencil bases; Lagrangian: twice the densest
+    // reference cell's particles per base cell (at least 16), room for
+    // compression; Eulerian: every base of the box, l^d points each
     const int64_t box = (d == 3) ? 125 : 25;
     if (eul) {
         R->qb_cap = R->ns_max * box < R->nodes ? R->ns_max * box : R->nodes;
         R->q_cap = R->qb_cap * (d == 3 ? ell * ell * ell : ell * ell);
     } else {
-        const int64_t per = box * 16;
+        const int64_t per = box * (2 * ppc_max > 16 ? 2 * ppc_max : 16);
         R->q_cap = R->ns_max * per < R->P ? R->ns_max * per : R->P;
     }
     if (R->q_cap > INT32_MAX) {
@@ -876,27 +903,16 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
     // reference position (stable): the quadrature list, collected in this
     // order, then holds runs of particles sharing a stencil, which the
     // quadrature P2G sums within a wave before its atomics.
-    std::vector<float> Xh((size_t)d * P), Xs((size_t)d * P), mh, ms;
-    std::vector<int64_t> key(P);
+    std::vector<float> Xs((size_t)d * P), mh, ms;
     std::vector<int32_t> order(P), inv(P);
-    bool cp = hipMemcpy(Xh.data(), X_all, 4 * d * P, hipMemcpyDeviceToHost) == hipSuccess;
-    if (cp && m_all) {
+    bool cp = true;
+    if (m_all) {
         mh.resize(P);
         ms.resize(P);
         cp = hipMemcpy(mh.data(), m_all, 4 * P, hipMemcpyDeviceToHost) == hipSuccess;
     }
     if (cp) {
-        const int nn[3] = {g.n0, g.n1, g.n2};
-        for (int64_t p = 0; p < P; ++p) {
-            int64_t kk = 0;
-            for (int a = d - 1; a >= 0; --a) {
-                float bf = floorf(Xh[(size_t)a * P + p] * g.inv_dx - 0.5f);
-                int64_t bi = bf < 0.0f ? 0 : (bf > (float)(nn[a] - 1) ? nn[a] - 1 : (int64_t)bf);
-                kk = kk * nn[a] + bi;
-            }
-            key[p] = kk;
-            order[p] = (int32_t)p;
-        }
+        for (int64_t p = 0; p < P; ++p) order[p] = (int32_t)p;
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t a, int32_t b) { return key[a] < key[b]; });
         for (int64_t i = 0; i < P; ++i) {

@@ -66,15 +66,16 @@ def scene_2d(seed=1, literal_block=False):
                       (0.0, -9.8), FLOOR_STICKY, 0.0, 3, 1.0e-4, seed)
 
 
-def scene_3d(n=128, cube_cells=64, seed=2, E=5.0e4, v0=(0.0, -1.0, 0.0)):
+def scene_3d(n=128, cube_cells=64, seed=2, E=5.0e4, v0=(0.0, -1.0, 0.0), sub=2):
     """3D full-order scene: n^3 nodes (dx = 1/n), a jittered Neo-Hookean cube
-    of cube_cells^3 cells with 8 particles per cell (2,097,152 at the default
-    size), density 1000, E = 5e4, nu = 0.3, dropped with v0 onto a Coulomb
+    of cube_cells^3 cells with sub particles per cell per dimension (8 per
+    cell, 2,097,152 at the default size; sub = 4 is the same body sampled 2x
+    finer), density 1000, E = 5e4, nu = 0.3, dropped with v0 onto a Coulomb
     floor (mu = 0.3), other faces sticky, band 3 nodes, dt = 5e-5."""
     dx = 1.0 / n
     side = cube_cells * dx
     lo = (0.5 - side / 2, 5.12 * dx, 0.5 - side / 2)
-    return make_scene(3, n, (cube_cells,) * 3, lo, 2, 1000.0, E, 0.3,
+    return make_scene(3, n, (cube_cells,) * 3, lo, sub, 1000.0, E, 0.3,
                       MODEL_NEO_HOOKEAN, (0.0, -9.8, 0.0), FLOOR_COULOMB, 0.3, 3,
                       5.0e-5, seed, v0=v0)
 

@@ -405,3 +405,38 @@ def test_linear_decoder_matches_oracle(gpu):
     assert scaled_err(F[0].cpu().numpy().T.reshape(333, d, d), Fo, np.max(np.abs(Fo - np.eye(d)))) < 1e-5
     assert scaled_err(J[0].cpu().numpy().T.reshape(333, d, r), Jo, np.max(np.abs(Jo))) < 1e-5
     assert scaled_err(v[0].cpu().numpy().T, vo, np.max(np.abs(vo))) < 1e-5
+
+
+def test_lagrangian_quadrature_list_at_high_particle_density(gpu):
+    """A body sampled with 64 particles per cell (4 per dimension) and 4
+    samples: each interior sample reaches up to 125 x 64 = 8,000 neighbour
+    particles, beyond 16 per base cell.  The quadrature list (Algorithm 3:
+    particles whose stencil shares a node with a sample's stencil) must be
+    complete, equal to the host's enumeration, with no capacity flag."""
+    s = scenes.scene_3d(n=32, cube_cells=8, seed=4, sub=4)
+    d, P = 3, s["P"]
+    X = s["X"]
+    W = np.concatenate([np.zeros((d, d)), np.eye(d)], axis=1).astype(np.float32)
+    gdec = B.Decoder([W], [np.zeros(d, np.float32)], X.min(0), X.max(0), np.zeros(d), np.ones(d))
+    grid = B.Grid(3, s["n"], s["dx"], 0, B.FLOOR_STICKY, 0.0, s["gravity"])
+    ns = 4
+    rom = B.Rom(gdec, grid, T(soa(X)), T(np.array([5e4], np.float32)),
+                T(np.array([ns], np.int32), torch.int32), B.gn_opts(mode=B.VEL_ONLY), seed=12,
+                rho0=1000.0, m_uniform=float(s["m"]))
+    z = torch.zeros(1, d, dtype=torch.float64, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    rom.step(1, 0, s["dt"], z, z.clone(), torch.zeros_like(z), status=st)
+    q, a = rom.last_counts(0)
+    rom.close()
+    # host enumeration at x = X (the decoder is the identity at xhat = 0)
+    base = np.floor(X.astype(np.float32) * np.float32(s["n"][0]) - np.float32(0.5)).astype(np.int64)
+    smp = OR.sample_indices(12, 0, 0, ns, P)
+    near = np.zeros(P, dtype=bool)
+    for i in smp:
+        near |= np.all(np.abs(base - base[i]) <= 2, axis=1)
+    nodes = {tuple(base[i] + o) for i in smp for o in np.ndindex(3, 3, 3)}
+    print("quadrature particles %d (host %d), active nodes %d (host %d)"
+          % (q, near.sum(), a, len(nodes)))
+    assert st.item() == 0
+    assert q == int(near.sum()) and a == len(nodes)
+    assert q > ns * 125 * 16      # more than 16 particles per base cell of every box
