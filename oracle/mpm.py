@@ -32,6 +32,8 @@ def _load():
         lib.orc_kirchhoff.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_double, _dp, _dp]
         lib.orc_kirchhoff.restype = ctypes.c_int
+        lib.orc_closest_rotation.argtypes = [ctypes.c_int, _dp, _dp]
+        lib.orc_closest_rotation.restype = None
         lib.orc_p2g.argtypes = [ctypes.c_int, _ip, ctypes.c_double, ctypes.c_long, _lp,
                                 _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -102,6 +104,16 @@ def kirchhoff(dim, model, mu, la, F):
     if rc != 0:
         raise OracleDomainError("stress undefined (J <= 0 or unsupported model)")
     return tau
+
+
+def closest_rotation(dim, F):
+    """The rotation (det +1) closest to F in the Frobenius norm, which the
+    fixed-corotated stress uses (the polar rotation when det F > 0)."""
+    lib = _load()
+    F = _f64(F, (dim, dim))
+    R = np.zeros((dim, dim))
+    lib.orc_closest_rotation(dim, _d(F), _d(R))
+    return R
 
 
 def num_nodes(n):

@@ -100,15 +100,110 @@ static double det(int dim, const double *F)
          + F[2] * (F[3] * F[7] - F[4] * F[6]);
 }
 
+/* Cyclic Jacobi eigenvalue iteration for a symmetric 4x4 matrix A (textbook
+ * form: each rotation in the (p, q) plane zeroes A[p][q]).  On return the
+ * diagonal of A holds the eigenvalues and the columns of V the eigenvectors. */
+static void jacobi_eig4(double A[4][4], double V[4][4])
+{
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int p = 0; p < 4; ++p) {
+            diag += A[p][p] * A[p][p];
+            for (int q = p + 1; q < 4; ++q) off += A[p][q] * A[p][q];
+        }
+        if (off <= 1e-34 * (diag + off) || off == 0.0) break;
+        for (int p = 0; p < 4; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                if (A[p][q] == 0.0) continue;
+                /* J = [[c, s], [-s, c]] in the (p, q) plane; A <- J^T A J
+                 * zeroes A[p][q] when cot(2 phi) = (A_qq - A_pp) / (2 A_pq)
+                 * and t = tan(phi) is the smaller root of t^2 + 2 theta t - 1 */
+                double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < 4; ++k) {
+                    double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - sn * akq;
+                    A[k][q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - sn * aqk;
+                    A[q][k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = c * vkp - sn * vkq;
+                    V[k][q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+}
+
+/* The rotation R (det R = +1) closest to F in the Frobenius norm, i.e. the
+ * one maximising tr(R^T F).  For det F > 0 it is the rotation factor of the
+ * polar decomposition F = R S with S symmetric positive definite; for
+ * det F <= 0 it is the rotation the fixed-corotated model of Stomakhin et
+ * al. (2012) uses for inverted elements.
+ * d = 2: R is the rotation by the angle of (F00 + F11, F10 - F01); R = I
+ * when both vanish.
+ * d = 3: with R(q) the rotation of the unit quaternion q = (w, x, y, z),
+ * tr(R(q)^T F) is the quadratic form q^T K q of the symmetric 4x4 matrix K
+ * below (expanded from the entries of R(q)), so the best q is the
+ * eigenvector of K's largest eigenvalue (a Rayleigh quotient over the unit
+ * sphere); the eigenvectors come from cyclic Jacobi rotations. */
+void orc_closest_rotation(int dim, const double *F, double *R)
+{
+    if (dim == 2) {
+        double cs = F[0] + F[3], sn = F[2] - F[1];
+        double h = sqrt(cs * cs + sn * sn);
+        double c = 1.0, s = 0.0;
+        if (h > 0.0) {
+            c = cs / h;
+            s = sn / h;
+        }
+        R[0] = c; R[1] = -s; R[2] = s; R[3] = c;
+        return;
+    }
+    const double F00 = F[0], F01 = F[1], F02 = F[2], F10 = F[3], F11 = F[4], F12 = F[5],
+                 F20 = F[6], F21 = F[7], F22 = F[8];
+    double K[4][4], V[4][4];
+    K[0][0] = F00 + F11 + F22;
+    K[1][1] = F00 - F11 - F22;
+    K[2][2] = -F00 + F11 - F22;
+    K[3][3] = -F00 - F11 + F22;
+    K[0][1] = K[1][0] = F21 - F12;
+    K[0][2] = K[2][0] = F02 - F20;
+    K[0][3] = K[3][0] = F10 - F01;
+    K[1][2] = K[2][1] = F01 + F10;
+    K[1][3] = K[3][1] = F02 + F20;
+    K[2][3] = K[3][2] = F12 + F21;
+    jacobi_eig4(K, V);
+    int best = 0;
+    for (int i = 1; i < 4; ++i)
+        if (K[i][i] > K[best][best]) best = i;
+    double w = V[0][best], x = V[1][best], y = V[2][best], z = V[3][best];
+    double nq = sqrt(w * w + x * x + y * y + z * z);
+    w /= nq; x /= nq; y /= nq; z /= nq;
+    R[0] = w * w + x * x - y * y - z * z;
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = w * w - x * x + y * y - z * z;
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = w * w - x * x - y * y + z * z;
+}
+
 /* Kirchhoff stress tau = P F^T.
  * model 0: fixed-corotated (Stomakhin et al. 2012, the constitutive law of
  *          the paper's experiments), tau = 2 mu (F - R) F^T + la (J-1) J I,
- *          R the rotation of the polar decomposition.  Only d = 2 here, with
- *          the closed-form 2x2 polar rotation; R = I when F00+F11 and
- *          F10-F01 both vanish.
+ *          R the rotation closest to F (orc_closest_rotation).
  * model 1: compressible Neo-Hookean, tau = mu (F F^T - I) + la ln(J) I.
- * Returns ORC_EDOMAIN for J <= 0 with the Neo-Hookean model, or for the
- * fixed-corotated model in 3D (not provided). */
+ * Returns ORC_EDOMAIN for J <= 0 with the Neo-Hookean model. */
 int orc_kirchhoff(int dim, int model, double mu, double la, const double *F,
                   double *tau)
 {
@@ -121,20 +216,15 @@ int orc_kirchhoff(int dim, int model, double mu, double la, const double *F,
             FFt[a * dim + b] = s;
         }
     if (model == 0) {
-        if (dim != 2) return ORC_EDOMAIN;
-        double cs = F[0] + F[3], sn = F[2] - F[1];
-        double R[4] = {1.0, 0.0, 0.0, 1.0};
-        double h = sqrt(cs * cs + sn * sn);
-        if (h > 0.0) {
-            double c = cs / h, s = sn / h;
-            R[0] = c; R[1] = -s; R[2] = s; R[3] = c;
-        }
+        double R[9];
+        orc_closest_rotation(dim, F, R);
         /* tau = 2 mu (F F^T - R F^T) + la (J - 1) J I */
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                double RFt = R[a * 2 + 0] * F[b * 2 + 0] + R[a * 2 + 1] * F[b * 2 + 1];
-                tau[a * 2 + b] = 2.0 * mu * (FFt[a * 2 + b] - RFt)
-                               + (a == b ? la * (J - 1.0) * J : 0.0);
+        for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b) {
+                double RFt = 0.0;
+                for (int k = 0; k < dim; ++k) RFt += R[a * dim + k] * F[b * dim + k];
+                tau[a * dim + b] = 2.0 * mu * (FFt[a * dim + b] - RFt)
+                                 + (a == b ? la * (J - 1.0) * J : 0.0);
             }
         return ORC_OK;
     }

@@ -194,7 +194,7 @@ def psi_nh(F, mu, la):
     return 0.5 * mu * (np.trace(F.T @ F) - d) - mu * np.log(J) + 0.5 * la * np.log(J) ** 2
 
 
-@pytest.mark.parametrize("dim,model", [(2, 0), (2, 1), (3, 1)])
+@pytest.mark.parametrize("dim,model", [(2, 0), (2, 1), (3, 0), (3, 1)])
 def test_stress_zero_at_rest_and_rotation(dim, model):
     rng = np.random.default_rng(6)
     np.testing.assert_allclose(mpm.kirchhoff(dim, model, 3.0, 4.0, np.eye(dim)), 0, atol=0)
@@ -202,7 +202,8 @@ def test_stress_zero_at_rest_and_rotation(dim, model):
     np.testing.assert_allclose(mpm.kirchhoff(dim, model, 3.0, 4.0, R), 0, atol=1e-14)
 
 
-@pytest.mark.parametrize("dim,model,psi", [(2, 0, psi_fcr), (2, 1, psi_nh), (3, 1, psi_nh)])
+@pytest.mark.parametrize("dim,model,psi", [(2, 0, psi_fcr), (2, 1, psi_nh), (3, 0, psi_fcr),
+                                           (3, 1, psi_nh)])
 def test_stress_is_energy_derivative(dim, model, psi):
     """P = dPsi/dF by central differences; tau = P F^T."""
     rng = np.random.default_rng(7)
@@ -222,8 +223,13 @@ def test_stress_is_energy_derivative(dim, model, psi):
         np.testing.assert_allclose(P, Pfd, rtol=1e-6, atol=1e-7)
 
 
-@pytest.mark.parametrize("dim,model", [(2, 0), (2, 1), (3, 1)])
+@pytest.mark.parametrize("dim,model", [(2, 0), (2, 1), (3, 0), (3, 1)])
 def test_stress_small_strain_limit(dim, model):
+    """F = I + e, e symmetric: tau = 2 mu e + la tr(e) I + O(|e|^2).  The
+    remainder is bounded by (2 mu + 4 la) |e|_F^2: the mu term by
+    2 mu |e^2| (fixed-corotated, R = I) or mu |e^2| (Neo-Hookean), the la
+    term by la (tr(e)^2 + |sum of 2x2 minors| + higher), each at most
+    d |e|_F^2 <= 3 |e|_F^2 and |e|_F^2."""
     rng = np.random.default_rng(8)
     mu, la = 3.0, 5.0
     eps = 1e-6
@@ -231,7 +237,106 @@ def test_stress_small_strain_limit(dim, model):
     e = eps * 0.5 * (H + H.T)
     tau = mpm.kirchhoff(dim, model, mu, la, np.eye(dim) + e)
     lin = 2 * mu * e + la * np.trace(e) * np.eye(dim)
-    np.testing.assert_allclose(tau, lin, atol=50 * eps * eps)
+    np.testing.assert_allclose(tau, lin, atol=(2 * mu + 4 * la) * np.sum(e * e))
+
+
+def _kabsch(F):
+    """Closest rotation from numpy's SVD: U diag(1, .., det(U V^T)) V^T."""
+    U, _, Vt = np.linalg.svd(F)
+    D = np.eye(F.shape[0])
+    D[-1, -1] = np.sign(np.linalg.det(U @ Vt))
+    return U @ D @ Vt
+
+
+def _random_F(rng, dim, n, inverted=False):
+    out = []
+    while len(out) < n:
+        F = np.eye(dim) + 0.6 * rng.standard_normal((dim, dim))
+        J = np.linalg.det(F)
+        s = np.linalg.svd(F, compute_uv=False)
+        # away from the degenerate cases (repeated or vanishing singular values)
+        if (J < 0) == inverted and abs(J) > 0.05 and np.min(np.abs(np.diff(s))) > 0.05:
+            out.append(F)
+    return out
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_closest_rotation_is_the_polar_rotation(dim):
+    """det F > 0: the rotation factor of F = R S with S symmetric positive
+    definite, as scipy's polar decomposition gives it."""
+    from scipy.linalg import polar
+    rng = np.random.default_rng(31)
+    for F in _random_F(rng, dim, 20):
+        R = mpm.closest_rotation(dim, F)
+        np.testing.assert_allclose(R, polar(F)[0], atol=1e-12)
+        S = R.T @ F
+        np.testing.assert_allclose(S, S.T, atol=1e-12)
+        assert np.all(np.linalg.eigvalsh(0.5 * (S + S.T)) > 0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_closest_rotation_of_inverted_elements(dim):
+    """det F < 0: the rotation of the SVD with the sign moved onto the
+    smallest singular value (the Kabsch construction), and it maximises
+    tr(R^T F) over 4,000 random rotations."""
+    rng = np.random.default_rng(32)
+    for F in _random_F(rng, dim, 20, inverted=True):
+        R = mpm.closest_rotation(dim, F)
+        np.testing.assert_allclose(R.T @ R, np.eye(dim), atol=1e-13)
+        assert np.linalg.det(R) == pytest.approx(1.0, abs=1e-13)
+        np.testing.assert_allclose(R, _kabsch(F), atol=1e-11)
+    F = _random_F(rng, dim, 1, inverted=True)[0]
+    best = np.trace(mpm.closest_rotation(dim, F).T @ F)
+    trials = [np.trace(_rot(dim, rng).T @ F) for _ in range(4000)]
+    assert best >= max(trials) - 1e-12
+
+
+def test_closest_rotation_reduces_to_the_2d_closed_form():
+    """F = blockdiag(F2, 1): the 3D rotation is blockdiag(R2, 1), R2 from
+    the closed-form 2D rotation, and a known rotation times a symmetric
+    positive definite stretch gives that rotation back."""
+    rng = np.random.default_rng(33)
+    for F2 in _random_F(rng, 2, 10):
+        F = np.eye(3)
+        F[:2, :2] = F2
+        R = mpm.closest_rotation(3, F)
+        want = np.eye(3)
+        want[:2, :2] = mpm.closest_rotation(2, F2)
+        np.testing.assert_allclose(R, want, atol=1e-12)
+    for _ in range(10):
+        R0 = _rot(3, rng)
+        A = rng.standard_normal((3, 3))
+        S = A @ A.T + 0.3 * np.eye(3)
+        np.testing.assert_allclose(mpm.closest_rotation(3, R0 @ S), R0, atol=1e-11)
+
+
+def test_fcr_stress_is_rotation_covariant_and_defined_when_inverted():
+    """tau(Q F) = Q tau(F) Q^T; for det F < 0 the stress is the derivative
+    of the energy with the signed smallest singular value (the inverted
+    branch of the fixed-corotated model), by central differences."""
+    rng = np.random.default_rng(34)
+    mu, la = 3.0, 5.0
+    for F in _random_F(rng, 3, 5):
+        Q = _rot(3, rng)
+        np.testing.assert_allclose(mpm.kirchhoff(3, 0, mu, la, Q @ F),
+                                   Q @ mpm.kirchhoff(3, 0, mu, la, F) @ Q.T, atol=1e-11)
+
+    def psi_signed(F):
+        s = np.linalg.svd(F, compute_uv=False)
+        J = np.linalg.det(F)
+        s[-1] *= np.sign(J)
+        return mu * np.sum((s - 1.0) ** 2) + 0.5 * la * (J - 1.0) ** 2
+
+    for F in _random_F(rng, 3, 5, inverted=True):
+        P = mpm.kirchhoff(3, 0, mu, la, F) @ np.linalg.inv(F).T
+        h = 1e-6
+        Pfd = np.zeros((3, 3))
+        for a in range(3):
+            for b in range(3):
+                E = np.zeros((3, 3))
+                E[a, b] = h
+                Pfd[a, b] = (psi_signed(F + E) - psi_signed(F - E)) / (2 * h)
+        np.testing.assert_allclose(P, Pfd, rtol=1e-6, atol=1e-6)
 
 
 def test_nh_rejects_inverted_element():
