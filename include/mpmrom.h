@@ -63,7 +63,14 @@ extern "C" {
 /* ---- enums ------------------------------------------------------------- */
 #define MR_FLOOR_STICKY 0        /* every face of the boundary band sticky  */
 #define MR_FLOOR_COULOMB 1       /* low-y face Coulomb friction, rest sticky */
-#define MR_FIXED_COROTATED 0     /* 2D only                                  */
+/* Constitutive models (Kirchhoff stress tau = P F^T, Section 2.1):
+ * fixed-corotated (Stomakhin et al. 2012, the law of the paper's
+ * experiments): tau = 2 mu (F - R) F^T + la (J - 1) J I, R the rotation
+ * closest to F (the polar rotation for J > 0; for J <= 0 the sign moves onto
+ * the smallest singular value, so inverted states keep a defined stress);
+ * compressible Neo-Hookean: tau = mu (F F^T - I) + la ln(J) I, undefined
+ * for J <= 0 (MR_FLAG_DOMAIN). */
+#define MR_FIXED_COROTATED 0
 #define MR_NEO_HOOKEAN 1
 
 /* mpm_p2g / mpm_g2p flags */
@@ -114,7 +121,7 @@ typedef struct {
 } mr_grid;
 
 typedef struct {
-    int32_t model; /* MR_FIXED_COROTATED (dim 2) or MR_NEO_HOOKEAN           */
+    int32_t model; /* MR_FIXED_COROTATED or MR_NEO_HOOKEAN                   */
     float E, nu;   /* Young's modulus and Poisson ratio                      */
 } mr_material;
 

@@ -952,7 +952,6 @@ extern "C" int32_t mpm_p2g(const mr_grid *grid_desc, const mr_material *mat,
     if (!grid_from_desc(grid_desc, g) || !mat || !grid || !check_parts(parts, grid_desc->dim, true))
         return MR_EINVAL;
     if (!(flags & MR_NO_AFFINE) && !parts->C && parts->n > 0) return MR_EINVAL;
-    if (mat->model == MR_FIXED_COROTATED && grid_desc->dim != 2) return MR_EINVAL;
     if (mat->model != MR_FIXED_COROTATED && mat->model != MR_NEO_HOOKEAN) return MR_EINVAL;
     if ((flags & MR_SORTED) && !workspace) return MR_EINVAL;
     if ((flags & MR_DETERMINISTIC) && (!(flags & MR_SORTED) || subset)) return MR_EINVAL;
@@ -1123,7 +1122,6 @@ extern "C" int32_t mpm_g2p2g(const mr_grid *grid_desc, const mr_material *mat,
     if (!grid_from_desc(grid_desc, g) || !mat || !grid_in || !grid_out || grid_in == grid_out ||
         !workspace || !check_parts(parts, grid_desc->dim, true))
         return MR_EINVAL;
-    if (mat->model == MR_FIXED_COROTATED && grid_desc->dim != 2) return MR_EINVAL;
     if (mat->model != MR_FIXED_COROTATED && mat->model != MR_NEO_HOOKEAN) return MR_EINVAL;
     hipStream_t st = as_stream(stream);
     float *vo = (flags & MR_NO_VC_OUT) ? nullptr : parts->v;

@@ -32,12 +32,128 @@ __device__ __forceinline__ int64_t node_lin(const GridK &g, int i, int j, int k)
     return (int64_t)i + (int64_t)g.n0 * ((int64_t)j + (int64_t)g.n1 * k);
 }
 
+// One Jacobi rotation of a symmetric 3x3 matrix A in the (p, q) plane (r
+// the third index) that zeroes A[p][q]: with t = tan(phi) the smaller root
+// of t^2 + 2 theta t - 1 = 0, theta = (A_qq - A_pp) / (2 A_pq), the diagonal
+// moves by -+ t A_pq and the other row/column rotates; V accumulates the
+// rotations (columns: eigenvectors).
+template <int p, int q, int r>
+__device__ __forceinline__ void jacobi_rotate3(float (&A)[3][3], float (&V)[3][3])
+{
+    const float apq = A[p][q];
+    if (apq == 0.0f) return;
+    const float theta = (A[q][q] - A[p][p]) / (2.0f * apq);
+    // theta^2 overflows to inf for |theta| > 1.8e19, giving t = 0 (no turn)
+    const float t = copysignf(1.0f, theta) / (fabsf(theta) + sqrtf(theta * theta + 1.0f));
+    const float c = 1.0f / sqrtf(t * t + 1.0f), s = t * c;
+    A[p][p] -= t * apq;
+    A[q][q] += t * apq;
+    A[p][q] = A[q][p] = 0.0f;
+    const float arp = A[r][p], arq = A[r][q];
+    A[r][p] = A[p][r] = c * arp - s * arq;
+    A[r][q] = A[q][r] = s * arp + c * arq;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float vp = V[k][p], vq = V[k][q];
+        V[k][p] = c * vp - s * vq;
+        V[k][q] = s * vp + c * vq;
+    }
+}
+
+// Fixed-corotated rotation term in 3D: M = R F^T - I, R the rotation
+// closest to F (the polar rotation when J > 0; for J <= 0 the sign moves
+// onto the smallest singular value).  With F V = U Sigma' (V, U orthonormal,
+// Sigma' the singular values with that sign), R F^T = U Sigma' U^T, so
+// M = sum_i (sigma'_i - 1) u_i u_i^T.  The eigen-pairs come from cyclic
+// Jacobi on E = F^T F - I = H + H^T + H^T H (H = F - I), whose eigenvalues
+// e_i = sigma_i^2 - 1 keep their relative accuracy near the rest state, and
+// sigma_i - 1 = e_i / (sqrt(1 + e_i) + 1); u_1, u_2 are the normalised,
+// orthogonalised columns F v_1, F v_2 (by decreasing e) and u_3 = u_1 x u_2
+// (its sign does not enter M).
+__device__ __forceinline__ void corotated_term3(const float *F, const float *H, float Jm1,
+                                                float *M)
+{
+    float E[3][3], V[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            float s = H[a * 3 + b] + H[b * 3 + a];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s += H[k * 3 + a] * H[k * 3 + b];
+            E[a][b] = s;
+            V[a][b] = a == b ? 1.0f : 0.0f;
+        }
+    for (int sweep = 0; sweep < 6; ++sweep) {
+        const float off = E[0][1] * E[0][1] + E[0][2] * E[0][2] + E[1][2] * E[1][2];
+        const float dg = E[0][0] * E[0][0] + E[1][1] * E[1][1] + E[2][2] * E[2][2];
+        if (!(off > 1e-15f * dg)) break;
+        jacobi_rotate3<0, 1, 2>(E, V);
+        jacobi_rotate3<0, 2, 1>(E, V);
+        jacobi_rotate3<1, 2, 0>(E, V);
+    }
+    // order by decreasing eigenvalue (permuting the columns of V)
+    float e[3] = {E[0][0], E[1][1], E[2][2]};
+    int o0 = 0, o1 = 1, o2 = 2, tmp;
+    if (e[o0] < e[o1]) { tmp = o0; o0 = o1; o1 = tmp; }
+    if (e[o0] < e[o2]) { tmp = o0; o0 = o2; o2 = tmp; }
+    if (e[o1] < e[o2]) { tmp = o1; o1 = o2; o2 = tmp; }
+    float u1[3], u2[3], u3[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        u1[a] = F[a * 3 + 0] * V[0][o0] + F[a * 3 + 1] * V[1][o0] + F[a * 3 + 2] * V[2][o0];
+        u2[a] = F[a * 3 + 0] * V[0][o1] + F[a * 3 + 1] * V[1][o1] + F[a * 3 + 2] * V[2][o1];
+    }
+    float n1 = u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2];
+    if (!(n1 > 1e-30f)) {            // F = 0: any orthonormal frame
+        u1[0] = 1.0f; u1[1] = 0.0f; u1[2] = 0.0f;
+        n1 = 1.0f;
+    }
+    const float r1 = 1.0f / sqrtf(n1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u1[a] *= r1;
+    const float d12 = u1[0] * u2[0] + u1[1] * u2[1] + u1[2] * u2[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u2[a] -= d12 * u1[a];
+    float n2 = u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2];
+    if (!(n2 > 1e-30f)) {            // rank one: any unit vector normal to u1
+        const int k = (fabsf(u1[0]) <= fabsf(u1[1]) && fabsf(u1[0]) <= fabsf(u1[2])) ? 0
+                      : (fabsf(u1[1]) <= fabsf(u1[2]) ? 1 : 2);
+        float ek[3] = {0.0f, 0.0f, 0.0f};
+        ek[k] = 1.0f;
+        u2[0] = u1[1] * ek[2] - u1[2] * ek[1];
+        u2[1] = u1[2] * ek[0] - u1[0] * ek[2];
+        u2[2] = u1[0] * ek[1] - u1[1] * ek[0];
+        n2 = u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2];
+    }
+    const float r2 = 1.0f / sqrtf(n2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u2[a] *= r2;
+    u3[0] = u1[1] * u2[2] - u1[2] * u2[1];
+    u3[1] = u1[2] * u2[0] - u1[0] * u2[2];
+    u3[2] = u1[0] * u2[1] - u1[1] * u2[0];
+    const float ea = fmaxf(e[o0], -1.0f), eb = fmaxf(e[o1], -1.0f), ec = fmaxf(e[o2], -1.0f);
+    const float s1 = ea / (sqrtf(1.0f + ea) + 1.0f);
+    const float s2 = eb / (sqrtf(1.0f + eb) + 1.0f);
+    const float s3 = Jm1 > -1.0f ? ec / (sqrtf(1.0f + ec) + 1.0f) : -sqrtf(1.0f + ec) - 1.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) {
+            const float m = s1 * u1[a] * u1[b] + s2 * u2[a] * u2[b] + s3 * u3[a] * u3[b];
+            M[a * 3 + b] = m;
+            M[b * 3 + a] = m;
+        }
+}
+
 // Kirchhoff stress tau = P F^T (symmetric), written as tau[a*D+b].
 // Neo-Hookean: tau = mu (F F^T - I) + la ln(J) I.
-// Fixed-corotated (D == 2): tau = 2 mu (F - R) F^T + la (J - 1) J I with R
-// the rotation of the closed-form 2x2 polar decomposition (R = I when F is
-// a pure zero of both invariants).  F F^T - I, J - 1 and ln J are formed
-// from H = F - I to keep their relative accuracy near the rest state.
+// Fixed-corotated: tau = 2 mu (F - R) F^T + la (J - 1) J I with R the
+// rotation closest to F: in 2D the closed-form rotation by the angle of
+// (F00 + F11, F10 - F01) (R = I when both vanish); in 3D
+// (F - R) F^T = (F F^T - I) - (R F^T - I) with the second term from
+// corotated_term3.  F F^T - I, J - 1 and ln J are formed from H = F - I to
+// keep their relative accuracy near the rest state.
 // Returns false for J <= 0 (Neo-Hookean) or a non-finite result.
 template <int D>
 __device__ __forceinline__ bool kirchhoff(int model, float mu, float la, const float *F, float *tau)
@@ -75,6 +191,25 @@ __device__ __forceinline__ bool kirchhoff(int model, float mu, float la, const f
                 tau[b * D + a] = t;
             }
         return isfinite(lnJ);
+    }
+    if constexpr (D == 3) {
+        float M[9];
+        corotated_term3(F, H, Jm1, M);
+        const float vol = la * Jm1 * (1.0f + Jm1);
+        bool fin = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = a; b < 3; ++b) {
+                float s = H[a * 3 + b] + H[b * 3 + a];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) s += H[a * 3 + k] * H[b * 3 + k];
+                const float t = 2.0f * mu * (s - M[a * 3 + b]) + (a == b ? vol : 0.0f);
+                tau[a * 3 + b] = t;
+                tau[b * 3 + a] = t;
+                fin = fin && isfinite(t);
+            }
+        return fin;
     }
     // fixed-corotated, D == 2
     float cs = F[0] + F[3], sn = F[2] - F[1];

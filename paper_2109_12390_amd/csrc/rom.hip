@@ -775,7 +775,6 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
         cfg->n_particles > INT32_MAX || cfg->n_samples_max < 1 ||
         cfg->n_samples_max > cfg->n_particles || !(cfg->rho0 > 0.0f))
         return MR_EINVAL;
-    if (cfg->model == MR_FIXED_COROTATED && d != 2) return MR_EINVAL;
     if ((int64_t)cfg->B * (opts->max_backtrack + 1) > 65535) return MR_EINVAL;
     if (cfg->quadrature != MR_QUAD_LAGRANGIAN && cfg->quadrature != MR_QUAD_EULERIAN)
         return MR_EINVAL;

@@ -225,11 +225,14 @@ def test_rom_step_translation_manifold_closed_form(gpu):
             rom.close()
 
 
-def test_rom_step_matches_oracle(gpu):
+@pytest.mark.parametrize("model", [B.NEO_HOOKEAN, B.FIXED_COROTATED])
+def test_rom_step_matches_oracle(gpu, model):
     """Random fp32 decoder, 3D scene on a 32^3 grid (4,096 particles), two
     instances with different Young's moduli and sample counts, 3 steps of the
-    position-velocity scheme against the oracle's ROM step."""
+    position-velocity scheme against the oracle's ROM step, for both
+    constitutive laws."""
     s = _rom_inputs(seed=6)
+    s["model"] = model
     d, r = 3, 8
     X = s["X"]
     odec, gdec = make_decoder(d, r, 32, 3, 51, X, out_std=0.01)
@@ -238,7 +241,7 @@ def test_rom_step_matches_oracle(gpu):
     nss = np.array([24, 12], np.int32)
     opts = B.gn_opts(mode=B.POS_VEL, max_iter=3)
     rom = B.Rom(gdec, grid, T(soa(X)), T(Es), T(nss, torch.int32), opts, seed=99, rho0=1000.0,
-                m_uniform=float(s["m"]))
+                m_uniform=float(s["m"]), model=model, nu=s["nu"])
     rng = np.random.default_rng(52)
     z0 = 0.2 * rng.standard_normal((2, r))
     v0 = 0.5 * rng.standard_normal((2, r))

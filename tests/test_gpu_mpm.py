@@ -53,7 +53,8 @@ def close_channels(got, ref, frac=2e-5, name=""):
     assert err <= frac, name
 
 
-@pytest.mark.parametrize("dim,model,apic", [(2, 0, True), (3, 1, True), (3, 1, False), (2, 1, False)])
+@pytest.mark.parametrize("dim,model,apic", [(2, 0, True), (3, 1, True), (3, 1, False), (2, 1, False),
+                                            (3, 0, True), (3, 0, False)])
 @pytest.mark.parametrize("P", [1, 777, 5000])
 def test_p2g_matches_oracle(gpu, dim, model, apic, P):
     rng = np.random.default_rng(10 + dim + P)
@@ -71,6 +72,58 @@ def test_p2g_matches_oracle(gpu, dim, model, apic, P):
     close_channels(g[:, 0], gm, name="mass")
     close_channels(g[:, 1:1 + dim], gmv + dt * gf, name="momentum")
     assert np.all(g[:, 1 + dim:] == 0)
+
+
+def _large_deformations(rng, P):
+    """Every third particle a rotation with 1e-4 strain; the others
+    rotations times symmetric stretches (singular values 0.3-2.5), half of
+    them reflected (det F < 0) with the two smallest singular values at
+    least 0.1 apart.  (A reflection with nearly equal smallest singular
+    values has two almost equally close rotations, and its stress jumps
+    between them: no finite precision resolves which one, so such states
+    are left out.)"""
+    out = np.empty((P, 3, 3))
+    for p in range(P):
+        Q, R = np.linalg.qr(rng.standard_normal((3, 3)))
+        Q = Q @ np.diag(np.sign(np.diag(R)))
+        if np.linalg.det(Q) < 0:
+            Q[:, 0] = -Q[:, 0]
+        W, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+        if p % 3 == 0:
+            sv = 1.0 + 1e-4 * rng.standard_normal(3)
+        else:
+            while True:
+                sv = np.sort(rng.uniform(0.3, 2.5, size=3))[::-1].copy()
+                if sv[1] - sv[2] >= 0.1:
+                    break
+            if p % 2:
+                sv[2] = -sv[2]
+        out[p] = Q @ W @ np.diag(sv) @ W.T
+    return out.astype(np.float32)
+
+
+@pytest.mark.parametrize("P", [2, 3000])
+def test_fixed_corotated_forces_under_large_deformation(gpu, P):
+    """3D fixed-corotated internal forces (v = C = 0, so the momentum
+    channel is dt f) for rotated, stretched and inverted deformation
+    gradients against the oracle's closest-rotation stress, to 1e-4 of the
+    channel scale.  (The rotated small-strain particles carry an fp32 error
+    of about 1e-7 of 2 mu, from forming F F^T - I out of O(1) entries.)"""
+    rng = np.random.default_rng(71 + P)
+    dim, n, dx, dt = 3, [24] * 3, 1.0 / 24, 1e-4
+    x = rng.uniform(0.3, 0.7, size=(P, dim)).astype(np.float32)
+    F = _large_deformations(rng, P)
+    zeros = np.zeros((P, dim), np.float32)
+    m = np.full(P, 1e-3, np.float32)
+    V0 = np.full(P, 1e-6, np.float32)
+    mu, la = OM.lame(1e4, 0.3)
+    gm, gmv, gf = OM.p2g(dim, n, dx, x, zeros, np.zeros((P, 3, 3)), F, m, V0, 0, mu, la, apic=False)
+    gbuf = torch.zeros(int(np.prod(n)) * 4, device=dev)
+    parts = make_parts(B, x, zeros, np.zeros((P, 3, 3), np.float32), F, m, V0)
+    B.mpm_p2g(B.Grid(dim, n, dx, bound=3), (B.FIXED_COROTATED, 1e4, 0.3), parts, gbuf, dt,
+              flags=B.NO_AFFINE)
+    g = gbuf.cpu().numpy().reshape(-1, 4)
+    close_channels(g[:, 1:4] / dt, gf, frac=1e-4, name="force")
 
 
 @pytest.mark.parametrize("dim", [2, 3])
@@ -341,6 +394,34 @@ def test_three_dimensional_scene_small(gpu):
     assert ex <= 1e-3 and ev <= 1e-2 and ed <= 1e-2
 
 
+def test_three_dimensional_fixed_corotated_scene(gpu):
+    """The 3D scene above with the fixed-corotated law (the paper's
+    constitutive model), 100 steps, sorting every 10."""
+    s = scenes.scene_3d(n=32, cube_cells=8, seed=5, v0=(0.3, -2.0, 0.1))
+    s["model"] = scenes.MODEL_FIXED_COROTATED
+    st0 = scenes.initial_state(s)
+    steps = 100
+    ref = _run_oracle(oracle_scene(s), st0, s["dt"], steps)
+    parts = make_parts(B, st0["x"], st0["v"], st0["C"], st0["F"], m_u=float(s["m"]), V0_u=float(s["V0"]))
+    grid = _gpu_scene(B, s)
+    gbuf = torch.zeros(grid.nodes() * 4, device=dev)
+    ws = torch.zeros(B.mpm_step_workspace_bytes(grid, s["P"]), dtype=torch.uint8, device=dev)
+    perm = torch.zeros(s["P"], dtype=torch.int32, device=dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    B.mpm_step(grid, (s["model"], s["E"], s["nu"]), parts, s["dt"], steps, 10, 0, gbuf, ws,
+               perm_accum=perm, status=flag)
+    p = perm.cpu().numpy()
+    inv = np.empty_like(p)
+    inv[p] = np.arange(len(p))
+    x = aos(parts.x.cpu().numpy(), 3)[inv]
+    v = aos(parts.v.cpu().numpy(), 3)[inv]
+    ex, ev = rel_l2(x, ref["x"]), rel_l2(v, ref["v"])
+    ed = rel_l2(x - s["X"], ref["x"] - s["X"])
+    print("3D fixed-corotated 100 steps: x %.3e v %.3e displacement %.3e" % (ex, ev, ed))
+    assert flag.item() == 0
+    assert ex <= 1e-3 and ev <= 1e-2 and ed <= 1e-2
+
+
 def test_launch_timer_sampling(gpu):
     """mr_timing_sample: only the chosen classes, every k-th launch of each;
     the timed run's state matches an untimed run's (up to the order of the
@@ -425,7 +506,7 @@ def test_invalid_arguments_rejected(gpu):
     x, v, C, F, m, V0 = random_state(rng, 3, 10)
     gbuf = torch.zeros(16 ** 3 * 4, device=dev)
     with pytest.raises(B.MrError) as e:
-        B.mpm_p2g(B.Grid(3, [16] * 3, 1 / 16), (B.FIXED_COROTATED, 1e4, 0.3),
+        B.mpm_p2g(B.Grid(3, [16] * 3, 1 / 16), (7, 1e4, 0.3),      # no such model
                   make_parts(B, x, v, C, F, m, V0), gbuf, 1e-4)
     assert e.value.code == B.MR_EINVAL
     with pytest.raises(B.MrError):
