@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rom", action="store_true")
+    ap.add_argument("--no-fcr", action="store_true",
+                    help="skip the fixed-corotated variant of the full-order scene")
     ap.add_argument("--rom-steps", type=int, default=100)
     ap.add_argument("--rom-instances", type=int, default=256)
     ap.add_argument("--rom-accuracy-steps", type=int, default=500,
@@ -210,6 +212,10 @@ def main():
         "active_nodes": active_nodes,
         "kernel_source_hash": src_hash,
     }
+    if not args.no_fcr:
+        out["fixed_corotated"] = fom_fixed_corotated(B, scenes, s, min(args.steps, 200),
+                                                     args.warmup)
+        log("fixed-corotated:", json.dumps(out["fixed_corotated"]))
     if not args.no_rom:
         out["rom"] = rom_throughput(B, scenes, s, args.rom_steps)
         if args.rom_pareto_steps > 0:
@@ -225,6 +231,40 @@ def main():
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out), flush=True)
+
+
+def fom_fixed_corotated(B, scenes, s, steps, warmup):
+    """The same scene and loop with the fixed-corotated law (the paper's
+    constitutive model; a closest-rotation eigen-solve per particle inside
+    the scatter): time per step and the scatter's average launch time."""
+    import torch
+    dev = "cuda:0"
+    P = s["P"]
+    st = scenes.initial_state(s)
+    soa = lambda a: torch.tensor(np.ascontiguousarray(a.reshape(P, -1).T), device=dev)
+    parts = B.Particles(soa(st["x"]), soa(st["v"]), soa(st["C"]), soa(st["F"]),
+                        m_uniform=float(s["m"]), V0_uniform=float(s["V0"]))
+    grid = B.Grid(3, s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
+    gbuf = torch.zeros(grid.nodes() * 4, device=dev)
+    ws = torch.zeros(B.mpm_step_workspace_bytes(grid, P), dtype=torch.uint8, device=dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    mat = (scenes.MODEL_FIXED_COROTATED, s["E"], s["nu"])
+    timing = B.Timing(capacity=16 * (steps + 8))
+    timing.sample(TIMING_EVERY, ["p2g"])
+    B.mpm_step(grid, mat, parts, s["dt"], warmup, SORT_EVERY, 0, gbuf, ws, status=flag)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    B.mpm_step(grid, mat, parts, s["dt"], steps, SORT_EVERY, 0, gbuf, ws, status=flag,
+               timing=timing)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    n, p2g_ms = timing.read()["p2g"]
+    timing.close()
+    return {"ms_per_step": round(ms, 4), "particle_steps_per_s": P / (ms * 1e-3),
+            "p2g_avg_ms": round(p2g_ms / n, 5), "steps": steps, "status": int(flag.item())}
 
 
 def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden=5,
