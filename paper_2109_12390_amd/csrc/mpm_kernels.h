@@ -41,11 +41,19 @@ template <int p, int q, int r>
 __device__ __forceinline__ void jacobi_rotate3(float (&A)[3][3], float (&V)[3][3])
 {
     const float apq = A[p][q];
-    if (apq == 0.0f) return;
-    const float theta = (A[q][q] - A[p][p]) / (2.0f * apq);
-    // theta^2 overflows to inf for |theta| > 1.8e19, giving t = 0 (no turn)
-    const float t = copysignf(1.0f, theta) / (fabsf(theta) + sqrtf(theta * theta + 1.0f));
-    const float c = 1.0f / sqrtf(t * t + 1.0f), s = t * c;
+    // below 1e-30 the entry is negligible against any stress this code
+    // resolves, and its reciprocal could overflow
+    if (fabsf(apq) < 1e-30f) return;
+    // hardware reciprocal and reciprocal square root (1 ulp): the rotation
+    // only needs to be orthogonal to rounding, and these keep the dependent
+    // chain of the sweep short
+    const float theta = (A[q][q] - A[p][p]) * __builtin_amdgcn_rcpf(2.0f * apq);
+    const float at = fabsf(theta);
+    // |theta| > 1e4: t = 1/(2 theta) to within theta^-3 (and theta^2 stays finite)
+    const float h = at > 1e4f ? at : at * at + 1.0f;
+    const float root = at > 1e4f ? at : h * __builtin_amdgcn_rsqf(h);
+    const float t = copysignf(__builtin_amdgcn_rcpf(at + root), theta);
+    const float c = __builtin_amdgcn_rsqf(t * t + 1.0f), s = t * c;
     A[p][p] -= t * apq;
     A[q][q] += t * apq;
     A[p][q] = A[q][p] = 0.0f;
@@ -109,7 +117,7 @@ __device__ __forceinline__ void corotated_term3(const float *F, const float *H, 
         u1[0] = 1.0f; u1[1] = 0.0f; u1[2] = 0.0f;
         n1 = 1.0f;
     }
-    const float r1 = 1.0f / sqrtf(n1);
+    const float r1 = __builtin_amdgcn_rsqf(n1);
 #pragma unroll
     for (int a = 0; a < 3; ++a) u1[a] *= r1;
     const float d12 = u1[0] * u2[0] + u1[1] * u2[1] + u1[2] * u2[2];
@@ -126,7 +134,7 @@ __device__ __forceinline__ void corotated_term3(const float *F, const float *H, 
         u2[2] = u1[0] * ek[1] - u1[1] * ek[0];
         n2 = u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2];
     }
-    const float r2 = 1.0f / sqrtf(n2);
+    const float r2 = __builtin_amdgcn_rsqf(n2);
 #pragma unroll
     for (int a = 0; a < 3; ++a) u2[a] *= r2;
     u3[0] = u1[1] * u2[2] - u1[2] * u2[1];
