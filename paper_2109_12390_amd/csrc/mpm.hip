@@ -373,7 +373,7 @@ struct CellTile {
     static constexpr int TS = Tiling<D>::TS;        // cells per tile edge
     static constexpr int R = TS + 4;                // region nodes per edge
     static constexpr int RC = TS + 2;               // region cells per edge
-    static constexpr int SY = (D == 3) ? 12 : 24;   // padded row stride (float4)
+    static constexpr int SY = (D == 3) ? R : 24;    // row stride (float4; 2D rows padded)
     static constexpr int SZ = (D == 3) ? SY * R : 0;
     static constexpr int RNP = (D == 3) ? SZ * R : SY * R;
     static constexpr int RCN = (D == 3) ? RC * RC * RC : RC * RC;
