@@ -442,7 +442,7 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
 
 
 SHAPE_NAMES = ["1 point tile per wave", "2 point tiles per wave", "4 point tiles per wave",
-               "units split over a block"]
+               "units split over a block", "points split, activations in registers"]
 
 
 def decoder_shapes(dec, n_inst, P, n_samples):

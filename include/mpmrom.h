@@ -295,7 +295,9 @@ void rom_decoder_destroy(mr_decoder *dec);
  * points (capped at 2^22 points, 2^20 for cfg 9, with one instance), `reps`
  * launches each, and records the fastest for that size class
  * (floor(log2(B n))) in the decoder.  Untuned size classes use the nearest
- * tuned class within a factor of 4, else row splitting up to 8192 points.
+ * tuned class within a factor of 4, else row splitting up to 8192 points
+ * and, above, the register-resident shape where the configuration offers it
+ * (bf16 decoders, cfg 1 and 5), else point splitting.
  * Every shape computes identical results.  Synchronous on `stream`;
  * allocates and frees scratch.  Returns MR_EINVAL for B < 1, n < 1,
  * reps < 1 or unknown mask bits. */
@@ -304,8 +306,18 @@ int32_t rom_decoder_autotune(mr_decoder *dec, int32_t B, int64_t n,
 
 /* Shape a launch of configuration cfg (1, 5 or 9) on B instances of n
  * points would use: 0 points split one tile per wave, 1 two tiles, 2 four
- * tiles, 3 units split across the waves of a block; negative on error. */
+ * tiles, 3 units split across the waves of a block, 4 points split with the
+ * hidden activations kept in registers (bf16 decoders, cfg 1 and 5);
+ * negative on error. */
 int32_t rom_decoder_shape(const mr_decoder *dec, int32_t cfg, int32_t B, int64_t n);
+
+/* Records `shape` (numbered as above) for the size class of B instances of
+ * n points of configuration cfg, as rom_decoder_autotune would: for callers
+ * that tune offline or pin a shape.  Every shape computes identical
+ * results.  Returns MR_EINVAL for a shape the configuration or the
+ * decoder's precision does not offer. */
+int32_t rom_decoder_set_shape(mr_decoder *dec, int32_t cfg, int32_t B, int64_t n,
+                              int32_t shape);
 
 /* Replaces the parameters of an existing decoder (same shapes); params is a
  * device or host pointer as flagged by `params_on_device`.  Stream-ordered

@@ -107,6 +107,7 @@ SIGNATURES = {
     "rom_decoder_set_params": (_i32, [_vp, _vp, _i32, _vp]),
     "rom_decoder_autotune": (_i32, [_vp, _i32, _i64, _i32, _i32, _vp]),
     "rom_decoder_shape": (_i32, [_vp, _i32, _i32, _i64]),
+    "rom_decoder_set_shape": (_i32, [_vp, _i32, _i32, _i64, _i32]),
     "rom_decode": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _vp, _vp, _vp]),
     "rom_decode_jac": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                               _vp, _vp]),
@@ -408,6 +409,11 @@ class Decoder:
     def shape(self, cfg, B, n):
         """Launch shape a configuration (1, 5 or 9) uses at B x n points."""
         return int(load().rom_decoder_shape(self.handle, cfg, B, n))
+
+    def set_shape(self, cfg, B, n, shape):
+        """Pins the launch shape of a configuration's size class
+        (rom_decoder_set_shape)."""
+        _check("rom_decoder_set_shape", load().rom_decoder_set_shape(self.handle, cfg, B, n, shape))
 
     def close(self):
         if self.handle:

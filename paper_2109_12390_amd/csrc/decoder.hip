@@ -26,7 +26,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // launch shapes of the decoder kernels (see launch_w)
-enum DecVariant { DEC_COL = 0, DEC_COL_NP2 = 1, DEC_COL_NP4 = 2, DEC_ROWS = 3, DEC_NVARIANT = 4 };
+enum DecVariant { DEC_COL = 0, DEC_COL_NP2 = 1, DEC_COL_NP4 = 2, DEC_ROWS = 3, DEC_REG = 4,
+                  DEC_NVARIANT = 5 };
 constexpr int DEC_BUCKETS = 32;   // size classes: floor(log2(instances x points))
 
 struct mr_decoder {
@@ -101,6 +102,28 @@ __host__ __device__ __forceinline__ uint16_t bf16_bits(float f)
     return (uint16_t)(u >> 16);
 }
 
+// Unit order of bf16 activation panels and of the bf16 copy of the hidden
+// weights (the k dimension of every hidden-layer product): within each block
+// of 32 units, unit u = 32 m + 16 h + 4 g + q (h in 0..1, g in 0..3, q in
+// 0..3) sits at position 32 m + 8 g + 4 h + q.  A 16x16 MFMA output tile
+// pair (row tiles 2m and 2m + 1) leaves lane l holding units 32 m + 4 g + q
+// and 32 m + 16 + 4 g + q of one column, g = l / 16; the B operand of a
+// 16x16x32 k-step takes positions 32 m + 8 g + 0..7 of a column from lane l.
+// With this order the two coincide, so one layer's activated accumulators
+// are the next layer's B operands without leaving the registers.  The order
+// is a relabelling of k applied to activations and weights alike.
+__host__ __device__ constexpr int unit_pos(int u)
+{
+    return (u & ~31) | (((u >> 2) & 3) << 3) | (((u >> 4) & 1) << 2) | (u & 3);
+}
+__host__ __device__ constexpr int pos_unit(int p)
+{
+    return (p & ~31) | (((p >> 2) & 1) << 4) | (((p >> 3) & 3) << 2) | (p & 3);
+}
+static_assert(unit_pos(pos_unit(45)) == 45 && pos_unit(unit_pos(53)) == 53 &&
+                  unit_pos(16 + 4) == 12 && unit_pos(4) == 8,
+              "unit order");
+
 template <typename T>
 struct Elem;
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -120,6 +143,9 @@ struct Elem<float> {
     }
     __device__ static void store4(float *p, f32x4 v) { *reinterpret_cast<f32x4 *>(p) = v; }
     __device__ static f32x4 load4(const float *p) { return *reinterpret_cast<const f32x4 *>(p); }
+    // panel position of unit u (a multiple of 4) and unit at position p
+    __device__ static constexpr int pos(int u) { return u; }
+    __device__ static constexpr int unit(int p) { return p; }
 };
 template <>
 struct Elem<uint16_t> {
@@ -134,6 +160,8 @@ struct Elem<uint16_t> {
     {
         return __builtin_convertvector(*reinterpret_cast<const bf16x4 *>(p), f32x4);
     }
+    __device__ static constexpr int pos(int u) { return unit_pos(u); }
+    __device__ static constexpr int unit(int p) { return pos_unit(p); }
 };
 
 // One MFMA k-step: acc += A(16 x KS) * B(KS x 16).
@@ -322,7 +350,7 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
                     else if (kind == SK_LATENT) val[q] = e4[q] * P.W0[(size_t)(i0 + q) * in0 + P.d + arg];
                     else val[q] = 0.0f;
                 }
-                E::store4(pin + ((pt * S + st) * 16 + j) * LD + i0, val);
+                E::store4(pin + ((pt * S + st) * 16 + j) * LD + E::pos(i0), val);
             }
         }
     }
@@ -386,10 +414,10 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
                         h4[q] = h;
                         e4[q] = e;
                     }
-                    E::store4(pout + ((pt * S) * 16 + j) * LD + i0, h4);
+                    E::store4(pout + ((pt * S) * 16 + j) * LD + E::pos(i0), h4);
 #pragma unroll
                     for (int st = 1; st < S; ++st)
-                        E::store4(pout + ((pt * S + st) * 16 + j) * LD + i0,
+                        E::store4(pout + ((pt * S + st) * 16 + j) * LD + E::pos(i0),
                                   e4 * acc[rt][pt * S + st]);
                 }
             }
@@ -421,10 +449,10 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
                         h4[q] = h;
                         e4[q] = e;
                     }
-                    E::store4(pout + ((pt * S) * 16 + j) * LD + i0, h4);
+                    E::store4(pout + ((pt * S) * 16 + j) * LD + E::pos(i0), h4);
 #pragma unroll
                     for (int st = 1; st < S; ++st)
-                        E::store4(pout + ((pt * S + st) * 16 + j) * LD + i0, e4 * acc[pt * S + st]);
+                        E::store4(pout + ((pt * S + st) * 16 + j) * LD + E::pos(i0), e4 * acc[pt * S + st]);
                 }
             }
             T *tmp = pin;
@@ -447,7 +475,8 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
         float y = 0.0f;
         for (int i = 0; i < W; i += 4) {
             const f32x4 h4 = E::load4(h + i);
-            y += wl[i] * h4[0] + wl[i + 1] * h4[1] + wl[i + 2] * h4[2] + wl[i + 3] * h4[3];
+            const int k = E::unit(i);
+            y += wl[k] * h4[0] + wl[k + 1] * h4[1] + wl[k + 2] * h4[2] + wl[k + 3] * h4[3];
         }
         emit_output(P, ss, io, b, s, st, a, y);
     }
@@ -522,7 +551,7 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
                 else if (kind == SK_LATENT) val[q] = e4[q] * P.W0[(size_t)(i0 + q) * in0 + P.d + arg];
                 else val[q] = 0.0f;
             }
-            E::store4(pin + (st * 16 + j) * LD + i0, val);
+            E::store4(pin + (st * 16 + j) * LD + E::pos(i0), val);
         }
     }
     __syncthreads();
@@ -567,9 +596,9 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
             h4[q] = h;
             e4[q] = e;
         }
-        E::store4(pout + j * LD + i0, h4);
+        E::store4(pout + j * LD + E::pos(i0), h4);
 #pragma unroll
-        for (int st = 1; st < S; ++st) E::store4(pout + (st * 16 + j) * LD + i0, e4 * acc[st]);
+        for (int st = 1; st < S; ++st) E::store4(pout + (st * 16 + j) * LD + E::pos(i0), e4 * acc[st]);
         __syncthreads();   // the new panel is complete; the old one and the weights are free
         T *tmp = pin;
         pin = pout;
@@ -587,9 +616,185 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
         float y = 0.0f;
         for (int i = 0; i < W; i += 4) {
             const f32x4 h4 = E::load4(h + i);
-            y += wl[i] * h4[0] + wl[i + 1] * h4[1] + wl[i + 2] * h4[2] + wl[i + 3] * h4[3];
+            const int k = E::unit(i);
+            y += wl[k] * h4[0] + wl[k + 1] * h4[1] + wl[k + 2] * h4[2] + wl[k + 3] * h4[3];
         }
         emit_output(P, ss, io, b, s, st, a, y);
+    }
+}
+
+// Register-resident shape (bf16): waves split the points as in
+// decoder_kernel, but the hidden layers keep their activations in registers.
+// Under the panel unit order a lane's activated, converted accumulators of
+// row tiles 2m and 2m + 1 are exactly its B operand of k-step m for the next
+// layer, so only the staged weights (A operands) come from LDS.  The last
+// hidden layer's activations pass through a small per-wave LDS panel, one
+// column tile at a time, for the fp32 output layer.  Every value is formed
+// by the same arithmetic in the same order as in the panel shapes.
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+
+template <int W, int S, int NP, int WPB>
+__global__ void __launch_bounds__(64 * WPB) decoder_reg_kernel(DecK P, StreamSpec ss, DecIO io)
+{
+    using T = uint16_t;
+    using E = Elem<T>;
+    using SM = DecSmem<T, W>;
+    constexpr int NCT = NP * S;          // column tiles per wave
+    constexpr int LD = W + E::PAD;
+    constexpr int NRT = W / 16;          // row tiles
+    constexpr int NKS = W / 32;          // k-steps
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int b = blockIdx.y;
+    const int64_t n_b = io.n_inst ? (int64_t)io.n_inst[b] : io.n;
+    if ((int64_t)blockIdx.x * WPB * (NP * 16) >= n_b) return;    // block-uniform
+    float *c0 = reinterpret_cast<float *>(smem);
+    float *u = c0 + W;
+    float *w0x = u + W;
+    float *wls = w0x + 3 * W;
+    T *wsh = reinterpret_cast<T *>(smem + SM::vec);
+    T *panel = reinterpret_cast<T *>(smem + SM::fixed) + (size_t)wave * 16 * LD;
+    const double *xh = io.xhat + (size_t)b * P.r;
+    const double *vh = io.vhat ? io.vhat + (size_t)b * P.r : nullptr;
+    load_block_vectors<W>(P, xh, vh, c0, u, w0x, wls);
+    __syncthreads();
+
+    const int64_t wbase = ((int64_t)blockIdx.x * WPB + wave) * (NP * 16);
+    const int j = lane & 15;
+    const int g = lane >> 4;
+    const int in0 = P.d + P.r;
+    bf16x8v Bop[NKS][NCT];
+    bf16x4 lo[NCT];
+
+    // ---- first layer (fp32 vector arithmetic, as in decoder_kernel)
+#pragma unroll
+    for (int pt = 0; pt < NP; ++pt) {
+        const int64_t s = wbase + pt * 16 + j;
+        float Xn[3] = {0.0f, 0.0f, 0.0f};
+        if (s < n_b) {
+            int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * io.n : 0) + s] : s;
+            for (int a = 0; a < P.d; ++a) Xn[a] = io.X[(int64_t)b * io.x_stride + a * io.n_ref + row] * P.scale[a] + P.shift[a];
+        }
+#pragma unroll
+        for (int m = 0; m < NRT; ++m) {
+            const int i0 = 16 * m + 4 * g;
+            f32x4 h4, e4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float *w0 = w0x + (i0 + q) * 3;
+                float z = c0[i0 + q];
+                for (int a = 0; a < P.d; ++a) z += w0[a] * Xn[a];
+                float h, e;
+                E::act(z, h, e);
+                h4[q] = h;
+                e4[q] = e;
+            }
+#pragma unroll
+            for (int st = 0; st < S; ++st) {
+                const int kind = ss.kind[st], arg = ss.arg[st];
+                f32x4 val;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (kind == SK_PRIMAL) val[q] = h4[q];
+                    else if (kind == SK_SPATIAL) val[q] = e4[q] * w0x[(i0 + q) * 3 + arg] * P.scale[arg];
+                    else if (kind == SK_VELOCITY) val[q] = e4[q] * u[i0 + q];
+                    else if (kind == SK_LATENT) val[q] = e4[q] * P.W0[(size_t)(i0 + q) * in0 + P.d + arg];
+                    else val[q] = 0.0f;
+                }
+                const bf16x4 v4 = __builtin_convertvector(val, bf16x4);
+                if (m & 1)
+                    Bop[m >> 1][pt * S + st] = __builtin_shufflevector(lo[pt * S + st], v4, 0, 1, 2, 3, 4, 5, 6, 7);
+                else
+                    lo[pt * S + st] = v4;
+            }
+        }
+    }
+
+    // ---- hidden layers on matrix cores, activations in registers
+    for (int l = 0; l < P.nh - 1; ++l) {
+        const T *src = reinterpret_cast<const T *>(P.Whb) + (size_t)l * W * W;
+        __syncthreads();   // every wave is done with the previous layer's weights
+        constexpr int V = W / 8;
+        for (int t = threadIdx.x; t < W * V; t += 64 * WPB) {
+            const int row = t / V, c8 = t % V;
+            *reinterpret_cast<uint4 *>(wsh + row * LD + 8 * c8) = reinterpret_cast<const uint4 *>(src)[t];
+        }
+        __syncthreads();
+        const float *bl = P.bh + (size_t)l * W;
+        bf16x8v Bn[NKS][NCT];
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt) {
+            f32x4 acc[NCT];
+            f32x4 b4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b4[q] = bl[rt * 16 + 4 * g + q];
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+                acc[ct] = (ct % S == 0) ? b4 : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            const T *Arow = wsh + (rt * 16 + j) * LD + 8 * g;
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) {
+                const bf16x8v a = *reinterpret_cast<const bf16x8v *>(Arow + ks * 32);
+#pragma unroll
+                for (int ct = 0; ct < NCT; ++ct)
+                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, Bop[ks][ct], acc[ct], 0, 0, 0);
+            }
+#pragma unroll
+            for (int pt = 0; pt < NP; ++pt) {
+                f32x4 h4, e4;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float h, e;
+                    E::act(acc[pt * S][q], h, e);
+                    h4[q] = h;
+                    e4[q] = e;
+                }
+#pragma unroll
+                for (int st = 0; st < S; ++st) {
+                    const f32x4 val = st == 0 ? h4 : e4 * acc[pt * S + st];
+                    const bf16x4 v4 = __builtin_convertvector(val, bf16x4);
+                    if (rt & 1)
+                        Bn[rt >> 1][pt * S + st] = __builtin_shufflevector(lo[pt * S + st], v4, 0, 1, 2, 3, 4, 5, 6, 7);
+                    else
+                        lo[pt * S + st] = v4;
+                }
+            }
+        }
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) Bop[ks][ct] = Bn[ks][ct];
+    }
+
+    // ---- output layer (fp32), one column tile at a time through the panel
+    const int D = P.d;
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks)
+            *reinterpret_cast<bf16x8v *>(panel + j * LD + ks * 32 + 8 * g) = Bop[ks][ct];
+        // the panel is this wave's own and the LDS pipeline keeps a wave's
+        // accesses in program order; the compiler barriers keep the compiler
+        // from moving the reads above these stores (or the next column
+        // tile's stores above these reads): their pointer types differ
+        asm volatile("" ::: "memory");
+        const int pt = ct / S, st = ct % S;
+        for (int it = lane; it < 16 * D; it += 64) {
+            const int col = it / D, a = it % D;
+            const int64_t s = wbase + pt * 16 + col;
+            if (s >= n_b) continue;
+            const T *h = panel + (size_t)col * LD;
+            const float *wl = wls + a * W;
+            float y = 0.0f;
+            for (int i = 0; i < W; i += 4) {
+                const f32x4 h4 = E::load4(h + i);
+                const int k = E::unit(i);
+                y += wl[k] * h4[0] + wl[k + 1] * h4[1] + wl[k + 2] * h4[2] + wl[k + 3] * h4[3];
+            }
+            emit_output(P, ss, io, b, s, st, a, y);
+        }
+        asm volatile("" ::: "memory");
     }
 }
 
@@ -643,18 +848,51 @@ int32_t launch_rows(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStr
     return MR_OK;
 }
 
+// waves per block of the register-resident shape
+#ifndef MR_DEC_REG_WPB
+#define MR_DEC_REG_WPB 8
+#endif
+
+template <int W, int S, int NP>
+int32_t launch_reg(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStream_t st)
+{
+    constexpr int WPB = MR_DEC_REG_WPB;
+    constexpr size_t lds = DecSmem<uint16_t, W>::fixed +
+                           (size_t)WPB * 16 * (W + Elem<uint16_t>::PAD) * sizeof(uint16_t);
+    static_assert(lds <= 160 * 1024, "decoder block does not fit the LDS of a compute unit");
+    dim3 grid((unsigned)ceil_div(io.n, (int64_t)WPB * NP * 16), (unsigned)io.B);
+    auto kern = decoder_reg_kernel<W, S, NP, WPB>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        MR_CHECK_HIP(hipFuncSetAttribute((const void *)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    kern<<<grid, 64 * WPB, lds, st>>>(P, ss, io);
+    MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
 // Launch shapes per stream configuration (1: primal only, 5: x, F, v;
 // 9: x and 8 latent-Jacobian columns):
 //   DEC_COL      one or more point tiles per wave, waves split the points
 //   DEC_COL_NP2  two point tiles per wave (primal only)
 //   DEC_COL_NP4  four point tiles per wave (primal only)
 //   DEC_ROWS     waves of a block split a layer's units (small point sets)
+//   DEC_REG      waves split the points, hidden activations in registers
+//                (bf16 only; two point tiles per wave for cfg 1, one for
+//                cfg 5; not offered for cfg 9, whose 9 streams would not fit)
 template <typename T, int W>
 int32_t launch_w(int cfg, int variant, const DecK &P, const StreamSpec &ss, const DecIO &io,
                  hipStream_t st)
 {
     constexpr int NP1 = MR_DEC_PRIMAL_NP;
     constexpr bool DB1 = MR_DEC_PRIMAL_DB, DB5 = MR_DEC_TANGENT_DB;
+    if constexpr (sizeof(T) == 2 && W >= 32) {   // bf16 decoders have W >= 32
+        if (variant == DEC_REG && cfg == 1) return launch_reg<W, 1, 2>(P, ss, io, st);
+        if (variant == DEC_REG && cfg == 5) return launch_reg<W, 5, 1>(P, ss, io, st);
+    }
+    if (variant == DEC_REG) variant = DEC_COL;
     if (cfg == 1) {
         if (variant == DEC_ROWS) return launch_rows<T, W, 1>(P, ss, io, st);
         if (variant == DEC_COL_NP2)
@@ -718,6 +956,15 @@ __global__ void linear_decoder_kernel(DecK P, DecIO io)
 
 inline int cfg_index(int cfg) { return cfg == 1 ? 0 : (cfg == 5 ? 1 : 2); }
 
+// whether a shape can run configuration cfg of this decoder
+inline bool shape_available(const mr_decoder *dec, int cfg, int v)
+{
+    if (v < 0 || v >= DEC_NVARIANT) return false;
+    if (cfg != 1 && (v == DEC_COL_NP2 || v == DEC_COL_NP4)) return false;
+    if (v == DEC_REG) return dec->prec == MR_PREC_BF16 && cfg != 9;
+    return true;
+}
+
 // size class of a launch: floor(log2(instances x points))
 inline int size_bucket(int64_t pts)
 {
@@ -727,7 +974,9 @@ inline int size_bucket(int64_t pts)
 }
 
 // Shape for a launch: the autotuned choice of the nearest tuned size class
-// (within a factor 4), else the size rule (row split below 8192 points).
+// (within a factor 4), else the size rule: row split up to 8192 points,
+// above that registers-resident activations where available (bf16, cfg 1
+// and 5), else point split.
 int dec_variant(const mr_decoder *dec, int cfg, int64_t pts)
 {
     const int ci = cfg_index(cfg), bk = size_bucket(pts);
@@ -736,7 +985,8 @@ int dec_variant(const mr_decoder *dec, int cfg, int64_t pts)
             const int q = bk + sgn * dist;
             if (q >= 0 && q < DEC_BUCKETS && dec->tuned[ci][q] >= 0) return dec->tuned[ci][q];
         }
-    return pts <= 8192 ? DEC_ROWS : DEC_COL;
+    if (pts <= 8192) return DEC_ROWS;
+    return shape_available(dec, cfg, DEC_REG) ? DEC_REG : DEC_COL;
 }
 
 int32_t launch_cfg(const mr_decoder *dec, int cfg, const StreamSpec &ss, const DecIO &io,
@@ -825,7 +1075,9 @@ __global__ void pack_params_kernel(const float *src, float *dst, uint16_t *hid, 
             int i = (int)(rem / W), k = (int)(rem % W);
             if (i < width && k < width) val = src[s_h + l * hsz + (size_t)i * width + k];
             dst[oWh + q] = val;
-            hid[q] = bf16_bits(val);
+            // bf16 copy in the panel unit order (W >= 32 in bf16 mode; the
+            // copy of an fp32 decoder is never read)
+            hid[q - k + (W % 32 == 0 ? unit_pos(k) : k)] = bf16_bits(val);
             continue;
         }
         q -= (size_t)(nh - 1) * W * W;
@@ -952,12 +1204,13 @@ int32_t decoder_autotune(const mr_decoder *dec, int32_t B, int64_t n, int32_t cf
             io.Jz = out + (size_t)Bt * d * nt;
         }
         const StreamSpec ss = spec_of(cfg, d);
-        const int cand[4] = {DEC_COL, DEC_COL_NP2, DEC_COL_NP4, DEC_ROWS};
+        const int cand[5] = {DEC_COL, DEC_COL_NP2, DEC_COL_NP4, DEC_ROWS, DEC_REG};
         float best = 0.0f;
         int best_v = DEC_COL;
-        for (int k = 0; k < 4 && rc == MR_OK; ++k) {
+        for (int k = 0; k < 5 && rc == MR_OK; ++k) {
             const int v = cand[k];
             if (cfg != 1 && (v == DEC_COL_NP2 || v == DEC_COL_NP4)) continue;
+            if (v == DEC_REG && !shape_available(dec, cfg, v)) continue;
             rc = launch_cfg(dec, cfg, ss, io, st, v);   // warm-up (and LDS attribute)
             if (rc != MR_OK) break;
             if (hipEventRecord(e0, st) != hipSuccess) rc = MR_EDEVICE;
@@ -996,6 +1249,15 @@ extern "C" int32_t rom_decoder_shape(const mr_decoder *dec, int32_t cfg, int32_t
     if (!dec || B < 1 || n < 0 || (cfg != 1 && cfg != 5 && cfg != 9)) return MR_EINVAL;
     if (dec->nh == 0) return DEC_COL;
     return dec_variant(dec, cfg, (int64_t)B * n);
+}
+
+extern "C" int32_t rom_decoder_set_shape(mr_decoder *dec, int32_t cfg, int32_t B, int64_t n,
+                                         int32_t shape)
+{
+    if (!dec || B < 1 || n < 1 || (cfg != 1 && cfg != 5 && cfg != 9)) return MR_EINVAL;
+    if (!shape_available(dec, cfg, shape)) return MR_EINVAL;
+    dec->tuned[cfg_index(cfg)][size_bucket((int64_t)B * n)] = (int8_t)shape;
+    return MR_OK;
 }
 
 extern "C" int32_t rom_decoder_create(int32_t d, int32_t r, int32_t width, int32_t n_hidden,

@@ -40,8 +40,10 @@ def test_shapes_agree_and_autotune(gpu, prec):
     z = torch.tensor(0.3 * rng.standard_normal((1, 16)), device=dev)
     vh = torch.tensor(0.3 * rng.standard_normal((1, 16)), device=dev)
     dec = _dec(prec)
-    # untuned size rule: points split for 40,000 points, units split for 2,000
-    assert dec.shape(1, 1, n) == 0 and dec.shape(1, 1, 2000) == 3
+    # untuned size rule: units split for 2,000 points; for 40,000 points the
+    # register-resident shape (bf16) or points split (fp32)
+    assert dec.shape(1, 1, n) == (4 if prec == B.PREC_BF16 else 0)
+    assert dec.shape(1, 1, 2000) == 3 and dec.shape(9, 1, n) == 0
     big = _decode_all(dec, X, z, vh)
     idx = torch.arange(0, n, 20, dtype=torch.int32, device=dev)
     small = _decode_all(dec, X, z, vh, idx=idx)
@@ -56,12 +58,62 @@ def test_shapes_agree_and_autotune(gpu, prec):
     dec.autotune(1, n, cfg_mask=7, reps=2)
     tuned = [dec.shape(c, 1, n) for c in (1, 5, 9)]
     print("tuned shapes at %d points (cfg 1, 5, 9):" % n, tuned)
-    assert all(0 <= t <= 3 for t in tuned)
+    assert all(0 <= t <= 4 for t in tuned)
     again = _decode_all(dec, X, z, vh)
     for k in big:
         e = float((again[k] - big[k]).abs().max() / (big[k].abs().max() + 1e-30))
         assert e < 1e-5, k
     dec.close()
+
+
+@pytest.mark.parametrize("width,nh", [(128, 5), (32, 2)])
+def test_every_shape_agrees(gpu, width, nh):
+    """Each shape pinned in turn (rom_decoder_set_shape) for the primal and
+    the five-stream configurations of a bf16 decoder, against the first:
+    the register-resident shape keeps the hidden activations in registers
+    under the panel unit order, with the same arithmetic."""
+    rng = np.random.default_rng(11)
+    n = 20000 + 37                      # several blocks and a ragged tail
+    X = torch.tensor(rng.uniform(0, 1, size=(3, n)).astype(np.float32), device=dev)
+    z = torch.tensor(0.3 * rng.standard_normal((1, 16)), device=dev)
+    vh = torch.tensor(0.3 * rng.standard_normal((1, 16)), device=dev)
+    dec = _dec(B.PREC_BF16, width=width, nh=nh)
+    outs = {}
+    for shape in (0, 1, 2, 3, 4):
+        dec.set_shape(1, 1, n, shape)
+        if shape in (0, 3, 4):
+            dec.set_shape(5, 1, n, shape)
+        assert dec.shape(1, 1, n) == shape
+        xo = torch.zeros(1, 3, n, device=dev)
+        B.rom_decode(dec, X, z, xo)
+        o = {"x_only": xo}
+        if shape in (0, 3, 4):
+            o.update(x=torch.zeros(1, 3, n, device=dev), F=torch.zeros(1, 9, n, device=dev),
+                     v=torch.zeros(1, 3, n, device=dev))
+            B.rom_decode_jac(dec, X, z, vhat=vh, x=o["x"], F=o["F"], v=o["v"])
+        outs[shape] = o
+    worst = 0.0
+    for shape, o in outs.items():
+        for k, t in o.items():
+            ref = outs[0][k]
+            e = float((t - ref).abs().max() / (ref.abs().max() + 1e-30))
+            worst = max(worst, e)
+            assert e < 1e-5, (shape, k, e)
+    print("width %d: all shapes against shape 0, worst relative difference %.2e" % (width, worst))
+    dec.close()
+
+
+def test_set_shape_rejects_unavailable_shapes(gpu):
+    dec32 = _dec(B.PREC_FP32, width=32, nh=2, r=4)
+    dec16 = _dec(B.PREC_BF16, width=32, nh=2, r=4)
+    lib = B.load()
+    assert lib.rom_decoder_set_shape(dec32.handle, 1, 1, 1000, 4) == B.MR_EINVAL   # fp32
+    assert lib.rom_decoder_set_shape(dec16.handle, 9, 1, 1000, 4) == B.MR_EINVAL   # 9 streams
+    assert lib.rom_decoder_set_shape(dec16.handle, 5, 1, 1000, 1) == B.MR_EINVAL   # primal only
+    assert lib.rom_decoder_set_shape(dec16.handle, 1, 1, 1000, 5) == B.MR_EINVAL
+    assert lib.rom_decoder_set_shape(dec16.handle, 1, 1, 1000, 4) == B.MR_OK
+    dec32.close()
+    dec16.close()
 
 
 def test_autotune_rejects_bad_arguments(gpu):
