@@ -891,8 +891,12 @@ int32_t launch_w(int cfg, int variant, const DecK &P, const StreamSpec &ss, cons
     if constexpr (sizeof(T) == 2 && W >= 32) {   // bf16 decoders have W >= 32
         if (variant == DEC_REG && cfg == 1) return launch_reg<W, 1, 2>(P, ss, io, st);
         if (variant == DEC_REG && cfg == 5) return launch_reg<W, 5, 1>(P, ss, io, st);
+        if (variant == DEC_REG && cfg == 4) return launch_reg<W, 4, 1>(P, ss, io, st);
     }
     if (variant == DEC_REG) variant = DEC_COL;
+    // x and F without v: the other shapes run the five-stream kernels with
+    // the velocity stream zero
+    if (cfg == 4) cfg = 5;
     if (cfg == 1) {
         if (variant == DEC_ROWS) return launch_rows<T, W, 1>(P, ss, io, st);
         if (variant == DEC_COL_NP2)
@@ -954,7 +958,8 @@ __global__ void linear_decoder_kernel(DecK P, DecIO io)
     }
 }
 
-inline int cfg_index(int cfg) { return cfg == 1 ? 0 : (cfg == 5 ? 1 : 2); }
+// tuning slot of a configuration (4, x and F only, shares the slot of 5)
+inline int cfg_index(int cfg) { return cfg == 1 ? 0 : (cfg == 5 || cfg == 4 ? 1 : 2); }
 
 // whether a shape can run configuration cfg of this decoder
 inline bool shape_available(const mr_decoder *dec, int cfg, int v)
@@ -1404,7 +1409,7 @@ int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const flo
             ss.arg[1 + a] = a;
         }
         ss.kind[4] = v ? SK_VELOCITY : SK_ZERO;
-        rc = launch_cfg(dec, 5, ss, io, st);
+        rc = launch_cfg(dec, (F && !v) ? 4 : 5, ss, io, st);
         if (rc != MR_OK) return rc;
         wrote_x = true;
     }

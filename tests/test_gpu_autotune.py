@@ -91,6 +91,10 @@ def test_every_shape_agrees(gpu, width, nh):
             o.update(x=torch.zeros(1, 3, n, device=dev), F=torch.zeros(1, 9, n, device=dev),
                      v=torch.zeros(1, 3, n, device=dev))
             B.rom_decode_jac(dec, X, z, vhat=vh, x=o["x"], F=o["F"], v=o["v"])
+            # x and F without v (the four-stream launch)
+            o.update(x4=torch.zeros(1, 3, n, device=dev), F4=torch.zeros(1, 9, n, device=dev))
+            B.rom_decode_jac(dec, X, z, x=o["x4"], F=o["F4"])
+            assert torch.equal(o["F4"], o["F"]) and torch.equal(o["x4"], o["x"])
         outs[shape] = o
     worst = 0.0
     for shape, o in outs.items():
