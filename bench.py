@@ -31,7 +31,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 SORT_EVERY = 10
-TIMING_EVERY = 10
+# launch-timer sampling interval: coprime with SORT_EVERY, so the sampled
+# scatters cover every number of steps since the last sort (the scatter
+# slows by ~20% over the ten steps as particles drift from their sorted
+# cells; a multiple of the sort interval would sample one phase only)
+TIMING_EVERY = 7
 
 
 def log(*a):
