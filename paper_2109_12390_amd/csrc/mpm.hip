@@ -278,7 +278,28 @@ __global__ void cell_segment_sort_kernel(const int32_t *offsets, const int32_t *
     // cells hold a few tens of particles; a pathological pile-up (or the
     // overflow bucket of flagged particles) keeps its arrival order rather
     // than paying a quadratic sort in one thread
-    if (len > 1024) return;
+    if (len > 1024 || len < 2) return;
+    if (!canonical && len <= 32) {
+        // the common case: sort by index in registers (one load and one
+        // store per element instead of a dependent chain of global accesses)
+        int buf[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            if (i < len) buf[i] = cell_sorted[s + i];
+        for (int i = 1; i < len; ++i) {
+            const int v = buf[i];
+            int j = i - 1;
+            while (j >= 0 && v < buf[j]) {
+                buf[j + 1] = buf[j];
+                --j;
+            }
+            buf[j + 1] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            if (i < len) cell_sorted[s + i] = buf[i];
+        return;
+    }
     for (int i = 1; i < len; ++i) {
         int v = cell_sorted[s + i];
         int j = i - 1;
@@ -326,13 +347,24 @@ __global__ void tail_copy_kernel(const int32_t *cell_sorted, int32_t *perm, cons
     if (i < n) perm[i] = cell_sorted[i];
 }
 
-__global__ void gather_plane_kernel(const float *src, float *dst, const int32_t *perm, int64_t n,
-                                    int planes)
+__global__ void gather_plane_kernel(const float *__restrict__ src, float *__restrict__ dst,
+                                    const int32_t *__restrict__ perm, int64_t n, int planes)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t q = perm[i];
-    for (int k = 0; k < planes; ++k) dst[k * n + i] = src[k * n + q];
+    // source and destination never overlap (a separate set or the copy
+    // buffer), so the loads of all planes can be in flight together
+    int k = 0;
+    for (; k + 3 < planes; k += 4) {
+        const float a0 = src[k * n + q], a1 = src[(k + 1) * n + q];
+        const float a2 = src[(k + 2) * n + q], a3 = src[(k + 3) * n + q];
+        dst[k * n + i] = a0;
+        dst[(k + 1) * n + i] = a1;
+        dst[(k + 2) * n + i] = a2;
+        dst[(k + 3) * n + i] = a3;
+    }
+    for (; k < planes; ++k) dst[k * n + i] = src[k * n + q];
 }
 
 // ---------------------------------------------------------------------------
