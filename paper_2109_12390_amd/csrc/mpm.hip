@@ -381,11 +381,12 @@ __global__ void gather_plane_kernel(const float *__restrict__ src, float *__rest
 // accesses of one wave are kept in program order by a compiler barrier after
 // every node, which the in-order LDS pipeline then preserves across lanes.
 // Particles that drifted out of their sort-time cell may share a base cell
-// with another lane; when a wave has any such particle, lanes claim their
-// base cell in an owner table and the losers retry in a later round.  A
-// particle whose stencil left the region entirely goes to HBM atomics.  The
-// padded region layout (row stride 12 / 24 float4) keeps the 16 lanes of a
-// LDS cycle on distinct banks.
+// with another lane.  The sorted P2G defers them to a per-tile index list
+// and scatters them after the slots, 64 at a time, with lanes claiming
+// their base cell in an owner table and the losers retrying in a later
+// round; the fused kernel (and a full list) claims inside the slot.  A
+// particle whose stencil left the region entirely goes to HBM atomics.
+// Region rows are unpadded in 3D (8 float4) and padded to 24 in 2D.
 
 // tiles (one wave each) per workgroup of the tile kernels
 #ifndef MR_TILE_WPB
@@ -449,11 +450,19 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
     float *C_out, int32_t *flag, float4 *stage = nullptr)
 {
     using CT = CellTile<D>;
+    // sorted P2G: particles that drifted out of their sort-time cell are
+    // deferred to the end of the tile (index list), so the slots themselves
+    // never need base-cell claims
+    constexpr bool DEFER = !FUSED && !DET;
+    constexpr int DEFER_CAP = DEFER ? 512 : 1;
     __shared__ float4 acc_all[CT::WPB][CT::RNP];
     __shared__ int owner_all[CT::WPB][CT::RCN];
+    __shared__ int32_t defer_all[CT::WPB][DEFER_CAP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float4 *acc = acc_all[wave];
     int *owner = owner_all[wave];
+    int32_t *deferred = defer_all[wave];
+    int ndef = 0;                                   // wave-uniform
     const int64_t t = (int64_t)blockIdx.x * CT::WPB + wave;
     if (t >= tg.ntiles) return;                    // wave-uniform; no block barriers below
     const int64_t c0 = offsets[t * Tiling<D>::CELLS];
@@ -601,7 +610,17 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
             }
         }
         bool pending = scat && inreg;
-        const bool drifted = pending && (m0 != h0 || m1 != h1 || (D == 3 && m2 != h2));
+        bool drifted = pending && (m0 != h0 || m1 != h1 || (D == 3 && m2 != h2));
+        if (DEFER) {
+            const uint64_t dm = __ballot(drifted);
+            const int nd = __popcll(dm);
+            if (nd != 0 && ndef + nd <= DEFER_CAP) {
+                if (drifted) deferred[ndef + __popcll(dm & below)] = (int32_t)p;
+                ndef += nd;
+                pending = pending && !drifted;
+                drifted = false;
+            }
+        }
         const bool any_drift = __ballot(drifted) != 0;
         const int key = m0 + CT::RC * (m1 + (D == 3 ? CT::RC * m2 : 0));
         const int nb = m0 + CT::SY * m1 + (D == 3 ? CT::SZ * m2 : 0);
@@ -637,6 +656,72 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
                 };
                 p2g_separable<D, decltype(rmw) &, MR_TILE_ORDERED != 0>(g, sn, pl, rmw);
                 pending = false;
+            }
+        }
+    }
+    if (DEFER && ndef > 0) {
+        // the deferred particles, 64 at a time: reload, form the payload
+        // again and scatter in claim rounds (lanes sharing a base cell go
+        // in turn; any two distinct base cells touch distinct nodes per
+        // stencil offset)
+        lds_order();
+        for (int i0 = 0; i0 < ndef; i0 += 64) {
+            bool pending = false;
+            Stencil<D> sn;
+            P2GPayload<D> pl;
+            int key = 0, nb = 0;
+            if (i0 + lane < ndef) {
+                const int64_t p = deferred[i0 + lane];
+                float xn[D], vp[D], Cp[D * D], Fn[D * D], tau[D * D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    xn[a] = x[a * n + p];
+                    vp[a] = v[a * n + p];
+                }
+#pragma unroll
+                for (int q = 0; q < D * D; ++q) {
+                    Fn[q] = F[q * n + p];
+                    Cp[q] = apic ? C[q * n + p] : 0.0f;
+                }
+                // both succeeded when the particle was deferred
+                make_stencil<D>(g, xn, sn);
+                kirchhoff<D>(model, mu, la, Fn, tau);
+                const float mp = m ? m[p] : m_u;
+                const float sc = dt * (V0 ? V0[p] : V0_u);
+                pl.m = mp;
+#pragma unroll
+                for (int a = 0; a < D; ++a) pl.mv[a] = mp * vp[a];
+#pragma unroll
+                for (int q = 0; q < D * D; ++q) {
+                    pl.mC[q] = mp * Cp[q];
+                    pl.S[q] = sc * tau[q];
+                }
+                const int m0 = sn.base[0] - r0, m1 = sn.base[1] - r1;
+                const int m2 = D == 3 ? sn.base[2] - r2 : 0;
+                key = m0 + CT::RC * (m1 + (D == 3 ? CT::RC * m2 : 0));
+                nb = m0 + CT::SY * m1 + (D == 3 ? CT::SZ * m2 : 0);
+                pending = true;
+            }
+            while (__ballot(pending) != 0) {
+                if (pending) owner[key] = lane;
+                lds_order();
+                const bool go = pending && owner[key] == lane;
+                lds_order();
+                if (go) {
+                    opaque_payload<D>(sn, pl);
+                    auto rmw = [&](int o0, int o1, int o2, float mw, float q0, float q1, float q2) {
+                        float4 *a4 = acc + nb + o0 + CT::SY * o1 + (D == 3 ? CT::SZ * o2 : 0);
+                        float4 q = *a4;
+                        q.x += mw;
+                        q.y += q0;
+                        q.z += q1;
+                        q.w += q2;
+                        *a4 = q;
+                        lds_order();
+                    };
+                    p2g_separable<D, decltype(rmw) &, MR_TILE_ORDERED != 0>(g, sn, pl, rmw);
+                    pending = false;
+                }
             }
         }
     }
