@@ -215,24 +215,29 @@ def test_cell_sort_permutation_is_bit_exact(gpu, dim, P):
 
 @pytest.mark.parametrize("dim,P,move", [(3, 20000, "random"), (2, 6000, "random"),
                                         (3, 20000, "none"), (2, 6000, "none"),
-                                        (3, 20000, "rigid"), (2, 6000, "rigid")])
+                                        (3, 20000, "rigid"), (2, 6000, "rigid"),
+                                        (3, 60000, "dense")])
 def test_sorted_tiled_p2g_matches_oracle(gpu, dim, P, move):
     """Cell-sort, then the tiled P2G with the particles moved since the sort:
     random: by up to 1.4 cells each (mixed drifts, some beyond the drift
-    margin: base-cell claims and the global fallback); none: every particle
-    in its sort-time cell (no claims); rigid: all translated by one cell
-    diagonally (every lane drifted, distinct base cells)."""
+    margin: deferred particles, claims and the global fallback); none: every
+    particle in its sort-time cell; rigid: all translated by one cell
+    diagonally (every lane drifted, distinct base cells); dense: 60,000
+    particles in a 4-cell cube moved randomly, thousands of drifted
+    particles per tile (the deferred list fills and the rest claim inside
+    their slots)."""
     rng = np.random.default_rng(50 + dim)
     n = [40] * dim
     dx = 1 / 40
-    x, v, C, F, m, V0 = random_state(rng, dim, P, lo=0.2, hi=0.8)
+    lo, hi = (0.45, 0.55) if move == "dense" else (0.2, 0.8)
+    x, v, C, F, m, V0 = random_state(rng, dim, P, lo=lo, hi=hi)
     grid = B.Grid(dim, n, dx)
     parts = make_parts(B, x, v, C, F, m, V0)
     ws = B.new_workspace(grid, P)
     perm = torch.zeros(P, dtype=torch.int32, device=dev)
     B.mpm_cell_sort(grid, parts, ws, perm_out=perm)
     p = perm.cpu().numpy()
-    if move == "random":
+    if move in ("random", "dense"):
         xs = x[p] + (rng.uniform(-1.4, 1.4, size=(P, dim)) * dx).astype(np.float32)
     elif move == "rigid":
         xs = x[p] + np.float32(dx) * np.array([1.0, -1.0, 1.0][:dim], dtype=np.float32)
