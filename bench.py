@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0     # dense bf16 matrix cores, nominal
 SORT_EVERY = 10
 # launch-timer sampling interval: coprime with SORT_EVERY, so the sampled
 # scatters cover every number of steps since the last sort (the scatter
@@ -109,7 +110,7 @@ def main():
                          "kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -216,12 +217,20 @@ def main():
         "active_nodes": active_nodes,
         "kernel_source_hash": src_hash,
     }
+    peaks = measured_peaks(B)
+    out["peaks_measured"] = peaks
+    roofline["measured_peak"] = peaks["hbm_copy_GBps"]
+    roofline["frac_measured"] = round(achieved / peaks["hbm_copy_GBps"], 4)
+    log("measured peaks:", json.dumps(peaks))
     if not args.no_fcr:
         out["fixed_corotated"] = fom_fixed_corotated(B, scenes, s, min(args.steps, 200),
                                                      args.warmup)
         log("fixed-corotated:", json.dumps(out["fixed_corotated"]))
+        out["two_dimensional"] = fom_two_dimensional(B, scenes)
+        log("2D:", json.dumps(out["two_dimensional"]))
     if not args.no_rom:
-        out["rom"] = rom_throughput(B, scenes, s, args.rom_steps)
+        out["rom"] = rom_throughput(B, scenes, s, args.rom_steps, peaks=peaks)
+        log("decoder roofline:", json.dumps(out["rom"]["decoder_roofline"]))
         if args.rom_pareto_steps > 0:
             out["rom_pareto"] = rom_pareto(B, scenes, s, args.rom_pareto_steps)
         if args.rom_instances > 0:
@@ -235,6 +244,73 @@ def main():
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out), flush=True)
+
+
+def measured_peaks(B):
+    """What this GPU sustains, beside the nominal peaks: a plain 1 GiB
+    device-to-device copy (bytes read + written per second, best of 5) and
+    the dense bf16 matrix-core loop of mr_mfma_probe (2,048 workgroups)."""
+    import torch
+    dev = "cuda:0"
+    a = torch.ones(256 << 20, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    hbm = 2 * a.numel() * 4 / (best * 1e-3) / 1e9
+    del a, b
+    blocks, iters = 2048, 20000
+    sink = torch.empty(blocks * 256, device=dev)
+    B.mfma_probe(blocks, 100, sink)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    B.mfma_probe(blocks, iters, sink)
+    e1.record()
+    torch.cuda.synchronize()
+    flop = blocks * 4 * iters * 8 * 16384
+    mfma = flop / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    return {"hbm_copy_GBps": round(hbm, 1), "mfma_bf16_TFLOPs": round(mfma, 1)}
+
+
+def fom_two_dimensional(B, scenes, steps=100, sort_every=10):
+    """The 2D scene (64^2 grid, 4,096 particles, fixed-corotated): its
+    working set stays in the caches and the run is bound by launch latency,
+    so only the absolute rate is reported."""
+    import torch
+    dev = "cuda:0"
+    s = scenes.scene_2d()
+    P = s["P"]
+    st = scenes.initial_state(s)
+    soa = lambda a: torch.tensor(np.ascontiguousarray(a.reshape(P, -1).T), device=dev)
+    parts = B.Particles(soa(st["x"]), soa(st["v"]), soa(st["C"]), soa(st["F"]),
+                        m_uniform=float(s["m"]), V0_uniform=float(s["V0"]))
+    grid = B.Grid(2, s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
+    gbuf = torch.zeros(grid.nodes() * 4, device=dev)
+    ws = torch.zeros(B.mpm_step_workspace_bytes(grid, P), dtype=torch.uint8, device=dev)
+    mat = (s["model"], s["E"], s["nu"])
+    B.mpm_step(grid, mat, parts, s["dt"], 10, sort_every, 0, gbuf, ws)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    B.mpm_step(grid, mat, parts, s["dt"], steps, sort_every, 0, gbuf, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"workload": "2D full-order MPM, 64^2 grid, 4,096 particles, fixed-corotated, "
+                        "dt 1e-4, sort every %d steps" % sort_every,
+            "ms_per_step": round(ms, 4), "particle_steps_per_s": P / (ms * 1e-3), "steps": steps}
 
 
 def fom_fixed_corotated(B, scenes, s, steps, warmup):
@@ -272,7 +348,7 @@ def fom_fixed_corotated(B, scenes, s, steps, warmup):
 
 
 def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden=5,
-                   quadrature=None, mode=None):
+                   quadrature=None, mode=None, peaks=None):
     """Reduced-order steps on the same 2,097,152-particle scene: one
     instance, r = 16, 512 sample points per step, Lagrangian quadrature
     (all particles decoded to find the neighbours), bf16 decoder of width
@@ -317,16 +393,37 @@ def rom_throughput(B, scenes, s, steps, n_samples=512, r=16, width=128, n_hidden
         times.append(a.elapsed_time(b) / k)
     n_quad, n_active = rom.last_counts(0)
     rom.close()
+    # the dominant launch of the step, alone: positions of every particle
+    xo = torch.empty(1, 3, P, device=dev)
+    B.rom_decode(dec, Xg, z, xo)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(5):
+        B.rom_decode(dec, Xg, z, xo)
+    b.record()
+    torch.cuda.synchronize()
+    dec_ms = a.elapsed_time(b) / 5
+    flop_pt = 2 * (width * (3 + r) + (n_hidden - 1) * width * width + 3 * width)
+    tflops = P * flop_pt / (dec_ms * 1e-3) / 1e12
+    dec_roof = {"bound": "mfma", "kernel": "bf16 decoder, positions of all %d particles" % P,
+                "shape": SHAPE_NAMES[dec.shape(1, 1, P)], "ms": round(dec_ms, 4),
+                "flop_per_point": flop_pt, "achieved": round(tflops, 1), "peak": MFMA_BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4)}
+    if peaks:
+        dec_roof["measured_peak"] = peaks["mfma_bf16_TFLOPs"]
+        dec_roof["frac_measured"] = round(tflops / peaks["mfma_bf16_TFLOPs"], 4)
     dec.close()
     times = np.array(times)
     return {"metric": "ROM latent steps/s", "value": float(1e3 / times.mean()), "unit": "latent steps/s",
-            "decoder_shapes": shapes,
+            "decoder_shapes": shapes, "decoder_roofline": dec_roof,
             "ms_per_step": float(times.mean()), "p50_ms": float(np.percentile(times, 50)),
             "p99_ms": float(np.percentile(times, 99)), "steps": int(n_rep * k),
             "n_quadrature_points": int(n_quad), "n_active_nodes": int(n_active),
             "config": {"instances": 1, "particles": P, "samples": n_samples, "r": r,
                        "decoder": "bf16 MLP %d x %d, random init" % (width, n_hidden),
-                       "quadrature": "Eulerian (l = 2, 4 Newton iterations)"
+                       "quadrature": "Eulerian (l = 2, a displacement step and one Newton step)"
                        if quadrature == B.QUAD_EULERIAN else "Lagrangian",
                        "projection": "position-velocity, 3 Gauss-Newton iterations"
                        if mode == B.POS_VEL else "velocity only",

@@ -479,6 +479,16 @@ int32_t rom_step(mr_rom *rom, int32_t n_steps, int64_t step0, double dt,
 int32_t rom_last_counts(const mr_rom *rom, int32_t b, int64_t *n_quad,
                         int64_t *n_active, void *stream);
 
+/* ---- measurement aid (not part of the method) ------------------------- */
+
+/* Dense bf16 matrix-core loop for the sustained MFMA rate: `blocks`
+ * workgroups of 256 threads, every wave running `iters` rounds of 8
+ * independent 16x16x32 bf16 products (16,384 FLOP each) on register
+ * operands, blocks x 4 x iters x 8 x 16,384 FLOP in all.  sink: device
+ * float32 [blocks x 256], written (keeps the products live).  Stream-
+ * ordered; MR_EINVAL for blocks < 1, iters < 1 or a NULL sink. */
+int32_t mr_mfma_probe(int32_t blocks, int32_t iters, float *sink, void *stream);
+
 /* ---- decoder training (Section 4.2 loss; Appendix B training details) --- */
 
 typedef struct mr_trainer mr_trainer;

@@ -108,6 +108,7 @@ SIGNATURES = {
     "rom_decoder_autotune": (_i32, [_vp, _i32, _i64, _i32, _i32, _vp]),
     "rom_decoder_shape": (_i32, [_vp, _i32, _i32, _i64]),
     "rom_decoder_set_shape": (_i32, [_vp, _i32, _i32, _i64, _i32]),
+    "mr_mfma_probe": (_i32, [_i32, _i32, _vp, _vp]),
     "rom_decode": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _vp, _vp, _vp]),
     "rom_decode_jac": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                               _vp, _vp]),
@@ -357,6 +358,13 @@ def sync_status(flags_dev, stream=None):
     host = (ctypes.c_int32 * max(n, 1))()
     rc = lib.mr_sync_status(_stream(stream), _ptr(flags_dev, torch.int32), n, host)
     return rc, list(host)[:n]
+
+
+def mfma_probe(blocks, iters, sink, stream=None):
+    """Dense bf16 matrix-core loop (measurement aid): blocks x 4 x iters x 8
+    x 16,384 FLOP; sink is a float32 device tensor of blocks x 256."""
+    _check("mr_mfma_probe", load().mr_mfma_probe(blocks, iters, _ptr(sink, torch.float32),
+                                                 _stream(stream)))
 
 
 def version():

@@ -128,3 +128,15 @@ def test_autotune_rejects_bad_arguments(gpu):
     assert lib.rom_decoder_autotune(dec.handle, 1, 100, 1, 0, None) == B.MR_EINVAL
     assert lib.rom_decoder_shape(dec.handle, 2, 1, 100) == B.MR_EINVAL
     dec.close()
+
+
+def test_mfma_probe_runs(gpu):
+    """The matrix-core probe (a measurement aid) writes finite values and
+    rejects bad arguments."""
+    sink = torch.zeros(4 * 256, device=dev)
+    B.mfma_probe(4, 10, sink)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(sink).all()) and float(sink.abs().sum()) > 0
+    lib = B.load()
+    assert lib.mr_mfma_probe(0, 10, B._ptr(sink, torch.float32), None) == B.MR_EINVAL
+    assert lib.mr_mfma_probe(4, 0, B._ptr(sink, torch.float32), None) == B.MR_EINVAL
