@@ -250,7 +250,10 @@ int32_t mpm_g2p2g(const mr_grid *grid_desc, const mr_material *mat,
  * MR_DETERMINISTIC (requires sort_every >= 1): canonical sorts and the
  * deterministic P2G, so the final state does not depend on the input order
  * of the particles (up to their relabelling, given by perm_accum) or on the
- * run; particles must move less than a cell between sorts. */
+ * run; particles must move less than a cell between sorts.  Every launch
+ * is a kernel or a device-to-device copy on `stream` (no host
+ * synchronisation, no memset), so a call can be captured in a graph when
+ * timing is NULL. */
 int32_t mpm_step(const mr_grid *grid_desc, const mr_material *mat,
                  mr_particles *parts, float dt, int32_t n_steps,
                  int32_t sort_every, int32_t flags, float *grid,

@@ -16,6 +16,28 @@
 //    the margin since the sort fall back to global atomics.
 #include "mpm_kernels.h"
 
+namespace mr {
+
+// zero fill by a kernel rather than hipMemsetAsync, so that every launch of
+// the full-order path can be captured in a graph (memset nodes are avoided
+// there); count in 32-bit words
+__global__ void zero_words_kernel(uint32_t *p, int64_t words)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+inline void zero_words(void *p, int64_t words, hipStream_t st)
+{
+    if (words <= 0) return;
+    const int64_t blocks = (words + 255) / 256;
+    zero_words_kernel<<<(unsigned)(blocks < 4096 ? blocks : 4096), 256, 0, st>>>(
+        reinterpret_cast<uint32_t *>(p), words);
+}
+
+}  // namespace mr
+
 #include <stdio.h>
 
 namespace mr {
@@ -937,10 +959,11 @@ int32_t cell_sort_impl(const GridK &g, mr_particles *parts, int32_t *perm_out, v
     sort_ws_bytes<D>(g, n, &ws, (char *)workspace);
     TileGeom tg = tile_geom<D>(g);
     const int64_t ncells = ws.ncells;
-    MR_CHECK_HIP(hipMemsetAsync(ws.counts, 0, 4 * (ncells + 1), st));
-    MR_CHECK_HIP(hipMemsetAsync(ws.fill, 0, 4 * (ncells + 1), st));
+    zero_words(ws.counts, ncells + 1, st);
+    zero_words(ws.fill, ncells + 1, st);
     if (n == 0) {
-        MR_CHECK_HIP(hipMemsetAsync(ws.offsets, 0, 4 * (ncells + 1), st));
+        zero_words(ws.offsets, ncells + 1, st);
+        MR_LAUNCH_CHECK();
         return MR_OK;
     }
     const int TB = 256;
@@ -1023,8 +1046,7 @@ int32_t p2g_impl(const GridK &g, const mr_material *mat, const mr_particles *par
         MR_LAUNCH_CHECK();
         return MR_OK;
     }
-    if (!(flags & MR_ACCUMULATE))
-        MR_CHECK_HIP(hipMemsetAsync(grid, 0, sizeof(float) * 4 * grid_nodes(g), st));
+    if (!(flags & MR_ACCUMULATE)) zero_words(grid, 4 * grid_nodes(g), st);
     if ((flags & MR_SORTED) && !subset) {
         SortWorkspace ws;
         sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
@@ -1215,8 +1237,7 @@ int32_t g2p2g_impl(const GridK &g, const mr_material *mat, mr_particles *parts, 
 {
     Lame lm = lame_of(mat->E, mat->nu);
     int apic = (flags & MR_NO_AFFINE) ? 0 : 1;
-    if (!(flags & MR_ACCUMULATE))
-        MR_CHECK_HIP(hipMemsetAsync(grid_out, 0, sizeof(float) * 4 * grid_nodes(g), st));
+    if (!(flags & MR_ACCUMULATE)) zero_words(grid_out, 4 * grid_nodes(g), st);
     SortWorkspace ws;
     sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
     TileGeom tg = tile_geom<D>(g);

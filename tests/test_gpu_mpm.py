@@ -573,3 +573,50 @@ def test_empty_particle_set(gpu):
     assert float(gbuf.abs().sum()) == 0.0
     B.mpm_g2p(grid, parts, 1e-4, gbuf)
     torch.cuda.synchronize()
+
+
+def test_time_loop_captured_in_a_graph(gpu):
+    """mpm_step launches only kernels and device copies, so a call can be
+    captured in a graph.  Three replays from the initial state, with eager
+    work (state reset, grid clear) and synchronisation between them, each
+    match the eager run bit for bit (deterministic mode)."""
+    s = scenes.scene_3d(n=32, cube_cells=8, seed=5, v0=(0.3, -2.0, 0.1))
+    st0 = scenes.initial_state(s)
+    P = s["P"]
+    grid = _gpu_scene(B, s)
+    mat = (s["model"], s["E"], s["nu"])
+
+    def fresh():
+        return make_parts(B, st0["x"], st0["v"], st0["C"], st0["F"], m_u=float(s["m"]),
+                          V0_u=float(s["V0"]))
+
+    gbuf = torch.zeros(grid.nodes() * 4, device=dev)
+    ws = torch.zeros(B.mpm_step_workspace_bytes(grid, P), dtype=torch.uint8, device=dev)
+    perm = torch.zeros(P, dtype=torch.int32, device=dev)
+    eager = fresh()
+    B.mpm_step(grid, mat, eager, s["dt"], 20, 10, B.DETERMINISTIC, gbuf, ws, perm_accum=perm)
+    torch.cuda.synchronize()
+    want = {k: getattr(eager, k).clone() for k in ("x", "v", "C", "F")}
+    want_perm = perm.clone()
+    static = fresh()
+    init = fresh()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):       # warm-up outside the capture
+        B.mpm_step(grid, mat, static, s["dt"], 1, 10, B.DETERMINISTIC, gbuf, ws, perm_accum=perm)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        B.mpm_step(grid, mat, static, s["dt"], 20, 10, B.DETERMINISTIC, gbuf, ws, perm_accum=perm)
+    for rep in range(3):
+        for k in ("x", "v", "C", "F"):
+            getattr(static, k).copy_(getattr(init, k))
+        gbuf.zero_()
+        perm.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in ("x", "v", "C", "F"):
+            assert torch.equal(getattr(static, k), want[k]), (rep, k)
+        assert torch.equal(perm, want_perm), rep
