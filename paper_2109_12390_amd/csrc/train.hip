@@ -259,13 +259,15 @@ __global__ void output_adjoint_kernel(TrainDims td, int64_t rows, const float *d
 // adjoint of the pre-activations of a hidden layer:
 //   primal: Pbar = e Abar + sum_t e' Pdot_t Abar_t ;  tangent t: Pbar_t = e Abar_t
 // with e = ELU'(p), e' = ELU''(p); the bias gradient sums the primal Pbar
-__global__ void activate_backward_kernel(TrainDims td, int64_t rows, const float *P,
-                                         const float *Abar, float *Pbar, float *db)
+// For width W <= 256 a thread keeps one unit i (256 / W rows per pass,
+// leftover lanes idle) and strides over rows, summing its bias gradient
+// locally: one atomic per thread instead of one per row (all rows of a
+// layer add into the same W addresses).  Wider layers: threads stride over
+// units, the block over rows.
+__device__ __forceinline__ float activate_backward_row(const TrainDims &td, int64_t row, int i,
+                                                       const float *P, const float *Abar,
+                                                       float *Pbar)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= rows * td.W) return;
-    const int64_t row = t / td.W;
-    const int i = (int)(t % td.W);
     const int64_t c0 = row * td.S;
     const float p = P[c0 * td.W + i];
     const float e = elu_d(p), e2 = elu_dd(p);
@@ -276,26 +278,73 @@ __global__ void activate_backward_kernel(TrainDims td, int64_t rows, const float
         Pbar[(c0 + st) * td.W + i] = e * ab;
     }
     Pbar[c0 * td.W + i] = pb;
-    atomicAdd(db + i, pb);
+    return pb;
 }
 
-// latent gradients: primal column -> z_s; velocity column -> (z_next - z_s)/dt
-__global__ void latent_grad_kernel(TrainDims td, int64_t rows, int rows_per_group,
-                                   const int32_t *snap, const int32_t *next, float inv_dt,
-                                   const float *A0bar, float *dZ)
+__global__ void __launch_bounds__(256) activate_backward_kernel(TrainDims td, int64_t rows,
+                                                                const float *P, const float *Abar,
+                                                                float *Pbar, float *db)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= rows * td.r) return;
-    const int64_t row = t / td.r;
-    const int k = (int)(t % td.r);
-    const int grp = (int)(row / rows_per_group);
+    if (td.W <= 256) {
+        const int rpp = 256 / td.W;
+        if ((int)threadIdx.x >= rpp * td.W) return;      // no barriers below
+        const int i = (int)(threadIdx.x % td.W);
+        const int64_t r0 = (int64_t)blockIdx.x * rpp + threadIdx.x / td.W;
+        const int64_t stride = (int64_t)gridDim.x * rpp;
+        float bsum = 0.0f;
+        for (int64_t row = r0; row < rows; row += stride)
+            bsum += activate_backward_row(td, row, i, P, Abar, Pbar);
+        if (r0 < rows) atomicAdd(db + i, bsum);
+        return;
+    }
+    for (int i = threadIdx.x; i < td.W; i += blockDim.x) {
+        float bsum = 0.0f;
+        for (int64_t row = blockIdx.x; row < rows; row += gridDim.x)
+            bsum += activate_backward_row(td, row, i, P, Abar, Pbar);
+        if ((int64_t)blockIdx.x < rows) atomicAdd(db + i, bsum);
+    }
+}
+
+// latent gradients: primal column -> z_s; velocity column -> (z_next - z_s)/dt.
+// Every row of a group shares its snapshot: one block per group sums the
+// group's rows per latent component in LDS (256 threads: r components times
+// floor(256 / r) row lanes, leftover lanes idle) and adds r (or 2r) values
+// to dZ.
+__global__ void __launch_bounds__(256) latent_grad_kernel(TrainDims td, int64_t rows,
+                                                          int rows_per_group, const int32_t *snap,
+                                                          const int32_t *next, float inv_dt,
+                                                          const float *A0bar, float *dZ)
+{
+    __shared__ float red0[256], red1[256];
+    const int grp = blockIdx.x;
+    const int lanes = 256 / td.r;                 // row lanes per component
+    const int k = threadIdx.x % td.r, lr = threadIdx.x / td.r;
     const int s = snap[grp], nx = next[grp];
-    const int64_t c0 = row * td.S;
-    atomicAdd(dZ + (int64_t)s * td.r + k, A0bar[c0 * td.r + k]);
-    if (nx >= 0) {
-        const float w = A0bar[(c0 + td.d + 1) * td.r + k] * inv_dt;
-        atomicAdd(dZ + (int64_t)nx * td.r + k, w);
-        atomicAdd(dZ + (int64_t)s * td.r + k, -w);
+    float a0 = 0.0f, a1 = 0.0f;
+    if (lr < lanes) {
+        for (int q = lr; q < rows_per_group; q += lanes) {
+            const int64_t row = (int64_t)grp * rows_per_group + q;
+            if (row >= rows) break;
+            const int64_t c0 = row * td.S;
+            a0 += A0bar[c0 * td.r + k];
+            if (nx >= 0) a1 += A0bar[(c0 + td.d + 1) * td.r + k];
+        }
+    }
+    red0[threadIdx.x] = lr < lanes ? a0 : 0.0f;
+    red1[threadIdx.x] = lr < lanes ? a1 : 0.0f;
+    __syncthreads();
+    if (threadIdx.x < td.r) {
+        float t0 = 0.0f, t1 = 0.0f;
+        for (int q = 0; q < lanes; ++q) {
+            t0 += red0[q * td.r + threadIdx.x];
+            t1 += red1[q * td.r + threadIdx.x];
+        }
+        atomicAdd(dZ + (int64_t)s * td.r + threadIdx.x, t0);
+        if (nx >= 0) {
+            const float w = t1 * inv_dt;
+            atomicAdd(dZ + (int64_t)nx * td.r + threadIdx.x, w);
+            atomicAdd(dZ + (int64_t)s * td.r + threadIdx.x, -w);
+        }
     }
 }
 
@@ -573,8 +622,12 @@ extern "C" int32_t rom_train_backward(mr_trainer *t, const float *dg, const floa
     ga.mode = 0;
     if ((rc = gemm(false, ga, st)) != MR_OK) return rc;
     for (int l = td.nh - 1; l >= 0; --l) {
-        activate_backward_kernel<<<(unsigned)ceil_div(rows * td.W, TB), TB, 0, st>>>(
-            td, rows, t->P[l], t->Abar, t->Pbar, dparams + t->ob[l]);
+        {
+            const int64_t rpp = td.W <= 256 ? 256 / td.W : 1;
+            const int64_t passes = ceil_div(rows, rpp);
+            activate_backward_kernel<<<(unsigned)(passes < 1024 ? passes : 1024), 256, 0, st>>>(
+                td, rows, t->P[l], t->Abar, t->Pbar, dparams + t->ob[l]);
+        }
         MR_LAUNCH_CHECK();
         const int Kin = (l == 0) ? td.K0 : td.W;
         const float *in = (l == 0) ? t->A0 : t->A[l - 1];
@@ -606,7 +659,7 @@ extern "C" int32_t rom_train_backward(mr_trainer *t, const float *dg, const floa
             if ((rc = gemm(false, gz, st)) != MR_OK) return rc;
         }
     }
-    latent_grad_kernel<<<(unsigned)ceil_div(rows * td.r, TB), TB, 0, st>>>(
+    latent_grad_kernel<<<(unsigned)ceil_div(rows, (int64_t)t->rows_per_group), 256, 0, st>>>(
         td, rows, t->rows_per_group, t->snap, t->next, t->inv_dt, t->A0bar, dZ);
     MR_LAUNCH_CHECK();
     return MR_OK;
