@@ -154,10 +154,17 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
             }
 }
 
+// splits < 0: split the k range (a batch reduction, accumulated with
+// atomics) so that about 1,024 blocks run, each over at least 256 k
 int32_t gemm(bool bf16, GemmArgs g, hipStream_t st, int splits = 1)
 {
     if (g.M <= 0 || g.N <= 0) return MR_OK;
     if (g.K <= 0) return MR_OK;
+    if (splits < 0) {
+        const int64_t tiles = ceil_div(g.M, GBM) * ceil_div(g.N, GBN);
+        const int64_t by_blocks = 1024 / tiles, by_k = g.K / 256;
+        splits = (int)(by_blocks < by_k ? by_blocks : by_k);
+    }
     if (splits < 1) splits = 1;
     int chunk = (int)ceil_div(ceil_div(g.K, splits), GBK) * GBK;
     splits = (int)ceil_div(g.K, chunk);
@@ -599,8 +606,8 @@ extern "C" int32_t rom_train_backward(mr_trainer *t, const float *dg, const floa
     const int64_t rows = t->rows, cols = rows * td.S;
     const float *params = t->params;
     const int TB = 256;
-    // split the batch reduction of the weight gradients over ~256 blocks
-    const int splits = (int)(cols / 2048) > 1 ? (int)(cols / 2048) : 1;
+    // the batch reductions of the weight gradients are split over ~1,024 blocks
+    const int splits = -1;
     int32_t rc;
     output_adjoint_kernel<<<(unsigned)ceil_div(rows, TB), TB, 0, st>>>(td, rows, dg, dG, dGv, t->Ybar,
                                                                        dparams + t->ob[td.nh]);
