@@ -552,6 +552,7 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
             "ms_per_step": st["ms_per_step"], "displacement_error": err,
             "position_error_percent": pos, "status": st["status"], "steps": n_steps,
             "train": {"steps": train_steps, "rows_per_step": 64 * 256, "objective": hist,
+                      "rows_per_s": train_steps * 64 * 256 / t_train,
                       "lam_F": lam_F, "lam_v": lam_v, "seconds": t_train,
                       "snapshot_seconds": t_data, "frames": snap.n_frames, "particles": 65536},
             "config": {"instances": 1, "particles": s["P"], "samples": n_samples, "r": r,
