@@ -837,7 +837,10 @@ __global__ void grid_update_kernel(GridK g, float dt, float *grid, const int32_t
     float4 *gp = reinterpret_cast<float4 *>(grid) + i;
     float4 q = *gp;
     if (!(q.x > 0.0f)) {
-        *gp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        // massless: v = 0; the untouched nodes of a scatter are zero already
+        // (most of the grid), so only a non-zero node is written
+        if (q.x != 0.0f || q.y != 0.0f || q.z != 0.0f || q.w != 0.0f)
+            *gp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         return;
     }
     float inv = 1.0f / q.x;
