@@ -60,6 +60,7 @@ struct DecK {
 struct StreamSpec {
     int kind[MAXS];
     int arg[MAXS];
+    int zk;   // latent streams of block z take latent arg + zk * z (0: one z)
 };
 
 struct DecIO {
@@ -79,6 +80,24 @@ struct DecIO {
 
 __device__ __forceinline__ float elu(float z) { return z > 0.0f ? z : expm1f(z); }
 __device__ __forceinline__ float elu_d(float z) { return z > 0.0f ? 1.0f : expf(z); }
+
+// kind and argument of stream st in this block (latent streams shifted by
+// zk * blockIdx.z; past the last latent they are zero streams)
+__device__ __forceinline__ void stream_of(const StreamSpec &ss, int r, int st, int &kind, int &arg)
+{
+    kind = ss.kind[st];
+    arg = ss.arg[st];
+    if (kind == SK_LATENT) {
+        arg += ss.zk * (int)blockIdx.z;
+        if (arg >= r) kind = SK_ZERO;
+    }
+}
+
+// blocks along z of a launch
+inline unsigned z_blocks(const StreamSpec &ss, int r)
+{
+    return ss.zk > 0 ? (unsigned)((r + ss.zk - 1) / ss.zk) : 1u;
+}
 
 // ELU and its derivative from one hardware exponential, for activations that
 // are stored in bf16: e^z - 1 is formed by subtraction, whose absolute error
@@ -192,11 +211,12 @@ __device__ __forceinline__ void emit_output(const DecK &P, const StreamSpec &ss,
                                             int b, int64_t s, int st, int a, float y)
 {
     const int D = P.d;
-    const int kind = ss.kind[st], arg = ss.arg[st];
+    int kind, arg;
+    stream_of(ss, P.r, st, kind, arg);
     const int64_t n = io.n;
     const size_t bo = (size_t)b;
     if (kind == SK_PRIMAL) {
-        if (io.x) {
+        if (io.x && blockIdx.z == 0) {
             float val = P.mean[a] + P.stdv[a] * (y + P.bL[a]);
             if (P.mode == MR_OUT_DISPLACEMENT && !io.disp_only) {
                 int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * n : 0) + s] : s;
@@ -340,7 +360,8 @@ __global__ void __launch_bounds__(64 * WPB) decoder_kernel(DecK P, StreamSpec ss
             }
 #pragma unroll
             for (int st = 0; st < S; ++st) {
-                const int kind = ss.kind[st], arg = ss.arg[st];
+                int kind, arg;
+    stream_of(ss, P.r, st, kind, arg);
                 f32x4 val;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -541,7 +562,8 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
         }
 #pragma unroll
         for (int st = 0; st < S; ++st) {
-            const int kind = ss.kind[st], arg = ss.arg[st];
+            int kind, arg;
+    stream_of(ss, P.r, st, kind, arg);
             f32x4 val;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -692,7 +714,8 @@ __global__ void __launch_bounds__(64 * WPB) decoder_reg_kernel(DecK P, StreamSpe
             }
 #pragma unroll
             for (int st = 0; st < S; ++st) {
-                const int kind = ss.kind[st], arg = ss.arg[st];
+                int kind, arg;
+    stream_of(ss, P.r, st, kind, arg);
                 f32x4 val;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -807,7 +830,7 @@ int32_t launch_one(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStre
     constexpr size_t lds = DecSmem<T, W>::fixed + (size_t)WPB * per_wave;
     static_assert(WPB >= 1 && lds <= 160 * 1024, "decoder block does not fit the LDS of a compute unit");
     const int64_t pts_per_block = (int64_t)WPB * NP * 16;
-    dim3 grid((unsigned)ceil_div(io.n, pts_per_block), (unsigned)io.B);
+    dim3 grid((unsigned)ceil_div(io.n, pts_per_block), (unsigned)io.B, z_blocks(ss, P.r));
     auto kern = decoder_kernel<T, W, S, NP, DB, WPB>;
     static bool attr_set = false;  // the LDS size of an instantiation is fixed
     if (!attr_set) {
@@ -835,7 +858,7 @@ int32_t launch_rows(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStr
 {
     constexpr size_t lds = DecSmem<T, W>::fixed + 2 * (size_t)S * 16 * (W + Elem<T>::PAD) * sizeof(T);
     static_assert(lds <= 160 * 1024, "decoder block does not fit the LDS of a compute unit");
-    dim3 grid((unsigned)ceil_div(io.n, 16), (unsigned)io.B);
+    dim3 grid((unsigned)ceil_div(io.n, 16), (unsigned)io.B, z_blocks(ss, P.r));
     auto kern = decoder_rows_kernel<T, W, S>;
     static bool attr_set = false;
     if (!attr_set) {
@@ -860,7 +883,7 @@ int32_t launch_reg(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStre
     constexpr size_t lds = DecSmem<uint16_t, W>::fixed +
                            (size_t)WPB * 16 * (W + Elem<uint16_t>::PAD) * sizeof(uint16_t);
     static_assert(lds <= 160 * 1024, "decoder block does not fit the LDS of a compute unit");
-    dim3 grid((unsigned)ceil_div(io.n, (int64_t)WPB * NP * 16), (unsigned)io.B);
+    dim3 grid((unsigned)ceil_div(io.n, (int64_t)WPB * NP * 16), (unsigned)io.B, z_blocks(ss, P.r));
     auto kern = decoder_reg_kernel<W, S, NP, WPB>;
     static bool attr_set = false;
     if (!attr_set) {
@@ -1417,18 +1440,18 @@ int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const flo
         io.Jz = Jz;
         io.F = nullptr;
         io.v = nullptr;
-        for (int k0 = 0; k0 < dec->r; k0 += 8) {
-            StreamSpec ss{};
-            ss.kind[0] = SK_PRIMAL;
-            for (int q = 0; q < 8; ++q) {
-                ss.kind[1 + q] = (k0 + q < dec->r) ? SK_LATENT : SK_ZERO;
-                ss.arg[1 + q] = k0 + q;
-            }
-            io.x = wrote_x ? nullptr : x;
-            rc = launch_cfg(dec, 9, ss, io, st);
-            if (rc != MR_OK) return rc;
-            wrote_x = wrote_x || x;
+        // one launch: block z takes latent columns 8z .. 8z + 7
+        StreamSpec ss{};
+        ss.kind[0] = SK_PRIMAL;
+        for (int q = 0; q < 8; ++q) {
+            ss.kind[1 + q] = SK_LATENT;
+            ss.arg[1 + q] = q;
         }
+        ss.zk = 8;
+        io.x = wrote_x ? nullptr : x;
+        rc = launch_cfg(dec, 9, ss, io, st);
+        if (rc != MR_OK) return rc;
+        wrote_x = wrote_x || x;
     }
     if (!wrote_x && x) {
         StreamSpec ss{};
