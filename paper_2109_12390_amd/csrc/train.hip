@@ -51,8 +51,73 @@ struct GemmArgs {
 
 constexpr int GBM = 64, GBN = 64, GBK = 32;
 
+// Stages the 64 x GBK tile of an operand whose element (r, k) sits at
+// P[r * sr + k * sk] into S[r][k] (as T); rows at or past rmax and k at or
+// past ke read as zero.  The unit-stride dimension runs across consecutive
+// threads.  VEC: that dimension is read four elements at a time (its
+// extent and the other stride are multiples of 4 and P is 16-byte
+// aligned, so a group of four is either all in range or all out).
+template <typename T, int LDK, bool VEC>
+__device__ __forceinline__ void stage_tile(T (*S)[LDK], const float *P, int64_t sr, int64_t sk,
+                                           int r0, int rmax, int k0, int ke, int tid)
+{
+    constexpr int R = 64;
+    if constexpr (VEC) {
+#pragma unroll
+        for (int e = 0; e < (R * GBK / 4) / 256; ++e) {
+            const int idx = e * 256 + tid;
+            if (sk == 1) {
+                const int rr = idx / (GBK / 4), kk = (idx % (GBK / 4)) * 4;
+                const int gr = r0 + rr, gk = k0 + kk;
+                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (gr < rmax && gk < ke) v = *reinterpret_cast<const float4 *>(P + (int64_t)gr * sr + gk);
+                if constexpr (sizeof(T) == 2) {
+                    uint2 w;
+                    w.x = (uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16);
+                    w.y = (uint32_t)to_bf16(v.z) | ((uint32_t)to_bf16(v.w) << 16);
+                    *reinterpret_cast<uint2 *>(&S[rr][kk]) = w;
+                } else {
+                    *reinterpret_cast<float4 *>(&S[rr][kk]) = v;
+                }
+            } else {
+                const int kk = idx / (R / 4), rr = (idx % (R / 4)) * 4;
+                const int gr = r0 + rr, gk = k0 + kk;
+                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (gr < rmax && gk < ke) v = *reinterpret_cast<const float4 *>(P + (int64_t)gk * sk + gr);
+                const float c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if constexpr (sizeof(T) == 2)
+                        S[rr + i][kk] = to_bf16(c[i]);
+                    else
+                        S[rr + i][kk] = c[i];
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < (R * GBK) / 256; ++e) {
+            const int idx = e * 256 + tid;
+            int rr, kk;
+            if (sk == 1) {
+                rr = idx / GBK;
+                kk = idx % GBK;
+            } else {
+                kk = idx / R;
+                rr = idx % R;
+            }
+            const int gr = r0 + rr, gk = k0 + kk;
+            const float v = (gr < rmax && gk < ke) ? P[(int64_t)gr * sr + (int64_t)gk * sk] : 0.0f;
+            if constexpr (sizeof(T) == 2)
+                S[rr][kk] = to_bf16(v);
+            else
+                S[rr][kk] = v;
+        }
+    }
+}
+
 // C(m, n) = sum_k A(m, k) B(k, n); block tile 64 x 64, four waves of 32 x 32
-template <bool BF16>
+template <bool BF16, bool VA, bool VB>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 {
     constexpr int PAD = BF16 ? 8 : 4;
@@ -72,44 +137,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = kb; k0 < ke; k0 += GBK) {
-        // stage A (64 x 32) and B (32 x 64); the unit-stride dimension of each
-        // operand runs across consecutive threads
-#pragma unroll
-        for (int e = 0; e < (GBM * GBK) / 256; ++e) {
-            int idx = e * 256 + tid;
-            int mm, kk;
-            if (g.sak == 1) {
-                mm = idx / GBK;
-                kk = idx % GBK;
-            } else {
-                kk = idx / GBM;
-                mm = idx % GBM;
-            }
-            int gm = m0 + mm, gk = k0 + kk;
-            float v = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.sam + (int64_t)gk * g.sak] : 0.0f;
-            if constexpr (BF16)
-                As[mm][kk] = to_bf16(v);
-            else
-                As[mm][kk] = v;
-        }
-#pragma unroll
-        for (int e = 0; e < (GBN * GBK) / 256; ++e) {
-            int idx = e * 256 + tid;
-            int nn, kk;
-            if (g.sbk == 1) {
-                nn = idx / GBK;
-                kk = idx % GBK;
-            } else {
-                kk = idx / GBN;
-                nn = idx % GBN;
-            }
-            int gn = n0 + nn, gk = k0 + kk;
-            float v = (gn < g.N && gk < ke) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0.0f;
-            if constexpr (BF16)
-                Bs[nn][kk] = to_bf16(v);
-            else
-                Bs[nn][kk] = v;
-        }
+        // A (64 x 32) as A(m, k); B (32 x 64) as its transpose B(n, k)
+        stage_tile<T, LDK, VA>(As, g.A, g.sam, g.sak, m0, g.M, k0, ke, tid);
+        stage_tile<T, LDK, VB>(Bs, g.B, g.sbn, g.sbk, n0, g.N, k0, ke, tid);
         __syncthreads();
         if constexpr (BF16) {
 #pragma unroll
@@ -154,6 +184,16 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
             }
 }
 
+// whether an operand with element (r, k) at P[r * sr + k * sk], r < R and
+// k < K, can be staged four elements at a time along its unit stride
+static bool vec_ok(const float *P, int64_t sr, int64_t sk, int R, int K)
+{
+    if ((uintptr_t)P % 16 != 0) return false;
+    if (sk == 1) return K % 4 == 0 && sr % 4 == 0;
+    if (sr == 1) return R % 4 == 0 && sk % 4 == 0;
+    return false;
+}
+
 // splits < 0: split the k range (a batch reduction, accumulated with
 // atomics) so that about 1,024 blocks run, each over at least 256 k
 int32_t gemm(bool bf16, GemmArgs g, hipStream_t st, int splits = 1)
@@ -171,10 +211,13 @@ int32_t gemm(bool bf16, GemmArgs g, hipStream_t st, int splits = 1)
     g.k_chunk = chunk;
     if (splits > 1) g.mode = 2;
     dim3 grid((unsigned)ceil_div(g.M, GBM), (unsigned)ceil_div(g.N, GBN), (unsigned)splits);
-    if (bf16)
-        gemm_kernel<true><<<grid, 256, 0, st>>>(g);
-    else
-        gemm_kernel<false><<<grid, 256, 0, st>>>(g);
+    const bool va = vec_ok(g.A, g.sam, g.sak, g.M, g.K);
+    const bool vb = vec_ok(g.B, g.sbn, g.sbk, g.N, g.K);
+    auto kern = bf16 ? (va ? (vb ? gemm_kernel<true, true, true> : gemm_kernel<true, true, false>)
+                           : (vb ? gemm_kernel<true, false, true> : gemm_kernel<true, false, false>))
+                     : (va ? (vb ? gemm_kernel<false, true, true> : gemm_kernel<false, true, false>)
+                           : (vb ? gemm_kernel<false, false, true> : gemm_kernel<false, false, false>));
+    kern<<<grid, 256, 0, st>>>(g);
     MR_LAUNCH_CHECK();
     return MR_OK;
 }
@@ -309,6 +352,70 @@ __global__ void __launch_bounds__(256) activate_backward_kernel(TrainDims td, in
         for (int64_t row = blockIdx.x; row < rows; row += gridDim.x)
             bsum += activate_backward_row(td, row, i, P, Abar, Pbar);
         if ((int64_t)blockIdx.x < rows) atomicAdd(db + i, bsum);
+    }
+}
+
+// The same for W % 4 == 0, W <= 1024 and at most 5 streams: a thread keeps
+// four units (float4 loads, all streams of a row issued together), 256 / (W / 4)
+// rows per pass; the block sums its rows' bias gradients in LDS and adds W
+// values.
+constexpr int ABV_MAXS = 5;
+__global__ void __launch_bounds__(256) activate_backward_vec_kernel(TrainDims td, int64_t rows,
+                                                                    const float *P,
+                                                                    const float *Abar, float *Pbar,
+                                                                    float *db)
+{
+    __shared__ float red[1024];
+    const int W = td.W, S = td.S, W4 = W / 4;
+    const int rpp = 256 / W4;
+    const int lane_row = (int)threadIdx.x / W4;
+    const int i = 4 * ((int)threadIdx.x % W4);
+    const bool active = lane_row < rpp;
+    float4 bsum = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (active) {
+        const int64_t stride = (int64_t)gridDim.x * rpp;
+        for (int64_t row = (int64_t)blockIdx.x * rpp + lane_row; row < rows; row += stride) {
+            const int64_t c0 = row * S;
+            float4 p[ABV_MAXS], ab[ABV_MAXS];
+#pragma unroll
+            for (int st = 0; st < ABV_MAXS; ++st)
+                if (st < S) {
+                    p[st] = *reinterpret_cast<const float4 *>(P + (c0 + st) * W + i);
+                    ab[st] = *reinterpret_cast<const float4 *>(Abar + (c0 + st) * W + i);
+                }
+            float pv[4] = {p[0].x, p[0].y, p[0].z, p[0].w};
+            float e[4], e2[4], pb[4];
+            const float a0[4] = {ab[0].x, ab[0].y, ab[0].z, ab[0].w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                e[q] = elu_d(pv[q]);
+                e2[q] = elu_dd(pv[q]);
+                pb[q] = e[q] * a0[q];
+            }
+#pragma unroll
+            for (int st = 1; st < ABV_MAXS; ++st)
+                if (st < S) {
+                    const float t[4] = {p[st].x, p[st].y, p[st].z, p[st].w};
+                    const float a[4] = {ab[st].x, ab[st].y, ab[st].z, ab[st].w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) pb[q] += e2[q] * t[q] * a[q];
+                    *reinterpret_cast<float4 *>(Pbar + (c0 + st) * W + i) =
+                        make_float4(e[0] * a[0], e[1] * a[1], e[2] * a[2], e[3] * a[3]);
+                }
+            *reinterpret_cast<float4 *>(Pbar + c0 * W + i) = make_float4(pb[0], pb[1], pb[2], pb[3]);
+            bsum.x += pb[0];
+            bsum.y += pb[1];
+            bsum.z += pb[2];
+            bsum.w += pb[3];
+        }
+        *reinterpret_cast<float4 *>(&red[lane_row * W + i]) = bsum;
+    }
+    __syncthreads();
+    // every block has at least one row (the grid is at most ceil(rows / rpp))
+    for (int u = threadIdx.x; u < W; u += blockDim.x) {
+        float sum = 0.0f;
+        for (int k = 0; k < rpp; ++k) sum += red[k * W + u];
+        atomicAdd(db + u, sum);
     }
 }
 
@@ -629,7 +736,12 @@ extern "C" int32_t rom_train_backward(mr_trainer *t, const float *dg, const floa
     ga.mode = 0;
     if ((rc = gemm(false, ga, st)) != MR_OK) return rc;
     for (int l = td.nh - 1; l >= 0; --l) {
-        {
+        if (td.W % 4 == 0 && td.W <= 1024 && td.S <= ABV_MAXS) {
+            const int64_t rpp = 256 / (td.W / 4);
+            const int64_t passes = ceil_div(rows, rpp);
+            activate_backward_vec_kernel<<<(unsigned)(passes < 1024 ? passes : 1024), 256, 0, st>>>(
+                td, rows, t->P[l], t->Abar, t->Pbar, dparams + t->ob[l]);
+        } else {
             const int64_t rpp = td.W <= 256 ? 256 / td.W : 1;
             const int64_t passes = ceil_div(rows, rpp);
             activate_backward_kernel<<<(unsigned)(passes < 1024 ? passes : 1024), 256, 0, st>>>(

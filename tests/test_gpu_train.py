@@ -40,7 +40,7 @@ def _batch(rng, d, r, n_groups, rpg, n_snap):
 
 @pytest.mark.parametrize("prec", [B.PREC_FP32, B.PREC_BF16])
 @pytest.mark.parametrize("d,r,width,nh", [(3, 3, 8, 2), (3, 16, 128, 5), (2, 4, 32, 3), (3, 5, 24, 2),
-                                         (2, 3, 300, 1)])
+                                         (2, 3, 300, 1), (3, 6, 30, 2)])
 def test_loss_and_gradients_match_oracle(gpu, prec, d, r, width, nh):
     rng = np.random.default_rng(width + r + prec)
     n_groups, rpg, n_snap = 3, 7, 5
