@@ -30,6 +30,16 @@ constexpr int NE_LD = NE_CH + 1;      // LDS row stride (doubles), off the bank 
 __host__ __device__ inline int ne_chunks(int64_t ns) { return (int)((ns + NE_CH - 1) / NE_CH); }
 __host__ __device__ inline int ne_entries(int r) { return r * r + r + 2; }
 
+// sum over one chunk of p[c] q[c] (ABS: |p[c]| q[c]), four partial sums
+template <bool ABS>
+__device__ __forceinline__ double chunk_dot(const double *p, const double *q)
+{
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < NE_CH; ++c) acc[c & 3] += (ABS ? fabs(p[c]) : p[c]) * q[c];
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
 // Partial sums of the normal equations over one chunk of NE_CH samples of
 // one instance (grid: chunks x B).  Entry e of the chunk's record:
 //   e < r^2        (J^T J)[k1][k2]       = sum_a,s J[a k1][s] J[a k2][s]
@@ -80,29 +90,23 @@ __global__ void __launch_bounds__(NE_THREADS) normal_eq_partial_kernel(
     __syncthreads();
     const int nent = ne_entries(r);
     double *pb = part + ((size_t)b * nch + ch) * nent;
+    // Rows are zero past len, so every sum runs over the whole chunk (a
+    // fixed trip count: the LDS loads of the loop are issued together).
     for (int e = threadIdx.x; e < nent; e += NE_THREADS) {
         double s = 0.0;
         if (e < r * r) {
             const int k1 = e / r, k2 = e % r;
-            for (int a = 0; a < d; ++a) {
-                const double *p1 = Js + (a * r + k1) * NE_LD;
-                const double *p2 = Js + (a * r + k2) * NE_LD;
-                for (int c = 0; c < len; ++c) s += p1[c] * p2[c];
-            }
+            for (int a = 0; a < d; ++a)
+                s += chunk_dot<false>(Js + (a * r + k1) * NE_LD, Js + (a * r + k2) * NE_LD);
         } else if (e < r * r + r) {
             const int k = e - r * r;
-            for (int a = 0; a < d; ++a) {
-                const double *p1 = Js + (a * r + k) * NE_LD;
-                const double *py = Ys + a * NE_LD;
-                for (int c = 0; c < len; ++c) s += p1[c] * py[c];
-            }
+            for (int a = 0; a < d; ++a) s += chunk_dot<false>(Js + (a * r + k) * NE_LD, Ys + a * NE_LD);
         } else if (MODE == 1 && e == r * r + r) {
-            for (int a = 0; a < d; ++a)
-                for (int c = 0; c < len; ++c) s += 0.5 * Ys[a * NE_LD + c] * Ys[a * NE_LD + c];
+            for (int a = 0; a < d; ++a) s += chunk_dot<false>(Ys + a * NE_LD, Ys + a * NE_LD);
+            s *= 0.5;
         } else if (MODE == 1) {
-            for (int a = 0; a < d; ++a)
-                for (int c = 0; c < len; ++c)
-                    s += fabs(Ys[a * NE_LD + c]) * Ms[a * NE_LD + c] * 0x1p-23;
+            for (int a = 0; a < d; ++a) s += chunk_dot<true>(Ys + a * NE_LD, Ms + a * NE_LD);
+            s *= 0x1p-23;
         }
         pb[e] = s;
     }
@@ -190,6 +194,7 @@ __global__ void __launch_bounds__(64) cholesky_solve_kernel(int B, int r, const 
 {
     __shared__ double Ls[32][33];
     __shared__ double dg[32];
+    __shared__ double inv[32];  // 1 / L[j][j]
     const int b = blockIdx.x;
     const int lane = threadIdx.x;
     if (b >= B) return;                                   // block-uniform
@@ -205,8 +210,14 @@ __global__ void __launch_bounds__(64) cholesky_solve_kernel(int B, int r, const 
         const bool act = lane >= j && lane < r;
         double s = 0.0;
         if (act) {
-            s = Ls[lane][j];
-            for (int k = 0; k < j; ++k) s -= Ls[lane][k] * Ls[j][k];
+            // L[lane][j] - sum_k L[lane][k] L[j][k], four partial sums
+            double p[4] = {0.0, 0.0, 0.0, 0.0};
+            int k = 0;
+            for (; k + 4 <= j; k += 4)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) p[q] += Ls[lane][k + q] * Ls[j][k + q];
+            for (; k < j; ++k) p[0] += Ls[lane][k] * Ls[j][k];
+            s = Ls[lane][j] - ((p[0] + p[1]) + (p[2] + p[3]));
         }
         const double piv = __shfl(s, j);
         if (!(piv > 1e-12 * dg[j]) || !(piv > 0.0)) {   // wave-uniform
@@ -214,7 +225,9 @@ __global__ void __launch_bounds__(64) cholesky_solve_kernel(int B, int r, const 
             break;
         }
         const double ljj = sqrt(piv);
-        if (act) Ls[lane][j] = lane == j ? ljj : s / ljj;
+        const double rl = 1.0 / ljj;
+        if (act) Ls[lane][j] = lane == j ? ljj : s * rl;
+        if (lane == j) inv[j] = rl;
         __syncthreads();
     }
     double* yb = y + (size_t)b * r;
@@ -229,12 +242,12 @@ __global__ void __launch_bounds__(64) cholesky_solve_kernel(int B, int r, const 
     // forward: L w = sign rhs ; backward: L^T y = w
     double yk = lane < r ? sign * rhs[(size_t)b * r + lane] : 0.0;
     for (int i = 0; i < r; ++i) {
-        const double wi = __shfl(yk, i) / Ls[i][i];
+        const double wi = __shfl(yk, i) * inv[i];
         if (lane == i) yk = wi;
         else if (lane > i && lane < r) yk -= Ls[lane][i] * wi;
     }
     for (int i = r - 1; i >= 0; --i) {
-        const double yi = __shfl(yk, i) / Ls[i][i];
+        const double yi = __shfl(yk, i) * inv[i];
         if (lane == i) yk = yi;
         else if (lane < i) yk -= Ls[i][lane] * yi;
     }
