@@ -464,6 +464,44 @@ __device__ __forceinline__ void opaque_payload(Stencil<D> &st, P2GPayload<D> &pl
 // MR_FLAG_DRIFT instead of scattering with atomics, and the region is stored
 // whole to the tile's staging area (summed per node in tile order by
 // det_combine_kernel) instead of being flushed with atomics.
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2: block b runs on XCD b % 8.  In 3D with one tile per workgroup the 8
+// tiles of a 2 x 2 x 2 brick run on one XCD, so the halo nodes they share
+// are fetched into, and flushed from, one L2; consecutive bricks go to
+// consecutive XCDs, which spreads the occupied tiles evenly.  Blocks b =
+// 64 j + 8 w + x take tile w of brick 8 j + x (a bijection onto the
+// bricks rounded up to a multiple of 8; tiles past the lattice get -1).
+constexpr int XCDS = 8;
+
+template <int D>
+inline unsigned tile_blocks(const TileGeom &tg)
+{
+    if (D == 3 && MR_TILE_WPB == 1) {
+        const int64_t nb = (int64_t)((tg.nt0 + 1) / 2) * ((tg.nt1 + 1) / 2) * ((tg.nt2 + 1) / 2);
+        return (unsigned)(64 * ceil_div(nb, (int64_t)XCDS));
+    }
+    return (unsigned)ceil_div(tg.ntiles, (int64_t)MR_TILE_WPB);
+}
+
+template <int D>
+__device__ __forceinline__ int64_t tile_of_block(const TileGeom &tg, int wave)
+{
+    if constexpr (D == 3 && MR_TILE_WPB == 1) {
+        const int64_t b = blockIdx.x;
+        const int64_t k = b / XCDS;
+        const int w = (int)(k & 7);
+        const int64_t brick = (k >> 3) * XCDS + (b % XCDS);
+        const int nb0 = (tg.nt0 + 1) / 2, nb1 = (tg.nt1 + 1) / 2;
+        const int t0 = 2 * (int)(brick % nb0) + (w & 1);
+        const int t1 = 2 * (int)((brick / nb0) % nb1) + ((w >> 1) & 1);
+        const int64_t t2 = 2 * (brick / ((int64_t)nb0 * nb1)) + (w >> 2);
+        if (t0 >= tg.nt0 || t1 >= tg.nt1 || t2 >= tg.nt2) return -1;
+        return t0 + (int64_t)tg.nt0 * (t1 + (int64_t)tg.nt1 * t2);
+    } else {
+        return (int64_t)blockIdx.x * MR_TILE_WPB + wave;
+    }
+}
+
 template <int D, bool FUSED, bool DET = false>
 __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scatter_kernel(
     GridK g, TileGeom tg, float *x, float *v, float *C, float *F, const float *m, const float *V0,
@@ -485,8 +523,8 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
     int *owner = owner_all[wave];
     int32_t *deferred = defer_all[wave];
     int ndef = 0;                                   // wave-uniform
-    const int64_t t = (int64_t)blockIdx.x * CT::WPB + wave;
-    if (t >= tg.ntiles) return;                    // wave-uniform; no block barriers below
+    const int64_t t = tile_of_block<D>(tg, wave);
+    if (t < 0 || t >= tg.ntiles) return;           // wave-uniform; no block barriers below
     const int64_t c0 = offsets[t * Tiling<D>::CELLS];
     const int64_t c1 = offsets[(t + 1) * Tiling<D>::CELLS];
     if (c0 == c1) return;
@@ -1039,7 +1077,7 @@ int32_t p2g_impl(const GridK &g, const mr_material *mat, const mr_particles *par
         sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
         TileGeom tg = tile_geom<D>(g);
         if (tg.ntiles > 0)
-            tile_scatter_kernel<D, false, true><<<(unsigned)ceil_div(tg.ntiles, CellTile<D>::WPB), 64 * CellTile<D>::WPB, 0, st>>>(
+            tile_scatter_kernel<D, false, true><<<tile_blocks<D>(tg), 64 * CellTile<D>::WPB, 0, st>>>(
                 g, tg, parts->x, parts->v, parts->C, parts->F, parts->m, parts->V0, parts->m_uniform,
                 parts->V0_uniform, parts->n, ws.offsets, ws.counts, apic, mat->model, lm.mu, lm.la, dt,
                 nullptr, grid, nullptr, nullptr, flag, ws.stage);
@@ -1055,7 +1093,7 @@ int32_t p2g_impl(const GridK &g, const mr_material *mat, const mr_particles *par
         sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
         TileGeom tg = tile_geom<D>(g);
         if (tg.ntiles > 0)
-            tile_scatter_kernel<D, false><<<(unsigned)ceil_div(tg.ntiles, CellTile<D>::WPB), 64 * CellTile<D>::WPB, 0, st>>>(
+            tile_scatter_kernel<D, false><<<tile_blocks<D>(tg), 64 * CellTile<D>::WPB, 0, st>>>(
                 g, tg, parts->x, parts->v, parts->C, parts->F, parts->m, parts->V0, parts->m_uniform,
                 parts->V0_uniform, parts->n, ws.offsets, ws.counts, apic, mat->model, lm.mu, lm.la, dt,
                 nullptr, grid, nullptr, nullptr, flag);
@@ -1245,7 +1283,7 @@ int32_t g2p2g_impl(const GridK &g, const mr_material *mat, mr_particles *parts, 
     sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
     TileGeom tg = tile_geom<D>(g);
     if (tg.ntiles > 0 && parts->n > 0)
-        tile_scatter_kernel<D, true><<<(unsigned)ceil_div(tg.ntiles, CellTile<D>::WPB), 64 * CellTile<D>::WPB, 0, st>>>(
+        tile_scatter_kernel<D, true><<<tile_blocks<D>(tg), 64 * CellTile<D>::WPB, 0, st>>>(
             g, tg, parts->x, parts->v, parts->C, parts->F, parts->m, parts->V0, parts->m_uniform,
             parts->V0_uniform, parts->n, ws.offsets, ws.counts, apic, mat->model, lm.mu, lm.la, dt,
             grid_in, grid_out, v_out, C_out, flag);
