@@ -431,12 +431,13 @@ typedef struct {
  * newton_iters iterations from X = x: a displacement step X = x - u(x)
  * (Jacobian replaced by I), then Newton steps with F = dg/dX, and
  * a point is kept when the residual is within newton_tol cells, det F > 0
- * and the reference density at X is positive; its mass is that density
- * times (dx / l)^d / det F.  The reference density is the reference
- * particles' mass spread with the quadratic B-spline on a lattice of
- * spacing dx / l, read by multilinear interpolation (rho0 inside a body
- * sampled at that spacing, tapering to 0 over one spacing at its surface);
- * rom_create builds it on the host. */
+ * and X lies in the reference body; its mass is rho0 (dx / l)^d / det F
+ * (Algorithm 4) times a body weight clamp(2 s - 1/2, 0, 1), with
+ * s = rho_ref(X) / rho0: exactly rho0 V / J wherever s >= 3/4 (a body's
+ * interior), a linear taper across the surface band, and the point dropped
+ * where s <= 1/4.  rho_ref is the reference particles' mass spread with the
+ * quadratic B-spline on the grid's node lattice (spacing dx) and read by
+ * multilinear interpolation; rom_create builds it on the host. */
 #define MR_QUAD_LAGRANGIAN 0
 #define MR_QUAD_EULERIAN 1
 

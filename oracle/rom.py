@@ -27,13 +27,17 @@ Readings:
     fixed total number of iterations; a point is kept when the final
     residual max-norm is within a tolerance, det F > 0 at the result and X
     lies in the reference body.
-  - The reference body and its density come from the reference particles:
-    rho_ref is their mass spread with the quadratic B-spline on a lattice of
-    spacing h = dx / ell (nodes k h), read at X by multilinear
-    interpolation.  It equals rho0 inside a body sampled at spacing h
-    (partition of unity), tapers over about h at the surface and is 0
-    outside; m^Q = rho_ref(X) (dx / ell)^d / J (rho0 V / J in the interior)
-    and V0 = m^Q / rho0; a point with rho_ref(X) = 0 is discarded.
+  - Mass (Algorithm 4, last step): m^Q = rho0 V^Q / J with V^Q = (dx / ell)^d
+    and J = det F, for every point inside the reference body.  The paper does
+    not say how a point is found to be in the body; reading used here: the
+    reference particles' mass spread with the quadratic B-spline on the
+    grid's node lattice (spacing dx), read at X by multilinear interpolation,
+    gives a smoothed density rho_ref; with s = rho_ref(X) / rho0 the point
+    carries the weight tau(s) = clamp(2 s - 1/2, 0, 1): 1 (mass exactly
+    rho0 V^Q / J) wherever s >= 3/4, i.e. everywhere inside a body sampled
+    at its nominal density, a linear taper across the surface band (where
+    rho_ref falls from rho0 to 0 over about a cell, centred on the half
+    level s = 1/2), and 0 (point discarded) where s <= 1/4.  V0 = m^Q / rho0.
     Sample points are not quadrature points.
 """
 import numpy as np
@@ -131,18 +135,19 @@ def active_nodes(dim, n, dx, x_samples):
     return np.unique(np.concatenate(nodes)) if len(base) else np.zeros(0, dtype=np.int64)
 
 
-def density_lattice_shape(n, ell):
-    """Nodes per axis of the reference-density lattice (spacing dx / ell)."""
-    return [(na - 1) * ell + 1 for na in n]
+def density_lattice_shape(n):
+    """Nodes per axis of the reference-density lattice (the grid's nodes)."""
+    return list(n)
 
 
-def reference_density(dim, n, dx, ell, X_all, m_all):
-    """rho_ref on the lattice of spacing h = dx / ell: sum over reference
-    particles of m_p N((X_k - X_p) / h) / h^d with the tensor quadratic
-    B-spline N (stencil base floor(X / h - 1/2)); particles whose stencil
-    leaves the lattice are skipped.  Returns a flat array (x fastest)."""
-    h = dx / ell
-    shape = density_lattice_shape(n, ell)
+def reference_density(dim, n, dx, X_all, m_all):
+    """rho_ref on the grid's node lattice (spacing h = dx): sum over
+    reference particles of m_p N((X_k - X_p) / h) / h^d with the tensor
+    quadratic B-spline N (stencil base floor(X / h - 1/2)); particles whose
+    stencil leaves the lattice are skipped.  Returns a flat array (x
+    fastest)."""
+    h = dx
+    shape = density_lattice_shape(n)
     rho = np.zeros(int(np.prod(shape)))
     X = np.asarray(X_all, dtype=np.float64)
     m = np.broadcast_to(np.asarray(m_all, dtype=np.float64), (X.shape[0],))
@@ -162,11 +167,11 @@ def reference_density(dim, n, dx, ell, X_all, m_all):
     return rho
 
 
-def density_at(rho, dim, n, dx, ell, X):
-    """Multilinear interpolation of the lattice density at points X (0
+def density_at(rho, dim, n, dx, X):
+    """Multilinear interpolation of the node-lattice density at points X (0
     outside the lattice)."""
-    h = dx / ell
-    shape = np.asarray(density_lattice_shape(n, ell))
+    h = dx
+    shape = np.asarray(density_lattice_shape(n))
     t = np.asarray(X, dtype=np.float64) / h
     i0 = np.floor(t).astype(np.int64)
     fr = t - i0
@@ -222,12 +227,20 @@ def invert_map(jac_fn, x_target, iters):
     return X
 
 
+def body_weight(s):
+    """Weight of a quadrature point whose reference position has smoothed
+    relative density s = rho_ref / rho0: 1 for s >= 3/4, 0 for s <= 1/4,
+    linear in between (the surface band)."""
+    return np.clip(2.0 * np.asarray(s, dtype=np.float64) - 0.5, 0.0, 1.0)
+
+
 def eulerian_quadrature(dec, dim, n, dx, x_samples, zhat, vhat, ell, iters, tol, rho0,
                         rho_ref):
     """Algorithm 4: quadrature points, their reference positions (inverse
-    map), F, v and masses (rho_ref: reference_density on the lattice of
-    spacing dx / ell).  Returns a dict with the kept points' xQ, FQ, vQ, mQ,
-    V0Q, their reference positions XQ, and I and the candidate count."""
+    map), F, v and masses m^Q = tau rho0 V^Q / J (rho_ref: reference_density
+    on the node lattice, tau = body_weight(rho_ref / rho0)).  Returns a dict
+    with the kept points' xQ, FQ, vQ, mQ, V0Q, their reference positions XQ,
+    and I and the candidate count."""
     I = active_nodes(dim, n, dx, x_samples)
     xq = eulerian_points(dim, n, dx, ell, I)
     jac = lambda X: _dec.decode_jac(dec, X, zhat)[:2]
@@ -235,13 +248,14 @@ def eulerian_quadrature(dec, dim, n, dx, x_samples, zhat, vhat, ell, iters, tol,
     x, F, _, v = _dec.decode_jac(dec, X, zhat, vhat)
     det = np.linalg.det(F) if len(F) else np.zeros(0)
     conv = np.max(np.abs(x - xq), axis=1) <= tol if len(x) else np.zeros(0, dtype=bool)
-    rho = density_at(rho_ref, dim, n, dx, ell, X)
-    keep = conv & (det > 0.0) & (rho > 0.0)
+    rho = density_at(rho_ref, dim, n, dx, X)
+    tau = body_weight(rho / rho0)
+    keep = conv & (det > 0.0) & (tau > 0.0)
     Vq = (dx / ell) ** dim
-    m = rho[keep] * Vq / det[keep]
+    m = tau[keep] * rho0 * Vq / det[keep]
     return {"xQ": xq[keep], "XQ": X[keep], "FQ": F[keep], "vQ": v[keep], "mQ": m,
             "V0Q": m / rho0, "I": I, "n_candidates": len(xq), "keep": keep,
-            "X_all": X, "x_candidates": xq, "rho": rho}
+            "X_all": X, "x_candidates": xq, "rho": rho, "tau": tau}
 
 
 def rom_step(dec, scene, X_all, m_all, V0_all, zhat, zhat_prev, vhat, dt,

@@ -27,13 +27,16 @@
 // per-instance list); expand every base into its l^d lattice points; invert
 // the decoder at them (a displacement step X = x - u(x) from a positions
 // decode, then Newton steps: decoder launches with the spatial tangents and
-// a per-point d x d solve); decode x, F, v at the result and
-// keep a point when the residual is small, det F > 0 and the reference
-// density at its reference position is positive; its mass is that density
-// times (dx / l)^d / det F.  The reference density is the particles' mass
-// spread with the quadratic B-spline on a lattice of spacing dx / l (rho0
-// inside a body sampled at that spacing, tapering over one spacing at the
-// surface), built once at creation.
+// a per-point d x d solve); decode x, F, v at the result and keep a
+// point when the residual is small, det F > 0 and its reference position
+// lies in the body; its mass is rho0 (dx / l)^d / det F (Algorithm 4),
+// times a body weight that is 1 inside the body and falls linearly to 0
+// across the surface band.  The body test reads a smoothed reference
+// density rho_ref, the particles' mass spread with the quadratic B-spline on
+// the grid's node lattice (built once at creation): with s = rho_ref / rho0
+// the weight is clamp(2 s - 1/2, 0, 1), so every point with s >= 3/4 (all
+// of a body's interior at its nominal sampling density) carries exactly
+// rho0 V / J and points with s <= 1/4 are dropped.
 #include "mpm_kernels.h"
 #include "project.h"
 
@@ -85,8 +88,8 @@ struct mr_rom {
     int32_t *qb_count;     // [B]
     float *XQ;             // [B][d][q_cap] reference positions (Newton iterate)
     float *mQ;             // [B][q_cap] point masses (0: discarded)
-    float *rho;            // reference density on the lattice of spacing dx / l
-    int rn[3];             // its nodes per axis
+    float *rho;            // smoothed reference density on the grid's node lattice
+    int rn[3];             // its nodes per axis (the grid's)
 };
 
 namespace mr {
@@ -530,7 +533,8 @@ template <int D>
 __global__ void eul_finish_kernel(GridK g, int64_t q_cap, const int32_t *q_count,
                                   const int32_t *qbase, int64_t qb_cap, int L, int LD,
                                   const float *XQ, float *xQ, const float *FQ, const float *rho,
-                                  int rn0, int rn1, int rn2, float vq, float tol, float *mQ)
+                                  int rn0, int rn1, int rn2, float rho0_vq, float inv_rho0,
+                                  float tol, float *mQ)
 {
     const int b = blockIdx.y;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -547,9 +551,9 @@ __global__ void eul_finish_kernel(GridK g, int64_t q_cap, const int32_t *q_count
 #pragma unroll
     for (int k = 0; k < D * D; ++k) F[k] = FQ[((int64_t)b * D * D + k) * q_cap + s];
     const float J = det_small<D>(F);
-    // multilinear reading of the reference density at X (0 off the lattice)
+    // multilinear reading of the smoothed density at X (0 off the lattice)
     const int rn[3] = {rn0, rn1, rn2};
-    const float inv_h = g.inv_dx * (float)L;
+    const float inv_h = g.inv_dx;
     int i0[3] = {0, 0, 0};
     float fr[3] = {0.0f, 0.0f, 0.0f};
     bool on = true;
@@ -577,8 +581,9 @@ __global__ void eul_finish_kernel(GridK g, int64_t q_cap, const int32_t *q_count
             dens += w * rho[idx];
         }
     }
-    const bool keep = res <= tol && J > 0.0f && dens > 0.0f;
-    mQ[(int64_t)b * q_cap + s] = keep ? dens * vq / J : 0.0f;
+    const float wbody = fminf(fmaxf(2.0f * dens * inv_rho0 - 0.5f, 0.0f), 1.0f);
+    const bool keep = res <= tol && J > 0.0f && wbody > 0.0f;
+    mQ[(int64_t)b * q_cap + s] = keep ? wbody * rho0_vq / J : 0.0f;
 }
 
 __global__ void fill_u32_kernel(uint32_t *a, int64_t n)
@@ -676,16 +681,19 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
         rc = decode_jac_ex(R->dec, B, R->q_cap, R->XQ, R->q_cap, nullptr, 0, R->q_count, xhat,
                            vhat, R->xQ, R->FQ, R->vQ, nullptr, st, 0, xstr);
         if (rc != MR_OK) return rc;
-        const float vq = d == 3 ? (g.dx / L) * (g.dx / L) * (g.dx / L) : (g.dx / L) * (g.dx / L);
+        const double hq = (double)g.dx / L;
+        const float rho0_vq = (float)(R->cfg.rho0 * (d == 3 ? hq * hq * hq : hq * hq));
         const float tol = R->newton_tol * g.dx;
         if (d == 2)
             eul_finish_kernel<2><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap, L,
                                                     LD, R->XQ, R->xQ, R->FQ, R->rho, R->rn[0],
-                                                    R->rn[1], R->rn[2], vq, tol, R->mQ);
+                                                    R->rn[1], R->rn[2], rho0_vq, inv_rho0, tol,
+                                                    R->mQ);
         else
             eul_finish_kernel<3><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap, L,
                                                     LD, R->XQ, R->xQ, R->FQ, R->rho, R->rn[0],
-                                                    R->rn[1], R->rn[2], vq, tol, R->mQ);
+                                                    R->rn[1], R->rn[2], rho0_vq, inv_rho0, tol,
+                                                    R->mQ);
         MR_LAUNCH_CHECK();
     } else {
     // Algorithm 3: decode every particle, mark I, collect Q
@@ -865,9 +873,9 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
         alloc((void **)&R->qb_count, 4 * B);
         alloc((void **)&R->XQ, 4 * B * d * R->q_cap);
         alloc((void **)&R->mQ, 4 * B * R->q_cap);
-        R->rn[0] = (g.n0 - 1) * ell + 1;
-        R->rn[1] = (g.n1 - 1) * ell + 1;
-        R->rn[2] = d == 3 ? (g.n2 - 1) * ell + 1 : 1;
+        R->rn[0] = g.n0;
+        R->rn[1] = g.n1;
+        R->rn[2] = d == 3 ? g.n2 : 1;
         alloc((void **)&R->rho, 4 * (int64_t)R->rn[0] * R->rn[1] * R->rn[2]);
     }
     alloc((void **)&R->bitmap, 4 * B * R->words);
@@ -923,10 +931,10 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
              hipMemcpy(R->internal_of, inv.data(), 4 * P, hipMemcpyHostToDevice) == hipSuccess &&
              (!m_all || hipMemcpy(R->m, ms.data(), 4 * P, hipMemcpyHostToDevice) == hipSuccess);
         if (cp && eul) {
-            // reference density: every particle's mass spread with the
-            // quadratic B-spline over the 3^d lattice nodes of its stencil
-            // (spacing h = dx / l), divided by h^d
-            const double h = (double)g.dx / ell;
+            // smoothed reference density: every particle's mass spread
+            // with the quadratic B-spline over the 3^d grid nodes of its
+            // stencil, divided by dx^d
+            const double h = (double)g.dx;
             const int64_t nl = (int64_t)R->rn[0] * R->rn[1] * R->rn[2];
             std::vector<double> rho(nl, 0.0);
             const double inv_hd = d == 3 ? 1.0 / (h * h * h) : 1.0 / (h * h);

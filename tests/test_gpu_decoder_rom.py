@@ -328,7 +328,7 @@ def eulerian_oracle_run(s, odec, Es, nss, z0, v0, nst, seed, ell=2, iters=4):
     P = s["P"]
     Xd = s["X"].astype(np.float32).astype(np.float64)
     n, dx = sc["n"], sc["dx"]
-    rho = OR.reference_density(3, n, dx, ell, Xd, float(np.float32(s["m"])))
+    rho = OR.reference_density(3, n, dx, Xd, float(np.float32(s["m"])))
     out = []
     for b in range(len(Es)):
         sc_b = dict(sc)
@@ -348,9 +348,9 @@ def eulerian_oracle_run(s, odec, Es, nss, z0, v0, nst, seed, ell=2, iters=4):
 def test_rom_step_eulerian_matches_oracle(gpu):
     """Random fp32 decoder, 3D scene on a 32^3 grid, two instances, 3 steps
     with Eulerian quadrature (l = 2, 4 Newton iterations) against the
-    oracle.  The point masses follow the reference density continuously, so
-    rounding differences in the reference positions change them by rounding
-    amounts only."""
+    oracle.  The point masses (rho0 V / J times the body weight, which is
+    continuous in the reference position) move by rounding amounts only when
+    rounding moves the reference positions."""
     s = _rom_inputs(seed=6)
     d, r = 3, 8
     X = s["X"]

@@ -126,53 +126,60 @@ def _box_particles(dim, n, lo, hi, ppc=2):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-def test_reference_density_partition_of_unity_and_mass(dim):
-    """Particles on the lattice of spacing h = dx / ell with m = rho0 h^d:
-    rho_ref = rho0 at every node whose whole stencil neighbourhood is inside
-    the sampled box (B-spline partition of unity), 0 two spacings outside,
-    and the lattice holds the particles' total mass."""
-    n, ell, rho0 = 16, 2, 1000.0
+@pytest.mark.parametrize("ppc", [1, 2])
+def test_reference_density_partition_of_unity_and_mass(dim, ppc):
+    """Particles on a regular lattice of spacing dx / ppc with m = rho0
+    (dx / ppc)^d: rho_ref = rho0 at every node whose whole stencil
+    neighbourhood is inside the sampled box (the quadratic B-spline's
+    integer shifts sum to 1, so its shifts by 1/ppc sum to ppc per axis), 0
+    two spacings outside, and the lattice holds the particles' total mass."""
+    n, rho0 = 16, 1000.0
     dx = 1 / n
-    h = dx / ell
-    X_all = _box_particles(dim, n, 0.25, 0.75, ppc=ell)
+    X_all = _box_particles(dim, n, 0.25, 0.75, ppc=ppc)
     X_all = X_all[X_all[:, 0] < 0.625]          # asymmetric: the box is [0.25, 0.625) in x
-    m = rho0 * h ** dim
-    rho = rom.reference_density(dim, [n] * dim, dx, ell, X_all, m)
-    shape = rom.density_lattice_shape([n] * dim, ell)
-    nodes = _lattice_nodes(shape, h)
+    m = rho0 * (dx / ppc) ** dim
+    rho = rom.reference_density(dim, [n] * dim, dx, X_all, m)
+    shape = rom.density_lattice_shape([n] * dim)
+    nodes = _lattice_nodes(shape, dx)
     hi = np.array([0.625, 0.75, 0.75][:dim])
-    inner = np.all((nodes >= 0.25 + h) & (nodes <= hi - h), axis=1)
-    outer = np.any((nodes <= 0.25 - 2 * h) | (nodes >= hi + 2 * h), axis=1)
+    inner = np.all((nodes >= 0.25 + 1.5 * dx) & (nodes <= hi - 1.5 * dx), axis=1)
+    outer = np.any((nodes <= 0.25 - 2 * dx) | (nodes >= hi + 2 * dx), axis=1)
     np.testing.assert_allclose(rho[inner], rho0, rtol=1e-12)
     assert np.all(rho[outer] == 0.0)
-    np.testing.assert_allclose(rho.sum() * h ** dim, m * len(X_all), rtol=1e-12)
+    np.testing.assert_allclose(rho.sum() * dx ** dim, m * len(X_all), rtol=1e-12)
     # multilinear reading: exact at nodes, rho0 between inner nodes
-    np.testing.assert_allclose(rom.density_at(rho, dim, [n] * dim, dx, ell, nodes[inner]),
+    np.testing.assert_allclose(rom.density_at(rho, dim, [n] * dim, dx, nodes[inner]),
                                rho0, rtol=1e-12)
 
 
 def test_density_reading_is_exact_for_linear_fields():
-    dim, n, ell = 3, 8, 2
+    dim, n = 3, 8
     dx = 1 / n
-    shape = rom.density_lattice_shape([n] * dim, ell)
-    nodes = _lattice_nodes(shape, dx / ell)
+    shape = rom.density_lattice_shape([n] * dim)
+    nodes = _lattice_nodes(shape, dx)
     coef = np.array([1.0, -2.0, 0.5])
     rho = 3.0 + nodes @ coef
     X = np.random.default_rng(8).uniform(0.1, 0.8, size=(50, dim))
-    np.testing.assert_allclose(rom.density_at(rho, dim, [n] * dim, dx, ell, X), 3.0 + X @ coef,
+    np.testing.assert_allclose(rom.density_at(rho, dim, [n] * dim, dx, X), 3.0 + X @ coef,
                                rtol=1e-12)
+
+
+def test_body_weight_ramp():
+    """tau(s): 0 up to s = 1/4, 1 from s = 3/4, linear in between, 1/2 at the
+    half level."""
+    s = np.array([0.0, 0.25, 0.375, 0.5, 0.625, 0.75, 0.9, 1.7])
+    np.testing.assert_allclose(rom.body_weight(s), [0, 0, 0.25, 0.5, 0.75, 1, 1, 1], atol=1e-15)
 
 
 @pytest.mark.parametrize("dim", [2, 3])
 def test_translation_positions_and_masses(dim):
-    """g = X + t: X^Q = x^Q - t exactly, J = 1; the mass is rho_ref(X^Q)
-    (dx / ell)^d: rho0 (dx / ell)^d well inside the box, zero (point
-    dropped) well outside it."""
+    """g = X + t: X^Q = x^Q - t exactly, J = 1; the mass is rho0 (dx / ell)^d
+    well inside the box and zero (point dropped) well outside it."""
     n, ell, rho0 = 16, 2, 1000.0
     dx = 1 / n
     h = dx / ell
     X_all = _box_particles(dim, n, 0.25, 0.75)
-    rho = rom.reference_density(dim, [n] * dim, dx, ell, X_all, rho0 * h ** dim)
+    rho = rom.reference_density(dim, [n] * dim, dx, X_all, rho0 * h ** dim)
     t = np.array([2 * dx, -1 * dx, dx][:dim])
     dec = translation_decoder(dim)
     xs = np.array([[0.7, 0.45, 0.5][:dim], [0.3, 0.6, 0.4][:dim]])
@@ -182,12 +189,72 @@ def test_translation_positions_and_masses(dim):
     np.testing.assert_allclose(eq["X_all"], Xc, atol=1e-15)
     np.testing.assert_allclose(np.linalg.det(eq["FQ"]), 1.0, atol=1e-15)
     inner = np.all((Xc >= 0.25 + 2 * h) & (Xc <= 0.75 - 2 * h), axis=1)
-    outer = np.any((Xc <= 0.25 - 2 * h) | (Xc >= 0.75 + 2 * h), axis=1)
+    outer = np.any((Xc <= 0.25 - 2 * dx) | (Xc >= 0.75 + 2 * dx), axis=1)
     assert inner.any() and outer.any()
-    np.testing.assert_allclose(eq["rho"][inner], rho0, rtol=1e-12)
     assert np.all(eq["keep"][inner]) and not np.any(eq["keep"][outer])
     kept_inner = inner[eq["keep"]]
-    np.testing.assert_allclose(eq["mQ"][kept_inner], rho0 * h ** dim, rtol=1e-12)
+    np.testing.assert_allclose(eq["mQ"][kept_inner], rho0 * h ** dim, rtol=1e-15)
+
+
+def _jittered_cube(n, cells, lo, seed, sub=2):
+    """A cube of cells^3 grid cells with sub^3 particles per cell, each
+    uniform in its sub-cell (the benchmark scenes' sampling)."""
+    dx = 1 / n
+    rng = np.random.default_rng(seed)
+    idx = np.indices((cells * sub,) * 3).reshape(3, -1).T.astype(np.float64)
+    return np.asarray(lo) + (idx + rng.random(idx.shape)) * (dx / sub)
+
+
+@pytest.mark.parametrize("kind", ["translation", "stretch"])
+def test_jittered_body_interior_masses_are_rho0_V_over_J(kind):
+    """Algorithm 4's mass m^Q = rho0 V^Q / J on a jittered body: every
+    lattice point whose reference position lies at least 1.5 dx inside the
+    cube carries exactly rho0 V^Q / J (the particles' scatter in the
+    smoothed density does not enter), points 2 dx outside are dropped, and
+    the kept mass equals the cube's mass up to its rounded edges and
+    corners.  Maps: a translation g = X + t (J = 1) and a uniform stretch
+    g = c + (1 + e)(X - c) (J = (1 + e)^3)."""
+    n, ell, rho0, cells = 32, 2, 1000.0, 8
+    dx = 1 / n
+    lo = np.array([0.5 - 4 * dx, 0.3, 0.5 - 4 * dx])
+    X_all = _jittered_cube(n, cells, lo, seed=11)
+    mp = rho0 * (dx / 2) ** 3
+    rho = rom.reference_density(3, [n] * 3, dx, X_all, mp)
+    d, r = 3, 3
+    if kind == "translation":
+        t = np.array([0.6, -1.3, 0.2]) * dx
+        W = np.concatenate([np.zeros((d, d)), np.eye(d)], axis=1)
+        dec = D.Decoder([W], [np.zeros(d)], np.zeros(d), np.ones(d), np.zeros(d), np.ones(d))
+        z, J, inv = t, 1.0, (lambda x: x - t)
+    else:
+        # normalised input 2X - 1 (in_min 0, in_max 1): g = X + (e/2)(2X - 1) + b
+        e = 0.04
+        c = lo + 4 * dx
+        W = np.concatenate([0.5 * e * np.eye(d), np.zeros((d, r))], axis=1)
+        b = 0.5 * e * np.ones(d) - e * c
+        dec = D.Decoder([W], [b], np.zeros(d), np.ones(d), np.zeros(d), np.ones(d))
+        z, J, inv = np.zeros(r), (1 + e) ** 3, (lambda x: c + (x - c) / (1 + e))
+    xs = D.decode(dec, X_all, z)
+    eq = rom.eulerian_quadrature(dec, 3, [n] * 3, dx, xs, z, np.zeros(r), ell, 3, 1e-3 * dx,
+                                 rho0, rho)
+    Xc = inv(eq["x_candidates"])
+    np.testing.assert_allclose(eq["X_all"], Xc, atol=1e-13)
+    inner = np.all((Xc >= lo + 1.5 * dx) & (Xc <= lo + cells * dx - 1.5 * dx), axis=1)
+    outer = np.any((Xc <= lo - 2 * dx) | (Xc >= lo + cells * dx + 2 * dx), axis=1)
+    assert inner.sum() > 500 and outer.any()
+    Vq = (dx / ell) ** 3
+    assert np.all(eq["keep"][inner]) and not np.any(eq["keep"][outer])
+    kept_inner = inner[eq["keep"]]
+    np.testing.assert_allclose(eq["mQ"][kept_inner], rho0 * Vq / J, rtol=1e-12)
+    # the smoothed density itself scatters well away from rho0 here, and
+    # only the weight is cut off by it
+    s_in = eq["rho"][inner] / rho0
+    assert s_in.min() >= 0.75 and s_in.std() > 0.01
+    # total kept mass (in the reference measure: m J = tau rho0 V^Q) within
+    # the rounding of the cube's 12 edges and 8 corners
+    body = rho0 * (cells * dx) ** 3
+    kept = float(np.sum(eq["mQ"] * np.linalg.det(eq["FQ"])))
+    assert abs(kept - body) / body < 0.1, kept / body
 
 
 @pytest.mark.parametrize("mode", [PR.MODE_POS_VEL, PR.MODE_VEL_ONLY])
@@ -200,7 +267,7 @@ def test_translation_manifold_eulerian_rom_equals_symplectic_euler(mode, dim):
     dx = 1 / n
     X_all = _box_particles(dim, n, 0.25, 0.75)
     P = len(X_all)
-    rho = rom.reference_density(dim, [n] * dim, dx, 2, X_all, 1000.0 * (dx / 2) ** dim)
+    rho = rom.reference_density(dim, [n] * dim, dx, X_all, 1000.0 * (dx / 2) ** dim)
     dec = translation_decoder(dim)
     mu, la = mpm.lame(1e4, 0.3)
     grav = [0.0] * dim

@@ -2,6 +2,8 @@
 neighbour sets against brute force, the translation-manifold ROM against
 the symplectic-Euler closed form, the Algorithm 5 / Algorithm 1 limit, the
 least-squares initial latents and the error metrics."""
+import os
+
 import numpy as np
 import pytest
 
@@ -10,6 +12,31 @@ from oracle import mpm
 from oracle import project as PR
 from oracle import rom
 from oracle import sampler
+
+
+def _golden_splitmix64():
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64.txt")
+    rows = []
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            vals = [int(t) for t in line.split()]
+            rows.append((vals[0], vals[1:]))
+    return rows
+
+
+def test_mix_reproduces_published_splitmix64_outputs():
+    """SplitMix64 run as a generator (state advanced by the golden gamma
+    before each output) must give the published sequences; mix(c) is the
+    output for state c, i.e. the k-th output from seed s is
+    mix(s + (k - 1) gamma)."""
+    rows = _golden_splitmix64()
+    assert len(rows) == 2
+    for seed, outs in rows:
+        state = seed
+        for want in outs:
+            assert sampler.mix(state) == want
+            state = (state + sampler.GOLDEN) & sampler.MASK
 
 
 def test_mix_is_injective_on_a_range_and_well_spread():
