@@ -382,17 +382,27 @@ typedef struct {
  * v_trial_p; with an MR_OUT_DISPLACEMENT decoder the position residual is
  * then formed from displacements g - X, which keeps fp32 cancellation in
  * the residual at the size of the motion, not of the coordinates.
- * The call keeps one library-owned device workspace, grown (after a stream
- * synchronisation) when a call needs more: calls that overlap in time, from
- * several host threads or on several streams, race on it and must be
- * serialised by the caller. */
+ * workspace: caller-owned device memory of at least
+ * rom_project_workspace_bytes(dec, B, ns, opts) bytes, 256-byte aligned
+ * (its contents need not be initialised and are dead after the call; it
+ * must not be shared by calls that overlap in time).  The call only enqueues
+ * kernels on `stream` (no allocation, no synchronisation), so it can be
+ * captured in a graph.  MR_EINVAL for a missing, short or misaligned
+ * workspace. */
 int32_t rom_project(const mr_decoder *dec, int32_t B, int64_t n_ref,
                     const float *X, int64_t ns, const int32_t *sample_idx,
                     const int32_t *ns_per_instance, const float *x_trial,
                     const float *v_trial, const double *xhat_n,
                     const double *xhat_prev, double dt, const mr_gn_opts *opts,
                     double *xhat_next, double *vhat_next, int32_t *iters_out,
-                    double *resid_out, int32_t *status_out, void *stream);
+                    double *resid_out, int32_t *status_out, void *workspace,
+                    size_t ws_bytes, void *stream);
+
+/* Bytes of device workspace rom_project needs for B instances of ns
+ * samples with these options (the decoder fixes d and r); MR_EINVAL
+ * (negative) for a null decoder or options, B < 1 or ns < 1. */
+int64_t rom_project_workspace_bytes(const mr_decoder *dec, int32_t B, int64_t ns,
+                                    const mr_gn_opts *opts);
 
 /* ---- reduced-order step (Section 3.2, Algorithm 2 with Algorithms 3, 5 and
  * 6 or 7) ----------------------------------------------------------------- */

@@ -113,7 +113,9 @@ SIGNATURES = {
     "rom_decode_jac": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                               _vp, _vp]),
     "rom_project": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _f64,
-                           ctypes.POINTER(MrGnOpts), _vp, _vp, _vp, _vp, _vp, _vp]),
+                           ctypes.POINTER(MrGnOpts), _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                           _vp]),
+    "rom_project_workspace_bytes": (_i64, [_vp, _i32, _i64, ctypes.POINTER(MrGnOpts)]),
     "rom_create": (_i32, [_vp, ctypes.POINTER(MrGrid), ctypes.POINTER(MrRomConfig), _vp, _vp,
                           _vp, _vp, ctypes.POINTER(MrGnOpts), ctypes.POINTER(_vp)]),
     "rom_destroy": (None, [_vp]),
@@ -459,18 +461,30 @@ def gn_opts(mode=POS_VEL, max_iter=3, max_backtrack=8, armijo_c=1e-4, damping=0.
     return MrGnOpts(mode, max_iter, max_backtrack, armijo_c, damping, tol_step)
 
 
+def rom_project_workspace_bytes(dec, B, ns, opts):
+    n = load().rom_project_workspace_bytes(dec.handle, B, ns, ctypes.byref(opts))
+    if n < 0:
+        raise MrError("rom_project_workspace_bytes", n)
+    return n
+
+
 def rom_project(dec, X, sample_idx, x_trial, v_trial, xhat_n, xhat_prev, dt, opts, xhat_next,
-                vhat_next, ns_per_instance=None, iters=None, resid=None, status=None, stream=None):
+                vhat_next, ns_per_instance=None, iters=None, resid=None, status=None,
+                workspace=None, stream=None):
     """sample_idx (B, ns) int32; x_trial, v_trial (B, d, ns) float32;
-    latents (B, r) float64."""
+    latents (B, r) float64; workspace: a uint8 device tensor of at least
+    rom_project_workspace_bytes bytes (allocated here when None)."""
     B_, ns = sample_idx.shape
+    if workspace is None:
+        workspace = torch.empty(rom_project_workspace_bytes(dec, B_, ns, opts), dtype=torch.uint8,
+                                device=sample_idx.device)
     _check("rom_project", load().rom_project(
         dec.handle, B_, X.shape[1], _ptr(X, torch.float32), ns, _ptr(sample_idx, torch.int32),
         _ptr(ns_per_instance, torch.int32), _ptr(x_trial, torch.float32),
         _ptr(v_trial, torch.float32), _ptr(xhat_n, torch.float64), _ptr(xhat_prev, torch.float64),
         dt, ctypes.byref(opts), _ptr(xhat_next, torch.float64), _ptr(vhat_next, torch.float64),
         _ptr(iters, torch.int32), _ptr(resid, torch.float64), _ptr(status, torch.int32),
-        _stream(stream)))
+        _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream)))
 
 
 class Rom:

@@ -24,6 +24,10 @@ struct ProjWS {
 int64_t proj_ws_bytes(int d, int r, int B, int64_t ns, int max_backtrack);
 ProjWS proj_ws_carve(void *base, int d, int r, int B, int64_t ns, int max_backtrack);
 bool opts_ok(const mr_gn_opts *o);
+int32_t project_args(const mr_decoder *dec, int32_t B, int64_t ns, const float *X,
+                     const int32_t *sample_idx, const float *v_trial, const double *xhat_n,
+                     const double *xhat_prev, const mr_gn_opts *opts, const double *xhat_next,
+                     const double *vhat_next, int &d, int &r);
 
 int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_ref, const float *X,
                      int64_t ns, const int32_t *idx, const int32_t *ns_inst, const float *x_trial,

@@ -499,13 +499,32 @@ bool opts_ok(const mr_gn_opts *o)
            o->damping >= 0.0;
 }
 
+// argument checks shared by the projection entry points; fills the sizes
+int32_t project_args(const mr_decoder *dec, int32_t B, int64_t ns, const float *X,
+                     const int32_t *sample_idx, const float *v_trial, const double *xhat_n,
+                     const double *xhat_prev, const mr_gn_opts *opts, const double *xhat_next,
+                     const double *vhat_next, int &d, int &r)
+{
+    if (!dec || B < 1 || ns < 1 || !X || !sample_idx || !v_trial || !xhat_n || !opts_ok(opts) ||
+        !xhat_next || !vhat_next)
+        return MR_EINVAL;
+    if (opts->mode == MR_POS_VEL && !xhat_prev) return MR_EINVAL;
+    if ((int64_t)B * (opts->max_backtrack + 1) > 65535) return MR_EINVAL;
+    d = decoder_dim(dec);
+    r = decoder_latent(dec);
+    return MR_OK;
+}
+
 }  // namespace mr
 
 using namespace mr;
 
-// Workspace cached per process for the stand-alone entry point.
-static void *g_proj_ws = nullptr;
-static int64_t g_proj_ws_bytes = 0;
+extern "C" int64_t rom_project_workspace_bytes(const mr_decoder *dec, int32_t B, int64_t ns,
+                                               const mr_gn_opts *opts)
+{
+    if (!dec || B < 1 || ns < 1 || !opts_ok(opts)) return MR_EINVAL;
+    return proj_ws_bytes(decoder_dim(dec), decoder_latent(dec), B, ns, opts->max_backtrack);
+}
 
 extern "C" int32_t rom_project(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X,
                                int64_t ns, const int32_t *sample_idx,
@@ -513,26 +532,18 @@ extern "C" int32_t rom_project(const mr_decoder *dec, int32_t B, int64_t n_ref, 
                                const float *v_trial, const double *xhat_n,
                                const double *xhat_prev, double dt, const mr_gn_opts *opts,
                                double *xhat_next, double *vhat_next, int32_t *iters_out,
-                               double *resid_out, int32_t *status_out, void *stream)
+                               double *resid_out, int32_t *status_out, void *workspace,
+                               size_t ws_bytes, void *stream)
 {
-    if (!dec || B < 1 || ns < 1 || !X || !sample_idx || !v_trial || !xhat_n || !opts_ok(opts) ||
-        !xhat_next || !vhat_next)
+    int d = 0, r = 0;
+    int32_t rc = project_args(dec, B, ns, X, sample_idx, v_trial, xhat_n, xhat_prev, opts,
+                              xhat_next, vhat_next, d, r);
+    if (rc != MR_OK) return rc;
+    if (!workspace || (int64_t)ws_bytes < proj_ws_bytes(d, r, B, ns, opts->max_backtrack) ||
+        (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return MR_EINVAL;
-    if (opts->mode == MR_POS_VEL && !xhat_prev) return MR_EINVAL;
-    int d = decoder_dim(dec), r = decoder_latent(dec);
-    if ((int64_t)B * (opts->max_backtrack + 1) > 65535) return MR_EINVAL;
-    hipStream_t st = as_stream(stream);
-    int64_t need = proj_ws_bytes(d, r, B, ns, opts->max_backtrack);
-    if (need > g_proj_ws_bytes) {
-        MR_CHECK_HIP(hipStreamSynchronize(st));
-        if (g_proj_ws) (void)hipFree(g_proj_ws);
-        g_proj_ws = nullptr;
-        g_proj_ws_bytes = 0;
-        if (hipMalloc(&g_proj_ws, need) != hipSuccess) return MR_ENOMEM;
-        g_proj_ws_bytes = need;
-    }
-    ProjWS w = proj_ws_carve(g_proj_ws, d, r, B, ns, opts->max_backtrack);
+    ProjWS w = proj_ws_carve(workspace, d, r, B, ns, opts->max_backtrack);
     return project_impl(dec, d, r, B, n_ref, X, ns, sample_idx, ns_per_instance, x_trial, v_trial,
                         xhat_n, xhat_prev ? xhat_prev : xhat_n, dt, *opts, xhat_next, vhat_next,
-                        iters_out, resid_out, status_out, w, st);
+                        iters_out, resid_out, status_out, w, as_stream(stream));
 }

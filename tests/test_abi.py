@@ -56,4 +56,6 @@ def test_host_side_validation_without_gpu():
                                   ctypes.byref(h)) == B.MR_EINVAL
     opts = B.gn_opts(max_backtrack=-1)
     assert lib.rom_project(None, 1, 1, None, 1, None, None, None, None, None, None, 0.1,
-                           ctypes.byref(opts), None, None, None, None, None, None) == B.MR_EINVAL
+                           ctypes.byref(opts), None, None, None, None, None, None, 0,
+                           None) == B.MR_EINVAL
+    assert lib.rom_project_workspace_bytes(None, 1, 1, ctypes.byref(opts)) == B.MR_EINVAL

@@ -141,6 +141,82 @@ def test_projection_matches_oracle(gpu, mode):
         assert st[b].item() == 0
 
 
+def _projection_case(seed, Bn=3, ns=64, d=3, r=6, P=2000):
+    """Random decoder, sample lists and trial data for the projection."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0.2, 0.8, size=(P, d)).astype(np.float32)
+    odec, gdec = make_decoder(d, r, 16, 3, 21, X, out_std=0.1, scale=1.5)
+    idx = np.sort(rng.choice(P, size=(Bn, ns), replace=True), axis=1).astype(np.int32)
+    zn = 0.4 * rng.standard_normal((Bn, r))
+    zp = zn - 0.01 * rng.standard_normal((Bn, r))
+    dt = 1e-2
+    xt = np.zeros((Bn, d, ns), np.float32)
+    vt = np.zeros((Bn, d, ns), np.float32)
+    for b in range(Bn):
+        zs = zn[b] + dt * rng.standard_normal(r)
+        xt[b] = (OD.decode(odec, X[idx[b]].astype(np.float64), zs)
+                 + 1e-4 * rng.standard_normal((ns, d))).T
+        vt[b] = rng.standard_normal((d, ns))
+    return dict(X=T(soa(X)), idx=T(idx, torch.int32), xt=T(xt), vt=T(vt), zn=T(zn, torch.float64),
+                zp=T(zp, torch.float64), dt=dt, gdec=gdec, Bn=Bn, r=r)
+
+
+def test_projection_captured_in_a_graph(gpu):
+    """rom_project with a caller workspace only enqueues kernels: captured in
+    a graph and replayed three times (outputs cleared and unrelated eager
+    work run between replays), every replay equals the eager call bit for
+    bit, in both projection modes."""
+    c = _projection_case(14)
+    for mode in (B.POS_VEL, B.VEL_ONLY):
+        opts = B.gn_opts(mode=mode, max_iter=3)
+        nbytes = B.rom_project_workspace_bytes(c["gdec"], c["Bn"], c["idx"].shape[1], opts)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        outs = [torch.zeros(c["Bn"], c["r"], dtype=torch.float64, device=dev) for _ in range(2)]
+        st = torch.zeros(c["Bn"], dtype=torch.int32, device=dev)
+
+        def call():
+            B.rom_project(c["gdec"], c["X"], c["idx"], c["xt"], c["vt"], c["zn"], c["zp"], c["dt"],
+                          opts, outs[0], outs[1], status=st, workspace=ws)
+
+        call()
+        torch.cuda.synchronize()
+        want = [o.clone() for o in outs]
+        want_st = st.clone()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):       # warm-up outside the capture
+            call()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            call()
+        for rep in range(3):
+            for o in outs:
+                o.zero_()
+            st.fill_(-1)
+            ws.fill_(rep + 1)
+            junk = torch.randn(1 << 16, device=dev).sum()
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.isfinite(junk)
+            for o, w in zip(outs, want):
+                assert torch.equal(o, w), (mode, rep)
+            assert torch.equal(st, want_st), (mode, rep)
+
+
+def test_projection_rejects_a_short_workspace(gpu):
+    c = _projection_case(15, Bn=1, ns=16)
+    opts = B.gn_opts()
+    nbytes = B.rom_project_workspace_bytes(c["gdec"], 1, 16, opts)
+    o = torch.zeros(1, c["r"], dtype=torch.float64, device=dev)
+    with pytest.raises(B.MrError):
+        B.rom_project(c["gdec"], c["X"], c["idx"], c["xt"], c["vt"], c["zn"], c["zp"], c["dt"],
+                      opts, o, o.clone(), workspace=torch.empty(nbytes - 256, dtype=torch.uint8,
+                                                               device=dev))
+
+
 def test_projection_appendix_a_identity_on_gpu(gpu):
     """One Gauss-Newton iteration from xhat_n with x_trial = g(X; xhat_n) +
     dt v_trial equals the velocity-only update (exact in exact arithmetic)."""
