@@ -811,6 +811,322 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
     }
 }
 
+// ---------------------------------------------------------------------------
+// sorted P2G in 3D: per-cell sums in registers
+//
+// One wave per 4 x 4 x 4 tile, lane c = local cell c, as in the tile scatter
+// above.  Every particle whose stencil base is still its sort-time (home)
+// cell is summed into the lane's registers instead of into LDS node by node.
+// A particle's contribution to stencil node o is, with the 1D weights w_b,
+// their derivatives dw_b (per unit length) and u_b = w_b (o_b - f_b) dx,
+//   mass   m w0 w1 w2
+//   mom_a  w1 w2 Px_a[o0] + w0 (w2 Qy_a[o1] + w1 Rz_a[o2]),
+//   Px_a = mv_a w0 + mC_a0 u0 - S_a0 dw0,  Qy_a = mC_a1 u1 - S_a1 dw1,
+//   Rz_a = mC_a2 u2 - S_a2 dw2          (S = dt V0 tau),
+// i.e. w (mv + mC (x_i - x_p)) - S grad w expanded per axis: one fused
+// multiply-add per node for the mass, two per momentum channel.  The two
+// lower z layers of the stencil (18 nodes x 4 channels) stay in registers
+// over all of the lane's particles; the top layer (9 nodes) is added to the
+// tile's LDS region particle by particle (ordered read-modify-write: lanes
+// sit in distinct cells, so one instruction touches 64 distinct nodes) --
+// all 27 in registers would not fit two waves per SIMD.  The next slot's
+// particle is loaded while the current one is summed.  After the slots the
+// lane adds its register sums to the region once; particles that left their
+// home cell since the sort are deferred (the first DEFER_CAP in LDS, the
+// rest in the tile's own range of a spill array) and scattered into the
+// region afterwards in claim rounds (those beyond the region with global
+// atomics); the region is flushed with one atomic per non-zero node
+// channel.  MODEL is the constitutive law (compiled separately, so that each
+// law's registers are allocated on their own); PER_PARTICLE selects
+// per-particle masses and volumes.  The loads of a slot are unconditional
+// (Cl is C, or any 9-plane array when the affine term is off, then scaled
+// by 0), so that they stay in flight while the previous slot is summed.
+template <int MODEL, bool PER_PARTICLE>
+__global__ void __launch_bounds__(64, 2) cell_sum_p2g_kernel(
+    GridK g, TileGeom tg, const float *__restrict__ x, const float *__restrict__ v,
+    const float *__restrict__ Cl, const float *__restrict__ F, const float *__restrict__ m,
+    const float *__restrict__ V0, float m_u, float V0_u, int64_t n,
+    const int32_t *__restrict__ offsets, const int32_t *__restrict__ counts, int apic, float mu,
+    float la, float dt, float *grid_out, int32_t *spill, int32_t *flag)
+{
+    using CT = CellTile<3>;
+    constexpr int DEFER_CAP = 512;                  // the rest spills
+    __shared__ float4 acc[CT::RNP];
+    __shared__ int owner[CT::RCN];
+    __shared__ int32_t deferred[DEFER_CAP];
+    const int lane = threadIdx.x;
+    const int64_t t = tile_of_block<3>(tg, 0);
+    if (t < 0 || t >= tg.ntiles) return;           // wave-uniform; no barriers below
+    const int64_t c0 = offsets[t * Tiling<3>::CELLS];
+    const int64_t c1 = offsets[(t + 1) * Tiling<3>::CELLS];
+    if (c0 == c1) return;
+    for (int i = lane; i < CT::RNP; i += 64) acc[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    lds_order();
+    const int tt0 = (int)(t % tg.nt0);
+    const int tt1 = (int)((t / tg.nt0) % tg.nt1);
+    const int tt2 = (int)(t / ((int64_t)tg.nt0 * tg.nt1));
+    const int r0 = tt0 * CT::TS - 1, r1 = tt1 * CT::TS - 1, r2 = tt2 * CT::TS - 1;
+    const int h0 = lane % CT::TS + 1, h1 = (lane / CT::TS) % CT::TS + 1, h2 = lane / 16 + 1;
+    const int cnt = counts[t * Tiling<3>::CELLS + lane];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const float cscale = apic ? 1.0f : 0.0f;
+    const int nb = h0 + CT::SY * h1 + CT::SZ * h2;  // the home stencil's base node
+    float4 *top = acc + nb + 2 * CT::SZ;            // its top layer
+
+    float sum[18][4];
+#pragma unroll
+    for (int q = 0; q < 18; ++q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sum[q][c] = 0.0f;
+    int ndef = 0;                                   // wave-uniform
+
+    // particle state of the next slot, loaded one slot ahead
+    float nx[3], nv[3], nC[9], nF[9], nm = m_u, nV = V0_u;
+    int64_t base = c0;
+    uint64_t mask = __ballot(0 < cnt);
+    int64_t np_ = base + __popcll(mask & below);
+    if (0 < cnt) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            nx[a] = x[a * n + np_];
+            nv[a] = v[a * n + np_];
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            nF[q] = F[q * n + np_];
+            nC[q] = Cl[q * n + np_];
+        }
+        if (PER_PARTICLE) {
+            nm = m[np_];
+            nV = V0[np_];
+        }
+    }
+    for (int k = 0; mask != 0; ++k) {
+        const bool act = k < cnt;
+        const int64_t p = np_;
+        float xp[3], vp[3], Cp[9], Fp[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            xp[a] = nx[a];
+            vp[a] = nv[a];
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            Cp[q] = nC[q];
+            Fp[q] = nF[q];
+        }
+        const float mp = nm, Vp = nV;
+        base += __popcll(mask);
+        const uint64_t mask1 = __ballot(k + 1 < cnt);
+        np_ = base + __popcll(mask1 & below);
+        if (k + 1 < cnt) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                nx[a] = x[a * n + np_];
+                nv[a] = v[a * n + np_];
+            }
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                nF[q] = F[q * n + np_];
+                nC[q] = Cl[q * n + np_];
+            }
+            if (PER_PARTICLE) {
+                nm = m[np_];
+                nV = V0[np_];
+            }
+        }
+        bool drifted = false;
+        if (act) {
+            float w[3][3], dw[3][3], f[3];
+            int b[3];
+            bool ok = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int na = a == 0 ? g.n0 : (a == 1 ? g.n1 : g.n2);
+                b[a] = bspline(xp[a], g.inv_dx, na, w[a], dw[a], ok);
+                f[a] = xp[a] * g.inv_dx - (float)b[a];
+            }
+            float tau[9];
+            ok = kirchhoff<3>(MODEL, mu, la, Fp, tau) && ok;
+            if (!ok) {
+                raise_flag(flag, MR_FLAG_DOMAIN);
+            } else if (b[0] - r0 == h0 && b[1] - r1 == h1 && b[2] - r2 == h2) {
+                const float sc = dt * Vp;
+                float P[3][3], Q[3][3], R[3][3];   // [a][o]
+#pragma unroll
+                for (int o = 0; o < 3; ++o) {
+                    const float u0 = w[0][o] * (((float)o - f[0]) * g.dx);
+                    const float u1 = w[1][o] * (((float)o - f[1]) * g.dx);
+                    const float u2 = w[2][o] * (((float)o - f[2]) * g.dx);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const float mca0 = cscale * mp * Cp[3 * a + 0];
+                        const float mca1 = cscale * mp * Cp[3 * a + 1];
+                        const float mca2 = cscale * mp * Cp[3 * a + 2];
+                        P[a][o] = (mp * vp[a]) * w[0][o] + mca0 * u0 - (sc * tau[3 * a + 0]) * dw[0][o];
+                        Q[a][o] = mca1 * u1 - (sc * tau[3 * a + 1]) * dw[1][o];
+                        R[a][o] = mca2 * u2 - (sc * tau[3 * a + 2]) * dw[2][o];
+                    }
+                }
+#pragma unroll
+                for (int o2 = 0; o2 < 3; ++o2)
+#pragma unroll
+                    for (int o1 = 0; o1 < 3; ++o1) {
+                        const float wyz = w[1][o1] * w[2][o2];
+                        const float mwyz = mp * wyz;
+                        float T[3];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) T[a] = Q[a][o1] * w[2][o2] + w[1][o1] * R[a][o2];
+#pragma unroll
+                        for (int o0 = 0; o0 < 3; ++o0) {
+                            if (o2 < 2) {
+                                float *s4 = sum[o0 + 3 * o1 + 9 * o2];
+                                s4[0] = fmaf(mwyz, w[0][o0], s4[0]);
+#pragma unroll
+                                for (int a = 0; a < 3; ++a)
+                                    s4[1 + a] = fmaf(w[0][o0], T[a], fmaf(P[a][o0], wyz, s4[1 + a]));
+                            } else {
+                                float4 *a4 = top + o0 + CT::SY * o1;
+                                float4 q = *a4;
+                                q.x = fmaf(mwyz, w[0][o0], q.x);
+                                q.y = fmaf(w[0][o0], T[0], fmaf(P[0][o0], wyz, q.y));
+                                q.z = fmaf(w[0][o0], T[1], fmaf(P[1][o0], wyz, q.z));
+                                q.w = fmaf(w[0][o0], T[2], fmaf(P[2][o0], wyz, q.w));
+                                *a4 = q;
+                                lds_order();
+                            }
+                        }
+                    }
+            } else {
+                drifted = true;
+            }
+        }
+        // particles that left their home cell wait for the claim rounds
+        // after the slots (each is deferred once, so a tile never defers
+        // more than its c1 - c0 particles)
+        const uint64_t dm = __ballot(drifted);
+        if (dm != 0) {
+            if (drifted) {
+                const int i = ndef + __popcll(dm & below);
+                if (i < DEFER_CAP)
+                    deferred[i] = (int32_t)p;
+                else
+                    spill[c0 + i - DEFER_CAP] = (int32_t)p;
+            }
+            ndef += __popcll(dm);
+        }
+        mask = mask1;
+    }
+    // the lanes' register sums (the two lower layers) into the region, in
+    // program order after the top-layer updates
+    lds_order();
+    if (cnt > 0) {
+#pragma unroll
+        for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+            for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+                for (int o0 = 0; o0 < 3; ++o0) {
+                    const float *s4 = sum[o0 + 3 * o1 + 9 * o2];
+                    float4 *a4 = acc + nb + o0 + CT::SY * o1 + CT::SZ * o2;
+                    float4 q = *a4;
+                    q.x += s4[0];
+                    q.y += s4[1];
+                    q.z += s4[2];
+                    q.w += s4[3];
+                    *a4 = q;
+                    lds_order();
+                }
+    }
+    if (ndef > 0) {
+        // the spilled indices were stored by this wave: complete and make its
+        // stores visible before reading them back
+        if (ndef > DEFER_CAP) __threadfence();
+        // the deferred particles, 64 at a time: lanes sharing a base cell go
+        // in turn (any two distinct base cells touch distinct nodes per
+        // stencil offset)
+        for (int i0 = 0; i0 < ndef; i0 += 64) {
+            bool pending = false;
+            Stencil<3> sn;
+            P2GPayload<3> pl;
+            int key = 0, nbd = 0;
+            if (i0 + lane < ndef) {
+                const int i = i0 + lane;
+                const int64_t p = i < DEFER_CAP ? deferred[i] : spill[c0 + i - DEFER_CAP];
+                float xn[3], vq[3], Cq[9], Fq[9], tau[9];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    xn[a] = x[a * n + p];
+                    vq[a] = v[a * n + p];
+                }
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    Fq[q] = F[q * n + p];
+                    Cq[q] = Cl[q * n + p];
+                }
+                // both succeeded when the particle was deferred
+                make_stencil<3>(g, xn, sn);
+                kirchhoff<3>(MODEL, mu, la, Fq, tau);
+                const float mp = PER_PARTICLE ? m[p] : m_u;
+                const float sc = dt * (PER_PARTICLE ? V0[p] : V0_u);
+                pl.m = mp;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) pl.mv[a] = mp * vq[a];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    pl.mC[q] = cscale * mp * Cq[q];
+                    pl.S[q] = sc * tau[q];
+                }
+                const int m0 = sn.base[0] - r0, m1 = sn.base[1] - r1, m2 = sn.base[2] - r2;
+                if (m0 >= 0 && m0 < CT::RC && m1 >= 0 && m1 < CT::RC && m2 >= 0 && m2 < CT::RC) {
+                    key = m0 + CT::RC * (m1 + CT::RC * m2);
+                    nbd = m0 + CT::SY * m1 + CT::SZ * m2;
+                    pending = true;
+                } else {
+                    // left the region since the sort: global atomics
+                    scatter_global<3>(g, sn, pl, grid_out);
+                }
+            }
+            while (__ballot(pending) != 0) {
+                if (pending) owner[key] = lane;
+                lds_order();
+                const bool go = pending && owner[key] == lane;
+                lds_order();
+                if (go) {
+                    opaque_payload<3>(sn, pl);
+                    auto rmw = [&](int o0, int o1, int o2, float mw, float q0, float q1, float q2) {
+                        float4 *a4 = acc + nbd + o0 + CT::SY * o1 + CT::SZ * o2;
+                        float4 q = *a4;
+                        q.x += mw;
+                        q.y += q0;
+                        q.z += q1;
+                        q.w += q2;
+                        *a4 = q;
+                        lds_order();
+                    };
+                    p2g_separable<3, decltype(rmw) &, MR_TILE_ORDERED != 0>(g, sn, pl, rmw);
+                    pending = false;
+                }
+            }
+        }
+    }
+    lds_order();
+    // flush the region: one global atomic per non-zero node channel
+    constexpr int RN = CT::R * CT::R * CT::R;
+    for (int li = lane; li < RN; li += 64) {
+        const int i0 = li % CT::R, i1 = (li / CT::R) % CT::R, i2 = li / (CT::R * CT::R);
+        const float4 q = acc[i0 + CT::SY * i1 + CT::SZ * i2];
+        if (q.x == 0.0f) continue;
+        const int gi = r0 + i0, gj = r1 + i1, gk = r2 + i2;
+        if (gi < 0 || gj < 0 || gk < 0 || gi >= g.n0 || gj >= g.n1 || gk >= g.n2) continue;
+        float *gp = grid_out + 4 * node_lin(g, gi, gj, gk);
+        atomicAdd(gp, q.x);
+        atomicAdd(gp + 1, q.y);
+        atomicAdd(gp + 2, q.z);
+        atomicAdd(gp + 3, q.w);
+    }
+}
+
 // Deterministic mode: node i of the grid sums the staged regions of the
 // tiles covering it (a tile's region spans nodes TS*tt - 1 .. TS*tt + TS + 2
 // per axis) in ascending tile order, skipping empty tiles, and writes (or
@@ -1092,11 +1408,44 @@ int32_t p2g_impl(const GridK &g, const mr_material *mat, const mr_particles *par
         SortWorkspace ws;
         sort_ws_bytes<D>(g, parts->n, &ws, (char *)workspace);
         TileGeom tg = tile_geom<D>(g);
-        if (tg.ntiles > 0)
+        if (tg.ntiles > 0 && D == 3 && MR_TILE_WPB == 1) {
+            // the per-cell kernel reads both per-particle arrays (masses and
+            // volumes) or neither; with only one of them the general tile
+            // kernel runs
+            const bool per = parts->m || parts->V0;
+            const float *Cl = apic && parts->C ? parts->C : parts->F;
+            const unsigned nb = tile_blocks<D>(tg);
+            // the sort's key array is dead until the next sort: the tiles'
+            // overflowing deferred lists go there
+            auto launch = [&](auto kern) {
+                kern<<<nb, 64, 0, st>>>(g, tg, parts->x, parts->v, Cl, parts->F, parts->m,
+                                        parts->V0, parts->m_uniform, parts->V0_uniform, parts->n,
+                                        ws.offsets, ws.counts, apic, lm.mu, lm.la, dt, grid,
+                                        ws.keys, flag);
+            };
+            if (per && !(parts->m && parts->V0)) {
+                // one per-particle array only: the general kernel
+                tile_scatter_kernel<D, false><<<nb, 64 * CellTile<D>::WPB, 0, st>>>(
+                    g, tg, parts->x, parts->v, parts->C, parts->F, parts->m, parts->V0,
+                    parts->m_uniform, parts->V0_uniform, parts->n, ws.offsets, ws.counts, apic,
+                    mat->model, lm.mu, lm.la, dt, nullptr, grid, nullptr, nullptr, flag);
+            } else if (mat->model == MR_NEO_HOOKEAN) {
+                if (per)
+                    launch(cell_sum_p2g_kernel<MR_NEO_HOOKEAN, true>);
+                else
+                    launch(cell_sum_p2g_kernel<MR_NEO_HOOKEAN, false>);
+            } else {
+                if (per)
+                    launch(cell_sum_p2g_kernel<MR_FIXED_COROTATED, true>);
+                else
+                    launch(cell_sum_p2g_kernel<MR_FIXED_COROTATED, false>);
+            }
+        } else if (tg.ntiles > 0) {
             tile_scatter_kernel<D, false><<<tile_blocks<D>(tg), 64 * CellTile<D>::WPB, 0, st>>>(
                 g, tg, parts->x, parts->v, parts->C, parts->F, parts->m, parts->V0, parts->m_uniform,
                 parts->V0_uniform, parts->n, ws.offsets, ws.counts, apic, mat->model, lm.mu, lm.la, dt,
                 nullptr, grid, nullptr, nullptr, flag);
+        }
         // particles in the overflow bucket (outside the lattice at sort time)
         // were flagged by the sort; the tiled kernel only covers tiles
         MR_LAUNCH_CHECK();

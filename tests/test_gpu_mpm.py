@@ -213,26 +213,39 @@ def test_cell_sort_permutation_is_bit_exact(gpu, dim, P):
     assert flag.item() & B.FLAG_DOMAIN
 
 
-@pytest.mark.parametrize("dim,P,move", [(3, 20000, "random"), (2, 6000, "random"),
-                                        (3, 20000, "none"), (2, 6000, "none"),
-                                        (3, 20000, "rigid"), (2, 6000, "rigid"),
-                                        (3, 60000, "dense")])
-def test_sorted_tiled_p2g_matches_oracle(gpu, dim, P, move):
+@pytest.mark.parametrize("dim,P,move,opts", [
+    (3, 20000, "random", ""), (2, 6000, "random", ""),
+    (3, 20000, "none", ""), (2, 6000, "none", ""),
+    (3, 20000, "rigid", ""), (2, 6000, "rigid", ""),
+    (3, 60000, "dense", ""),
+    (3, 20000, "random", "uniform"), (3, 20000, "random", "noaffine"),
+    (3, 20000, "random", "corotated"), (3, 60000, "dense", "uniform"),
+    (3, 9000, "random", "odd"), (3, 9000, "none", "odd-uniform")])
+def test_sorted_tiled_p2g_matches_oracle(gpu, dim, P, move, opts):
     """Cell-sort, then the tiled P2G with the particles moved since the sort:
     random: by up to 1.4 cells each (mixed drifts, some beyond the drift
     margin: deferred particles, claims and the global fallback); none: every
     particle in its sort-time cell; rigid: all translated by one cell
     diagonally (every lane drifted, distinct base cells); dense: 60,000
     particles in a 4-cell cube moved randomly, thousands of drifted
-    particles per tile (the deferred list fills and the rest claim inside
-    their slots)."""
-    rng = np.random.default_rng(50 + dim)
-    n = [40] * dim
-    dx = 1 / 40
+    particles per tile (the deferred list fills and the rest wait in the
+    tile's spill range).  Options: uniform masses and volumes instead of
+    per-particle arrays, the plain transfer (no affine term), the
+    fixed-corotated law, and an odd tile count per axis (22 nodes: 5 tiles,
+    a ragged brick of the XCD-aware tile order)."""
+    rng = np.random.default_rng(50 + dim + len(opts))
+    nn = 22 if "odd" in opts else 40
+    n = [nn] * dim
+    dx = 1 / nn
     lo, hi = (0.45, 0.55) if move == "dense" else (0.2, 0.8)
     x, v, C, F, m, V0 = random_state(rng, dim, P, lo=lo, hi=hi)
+    uniform = "uniform" in opts
+    if uniform:
+        m[:] = np.float32(1.3e-3)
+        V0[:] = np.float32(0.9e-6)
     grid = B.Grid(dim, n, dx)
-    parts = make_parts(B, x, v, C, F, m, V0)
+    parts = (make_parts(B, x, v, C, F, m_u=float(m[0]), V0_u=float(V0[0])) if uniform
+             else make_parts(B, x, v, C, F, m, V0))
     ws = B.new_workspace(grid, P)
     perm = torch.zeros(P, dtype=torch.int32, device=dev)
     B.mpm_cell_sort(grid, parts, ws, perm_out=perm)
@@ -244,11 +257,13 @@ def test_sorted_tiled_p2g_matches_oracle(gpu, dim, P, move):
     else:
         xs = x[p].copy()
     parts.x.copy_(T(soa(xs)))
-    model = 0 if dim == 2 else 1
+    model = 0 if (dim == 2 or opts == "corotated") else 1
+    apic = opts != "noaffine"
     mu, la = OM.lame(1e4, 0.3)
-    gm, gmv, gf = OM.p2g(dim, n, dx, xs, v[p], C[p], F[p], m[p], V0[p], model, mu, la)
+    gm, gmv, gf = OM.p2g(dim, n, dx, xs, v[p], C[p], F[p], m[p], V0[p], model, mu, la, apic=apic)
     gbuf = torch.zeros(int(np.prod(n)) * 4, device=dev)
-    B.mpm_p2g(grid, (model, 1e4, 0.3), parts, gbuf, 1e-4, flags=B.SORTED, workspace=ws)
+    flags = B.SORTED | (0 if apic else B.NO_AFFINE)
+    B.mpm_p2g(grid, (model, 1e4, 0.3), parts, gbuf, 1e-4, flags=flags, workspace=ws)
     g = gbuf.cpu().numpy().reshape(-1, 4)
     close_channels(g[:, 0], gm, name="mass")
     close_channels(g[:, 1:1 + dim], gmv + 1e-4 * gf, name="momentum")
