@@ -66,25 +66,49 @@ def measured_traffic(kernel, src_hash):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(scene, steps=2):
-    """The FP64 oracle (plain single-threaded C) on `steps` steps of the same
-    full-size scene."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scene, steps_single=2, steps_threaded=6):
+    """The FP64 oracle on the same full-size scene: the threaded driver
+    (private grids summed in thread order) on the host's threads -- the
+    baseline value -- and the plain single-threaded loop beside it.  The
+    thread count is OMP_NUM_THREADS when set (the host's share of cores),
+    else every core."""
     from oracle import mpm as OM
-    st = {k: v.astype(np.float64) for k, v in __import__(
+    st0 = {k: v.astype(np.float64) for k, v in __import__(
         "paper_2109_12390_amd.scenes", fromlist=["x"]).initial_state(scene).items()}
     mu, la = OM.lame(scene["E"], scene["nu"])
     sc = dict(dim=3, n=scene["n"], dx=scene["dx"], bound=scene["bound"],
               floor_mode=scene["floor_mode"], mu_f=scene["mu_f"], gravity=scene["gravity"],
               model=scene["model"], mu=mu, la=la,
               m=np.full(scene["P"], float(scene["m"])), V0=np.full(scene["P"], float(scene["V0"])))
-    OM.step(sc, st, scene["dt"])           # warm-up (builds / loads the oracle)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    st = OM.step_threaded(sc, st0, scene["dt"], threads=threads)    # warm-up (loads the oracle)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for _ in range(steps_threaded):
+        st = OM.step_threaded(sc, st, scene["dt"], threads=threads)
+    el_t = time.perf_counter() - t0
+    st = st0
+    t0 = time.perf_counter()
+    for _ in range(steps_single):
         st = OM.step(sc, st, scene["dt"])
-    el = time.perf_counter() - t0
-    return {"value": scene["P"] * steps / el, "unit": "particle-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "%d steps of the full %d-particle scene, FP64, single thread" % (steps, scene["P"])}
+    el_1 = time.perf_counter() - t0
+    return {"value": scene["P"] * steps_threaded / el_t, "unit": "particle-steps/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "%d steps of the full %d-particle scene, FP64, %d threads (OpenMP driver: "
+                      "private grids summed in thread order)" % (steps_threaded, scene["P"], threads),
+            "single_thread": {"value": scene["P"] * steps_single / el_1, "cores": 1,
+                              "sample": "%d steps, plain loop" % steps_single},
+            "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()}}
 
 
 def main():

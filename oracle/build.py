@@ -1,8 +1,8 @@
 """Builds the oracle's C part (test infrastructure only).
 
-Compiles ``mpm_oracle.c`` with gcc into ``oracle/_build/liboracle_mpm.so``.
-Plain -O2 without fast-math or contraction, so every double operation is
-performed as written.
+Compiles ``mpm_oracle.c`` (and its threaded driver ``mpm_oracle_omp.c``,
+OpenMP) with gcc into ``oracle/_build/liboracle_mpm.so``.  Plain -O2 without
+fast-math or contraction, so every double operation is performed as written.
 """
 import os
 import subprocess
@@ -10,7 +10,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(BUILD_DIR, "liboracle_mpm.so")
-SOURCES = [os.path.join(HERE, "mpm_oracle.c")]
+SOURCES = [os.path.join(HERE, "mpm_oracle.c"), os.path.join(HERE, "mpm_oracle_omp.c")]
 
 
 def build(force=True):
@@ -22,7 +22,7 @@ def build(force=True):
             return LIB_PATH
     tmp = LIB_PATH + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp] + SOURCES + ["-lm"]
+           "-fno-fast-math", "-fopenmp", "-Wall", "-Wextra", "-o", tmp] + SOURCES + ["-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH

@@ -50,6 +50,12 @@ def _load():
         lib.orc_cell_keys.argtypes = [ctypes.c_int, _ip, ctypes.c_double, ctypes.c_long,
                                       _dp, _lp]
         lib.orc_cell_keys.restype = None
+        lib.orc_step_threaded.argtypes = [ctypes.c_int, _ip, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_long, _dp, _dp, _dp, _dp, _dp, _dp,
+                                          ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_int]
+        lib.orc_step_threaded.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -198,6 +204,28 @@ def step(scene, state, dt, apic=True):
                      scene["floor_mode"], scene["mu_f"], gm, gmv, gf)
     x, v, C, F = g2p(dim, n, dx, dt, gv, state["x"], state["v"], state["C"],
                      state["F"], apic=apic)
+    return {"x": x, "v": v, "C": C, "F": F}
+
+
+def step_threaded(scene, state, dt, threads=0, apic=True):
+    """The same step as `step`, on `threads` host threads (0: all): particle
+    chunks scatter into private grids summed in thread order, then the grid
+    update and a chunked gather (mpm_oracle_omp.c).  Returns the new state."""
+    lib = _load()
+    dim, n, dx = scene["dim"], scene["n"], scene["dx"]
+    P = state["x"].shape[0]
+    x = _f64(state["x"], (P, dim)).copy(); v = _f64(state["v"], (P, dim)).copy()
+    C = _f64(state["C"], (P, dim, dim)).copy(); F = _f64(state["F"], (P, dim, dim)).copy()
+    m = _f64(np.broadcast_to(scene["m"], (P,))); V0 = _f64(np.broadcast_to(scene["V0"], (P,)))
+    g = _f64(list(scene["gravity"]) + [0.0] * (3 - len(scene["gravity"])))
+    rc = lib.orc_step_threaded(dim, _ivec(n), dx, dt, P, _d(x), _d(v), _d(C), _d(F), _d(m),
+                               _d(V0), scene["model"], scene["mu"], scene["la"],
+                               int(bool(apic)), _d(g), int(scene["bound"]),
+                               int(scene["floor_mode"]), float(scene["mu_f"]), int(threads))
+    if rc == -2:
+        raise MemoryError("step_threaded: private grids")
+    if rc != 0:
+        raise OracleDomainError("step_threaded: particle outside the lattice or J <= 0")
     return {"x": x, "v": v, "C": C, "F": F}
 
 
