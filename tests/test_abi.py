@@ -42,6 +42,27 @@ def test_binding_declares_every_symbol():
     assert lib is binding.load()
 
 
+def declared_arity():
+    """Parameter count of every function the header declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    out = {}
+    for m in re.finditer(r"\b((?:mpm|rom|mr)_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", text, flags=re.S):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_argument_counts_match_the_header():
+    from paper_2109_12390_amd import binding
+    arity = declared_arity()
+    bad = {n: (len(args), arity[n]) for n, (_, args) in binding.SIGNATURES.items()
+           if n in arity and len(args) != arity[n]}
+    assert not bad, bad
+    assert set(binding.SIGNATURES) <= set(arity)
+
+
 def test_host_side_validation_without_gpu():
     """Entry points reject bad arguments on the host before touching HIP."""
     from paper_2109_12390_amd import binding as B
