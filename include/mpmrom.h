@@ -51,6 +51,8 @@ extern "C" {
 #define MR_ESINGULAR (-4)
 #define MR_ENOCONV (-5)
 #define MR_EDOMAIN (-6)
+#define MR_ESCRATCH (-7)  /* rom_project_noalloc: the call needs more scratch than
+                              its fixed device array holds */
 
 #define MR_FLAG_DOMAIN 1     /* stencil left the lattice, NaN, or J <= 0    */
 #define MR_FLAG_SINGULAR 2   /* Cholesky of a normal matrix failed          */
@@ -397,6 +399,26 @@ int32_t rom_project(const mr_decoder *dec, int32_t B, int64_t n_ref,
                     double *xhat_next, double *vhat_next, int32_t *iters_out,
                     double *resid_out, int32_t *status_out, void *workspace,
                     size_t ws_bytes, void *stream);
+
+/* Allocation-free variant of rom_project, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and errors as
+ * rom_project, without the workspace: the scratch is a fixed 16 MiB device
+ * array inside the library, one per GPU, held until the process ends (its
+ * address is looked up on the first call on each device).  No hipMalloc,
+ * hipFree or allocating library call is made.  MR_ESCRATCH when
+ * rom_project_workspace_bytes(dec, B, ns, opts) exceeds 16 MiB (about 46
+ * instances of 1,024 samples at r = 16, d = 3 and 8 halvings).  Every call
+ * on one GPU shares that array and leaves its contents behind: calls that
+ * overlap in time on one GPU (several streams or host threads) race and
+ * must be serialised by the caller. */
+int32_t rom_project_noalloc(const mr_decoder *dec, int32_t B, int64_t n_ref,
+                            const float *X, int64_t ns, const int32_t *sample_idx,
+                            const int32_t *ns_per_instance, const float *x_trial,
+                            const float *v_trial, const double *xhat_n,
+                            const double *xhat_prev, double dt, const mr_gn_opts *opts,
+                            double *xhat_next, double *vhat_next, int32_t *iters_out,
+                            double *resid_out, int32_t *status_out, void *stream);
 
 /* Bytes of device workspace rom_project needs for B instances of ns
  * samples with these options (the decoder fixes d and r); MR_EINVAL

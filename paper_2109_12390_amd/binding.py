@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmpmrom.so")
 
 MR_OK = 0
 MR_EINVAL, MR_ENOMEM, MR_EDEVICE, MR_ESINGULAR, MR_ENOCONV, MR_EDOMAIN = -1, -2, -3, -4, -5, -6
+MR_ESCRATCH = -7
 FLAG_DOMAIN, FLAG_SINGULAR, FLAG_NOCONV, FLAG_LINESEARCH, FLAG_DRIFT = 1, 2, 4, 8, 16
 FLOOR_STICKY, FLOOR_COULOMB = 0, 1
 FIXED_COROTATED, NEO_HOOKEAN = 0, 1
@@ -25,7 +26,8 @@ PREC_FP32, PREC_BF16 = 0, 1
 POS_VEL, VEL_ONLY = 0, 1
 
 _ERRNAMES = {MR_EINVAL: "MR_EINVAL", MR_ENOMEM: "MR_ENOMEM", MR_EDEVICE: "MR_EDEVICE",
-             MR_ESINGULAR: "MR_ESINGULAR", MR_ENOCONV: "MR_ENOCONV", MR_EDOMAIN: "MR_EDOMAIN"}
+             MR_ESINGULAR: "MR_ESINGULAR", MR_ENOCONV: "MR_ENOCONV", MR_EDOMAIN: "MR_EDOMAIN",
+             MR_ESCRATCH: "MR_ESCRATCH"}
 
 
 class MrError(RuntimeError):
@@ -116,6 +118,8 @@ SIGNATURES = {
                            ctypes.POINTER(MrGnOpts), _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                            _vp]),
     "rom_project_workspace_bytes": (_i64, [_vp, _i32, _i64, ctypes.POINTER(MrGnOpts)]),
+    "rom_project_noalloc": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _f64,
+                                   ctypes.POINTER(MrGnOpts), _vp, _vp, _vp, _vp, _vp, _vp]),
     "rom_create": (_i32, [_vp, ctypes.POINTER(MrGrid), ctypes.POINTER(MrRomConfig), _vp, _vp,
                           _vp, _vp, ctypes.POINTER(MrGnOpts), ctypes.POINTER(_vp)]),
     "rom_destroy": (None, [_vp]),
