@@ -93,7 +93,7 @@ def decode_jac(dec, X, xhat, vhat=None, chunk=1024):
         for l in range(L):
             W = dec.weights[l]
             z = h @ W.T + dec.biases[l]
-            Tz = np.einsum("oi,pij->poj", W, T)
+            Tz = np.matmul(W, T)                 # W T_l for every point
             if l < L - 1:
                 h = elu(z)
                 T = elu_prime(z)[:, :, None] * Tz
