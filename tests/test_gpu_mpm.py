@@ -9,6 +9,8 @@ absolute tolerance of 2e-5 times the largest magnitude of that channel
 meaningless).  Whole steps use the stated targets: relative L2 of particle
 positions <= 1e-5 after one step and <= 1e-3 after 100 steps, plus the
 stricter checks on velocities listed in each test."""
+import os
+
 import numpy as np
 import pytest
 
@@ -411,6 +413,77 @@ def test_three_dimensional_scene_small(gpu):
     ex, ev = rel_l2(x, ref["x"]), rel_l2(v, ref["v"])
     ed = rel_l2(x - s["X"], ref["x"] - s["X"])
     print("3D small 100 steps: x %.3e v %.3e displacement %.3e" % (ex, ev, ed))
+    assert ex <= 1e-3 and ev <= 1e-2 and ed <= 1e-2
+
+
+def _gpu_trajectory(s, st0, steps, sort_every=10, model=None):
+    parts = make_parts(B, st0["x"], st0["v"], st0["C"], st0["F"], m_u=float(s["m"]),
+                       V0_u=float(s["V0"]))
+    grid = _gpu_scene(B, s)
+    gbuf = torch.zeros(grid.nodes() * 4, device=dev)
+    ws = torch.zeros(B.mpm_step_workspace_bytes(grid, s["P"]), dtype=torch.uint8, device=dev)
+    perm = torch.zeros(s["P"], dtype=torch.int32, device=dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    B.mpm_step(grid, (s["model"] if model is None else model, s["E"], s["nu"]), parts, s["dt"],
+               steps, sort_every, 0, gbuf, ws, perm_accum=perm, status=flag)
+    p = perm.cpu().numpy()
+    inv = np.empty_like(p)
+    inv[p] = np.arange(len(p))
+    return (aos(parts.x.cpu().numpy(), 3)[inv], aos(parts.v.cpu().numpy(), 3)[inv],
+            aos(parts.F.cpu().numpy(), 3, True)[inv], flag.item())
+
+
+@pytest.mark.parametrize("model", [scenes.MODEL_NEO_HOOKEAN, scenes.MODEL_FIXED_COROTATED])
+def test_three_dimensional_contact_100_steps(gpu, model):
+    """An 8^3-cell jittered cube released just above the Coulomb floor band
+    and thrown down and sideways, 100 steps with sorting every 10: the bottom
+    layers reach the floor band early in the run, stick or slide there (in
+    the oracle's run the lowest particles end above their free-flight height
+    and the bottom layer loses a third of its sideways speed to friction),
+    and the trajectory stays within the 1e-3 bound of the oracle."""
+    dx = 1 / 32
+    s = scenes.make_scene(3, 32, (8, 8, 8), (0.5 - 4 * dx, 3.8 * dx, 0.5 - 4 * dx), 2, 1000.0, 5.0e4,
+                          0.3, model, (0.0, -9.8, 0.0), scenes.FLOOR_COULOMB, 0.3, 3, 5.0e-5,
+                          seed=13, v0=(1.5, -6.0, 0.8))
+    st0 = scenes.initial_state(s)
+    steps = 100
+    ref = _run_oracle(oracle_scene(s), st0, s["dt"], steps)
+    # contact happened in the reference: the lowest particles stopped above
+    # where free flight would have taken them
+    t = steps * s["dt"]
+    y0 = s["X"][:, 1].astype(np.float64)
+    free = y0 - 6.0 * t - 0.5 * 9.8 * t * t
+    bottom = y0 < y0.min() + 0.5 * dx
+    assert np.mean(ref["x"][bottom, 1] - free[bottom]) > 0.03 * dx
+    assert np.mean(ref["v"][bottom, 0]) < 0.8 * 1.5
+    x, v, F, flag = _gpu_trajectory(s, st0, steps)
+    ex, ev = rel_l2(x, ref["x"]), rel_l2(v, ref["v"])
+    ed = rel_l2(x - s["X"], ref["x"] - s["X"])
+    eF = float(np.max(np.abs(F - ref["F"])))
+    print("3D contact model %d: x %.3e v %.3e displacement %.3e max|dF| %.3e; bottom layer "
+          "sideways speed %.3f (released at 1.5)" % (model, ex, ev, ed, eF,
+                                                     float(np.mean(ref["v"][bottom, 0]))))
+    assert flag == 0
+    assert ex <= 1e-3 and ev <= 1e-2 and ed <= 1e-2 and eF <= 1e-3
+
+
+def test_three_dimensional_full_size_100_steps(gpu):
+    """The 2,097,152-particle benchmark scene in the benchmark's launch
+    configuration (mpm_step, sort every 10), 100 steps against the threaded
+    FP64 oracle on every particle: relative L2 of positions within 1e-3."""
+    s = scenes.scene_3d()
+    st0 = scenes.initial_state(s)
+    steps = 100
+    sc = oracle_scene(s)
+    ref = {k: np.asarray(v, dtype=np.float64) for k, v in st0.items()}
+    for _ in range(steps):
+        ref = OM.step_threaded(sc, ref, s["dt"], threads=int(os.environ.get("OMP_NUM_THREADS",
+                                                                              "0") or 0))
+    x, v, F, flag = _gpu_trajectory(s, st0, steps)
+    ex, ev = rel_l2(x, ref["x"]), rel_l2(v, ref["v"])
+    ed = rel_l2(x - s["X"], ref["x"] - s["X"])
+    print("3D full size, 100 steps: x %.3e v %.3e displacement %.3e" % (ex, ev, ed))
+    assert flag == 0
     assert ex <= 1e-3 and ev <= 1e-2 and ed <= 1e-2
 
 
