@@ -127,6 +127,9 @@ def main():
                          "model (0: skip)")
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--rom-batched-steps", type=int, default=4)
+    ap.add_argument("--rom-study", action="store_true",
+                    help="the reduced model's error attribution and sample-count sweep with a "
+                         "trained decoder (adds a few minutes)")
     ap.add_argument("--rom-pareto-steps", type=int, default=30,
                     help="steps per point of the quadrature / samples / projection sweep (0: off)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -264,6 +267,9 @@ def main():
             log("training a decoder on full-order snapshots and judging the reduced model ...")
             out["rom_trained"] = rom_trained_accuracy(B, scenes, s, args.rom_accuracy_steps,
                                                       args.train_steps)
+    if args.rom_study:
+        log("reduced-model study ...")
+        out["rom_study"] = rom_study(B, scenes, s)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(s)
@@ -530,6 +536,28 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
                                  opts=B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4),
                                  z_guess=Z[0])
     err, pos = EV.displacement_error(x_rom, fom, s["X"])
+    del x_rom
+    # error floor: the decoder's best approximation of every recorded frame
+    # (frames every 10 steps, codes every 5)
+    Zs = [Z[min(2 * k, Z.shape[0] - 1)] for k in range(len(fom))]
+    proj = EV.best_projection(dec, s, fom, Zs)
+    err_proj = EV.displacement_error(proj, fom, s["X"])[0]
+    del proj
+    # the linear-manifold baseline (one linear layer, same r and objective)
+    Wl, bl, Zl, norml = TR.train_linear(snap, r, train_steps, lam_F=lam_F, lam_v=lam_v)
+    ldec = B.Decoder(Wl, bl, *norml, B.OUT_DISPLACEMENT, B.PREC_FP32)
+    proj = EV.best_projection(ldec, s, fom, [Zl[min(2 * k, Zl.shape[0] - 1)]
+                                              for k in range(len(fom))])
+    lin = {"best_projection_displacement_error": round(EV.displacement_error(proj, fom, s["X"])[0], 4)}
+    del proj
+    xl, sl = EV.rom_positions(ldec, s, E, v0, n_steps, 10, n_samples=n_samples,
+                              opts=B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4),
+                              z_guess=Zl[0])
+    lin.update({"displacement_error": round(EV.displacement_error(xl, fom, s["X"])[0], 4),
+                "status": sl["status"], "decoder": "one linear layer, r = %d, fp32" % r})
+    del xl
+    ldec.close()
+    log("linear manifold:", json.dumps(lin))
     # the same decoder under the other quadrature and the paper's fast
     # configuration (few samples, velocity-only projection)
     variants = []
@@ -551,7 +579,7 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
     # zero-shot super-resolution: the same body sampled 2x finer per
     # dimension (4 particles per cell per dimension, a new jitter), which the
     # decoder never saw, judged against the full-order model on that set
-    del x_rom, fom
+    del fom
     fine = scenes.scene_3d(seed=3, sub=4)
     fom_f = EV.fom_positions(fine, E, v0, n_steps, 10, affine=False)
     super_res = []
@@ -575,6 +603,8 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
             "value": float(1e3 / st["ms_per_step"]), "unit": "latent steps/s",
             "ms_per_step": st["ms_per_step"], "displacement_error": err,
             "position_error_percent": pos, "status": st["status"], "steps": n_steps,
+            "best_projection_displacement_error": round(err_proj, 4),
+            "linear_manifold": lin,
             "train": {"steps": train_steps, "rows_per_step": 64 * 256, "objective": hist,
                       "rows_per_s": train_steps * 64 * 256 / t_train,
                       "lam_F": lam_F, "lam_v": lam_v, "seconds": t_train,
@@ -585,6 +615,103 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
                        "quadrature": "Lagrangian",
                        "reference": "full-order model without the affine transfer term"},
             "variants": variants, "super_resolution": super_res}
+
+
+def rom_study(B, scenes, s, n_steps=500, train_steps=4000, r=16, width=128, n_hidden=5):
+    """Where the reduced model's error comes from, on the 2,097,152-particle
+    scene (E = 5e4, v0 = (0, -1, 0), n_steps steps, errors every 10 steps)
+    with one trained bf16 decoder (as in rom_trained_accuracy):
+      - error floors: the decoder's best projection of every full-order frame
+        (the latent fitting all positions, by Gauss-Newton), and the reduced
+        model with every particle sampled (Lagrangian quadrature);
+      - the sample-count sweep |P| in {10, 50, 100, 512} x {position-velocity,
+        velocity-only} x {Lagrangian, Eulerian quadrature}, plus the
+        undamped position-velocity scheme at 512;
+      - the same weights with fp32 hidden layers at 512 samples;
+      - the linear-manifold baseline (one linear layer, same r and objective)
+        at 512 samples, with its own best projection;
+    each against the full-order model without the affine transfer term (the
+    reduced substep's transfers) and with it (APIC).  Latent steps/s are
+    reported beside each error."""
+    import torch
+    from paper_2109_12390_amd import evaluate as EV
+    from paper_2109_12390_amd import train as TR
+    E, v0 = float(s["E"]), (0.0, -1.0, 0.0)
+    rec = 10
+    fom_pic = EV.fom_positions(s, E, v0, n_steps, rec, affine=False)
+    fom_apic = EV.fom_positions(s, E, v0, n_steps, rec, affine=True)
+    snap = TR.generate_snapshots(s, [(E, v0)], n_steps=n_steps, every=5, n_sub=65536, seed=4,
+                                 affine=False)
+    lam_F, lam_v = TR.balanced_penalties(snap)
+    Ws, bs, Z, norm, _ = TR.train(snap, width=width, n_hidden=n_hidden, r=r, steps=train_steps,
+                                  n_groups=64, rows_per_group=256, lr0=1e-2, lr1=1e-4,
+                                  lam_F=lam_F, lam_v=lam_v)
+    lo, hi, mean, std = norm
+    dec = B.Decoder(Ws, bs, lo, hi, mean, std, B.OUT_DISPLACEMENT, B.PREC_BF16)
+    Zs = [Z[min(2 * k, Z.shape[0] - 1)] for k in range(len(fom_pic))]   # frames every 5 steps
+    X = s["X"]
+
+    def errs(x):
+        e1, p1 = EV.displacement_error(x, fom_pic, X)
+        e2, _ = EV.displacement_error(x, fom_apic, X)
+        return {"e_u_vs_pic": round(e1, 4), "e_u_vs_apic": round(e2, 4),
+                "position_error_percent_vs_pic": round(p1, 4)}
+
+    out = {"config": {"particles": s["P"], "steps": n_steps, "r": r,
+                      "decoder": "bf16 MLP %d x %d, trained" % (width, n_hidden),
+                      "damping": 1e-4, "gauss_newton_iterations": 3},
+           "fom_pic_vs_apic": errs(fom_pic)["e_u_vs_apic"]}
+    proj = EV.best_projection(dec, s, fom_pic, Zs)
+    out["best_projection"] = errs(proj)
+    del proj
+    log("study: best projection", json.dumps(out["best_projection"]))
+    runs = []
+
+    def run(quad, qn, ns, mode, mn, damping=1e-4, d=dec, zg=Z[0], tag=None):
+        prog = (lambda k: log("study: %d samples, step %d" % (ns, k)) if k % 100 == 0 else None)
+        x, st = EV.rom_positions(d, s, E, v0, n_steps, rec, n_samples=ns,
+                                 opts=B.gn_opts(mode=mode, max_iter=3, damping=damping),
+                                 z_guess=zg, quadrature=quad, progress=prog)
+        row = {"quadrature": qn, "samples": ns, "projection": mn, "damping": damping,
+               "latent_steps_per_s": round(1e3 / st["ms_per_step"], 1),
+               "quadrature_points": st["n_quadrature_points"], "status": st["status"]}
+        if tag:
+            row["decoder"] = tag
+        row.update(errs(x))
+        del x
+        torch.cuda.synchronize()
+        runs.append(row)
+        log("study:", json.dumps(row))
+
+    run(B.QUAD_LAGRANGIAN, "lagrangian", s["P"], B.POS_VEL, "position-velocity")
+    for qn, quad in (("lagrangian", B.QUAD_LAGRANGIAN), ("eulerian", B.QUAD_EULERIAN)):
+        for ns in (10, 50, 100, 512):
+            for mode, mn in ((B.POS_VEL, "position-velocity"), (B.VEL_ONLY, "velocity-only")):
+                run(quad, qn, ns, mode, mn)
+    run(B.QUAD_LAGRANGIAN, "lagrangian", 512, B.POS_VEL, "position-velocity", damping=0.0)
+    dec.close()
+    # the same weights with fp32 hidden layers (the precision's share)
+    dec32 = B.Decoder(Ws, bs, lo, hi, mean, std, B.OUT_DISPLACEMENT, B.PREC_FP32)
+    run(B.QUAD_LAGRANGIAN, "lagrangian", 512, B.POS_VEL, "position-velocity", d=dec32,
+        tag="same weights, fp32")
+    dec32.close()
+    # the linear-manifold baseline
+    Wl, bl, Zl, norml = TR.train_linear(snap, r, train_steps, lam_F=lam_F, lam_v=lam_v)
+    lo, hi, mean, std = norml
+    ldec = B.Decoder(Wl, bl, lo, hi, mean, std, B.OUT_DISPLACEMENT, B.PREC_FP32)
+    Zls = [Zl[min(2 * k, Zl.shape[0] - 1)] for k in range(len(fom_pic))]
+    proj = EV.best_projection(ldec, s, fom_pic, Zls)
+    out["linear_best_projection"] = errs(proj)
+    del proj
+    log("study: linear best projection", json.dumps(out["linear_best_projection"]))
+    try:
+        run(B.QUAD_LAGRANGIAN, "lagrangian", 512, B.POS_VEL, "position-velocity", d=ldec,
+            zg=Zl[0], tag="linear, one layer")
+    except Exception as exc:           # a diverging run is a result, not a crash
+        runs.append({"decoder": "linear, one layer", "samples": 512, "failed": str(exc)})
+    ldec.close()
+    out["runs"] = runs
+    return out
 
 
 SHAPE_NAMES = ["1 point tile per wave", "2 point tiles per wave", "4 point tiles per wave",

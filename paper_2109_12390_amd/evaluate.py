@@ -87,11 +87,42 @@ def rom_initial_state(dec, scene, v0, z_guess=None, n_quad=65536, seed=0, iters=
     return z, vh2
 
 
+def best_projection(dec, scene, frames, z_guesses, n_quad=65536, seed=0, iters=6,
+                    device="cuda"):
+    """The decoder's best approximation of given full-order frames (the
+    error floor of any reduced trajectory on its manifold): for each frame,
+    the latent that minimises sum |g(X_p; z) - x_p|^2 over a random subset
+    of n_quad particles, by Gauss-Newton (rom_project) from z_guesses[k],
+    then every particle decoded there.  Returns the decoded frames."""
+    P, d, r = scene["P"], scene["dim"], dec.r
+    rng = np.random.default_rng(seed)
+    q = np.sort(rng.choice(P, size=min(n_quad, P), replace=False)).astype(np.int32)
+    X = torch.tensor(np.ascontiguousarray(scene["X"].T), device=device)
+    idx = torch.tensor(q[None, :], device=device)
+    qi = idx[0].long()
+    v_trial = torch.zeros(1, d, len(q), device=device)
+    opts = B.gn_opts(mode=B.POS_VEL, max_iter=iters)
+    ws = torch.empty(B.rom_project_workspace_bytes(dec, 1, len(q), opts), dtype=torch.uint8,
+                     device=device)
+    xbuf = torch.zeros(1, d, P, device=device)
+    out = []
+    for k, xf in enumerate(frames):
+        z0 = torch.as_tensor(np.asarray(z_guesses[k], dtype=np.float64), device=device)[None]
+        z = torch.zeros_like(z0)
+        vh = torch.zeros_like(z0)
+        B.rom_project(dec, X, idx, xf[:, qi].contiguous()[None], v_trial, z0.contiguous(),
+                      z0.contiguous(), 1.0, opts, z, vh, workspace=ws)
+        B.rom_decode(dec, X, z, xbuf)
+        out.append(xbuf[0].clone())
+    return out
+
+
 def rom_positions(dec, scene, E, v0, n_steps, record_every, n_samples, opts, seed=7,
-                  use_graph=True, z_guess=None, device="cuda", **rom_kwargs):
+                  use_graph=True, z_guess=None, device="cuda", progress=None, **rom_kwargs):
     """Reduced-order positions of every particle at the recorded steps and
     the step statistics.  rom_kwargs go to the runner (e.g. the Eulerian
-    quadrature options)."""
+    quadrature options); progress(step) is called after each recorded
+    chunk."""
     P, d = scene["P"], scene["dim"]
     X = torch.tensor(np.ascontiguousarray(scene["X"].T), device=device)
     grid = _grid(scene)
@@ -119,6 +150,8 @@ def rom_positions(dec, scene, E, v0, n_steps, record_every, n_samples, opts, see
         times.append(a.elapsed_time(b) / k)
         done += k
         out.append(xbuf[0].clone())
+        if progress is not None:
+            progress(done)
     nq, na = rom.last_counts(0)
     rom.close()
     return out, {"status": int(st.item()), "ms_per_step": float(np.mean(times[1:] if len(times) > 1 else times)),

@@ -280,3 +280,51 @@ def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B
         bs.append(flat[o:o + fo]); o += fo
     tr.close()
     return Ws, bs, Z.cpu().numpy(), (in_min, in_max, mean, std), history
+
+
+def train_linear(snap, r, steps, rows=16384, lr0=1e-2, lr1=1e-4, lam_F=100.0, lam_v=0.01,
+                 seed=0, device="cuda"):
+    """The linear-manifold baseline (a single linear layer g = X + mean +
+    std * (W [X~; z] + b), no activation, the comparison of the paper's
+    Section 5): its weights, bias and per-snapshot latent codes trained on
+    the same objective as the network (batch mean of the position, lam_F
+    deformation-gradient and lam_v velocity residuals) with Adam and the same
+    exponentially decaying learning rate.  Training runs as PyTorch
+    operations: this one-layer map is a baseline for comparison, outside the
+    reduced-order path (which evaluates it with the library's kernels).
+    Returns (weights, biases, Z, normalisation) like `train`."""
+    d = snap.X_sub.shape[1]
+    in_min, in_max, mean, std = normalisation(snap)
+    f32 = lambda a: torch.tensor(np.asarray(a, dtype=np.float32), device=device)
+    lo, hi, mu, sd = f32(in_min), f32(in_max), f32(mean), f32(std)
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    a = math.sqrt(6.0 / (d + r + d))
+    W = ((torch.rand(d, d + r, generator=gen) * 2 - 1) * a).to(device).requires_grad_(True)
+    b = torch.zeros(d, device=device, requires_grad=True)
+    Z = torch.zeros(snap.n_frames, r, device=device, requires_grad=True)
+    opt = torch.optim.Adam([W, b, Z], lr=lr0)
+    nxt = torch.tensor(snap.next_frame, device=device, dtype=torch.long)
+    scale_X = 2.0 / (hi - lo)
+    eye = torch.eye(d, device=device)
+    for it in range(steps):
+        for gr in opt.param_groups:
+            gr["lr"] = lr0 * (lr1 / lr0) ** (it / max(steps - 1, 1))
+        fr = torch.randint(0, snap.n_frames, (rows,), generator=gen).to(device)
+        pi = torch.randint(0, snap.P_sub, (rows,), generator=gen).to(device)
+        X = snap.X_sub[pi]
+        Xn = (X - lo) * scale_X - 1.0
+        g = X + mu + sd * (torch.cat([Xn, Z[fr]], 1) @ W.T + b)
+        Fg = eye + sd[:, None] * W[:, :d] * scale_X[None, :]
+        loss_x = ((g - snap.fx[fr, pi]) ** 2).sum(-1)
+        loss_F = ((Fg[None] - snap.fF[fr, pi]) ** 2).sum((-1, -2))
+        has = nxt[fr] >= 0
+        dz = (Z[nxt[fr].clamp(min=0)] - Z[fr]) / snap.dt_frame
+        gv = (sd[None, :] * (dz @ W[:, d:].T))
+        loss_v = torch.where(has, ((gv - snap.fv[fr, pi]) ** 2).sum(-1), torch.zeros_like(loss_x))
+        loss = (loss_x + lam_F * loss_F + lam_v * loss_v).mean()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+    Ws = [W.detach().cpu().numpy().astype(np.float32)]
+    bs = [b.detach().cpu().numpy().astype(np.float32)]
+    return Ws, bs, Z.detach().cpu().numpy(), (in_min, in_max, mean, std)

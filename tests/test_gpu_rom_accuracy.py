@@ -56,9 +56,12 @@ def fom_and_training(gpu):
                                      log_every=1000)
     print("training objective on the evaluation batch", hist)
     init = scenes.xavier_decoder(3, r, width, nh, 0)     # what train() starts from
+    # the linear-manifold baseline: one linear layer, same r, same objective
+    Wl, bl, Zl, norml = TR.train_linear(snap, r, 4000, rows=1024, lam_F=1.0, lam_v=1e-4)
     # initial latent: projection of the rest configuration, started from the
     # code the training gave the first frame (zero for the untrained network)
-    return s, E, v0, (fom, fom_apic), (Ws, bs, Z[0]), init + (None,), norm
+    return (s, E, v0, (fom, fom_apic), (Ws, bs, Z[0]), init + (None,), norm,
+            ((Wl, bl, Zl[0]), norml, Z, Zl))
 
 
 def _rom_error(s, E, v0, foms, weights, norm, prec, n_samples=256, mode=None, **rom_kwargs):
@@ -74,7 +77,7 @@ def _rom_error(s, E, v0, foms, weights, norm, prec, n_samples=256, mode=None, **
 
 @pytest.mark.parametrize("prec", [B.PREC_FP32, B.PREC_BF16])
 def test_trained_decoder_beats_the_untrained_one(fom_and_training, prec):
-    s, E, v0, foms, trained, init, norm = fom_and_training
+    s, E, v0, foms, trained, init, norm, _ = fom_and_training
     ((e_tr, p_tr), (e_tr_apic, _)), st_tr = _rom_error(s, E, v0, foms, trained, norm, prec)
     ((e_un, p_un), _), st_un = _rom_error(s, E, v0, foms, init, norm, prec)
     print("prec %d: displacement error trained %.3e (position %.4f%%), untrained %.3e "
@@ -90,13 +93,39 @@ def test_trained_decoder_beats_the_untrained_one(fom_and_training, prec):
     assert e_tr < 0.3
 
 
+def test_trained_network_beats_the_linear_manifold(fom_and_training):
+    """The learned nonlinear manifold against the paper's linear-manifold
+    baseline (a single linear layer, no activation, same latent dimension
+    and objective): the network's best approximation of the full-order
+    frames (the latent fitting all particles, per frame) and its reduced
+    trajectory are both better than the linear layer's; the linear
+    manifold can only translate the body and apply one fixed affine map."""
+    s, E, v0, foms, trained, init, norm, (lin, norml, Z, Zl) = fom_and_training
+    fom = foms[0]
+    Ws, bs, _ = trained
+    dec = B.Decoder(Ws, bs, *norm, B.OUT_DISPLACEMENT, B.PREC_FP32)
+    ldec = B.Decoder(lin[0], lin[1], *norml, B.OUT_DISPLACEMENT, B.PREC_FP32)
+    # recorded every 10 steps, snapshots every 5: frame k <-> code 2k
+    guess = lambda Zs: [Zs[min(2 * k, len(Zs) - 1)] for k in range(len(fom))]
+    bp_nn = EV.displacement_error(EV.best_projection(dec, s, fom, guess(Z)), fom, s["X"])[0]
+    bp_lin = EV.displacement_error(EV.best_projection(ldec, s, fom, guess(Zl)), fom, s["X"])[0]
+    dec.close()
+    ldec.close()
+    ((e_nn, _), _), _ = _rom_error(s, E, v0, foms, trained, norm, B.PREC_FP32)
+    ((e_lin, _), _), st = _rom_error(s, E, v0, foms, lin, norml, B.PREC_FP32)
+    print("best projection: network %.3e, linear %.3e; reduced model: network %.3e, linear %.3e "
+          "(status %d)" % (bp_nn, bp_lin, e_nn, e_lin, st["status"]))
+    assert bp_nn < 0.5 * bp_lin
+    assert not np.isfinite(e_lin) or e_nn < 0.5 * e_lin
+
+
 @pytest.mark.parametrize("n_samples,mode", [(256, B.POS_VEL), (32, B.VEL_ONLY)])
 def test_eulerian_quadrature_accuracy(fom_and_training, n_samples, mode):
     """The trained decoder with Eulerian quadrature (Algorithm 4: lattice
     points inverted through the decoder instead of the neighbour particles)
     against the same run with Lagrangian quadrature, both judged by the
     full-order model."""
-    s, E, v0, foms, trained, init, norm = fom_and_training
+    s, E, v0, foms, trained, init, norm, _ = fom_and_training
     ((e_eu, p_eu), _), st_eu = _rom_error(s, E, v0, foms, trained, norm, B.PREC_BF16,
                                           n_samples=n_samples, mode=mode,
                                           quadrature=B.QUAD_EULERIAN)
@@ -120,7 +149,7 @@ def test_zero_shot_super_resolution(fom_and_training, quad):
     the full-order model run on that finer set (Section 5, zero-shot
     super-resolution: the decoder is a function of the reference position,
     so any particle set of the body can be evaluated)."""
-    s, E, v0, foms, trained, init, norm = fom_and_training
+    s, E, v0, foms, trained, init, norm, _ = fom_and_training
     fine = _scene(sub=4, seed=15)
     assert fine["P"] == 8 * s["P"]
     fom_f = EV.fom_positions(fine, E, v0, N_STEPS, RECORD, affine=False)
