@@ -130,6 +130,12 @@ def main():
     ap.add_argument("--rom-study", action="store_true",
                     help="the reduced model's error attribution and sample-count sweep with a "
                          "trained decoder (adds a few minutes)")
+    ap.add_argument("--batched-study", action="store_true",
+                    help="train on several instances, then judge every instance of the batched "
+                         "reduced model against its own full-order run (adds several minutes)")
+    ap.add_argument("--batched-study-instances", type=int, default=256)
+    ap.add_argument("--batched-study-steps", type=int, default=400)
+    ap.add_argument("--batched-study-train-steps", type=int, default=8000)
     ap.add_argument("--rom-pareto-steps", type=int, default=30,
                     help="steps per point of the quadrature / samples / projection sweep (0: off)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -270,6 +276,11 @@ def main():
     if args.rom_study:
         log("reduced-model study ...")
         out["rom_study"] = rom_study(B, scenes, s)
+    if args.batched_study:
+        log("batched reduced-model study ...")
+        out["batched_study"] = batched_study(B, scenes, s, n_inst=args.batched_study_instances,
+                                             n_steps=args.batched_study_steps,
+                                             train_steps=args.batched_study_train_steps)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(s)
@@ -716,6 +727,179 @@ def rom_study(B, scenes, s, n_steps=500, train_steps=4000, r=16, width=128, n_hi
 
 SHAPE_NAMES = ["1 point tile per wave", "2 point tiles per wave", "4 point tiles per wave",
                "units split over a block", "points split, activations in registers"]
+
+
+def batched_study(B, scenes, s, n_inst=256, n_steps=400, record_every=20, train_steps=8000,
+                  n_train=8, n_held=2, train_frames=200, every=5, n_eval=65536, r=16, width=128,
+                  n_hidden=5):
+    """Training on several parameter instances and the batched reduced model
+    judged per instance against the full-order model.
+
+    Training data: n_train instances (E log-uniform in [1e4, 1e5], v0
+    uniform in [-2, 2]^3, seeded) of the 2,097,152-particle scene, frames
+    every `every` steps up to train_frames (65,536 particles each, PIC
+    transfers); the decoder (bf16, then fp32, same initial weights and
+    batches) is trained with Adam and judged by its final objective and by
+    the best projection of n_held held-out instances' trajectories onto its
+    manifold.  Then n_inst instances (E log-uniform in [1e3, 1e5], v0
+    uniform in [-2, 2]^3, 256-1024 samples each, a second seed) start from
+    the least-squares initial latents (position and velocity) and advance
+    together, one HIP graph per batched step, with each quadrature; every
+    instance is judged on n_eval particles every record_every steps against
+    its own full-order run (PIC transfers, the reduced substep's scheme)."""
+    import torch
+    from paper_2109_12390_amd import evaluate as EV
+    from paper_2109_12390_amd import train as TR
+    dev = "cuda:0"
+    P = s["P"]
+    t_all = time.perf_counter()
+    Et, vt = scenes.parameter_instances(n_train + n_held, 31, E_range=(1.0e4, 1.0e5))
+    train_inst = [(float(Et[i]), tuple(float(c) for c in vt[i])) for i in range(n_train)]
+    held = [(float(Et[i]), tuple(float(c) for c in vt[i])) for i in range(n_train, n_train + n_held)]
+    n_fom = every * train_frames
+    snap = TR.generate_snapshots(s, train_inst, n_steps=n_fom, every=every, n_sub=n_eval, seed=4,
+                                 affine=False)
+    torch.cuda.synchronize()
+    log("batched study: %d training frames of %d instances (%.1f s)"
+        % (snap.n_frames, n_train, time.perf_counter() - t_all))
+    lam_F, lam_v = TR.balanced_penalties(snap)
+    held_fom = [EV.fom_positions(s, E, v0, n_fom, 50, affine=False) for (E, v0) in held]
+    fpi = n_fom // every + 1                               # frames per training instance
+    decs, training = {}, {}
+    for prec, pname in ((B.PREC_BF16, "bf16"), (B.PREC_FP32, "fp32")):
+        t0 = time.perf_counter()
+        Ws, bs, Z, norm, hist = TR.train(snap, width=width, n_hidden=n_hidden, r=r,
+                                         steps=train_steps, n_groups=64, rows_per_group=256,
+                                         precision=prec, lr0=1e-2, lr1=1e-4, lam_F=lam_F,
+                                         lam_v=lam_v, log_every=train_steps // 4)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        dec = B.Decoder(Ws, bs, *norm, B.OUT_DISPLACEMENT, prec)
+        # held-out reconstruction: best projection of the held-out frames
+        # (every 50 steps), each from the training code that decodes closest
+        # to it
+        rec = []
+        for fr in held_fom:
+            zg = EV.nearest_codes(dec, s, fr, Z)
+            proj = EV.best_projection(dec, s, fr, zg)
+            rec.append(round(EV.displacement_error(proj, fr, s["X"])[0], 4))
+            del proj
+        training[pname] = {"objective": [(int(a), float(b)) for a, b in hist],
+                           "final_objective": float(hist[-1][1]), "seconds": round(t_train, 1),
+                           "rows_per_s": round(train_steps * 64 * 256 / t_train),
+                           "held_out_best_projection_error": rec}
+        log("batched study: training", pname, json.dumps(training[pname]))
+        decs[pname] = (dec, Z)
+    del snap
+    decs["fp32"][0].close()
+    dec, Z = decs["bf16"]
+    # the batched instances
+    Es, v0s = scenes.parameter_instances(n_inst, 32)
+    rng = np.random.default_rng(33)
+    ns = rng.integers(256, 1025, size=n_inst).astype(np.int32)
+    sub = np.sort(np.random.default_rng(34).choice(P, size=n_eval, replace=False))
+    X = s["X"]
+    Xg = torch.tensor(np.ascontiguousarray(X.T), device=dev)
+    sub_t = torch.tensor(sub, device=dev).long()
+    Xe = Xg[:, sub_t].contiguous()
+    # initial latents: least squares from the training instances' first
+    # codes, each instance at the one whose tangent space fits its velocity
+    z_init, v_init, choice = EV.rom_initial_states(dec, s, v0s, Z.reshape(n_train, fpi, r)[:, 0])
+    log("batched study: initial codes chosen per training instance:",
+        np.bincount(choice, minlength=n_train).tolist())
+    # full-order reference per instance on the evaluation subset
+    t0 = time.perf_counter()
+    fom = []
+    for b in range(n_inst):
+        fr = EV.fom_positions(s, float(Es[b]), v0s[b], n_steps, record_every, affine=False)
+        fom.append(np.stack([f[:, sub_t].cpu().numpy() for f in fr]))
+        del fr
+        if (b + 1) % 32 == 0:
+            log("batched study: full-order reference %d / %d (%.0f s)"
+                % (b + 1, n_inst, time.perf_counter() - t0))
+    fom = np.stack(fom)                                   # [inst][frame][d][n_eval]
+    Xs = X[sub].T.astype(np.float64)                      # [d][n_eval]
+    grid = B.Grid(3, s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
+    legs = {}
+    for qn, quad in (("lagrangian", B.QUAD_LAGRANGIAN), ("eulerian", B.QUAD_EULERIAN)):
+        rom = B.Rom(dec, grid, Xg, torch.tensor(Es.astype(np.float32), device=dev),
+                    torch.tensor(ns, device=dev),
+                    B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4, proj_fp32=1), seed=5,
+                    rho0=float(s["rho"]),
+                    m_uniform=float(s["m"]), autotune=True, quadrature=quad)
+        z = z_init.clone()
+        zp = z_init.clone()
+        vh = v_init.clone()
+        st = torch.zeros(n_inst, dtype=torch.int32, device=dev)
+        xbuf = torch.zeros(n_inst, 3, n_eval, device=dev)
+        B.rom_decode(dec, Xe, z, xbuf)
+        rec = [xbuf.cpu().numpy()]
+        times = []
+        for i in range(n_steps):
+            a = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            a.record()
+            rom.step(1, i, s["dt"], z, zp, vh, status=st, use_graph=True)
+            e.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(e))
+            if (i + 1) % record_every == 0:
+                B.rom_decode(dec, Xe, z, xbuf)
+                rec.append(xbuf.cpu().numpy())
+            if (i + 1) % 50 == 0:
+                log("batched study: %s step %d / %d, %.1f ms per batched step"
+                    % (qn, i + 1, n_steps, float(np.mean(times[1:]))))
+        rom.close()
+        dz = (z - z_init).abs().max(1).values / (1.0 + z_init.abs().max(1).values)
+        xr = np.stack(rec, axis=1)                        # [inst][frame][d][n_eval]
+        e_u = np.empty(n_inst)
+        for b in range(n_inst):
+            fb = fom[b].astype(np.float64)
+            num = ((xr[b].astype(np.float64) - fb) ** 2).sum()
+            den = ((fb - Xs[None]) ** 2).sum()
+            e_u[b] = np.sqrt(num / den)
+        del xr
+        flags = st.cpu().numpy()
+        t = np.array(times[1:])                           # the first replay includes the capture
+        soft = Es < 1.0e4
+
+        def dist(v):
+            return {"n": int(v.size), "mean": round(float(v.mean()), 4),
+                    "p50": round(float(np.percentile(v, 50)), 4),
+                    "p90": round(float(np.percentile(v, 90)), 4),
+                    "max": round(float(v.max()), 4)} if v.size else None
+        legs[qn] = {"latent_steps_per_s": round(n_inst * 1e3 / t.mean(), 1),
+                    "ms_per_batched_step": round(float(t.mean()), 3),
+                    "p50_ms": round(float(np.percentile(t, 50)), 3),
+                    "p99_ms": round(float(np.percentile(t, 99)), 3),
+                    "timed_steps": int(t.size),
+                    "latent_change_p50": round(float(dz.median().item()), 4),
+                    "e_u": dist(e_u), "e_u_E_below_1e4": dist(e_u[soft]),
+                    "e_u_E_from_1e4": dist(e_u[~soft]),
+                    "instances_with_flags": {"domain": int(((flags & B.FLAG_DOMAIN) != 0).sum()),
+                                             "singular": int(((flags & B.FLAG_SINGULAR) != 0).sum()),
+                                             "noconv": int(((flags & B.FLAG_NOCONV) != 0).sum()),
+                                             "linesearch": int(((flags & B.FLAG_LINESEARCH) != 0).sum())},
+                    "e_u_per_instance": [round(float(v), 4) for v in e_u]}
+        log("batched study:", qn, json.dumps({k: v for k, v in legs[qn].items()
+                                               if k != "e_u_per_instance"}))
+    dec.close()
+    return {"config": {"instances": n_inst, "particles": P, "samples": "256-1024 per instance",
+                       "r": r, "decoder": "bf16 MLP %d x %d, trained on %d instances" % (width, n_hidden, n_train),
+                       "E": "log-uniform [1e3, 1e5]", "v0": "uniform [-2, 2]^3",
+                       "initial_latents": "least squares (position, then velocity) from the "
+                                          "training instance's first code that fits v0 best",
+                       "projection": "position-velocity, 3 Gauss-Newton iterations, damping 1e-4, "
+                                     "positions of the projection decoded in fp32",
+                       "steps": n_steps, "judged_every": record_every, "eval_particles": n_eval,
+                       "reference": "full-order model per instance, no affine transfer term",
+                       "graph": "HIP graph of one step of all instances"},
+            "training_data": {"instances": n_train, "E": "log-uniform [1e4, 1e5]",
+                              "v0": "uniform [-2, 2]^3", "frames_per_instance": fpi,
+                              "every": every, "particles": n_eval, "held_out_instances": n_held},
+            "training": training, "legs": legs,
+            "E": [round(float(e), 1) for e in Es], "v0": [[round(float(c), 3) for c in v] for v in v0s],
+            "seconds": round(time.perf_counter() - t_all, 1)}
 
 
 def decoder_shapes(dec, n_inst, P, n_samples):

@@ -364,6 +364,17 @@ typedef struct {
     double damping;        /* added to the normal-matrix diagonal (0: none)    */
     double tol_step;       /* MR_FLAG_NOCONV when the last step exceeds
                               tol_step (1 + |xhat|); <= 0 disables the test  */
+    int32_t proj_fp32;     /* the projection's decodes of a bf16 decoder:
+                              0 all in bf16; 1 the positions (sample
+                              positions and line-search candidates, hence
+                              the objective) in fp32, the latent Jacobian in
+                              bf16; 2 both in fp32 (as an fp32 decoder of
+                              the same weights).  bf16 activations make g
+                              piecewise constant in xhat below about 2^-8 of
+                              the output scale, which can hide a step's
+                              motion from the objective and the Armijo
+                              test.  No effect on an fp32 decoder.  Values
+                              outside 0..2 are rejected (MR_EINVAL)     */
 } mr_gn_opts;
 
 /* Reduced-space dynamics for B instances with ns sample points each
@@ -482,7 +493,10 @@ typedef struct {
  * of stencil bases around it: Lagrangian, twice the particles of the
  * densest reference cell (at least 16) per base cell, at most P; Eulerian,
  * l^d points per base.  A step that would exceed it keeps the first entries
- * and raises MR_FLAG_DOMAIN.  With cfg->autotune set, the decoder's launch shapes are
+ * and raises MR_FLAG_DOMAIN.  Each instance has a dense node-major grid
+ * (16 bytes per node) and node bitmaps; only the nodes a step marks (the set
+ * I) are written, and the step zeroes exactly those again after its substep,
+ * so no step refills whole grids.  With cfg->autotune set, the decoder's launch shapes are
  * tuned for the runner's four decoder launches (all particles, the
  * quadrature list, the samples, the line-search candidates), which updates
  * the decoder's shape table. */

@@ -56,7 +56,8 @@ class MrParticles(ctypes.Structure):
 class MrGnOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("max_backtrack", ctypes.c_int32), ("armijo_c", ctypes.c_double),
-                ("damping", ctypes.c_double), ("tol_step", ctypes.c_double)]
+                ("damping", ctypes.c_double), ("tol_step", ctypes.c_double),
+                ("proj_fp32", ctypes.c_int32)]
 
 
 class MrRomConfig(ctypes.Structure):
@@ -461,8 +462,10 @@ def rom_decode_jac(dec, X, xhat, n=None, idx=None, idx_per_instance=0, vhat=None
         _ptr(Jz, torch.float32), _stream(stream)))
 
 
-def gn_opts(mode=POS_VEL, max_iter=3, max_backtrack=8, armijo_c=1e-4, damping=0.0, tol_step=0.0):
-    return MrGnOpts(mode, max_iter, max_backtrack, armijo_c, damping, tol_step)
+def gn_opts(mode=POS_VEL, max_iter=3, max_backtrack=8, armijo_c=1e-4, damping=0.0, tol_step=0.0,
+            proj_fp32=0):
+    """proj_fp32: 0, 1 (positions in fp32) or 2 (positions and Jacobian)."""
+    return MrGnOpts(mode, max_iter, max_backtrack, armijo_c, damping, tol_step, int(proj_fp32))
 
 
 def rom_project_workspace_bytes(dec, B, ns, opts):

@@ -1017,8 +1017,11 @@ int dec_variant(const mr_decoder *dec, int cfg, int64_t pts)
     return shape_available(dec, cfg, DEC_REG) ? DEC_REG : DEC_COL;
 }
 
+// force_fp32: run a bf16 decoder's launch on its fp32 parameters (the fp32
+// kernels at the same padded width; shapes by the size rule, since the tuned
+// table holds bf16 choices)
 int32_t launch_cfg(const mr_decoder *dec, int cfg, const StreamSpec &ss, const DecIO &io,
-                   hipStream_t st, int variant_override = -1)
+                   hipStream_t st, int variant_override = -1, int force_fp32 = 0)
 {
     DecK P;
     P.d = dec->d;
@@ -1045,9 +1048,11 @@ int32_t launch_cfg(const mr_decoder *dec, int cfg, const StreamSpec &ss, const D
         MR_LAUNCH_CHECK();
         return MR_OK;
     }
-    const int variant = variant_override >= 0 ? variant_override
-                                              : dec_variant(dec, cfg, (int64_t)io.B * io.n);
-    const bool bf = dec->prec == MR_PREC_BF16;
+    const bool bf = dec->prec == MR_PREC_BF16 && !force_fp32;
+    int variant = variant_override >= 0 ? variant_override
+                                        : dec_variant(dec, cfg, (int64_t)io.B * io.n);
+    if (dec->prec == MR_PREC_BF16 && !bf && variant_override < 0)
+        variant = (int64_t)io.B * io.n <= 8192 ? DEC_ROWS : DEC_COL;
     switch (dec->W) {
     case 16: return bf ? launch_w<uint16_t, 16>(cfg, variant, P, ss, io, st) : launch_w<float, 16>(cfg, variant, P, ss, io, st);
     case 32: return bf ? launch_w<uint16_t, 32>(cfg, variant, P, ss, io, st) : launch_w<float, 32>(cfg, variant, P, ss, io, st);
@@ -1403,7 +1408,7 @@ namespace mr {
 int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X, int64_t n,
                       const int32_t *idx, int32_t idx_per_instance, const int32_t *n_inst,
                       const double *xhat, const double *vhat, float *x, float *F, float *v,
-                      float *Jz, hipStream_t st, int disp_only, int64_t x_stride)
+                      float *Jz, hipStream_t st, int disp_only, int64_t x_stride, int force_fp32)
 {
     if (n == 0) return MR_OK;
     DecIO io{};
@@ -1432,7 +1437,7 @@ int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const flo
             ss.arg[1 + a] = a;
         }
         ss.kind[4] = v ? SK_VELOCITY : SK_ZERO;
-        rc = launch_cfg(dec, (F && !v) ? 4 : 5, ss, io, st);
+        rc = launch_cfg(dec, (F && !v) ? 4 : 5, ss, io, st, -1, force_fp32);
         if (rc != MR_OK) return rc;
         wrote_x = true;
     }
@@ -1449,7 +1454,7 @@ int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const flo
         }
         ss.zk = 8;
         io.x = wrote_x ? nullptr : x;
-        rc = launch_cfg(dec, 9, ss, io, st);
+        rc = launch_cfg(dec, 9, ss, io, st, -1, force_fp32);
         if (rc != MR_OK) return rc;
         wrote_x = wrote_x || x;
     }
@@ -1458,7 +1463,7 @@ int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const flo
         ss.kind[0] = SK_PRIMAL;
         io.x = x;
         io.Jz = nullptr;
-        return launch_cfg(dec, 1, ss, io, st);
+        return launch_cfg(dec, 1, ss, io, st, -1, force_fp32);
     }
     return MR_OK;
 }

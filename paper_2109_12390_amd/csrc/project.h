@@ -13,7 +13,8 @@ int32_t decoder_autotune(const mr_decoder *dec, int32_t B, int64_t n, int32_t cf
 int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X, int64_t n,
                       const int32_t *idx, int32_t idx_per_instance, const int32_t *n_inst,
                       const double *xhat, const double *vhat, float *x, float *F, float *v,
-                      float *Jz, hipStream_t st, int disp_only = 0, int64_t x_stride = 0);
+                      float *Jz, hipStream_t st, int disp_only = 0, int64_t x_stride = 0,
+                      int force_fp32 = 0);
 
 struct ProjWS {
     float *Jz, *x, *xc, *xt;

@@ -442,8 +442,20 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
     // motion, not of the coordinates, so fp32 keeps its relative accuracy.
     const int disp = (!x_trial && decoder_output_mode(dec) == MR_OUT_DISPLACEMENT) ? 1 : 0;
     // velocity least squares at zn
-    rc = decode_jac_ex(dec, B, n_ref, X, ns, idx, 1, ns_inst, zn, nullptr, w.x, nullptr, nullptr,
-                       w.Jz, st, disp);
+    // positions (objective, line search) and latent Jacobian, each in fp32
+    // or in the decoder's precision (proj_fp32 1: positions, 2: both)
+    const int f32x = o.proj_fp32 >= 1 ? 1 : 0, f32j = o.proj_fp32 >= 2 ? 1 : 0;
+    auto positions_and_jacobian = [&](const double *zq) -> int32_t {
+        if (f32x == f32j)
+            return decode_jac_ex(dec, B, n_ref, X, ns, idx, 1, ns_inst, zq, nullptr, w.x, nullptr,
+                                 nullptr, w.Jz, st, disp, 0, f32x);
+        int32_t e = decode_jac_ex(dec, B, n_ref, X, ns, idx, 1, ns_inst, zq, nullptr, nullptr,
+                                  nullptr, nullptr, w.Jz, st, disp, 0, f32j);
+        if (e != MR_OK) return e;
+        return decode_jac_ex(dec, B, n_ref, X, ns, idx, 1, ns_inst, zq, nullptr, w.x, nullptr,
+                             nullptr, nullptr, st, disp, 0, f32x);
+    };
+    rc = positions_and_jacobian(zn);
     if (rc != MR_OK) return rc;
     const float *xtp = x_trial;
     if (!x_trial) {
@@ -463,8 +475,7 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
     const double *fres = nullptr;
     if (o.mode == MR_POS_VEL) {
         for (int it = 0; it < o.max_iter; ++it) {
-            rc = decode_jac_ex(dec, B, n_ref, X, ns, idx, 1, ns_inst, w.z, nullptr, w.x, nullptr,
-                               nullptr, w.Jz, st, disp);
+            rc = positions_and_jacobian(w.z);
             if (rc != MR_OK) return rc;
             normal_eq<1>(d, r, B, ns, ns_inst, w.Jz, xtp, w.x, w.part, w.A, w.g, w.f, w.fe, st);
             cholesky_solve_kernel<<<(unsigned)B, 64, 0, st>>>(B, r, w.A, w.g, o.damping, -1.0,
@@ -473,7 +484,7 @@ int32_t project_impl(const mr_decoder *dec, int d, int r, int32_t B, int64_t n_r
                 B, r, nc, w.z, w.delta, w.zc);
             MR_LAUNCH_CHECK();
             rc = decode_jac_ex(dec, B * nc, n_ref, X, ns, idx, nc, nullptr, w.zc, nullptr, w.xc,
-                               nullptr, nullptr, nullptr, st, disp);
+                               nullptr, nullptr, nullptr, st, disp, 0, f32x);
             if (rc != MR_OK) return rc;
             objective_kernel<<<B * nc, 256, 0, st>>>(d, ns, nc, ns_inst, w.xc, xtp, w.fc, w.fce);
             select_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(
@@ -496,7 +507,7 @@ bool opts_ok(const mr_gn_opts *o)
 {
     return o && (o->mode == MR_POS_VEL || o->mode == MR_VEL_ONLY) && o->max_iter >= 0 &&
            o->max_iter <= 64 && o->max_backtrack >= 0 && o->max_backtrack <= 30 &&
-           o->damping >= 0.0;
+           o->damping >= 0.0 && o->proj_fp32 >= 0 && o->proj_fp32 <= 2;
 }
 
 // argument checks shared by the projection entry points; fills the sizes

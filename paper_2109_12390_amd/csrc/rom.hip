@@ -90,6 +90,9 @@ struct mr_rom {
     float *mQ;             // [B][q_cap] point masses (0: discarded)
     float *rho;            // smoothed reference density on the grid's node lattice
     int rn[3];             // its nodes per axis (the grid's)
+    // the per-instance grids and bitmaps are all zero between steps: a step
+    // clears only what it marked; set when a step was left unfinished
+    int dirty;
 };
 
 namespace mr {
@@ -616,6 +619,47 @@ __global__ void advance_kernel(int B, int r, double *z, double *zp, double *v, c
 
 __global__ void set_counter_kernel(int64_t *counter, int64_t v) { *counter = v; }
 
+// After the substep has read the grid: zero the grid nodes of every
+// instance's marked set I and the marks themselves (node bitmap and, for the
+// Eulerian quadrature, the stencil-base bitmap), so that the next step
+// starts from zero grids without refilling them (all other nodes are still
+// zero); counts |I| per instance on the way.  Grid (x blocks, B).
+__global__ void clear_marked_kernel(int64_t words, int64_t nodes, uint32_t *bitmap,
+                                    uint32_t *qb_bitmap, float4 *grid, int32_t *n_active)
+{
+    const int b = blockIdx.y;
+    int cnt = 0;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t wi = (int64_t)b * words + w;
+        if (qb_bitmap && qb_bitmap[wi] != 0u) qb_bitmap[wi] = 0u;
+        uint32_t m = bitmap[wi];
+        if (m == 0u) continue;
+        bitmap[wi] = 0u;
+        cnt += __popc(m);
+        while (m != 0u) {
+            const int k = __ffs(m) - 1;
+            m &= m - 1u;
+            const int64_t i = 32 * w + k;
+            if (i < nodes) grid[(int64_t)b * nodes + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt != 0) atomicAdd(n_active + b, cnt);
+}
+
+// every grid, bitmap and count of the runner to zero (creation, and after a
+// step that was left unfinished)
+void clear_all(mr_rom *R, hipStream_t st)
+{
+    const int TB = 256;
+    const int64_t B = R->B;
+    fill_u32_kernel<<<2048, TB, 0, st>>>(R->bitmap, B * R->words);
+    if (R->qb_bitmap) fill_u32_kernel<<<2048, TB, 0, st>>>(R->qb_bitmap, B * R->words);
+    fill_f4_kernel<<<4096, TB, 0, st>>>(reinterpret_cast<float4 *>(R->grid), B * R->nodes);
+    fill_u32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>((uint32_t *)R->n_active, B);
+}
+
 int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, double *vhat,
                      int32_t *status_out, hipStream_t st)
 {
@@ -626,8 +670,9 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
     dim3 gs((unsigned)ceil_div(R->ns_max, TB), (unsigned)B);
     fill_u32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>((uint32_t *)R->status_step, B);
     fill_u32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>((uint32_t *)R->q_count, B);
-    fill_u32_kernel<<<2048, TB, 0, st>>>(R->bitmap, (int64_t)B * R->words);
-    fill_f4_kernel<<<4096, TB, 0, st>>>(reinterpret_cast<float4 *>(R->grid), (int64_t)B * R->nodes);
+    fill_u32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>((uint32_t *)R->n_active, B);
+    // the grids and bitmaps are zero here (cleared by the previous step)
+    R->dirty = 1;
     sample_kernel<<<gs, TB, 0, st>>>(R->cfg.seed, R->counter, R->P, (int)R->ns_max, R->n_samples,
                                       R->internal_of, R->samples);
     MR_LAUNCH_CHECK();
@@ -637,7 +682,6 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
         // Algorithm 4
         const int L = R->ell;
         const int LD = d == 3 ? L * L * L : L * L;
-        fill_u32_kernel<<<2048, TB, 0, st>>>(R->qb_bitmap, (int64_t)B * R->words);
         fill_u32_kernel<<<(unsigned)ceil_div(B, TB), TB, 0, st>>>((uint32_t *)R->qb_count, B);
         rc = decode_jac_ex(R->dec, B, R->P, R->X, R->ns_max, R->samples, 1, R->n_samples, xhat,
                            nullptr, R->xs, nullptr, nullptr, nullptr, st);
@@ -737,6 +781,12 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
     else
         g2p_trial_kernel<3><<<gs, TB, 0, st>>>(g, (int)R->ns_max, R->n_samples, R->xs, R->grid,
                                                R->nodes, (float)dt, R->xt, R->vt);
+    {
+        const int64_t per = std::min<int64_t>(ceil_div(R->words, TB), 256);
+        clear_marked_kernel<<<dim3((unsigned)per, (unsigned)B), TB, 0, st>>>(
+            R->words, R->nodes, R->bitmap, R->qb_bitmap, reinterpret_cast<float4 *>(R->grid),
+            R->n_active);
+    }
     MR_LAUNCH_CHECK();
     // Algorithm 6 / 7
     ProjWS w = proj_ws_carve(R->proj_ws, d, r, B, R->ns_max, R->opts.max_backtrack);
@@ -747,6 +797,7 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
     advance_kernel<<<(unsigned)ceil_div((int64_t)B * r, TB), TB, 0, st>>>(
         B, r, xhat, xhat_prev, vhat, R->z_next, R->v_next, R->status_step, status_out, R->counter);
     MR_LAUNCH_CHECK();
+    R->dirty = 0;
     return MR_OK;
 }
 
@@ -880,6 +931,7 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
     }
     alloc((void **)&R->bitmap, 4 * B * R->words);
     alloc((void **)&R->q_count, 4 * B);
+    alloc((void **)&R->n_active, 4 * B);
     alloc((void **)&R->xQ, 4 * B * d * R->q_cap);
     alloc((void **)&R->FQ, 4 * B * d * d * R->q_cap);
     alloc((void **)&R->vQ, 4 * B * d * R->q_cap);
@@ -973,6 +1025,11 @@ extern "C" int32_t rom_create(const mr_decoder *dec, const mr_grid *grid_desc,
         rom_destroy(R);
         return MR_EDEVICE;
     }
+    clear_all(R, R->cap_stream);
+    if (hipStreamSynchronize(R->cap_stream) != hipSuccess) {
+        rom_destroy(R);
+        return MR_EDEVICE;
+    }
     if (cfg->autotune) {
         // the four decoder launches of a step: every particle (positions),
         // the quadrature list (x, F, v), the samples (latent Jacobian) and
@@ -999,6 +1056,10 @@ extern "C" int32_t rom_step(mr_rom *R, int32_t n_steps, int64_t step0, double dt
 {
     if (!R || n_steps < 0 || !xhat || !xhat_prev || !vhat || step0 < 0) return MR_EINVAL;
     hipStream_t st = as_stream(stream);
+    if (R->dirty) {
+        clear_all(R, st);
+        R->dirty = 0;
+    }
     set_counter_kernel<<<1, 1, 0, st>>>(R->counter, step0);
     MR_LAUNCH_CHECK();
     if (n_steps == 0) return MR_OK;
@@ -1047,16 +1108,11 @@ extern "C" int32_t rom_last_counts(const mr_rom *R, int32_t b, int64_t *n_quad, 
 {
     if (!R || b < 0 || b >= R->B || !n_quad || !n_active) return MR_EINVAL;
     hipStream_t st = as_stream(stream);
-    int32_t q = 0;
+    int32_t q = 0, a = 0;
     MR_CHECK_HIP(hipMemcpyAsync(&q, R->q_count + b, 4, hipMemcpyDeviceToHost, st));
-    // active nodes: population count of the instance's bitmap
-    std::vector<uint32_t> bm(R->words);
-    MR_CHECK_HIP(hipMemcpyAsync(bm.data(), R->bitmap + (int64_t)b * R->words, 4 * R->words,
-                                hipMemcpyDeviceToHost, st));
+    MR_CHECK_HIP(hipMemcpyAsync(&a, R->n_active + b, 4, hipMemcpyDeviceToHost, st));
     MR_CHECK_HIP(hipStreamSynchronize(st));
-    int64_t cnt = 0;
-    for (uint32_t w : bm) cnt += __builtin_popcount(w);
     *n_quad = q;
-    *n_active = cnt;
+    *n_active = a;
     return MR_OK;
 }

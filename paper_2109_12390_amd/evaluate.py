@@ -79,12 +79,91 @@ def rom_initial_state(dec, scene, v0, z_guess=None, n_quad=65536, seed=0, iters=
     z = torch.zeros_like(z0)
     vh = torch.zeros_like(z0)
     B.rom_project(dec, X, idx, x_trial.contiguous(), v_trial.contiguous(), z0, z0, 1.0,
-                  B.gn_opts(mode=B.POS_VEL, max_iter=iters), z, vh)
+                  B.gn_opts(mode=B.POS_VEL, max_iter=iters, proj_fp32=2), z, vh)
     vh2 = torch.zeros_like(z0)
     zz = torch.zeros_like(z0)
     B.rom_project(dec, X, idx, x_trial.contiguous(), v_trial.contiguous(), z, z, 0.0,
-                  B.gn_opts(mode=B.VEL_ONLY, max_iter=0), zz, vh2)
+                  B.gn_opts(mode=B.VEL_ONLY, max_iter=0, proj_fp32=2), zz, vh2)
     return z, vh2
+
+
+def rom_initial_states(dec, scene, v0s, z_candidates, n_quad=65536, seed=0, iters=8, chunk=64,
+                       device="cuda"):
+    """rom_initial_state for many initial velocities.  The position problem
+    (x = X at t = 0) is solved from each candidate code (z_candidates: [c][r],
+    e.g. the codes a decoder was trained with for the initial frames of its
+    simulations, which all start from the reference configuration); a
+    network can hold the reference configuration at several codes whose
+    tangent spaces differ, so each instance starts at the candidate whose
+    latent Jacobian J best represents its initial velocity: with v uniform
+    over the points, the least-squares residual is the quadratic form
+    v^T (n I - M (J^T J)^-1 M^T) v, M = sum_p J_p (d x r), formed once per
+    candidate.  The velocity problems then run at the chosen codes in
+    batched rom_project calls of `chunk` instances.  Returns z, vh: [len(v0s),
+    r] float64 device tensors and the chosen candidate per instance."""
+    P, d, r = scene["P"], scene["dim"], dec.r
+    rng = np.random.default_rng(seed)
+    q = np.sort(rng.choice(P, size=min(n_quad, P), replace=False)).astype(np.int32)
+    nq = len(q)
+    X = torch.tensor(np.ascontiguousarray(scene["X"].T), device=device)
+    qi = torch.tensor(q, device=device).long()
+    Xq = X[:, qi].contiguous()
+    cand = torch.as_tensor(np.asarray(z_candidates, dtype=np.float64), device=device)
+    nc = cand.shape[0]
+    # position least squares from every candidate (one batched projection)
+    idx = torch.tensor(np.tile(q[None, :], (nc, 1)), device=device)
+    x_trial = Xq[None].expand(nc, d, nq).contiguous()
+    v_zero = torch.zeros(nc, d, nq, device=device)
+    zc = torch.zeros_like(cand)
+    junk = torch.zeros_like(cand)
+    B.rom_project(dec, X, idx, x_trial, v_zero, cand.contiguous(), cand.contiguous(), 1.0,
+                  B.gn_opts(mode=B.POS_VEL, max_iter=iters, proj_fp32=2), zc, junk)
+    # per candidate: J^T J and M = sum_p J_p from the latent Jacobian
+    Jz = torch.zeros(nc, d * r, nq, device=device)
+    B.rom_decode_jac(dec, Xq, zc, Jz=Jz)
+    J = Jz.double().reshape(nc, d, r, nq).permute(0, 3, 1, 2).reshape(nc, nq * d, r)
+    JtJ = J.transpose(1, 2) @ J                               # [c][r][r]
+    M = Jz.double().reshape(nc, d, r, nq).sum(-1)             # [c][d][r]
+    Q = nq * torch.eye(d, dtype=torch.float64, device=device)[None] - \
+        M @ torch.linalg.solve(JtJ, M.transpose(1, 2))        # [c][d][d]
+    V = torch.as_tensor(np.asarray(v0s, dtype=np.float64), device=device)   # [b][d]
+    res = torch.einsum("bi,cij,bj->bc", V, Q, V)
+    choice = res.argmin(1)
+    z = zc[choice].contiguous()
+    Bn = len(v0s)
+    vh = torch.zeros(Bn, r, dtype=torch.float64, device=device)
+    opts = B.gn_opts(mode=B.VEL_ONLY, max_iter=0, proj_fp32=2)
+    for c0 in range(0, Bn, chunk):
+        c1 = min(Bn, c0 + chunk)
+        nb = c1 - c0
+        idx = torch.tensor(np.tile(q[None, :], (nb, 1)), device=device)
+        x_t = Xq[None].expand(nb, d, nq).contiguous()
+        v_t = V[c0:c1].float()[:, :, None].expand(nb, d, nq).contiguous()
+        zz = z[c0:c1].contiguous()
+        zo = torch.zeros_like(zz)
+        vv = torch.zeros_like(zz)
+        B.rom_project(dec, X, idx, x_t, v_t, zz, zz, 0.0, opts, zo, vv)
+        vh[c0:c1] = vv
+    return z, vh, choice.cpu().numpy()
+
+
+def nearest_codes(dec, scene, frames, codes, n_sub=4096, seed=1, device="cuda"):
+    """For each frame (d, P), the row of codes whose decoding of a random
+    subset of n_sub particles is closest to the frame on that subset: a
+    starting point for the projection of a frame of an unseen simulation."""
+    P, d = scene["P"], scene["dim"]
+    rng = np.random.default_rng(seed)
+    q = torch.tensor(np.sort(rng.choice(P, size=min(n_sub, P), replace=False)), device=device).long()
+    X = torch.tensor(np.ascontiguousarray(scene["X"].T), device=device)
+    Xq = X[:, q].contiguous()
+    C = torch.as_tensor(np.asarray(codes, dtype=np.float64), device=device).contiguous()
+    xb = torch.zeros(C.shape[0], d, len(q), device=device)
+    B.rom_decode(dec, Xq, C, xb)
+    out = []
+    for f in frames:
+        res = ((xb - f[:, q][None]) ** 2).sum((1, 2))
+        out.append(C[int(res.argmin().item())].cpu().numpy())
+    return out
 
 
 def best_projection(dec, scene, frames, z_guesses, n_quad=65536, seed=0, iters=6,
@@ -101,7 +180,7 @@ def best_projection(dec, scene, frames, z_guesses, n_quad=65536, seed=0, iters=6
     idx = torch.tensor(q[None, :], device=device)
     qi = idx[0].long()
     v_trial = torch.zeros(1, d, len(q), device=device)
-    opts = B.gn_opts(mode=B.POS_VEL, max_iter=iters)
+    opts = B.gn_opts(mode=B.POS_VEL, max_iter=iters, proj_fp32=2)
     ws = torch.empty(B.rom_project_workspace_bytes(dec, 1, len(q), opts), dtype=torch.uint8,
                      device=device)
     xbuf = torch.zeros(1, d, P, device=device)

@@ -190,11 +190,15 @@ def balanced_penalties(snap):
 def normalisation(snap):
     """Min-max input range of the reference positions and mean / standard
     deviation of the displacements (Appendix B feature scaling)."""
+    d = snap.X_sub.shape[1]
     X = snap.X_sub.cpu().numpy().astype(np.float64)
-    u = (snap.fx - snap.X_sub[None]).reshape(-1, snap.X_sub.shape[1]).cpu().numpy().astype(np.float64)
-    std = u.std(0)
+    # over every row of every frame, in float64 on the device (the frames
+    # can hold hundreds of millions of rows)
+    u = (snap.fx - snap.X_sub[None]).reshape(-1, d).double()
+    mean = u.mean(0)
+    std = torch.sqrt(((u - mean) ** 2).mean(0)).cpu().numpy()
     std = np.where(std > 0, std, 1.0)
-    return X.min(0), X.max(0), u.mean(0), std
+    return X.min(0), X.max(0), mean.cpu().numpy(), std
 
 
 def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B.PREC_BF16,

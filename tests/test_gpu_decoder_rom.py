@@ -206,6 +206,56 @@ def test_projection_captured_in_a_graph(gpu):
             assert torch.equal(st, want_st), (mode, rep)
 
 
+def test_projection_in_fp32_for_a_bf16_decoder(gpu):
+    """proj_fp32 = 2 runs all of the projection's decodes of a bf16 decoder on
+    its fp32 parameters: the result equals, bit for bit, the projection with
+    an fp32 decoder of the same weights (the fp32 path is the one checked
+    against the oracle), in both modes.  proj_fp32 = 1 (positions in fp32,
+    latent Jacobian in bf16): the position problem's minimiser is the fp32
+    objective's, so the latents land within the Gauss-Newton convergence of
+    the fp32 result; the velocity least squares (and with it the
+    velocity-only scheme) uses the bf16 Jacobian exactly as the all-bf16
+    projection does (bit-identical)."""
+    rng = np.random.default_rng(16)
+    d, r, P, Bn, ns = 3, 16, 3000, 3, 96
+    X = rng.uniform(0.2, 0.8, size=(P, d)).astype(np.float32)
+    odec, g32 = make_decoder(d, r, 128, 5, 23, X, out_std=0.05, prec=B.PREC_FP32)
+    _, g16 = make_decoder(d, r, 128, 5, 23, X, out_std=0.05, prec=B.PREC_BF16)
+    idx = np.sort(rng.choice(P, size=(Bn, ns), replace=False), axis=1).astype(np.int32)
+    zn = 0.3 * rng.standard_normal((Bn, r))
+    zp = zn - 0.01 * rng.standard_normal((Bn, r))
+    dt = 1e-2
+    xt = np.zeros((Bn, d, ns), np.float32)
+    for b in range(Bn):
+        xt[b] = OD.decode(odec, X[idx[b]].astype(np.float64), zn[b] + dt * rng.standard_normal(r)).T
+    vt = rng.standard_normal((Bn, d, ns)).astype(np.float32)
+    args = (T(soa(X)), T(idx, torch.int32), T(xt), T(vt), T(zn, torch.float64),
+            T(zp, torch.float64), dt)
+    for mode in (B.POS_VEL, B.VEL_ONLY):
+        outs = {}
+        for name, dec, f32 in (("fp32", g32, 0), ("bf16+fp32", g16, 2), ("bf16+x32", g16, 1),
+                               ("bf16", g16, 0)):
+            z = torch.zeros(Bn, r, dtype=torch.float64, device=dev)
+            v = torch.zeros_like(z)
+            B.rom_project(dec, *args, B.gn_opts(mode=mode, max_iter=3, proj_fp32=f32), z, v)
+            outs[name] = (z, v)
+        assert torch.equal(outs["fp32"][0], outs["bf16+fp32"][0]), mode
+        assert torch.equal(outs["fp32"][1], outs["bf16+fp32"][1]), mode
+        assert not torch.equal(outs["fp32"][1], outs["bf16"][1]), mode
+        assert torch.equal(outs["bf16+x32"][1], outs["bf16"][1]), mode
+        zr = outs["fp32"][0].cpu().numpy()
+        ez = np.max(np.abs(outs["bf16+x32"][0].cpu().numpy() - zr)) / (1.0 + np.max(np.abs(zr)))
+        e0 = np.max(np.abs(outs["bf16"][0].cpu().numpy() - zr)) / (1.0 + np.max(np.abs(zr)))
+        print("mode %d, latents against the fp32 projection: positions in fp32 %.2e, all bf16 %.2e"
+              % (mode, ez, e0))
+        if mode == B.POS_VEL:
+            assert ez < 1e-4
+        else:   # x_{n+1} = x_n + dt vhat: no position decode is involved
+            assert torch.equal(outs["bf16+x32"][0], outs["bf16"][0])
+    g32.close()
+    g16.close()
+
+
 def test_projection_rejects_a_short_workspace(gpu):
     c = _projection_case(15, Bn=1, ns=16)
     opts = B.gn_opts()
@@ -343,6 +393,9 @@ def test_rom_step_matches_oracle(gpu, model):
             zzp, zz, vv = zz, zn, vn
             if b == 0 and k == nst - 1:
                 print("oracle |Q| %d |I| %d ; gpu |Q| %d |I| %d" % (len(info["Q"]), len(info["I"]), q, a))
+                # the marked node set of the last step, counted while the
+                # step clears it again
+                assert a == len(info["I"])
         # the latent error is bounded by the fp32 resolution of the decoded
         # positions times the conditioning of the projection: compared to the
         # latent magnitude (and printed against the latent change)
@@ -529,6 +582,7 @@ def test_rom_step_eulerian_matches_oracle(gpu):
     ref = eulerian_oracle_run(s, odec, Es, nss, z0, v0, nst, 99)
     print("oracle lattice points %d |I| %d ; gpu %d %d"
           % (ref[0][2]["eulerian"]["n_candidates"], len(ref[0][2]["I"]), q, a))
+    assert a == len(ref[0][2]["I"])
     for b in range(2):
         zz, vv, _ = ref[b]
         dz = np.max(np.abs(z.cpu().numpy()[b] - zz))
