@@ -616,6 +616,54 @@ int32_t mr_sync_status(void *stream, const int32_t *device_flags, int32_t n,
 /* Library version string (static storage). */
 const char *mr_version(void);
 
+/* ---- encoder (Section 4.1, Table 1) ------------------------------------
+ * The network that maps the concatenated deformed positions of a fixed set
+ * of material points (point-major: x_1, y_1, z_1, x_2, ...; in_len = d x
+ * points) to generalized coordinates, trained with the decoder.  Shape of
+ * Table 1: 1D convolutions of kernel 6 and stride 2, added while the next
+ * output length stays >= 32 (the last length is d_conv), then dense
+ * d_conv -> 32 and 32 -> r.  Each convolution has one input and one output
+ * channel, no padding and a bias; ELU follows every convolution and the
+ * first dense layer; the input coordinates are mapped per axis to [-1, 1]
+ * by in_min / in_max (the decoder's reference-position scaling).  fp32.
+ * Parameter vector (device float32 [n_params]): per convolution 6 weights
+ * then the bias; W1 (32 x d_conv, row-major), b1 (32), W2 (r x 32), b2 (r).
+ */
+
+/* Sizes for an input length and latent dimension (all outputs nullable):
+ * the number of convolutions, d_conv, the parameter count, the floats per
+ * frame of the activation record that rom_encoder_forward writes and
+ * rom_encoder_backward reads, and the floats per frame of the backward
+ * work buffer.  MR_EINVAL for in_len < 32 or r outside 1..64. */
+int32_t rom_encoder_layout(int64_t in_len, int32_t r, int32_t *n_conv,
+                           int64_t *d_conv, int64_t *n_params,
+                           int64_t *act_floats, int64_t *work_floats);
+
+/* Encodes n frames.  x: device float32 frames of in_len floats; frame f is
+ * x + frame_idx[f] * in_len (frame_idx: nullable device int32 [n]; NULL:
+ * frame f).  in_min, in_max: host float32 [d].  act: device float32
+ * [n][act_floats], written (the record the backward pass needs).  z:
+ * device float32 [n][r].  MR_EINVAL for bad sizes, in_len not a multiple
+ * of d, fewer than one convolution, or n above 65535; no synchronisation. */
+int32_t rom_encoder_forward(int32_t d, int32_t r, int64_t in_len, int32_t n,
+                            const float *x, const int32_t *frame_idx,
+                            const float *params, const float *in_min,
+                            const float *in_max, float *act, float *z,
+                            void *stream);
+
+/* Gradient of sum_f dz[f] . z[f] with respect to the parameters, for the
+ * frames and the activation record of the matching rom_encoder_forward
+ * call.  dz: device float32 [n][r]; grad: device float32 [n_params],
+ * overwritten; work: device float32 [n][work_floats] scratch.  Weight
+ * gradients are summed with float atomics (their last bits depend on the
+ * schedule).  Errors as rom_encoder_forward. */
+int32_t rom_encoder_backward(int32_t d, int32_t r, int64_t in_len, int32_t n,
+                             const float *x, const int32_t *frame_idx,
+                             const float *params, const float *in_min,
+                             const float *in_max, const float *act,
+                             const float *dz, float *grad, float *work,
+                             void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,7 @@ Modules:
   sampler  sample-point selection (stratified, SplitMix64)
   rom      Algorithms 2 and 3, initial latents, error metrics
   train    training loss and its gradients
+  encoder  the encoder network of Section 4.1 / Table 1 and its gradient
 
 Parity status: every function above is pinned by the CPU test suite
 against closed forms, invariants or brute force, except the accuracy of a

@@ -9,6 +9,7 @@ or fails to load, `load()` raises.
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -136,6 +137,13 @@ SIGNATURES = {
     "rom_train_loss": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _f32, _f32,
                               _vp, _vp, _vp, _vp, _vp]),
     "rom_adam_step": (_i32, [_i64, _vp, _vp, _vp, _vp, _f32, _f32, _f32, _f32, _i32, _vp]),
+    "rom_encoder_layout": (_i32, [_i64, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64),
+                                  ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                  ctypes.POINTER(_i64)]),
+    "rom_encoder_forward": (_i32, [_i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   _vp]),
+    "rom_encoder_backward": (_i32, [_i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    _vp, _vp, _vp]),
     "rom_train_gather": (_i32, [_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, _vp, _vp]),
     "mr_sync_status": (_i32, [_vp, _vp, _i32, _vp]),
@@ -492,6 +500,48 @@ def rom_project(dec, X, sample_idx, x_trial, v_trial, xhat_n, xhat_prev, dt, opt
         dt, ctypes.byref(opts), _ptr(xhat_next, torch.float64), _ptr(vhat_next, torch.float64),
         _ptr(iters, torch.int32), _ptr(resid, torch.float64), _ptr(status, torch.int32),
         _ptr(workspace, torch.uint8), workspace.numel(), _stream(stream)))
+
+
+def encoder_layout(in_len, r):
+    """(n_conv, d_conv, n_params, act_floats, work_floats) of the encoder."""
+    nc = _i32()
+    dc, npar, act, work = _i64(), _i64(), _i64(), _i64()
+    _check("rom_encoder_layout", load().rom_encoder_layout(
+        in_len, r, ctypes.byref(nc), ctypes.byref(dc), ctypes.byref(npar), ctypes.byref(act),
+        ctypes.byref(work)))
+    return nc.value, dc.value, npar.value, act.value, work.value
+
+
+def _host_f32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    return a, ctypes.c_void_p(a.ctypes.data)
+
+
+def encoder_forward(d, r, x, params, in_min, in_max, act, z, frame_idx=None, n=None,
+                    stream=None):
+    """x: device float32 [frames][in_len]; frame_idx: device int32 [n] or
+    None (n = x.shape[0]); act: [n][act_floats]; z: [n][r]."""
+    in_len = x.shape[-1]
+    n = (frame_idx.numel() if frame_idx is not None else x.shape[0]) if n is None else n
+    lo, plo = _host_f32(in_min)
+    hi, phi = _host_f32(in_max)
+    _check("rom_encoder_forward", load().rom_encoder_forward(
+        d, r, in_len, n, _ptr(x, torch.float32), _ptr(frame_idx, torch.int32),
+        _ptr(params, torch.float32), plo, phi, _ptr(act, torch.float32), _ptr(z, torch.float32),
+        _stream(stream)))
+
+
+def encoder_backward(d, r, x, params, in_min, in_max, act, dz, grad, work, frame_idx=None,
+                     n=None, stream=None):
+    in_len = x.shape[-1]
+    n = (frame_idx.numel() if frame_idx is not None else x.shape[0]) if n is None else n
+    lo, plo = _host_f32(in_min)
+    hi, phi = _host_f32(in_max)
+    _check("rom_encoder_backward", load().rom_encoder_backward(
+        d, r, in_len, n, _ptr(x, torch.float32), _ptr(frame_idx, torch.int32),
+        _ptr(params, torch.float32), plo, phi, _ptr(act, torch.float32),
+        _ptr(dz, torch.float32), _ptr(grad, torch.float32), _ptr(work, torch.float32),
+        _stream(stream)))
 
 
 class Rom:

@@ -97,6 +97,58 @@ class TrainLossFn(torch.autograd.Function):
         return dg * dloss, dG * dloss, dGv * dloss, None, None, None, None, None, None, None, None
 
 
+class EncoderFn(torch.autograd.Function):
+    """(encoder params) -> z [n][r] for the frames frame_idx of x [frames][in_len]
+    (rom_encoder_forward / rom_encoder_backward)."""
+
+    @staticmethod
+    def forward(ctx, params, x, frame_idx, r, d, in_min, in_max):
+        n = frame_idx.numel()
+        _, _, _, actf, workf = B.encoder_layout(x.shape[1], r)
+        act = torch.empty(n, actf, device=x.device)
+        z = torch.empty(n, r, device=x.device)
+        B.encoder_forward(d, r, x, params, in_min, in_max, act, z, frame_idx=frame_idx)
+        ctx.keep = (params, x, frame_idx, act, r, d, in_min, in_max, workf)
+        return z
+
+    @staticmethod
+    def backward(ctx, dz):
+        params, x, frame_idx, act, r, d, in_min, in_max, workf = ctx.keep
+        g = torch.empty_like(params)
+        work = torch.empty(frame_idx.numel(), workf, device=x.device)
+        B.encoder_backward(d, r, x, params, in_min, in_max, act, dz.contiguous(), g, work,
+                           frame_idx=frame_idx)
+        return g, None, None, None, None, None, None
+
+
+def encoder_init(in_len, r, seed):
+    """Glorot-uniform encoder parameters (Appendix B), zero biases, in the
+    library's layout (rom_encoder_layout)."""
+    nc, dc, npar, _, _ = B.encoder_layout(in_len, r)
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nc):
+        a = math.sqrt(6.0 / 12.0)               # 6 taps in, 6 out
+        out.extend(rng.uniform(-a, a, 6).tolist() + [0.0])
+    a = math.sqrt(6.0 / (dc + 32))
+    out.extend(rng.uniform(-a, a, 32 * dc).tolist() + [0.0] * 32)
+    a = math.sqrt(6.0 / (32 + r))
+    out.extend(rng.uniform(-a, a, r * 32).tolist() + [0.0] * r)
+    assert len(out) == npar
+    return np.asarray(out, dtype=np.float32)
+
+
+def encode(params, frames, r, d, in_min, in_max, chunk=128):
+    """Codes of frames [n][in_len] (device) under encoder params (device)."""
+    n = frames.shape[0]
+    out = torch.empty(n, r, device=frames.device)
+    with torch.no_grad():
+        for c0 in range(0, n, chunk):
+            idx = torch.arange(c0, min(n, c0 + chunk), dtype=torch.int32, device=frames.device)
+            out[c0:c0 + idx.numel()] = EncoderFn.apply(params, frames, idx, r, d, in_min, in_max)
+    return out
+
+
 def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     B._check("rom_adam_step", B.load().rom_adam_step(
         param.numel(), B._ptr(param), B._ptr(grad), B._ptr(m), B._ptr(v), lr, beta1, beta2, eps,
@@ -108,10 +160,11 @@ class SnapshotSet:
     x [n_frames][P_sub][d], F [n_frames][P_sub][d][d], v [n_frames][P_sub][d];
     X_sub [P_sub][d]; next_frame[f] = f + 1 inside a simulation, -1 at its end."""
 
-    def __init__(self, X_sub, fx, fF, fv, next_frame, dt_frame):
+    def __init__(self, X_sub, fx, fF, fv, next_frame, dt_frame, sub=None):
         self.X_sub, self.fx, self.fF, self.fv = X_sub, fx, fF, fv
         self.next_frame = next_frame
         self.dt_frame = dt_frame
+        self.sub = sub          # indices of the subset in the scene's particles
 
     @property
     def n_frames(self):
@@ -172,7 +225,7 @@ def generate_snapshots(scene, instances, n_steps, every, n_sub, seed, sort_every
     n_frames = fx.shape[0]
     next_frame = np.array([i + 1 if nxt[i] else -1 for i in range(n_frames)], dtype=np.int32)
     X_sub = torch.tensor(scene["X"][sub], device=device)
-    return SnapshotSet(X_sub, fx, fF, fv, next_frame, every * scene["dt"])
+    return SnapshotSet(X_sub, fx, fF, fv, next_frame, every * scene["dt"], sub=sub)
 
 
 def balanced_penalties(snap):
@@ -203,13 +256,18 @@ def normalisation(snap):
 
 def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B.PREC_BF16,
           lr0=1e-3, lr1=1e-6, lam_F=100.0, lam_v=0.01, seed=0, log_every=0, init=None,
-          eval_rows_per_frame=64, device="cuda"):
-    """Trains decoder weights and per-snapshot latent codes with Adam, the
-    learning rate decaying exponentially from lr0 to lr1.  Returns
-    (weights, biases, Z, normalisation, loss history); with log_every > 0
-    the history holds (step, objective) on a fixed evaluation batch of
-    eval_rows_per_frame random particles of every frame, before step 0,
-    every log_every steps and after the last step."""
+          eval_rows_per_frame=64, encoder=False, device="cuda"):
+    """Trains decoder weights and the snapshots' latent codes with Adam, the
+    learning rate decaying exponentially from lr0 to lr1.  The codes are
+    free per-snapshot variables, or with encoder=True the encoder network of
+    Section 4.1 applied to each snapshot's concatenated positions, trained
+    with the decoder (each step encodes the batch's snapshots and their
+    successors).  Returns (weights, biases, Z, normalisation, loss history)
+    and, with encoder=True, the encoder parameters as a sixth item (Z then
+    holds every snapshot's code under the trained encoder); with
+    log_every > 0 the history holds (step, objective) on a fixed evaluation
+    batch of eval_rows_per_frame random particles of every frame, before
+    step 0, every log_every steps and after the last step."""
     from . import scenes
     d = snap.X_sub.shape[1]
     in_min, in_max, mean, std = normalisation(snap)
@@ -225,6 +283,16 @@ def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B
     Z = torch.zeros(snap.n_frames, r, device=device)
     m_p, v_p = torch.zeros_like(params), torch.zeros_like(params)
     m_z, v_z = torch.zeros_like(Z), torch.zeros_like(Z)
+    if encoder:
+        frames = snap.fx.reshape(snap.n_frames, -1)
+        pe = torch.tensor(encoder_init(frames.shape[1], r, seed + 3), device=device)
+        m_e, v_e = torch.zeros_like(pe), torch.zeros_like(pe)
+        enc_args = (r, d, in_min.astype(np.float32), in_max.astype(np.float32))
+
+        def codes(frame_ids):
+            """Z with the rows frame_ids encoded (differentiable), others 0."""
+            z = EncoderFn.apply(pe_var, frames, frame_ids, *enc_args)
+            return torch.zeros(snap.n_frames, r, device=device).index_copy(0, frame_ids.long(), z)
     nf = torch.tensor(snap.next_frame, device=device)
     rng = np.random.default_rng(seed + 1)
     X = torch.empty(rows, d, device=device)
@@ -250,6 +318,8 @@ def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B
 
         def evaluate():
             with torch.no_grad():
+                if encoder:
+                    Z.copy_(encode(pe, frames, *enc_args))
                 g, G, Gv = DecoderTrainFn.apply(params, Z, eX, e_fr, e_nxt, tr, snap.n_frames,
                                                 eval_rows_per_frame, float(snap.dt_frame))
                 return float(TrainLossFn.apply(g, G, Gv, ext, eFt, evt, e_nxt, snap.n_frames,
@@ -267,13 +337,21 @@ def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B
             B._ptr(snap.fF), B._ptr(snap.fv), B._ptr(fr_t, torch.int32), B._ptr(pid_t, torch.int32),
             B._ptr(X), B._ptr(xt), B._ptr(Ft), B._ptr(vt), B._stream(None)))
         p = params.detach().requires_grad_(True)
-        z = Z.detach().requires_grad_(True)
+        if encoder:
+            pe_var = pe.detach().requires_grad_(True)
+            need = torch.unique(torch.cat([fr_t, nxt_t[nxt_t >= 0]])).to(torch.int32)
+            z = codes(need)
+        else:
+            z = Z.detach().requires_grad_(True)
         g, G, Gv = DecoderTrainFn.apply(p, z, X, fr_t, nxt_t, tr, n_groups, rows_per_group,
                                         float(snap.dt_frame))
         loss = TrainLossFn.apply(g, G, Gv, xt, Ft, vt, nxt_t, n_groups, rows_per_group, lam_F, lam_v)
         loss.backward()
         adam_step(params, p.grad.contiguous(), m_p, v_p, it + 1, lr)
-        adam_step(Z, z.grad.contiguous(), m_z, v_z, it + 1, lr)
+        if encoder:
+            adam_step(pe, pe_var.grad.contiguous(), m_e, v_e, it + 1, lr)
+        else:
+            adam_step(Z, z.grad.contiguous(), m_z, v_z, it + 1, lr)
         if log_every and ((it + 1) % log_every == 0 or it == steps - 1):
             history.append((it + 1, evaluate()))
     sizes = [d + r] + [width] * n_hidden + [d]
@@ -283,6 +361,9 @@ def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B
         Ws.append(flat[o:o + fi * fo].reshape(fo, fi)); o += fi * fo
         bs.append(flat[o:o + fo]); o += fo
     tr.close()
+    if encoder:
+        Z = encode(pe, frames, *enc_args)
+        return Ws, bs, Z.cpu().numpy(), (in_min, in_max, mean, std), history, pe.cpu().numpy()
     return Ws, bs, Z.cpu().numpy(), (in_min, in_max, mean, std), history
 
 

@@ -115,3 +115,68 @@ def test_training_on_full_order_snapshots_reduces_the_loss(gpu):
     # lowers this objective about 13-fold
     assert hist[-1][1] < 0.3 * hist[0][1]
     assert np.all(np.isfinite(Z))
+
+
+def test_encoder_chain_gradient_matches_oracle(gpu):
+    """Codes from the encoder (Section 4.1): the gradient of the training
+    objective with respect to the encoder's parameters, through the decoder's
+    training kernels and the encoder's backward pass (chained by autograd),
+    against the oracle's loss gradient with respect to the codes pushed
+    through the oracle encoder's backward pass.  fp32 kernels."""
+    from oracle import encoder as OE
+    rng = np.random.default_rng(77)
+    d, r, width, nh = 3, 4, 32, 2
+    n_groups, rpg, n_snap, P_sub = 3, 7, 5, 40
+    X, snap, nxt, _, xt, Ft, vt = _batch(rng, d, r, n_groups, rpg, n_snap)
+    frames = rng.uniform(0.2, 0.8, size=(n_snap, P_sub * d)).astype(np.float32)
+    L_in = P_sub * d
+    pe = (OE.xavier(L_in, r, 5) + 0.05 * rng.standard_normal(OE.param_count(L_in, r))).astype(np.float32)
+    Ws, bs = scenes.random_decoder(d, r, width, nh, 9, scale=1.0, bias_scale=0.1)
+    lo, hi = np.zeros(d, np.float32), np.ones(d, np.float32)
+    mean, std = np.full(d, 0.01, np.float32), np.full(d, 0.05, np.float32)
+    elo, ehi = np.full(d, 0.2, np.float32), np.full(d, 0.8, np.float32)
+    dt, lam_F, lam_v = 0.01, 100.0, 0.01
+    T = lambda a, dt_=torch.float32: torch.tensor(np.ascontiguousarray(a), device=dev, dtype=dt_)
+    tr = TR.Trainer(d, r, width, nh, B.PREC_FP32, n_groups * rpg, lo, hi, mean, std)
+    params = T(B.pack_params(Ws, bs))
+    pe_t = T(pe).requires_grad_(True)
+    need = np.unique(np.concatenate([snap, nxt[nxt >= 0]])).astype(np.int32)
+    z = TR.EncoderFn.apply(pe_t, T(frames), T(need, torch.int32), r, d, elo, ehi)
+    Zfull = torch.zeros(n_snap, r, device=dev).index_copy(0, T(need, torch.int64), z)
+    g, G, Gv = TR.DecoderTrainFn.apply(params, Zfull, T(X), T(snap, torch.int32),
+                                       T(nxt, torch.int32), tr, n_groups, rpg, dt)
+    loss = TR.TrainLossFn.apply(g, G, Gv, T(xt), T(Ft), T(vt), T(nxt, torch.int32), n_groups, rpg,
+                                lam_F, lam_v)
+    loss.backward()
+    zo, cache = OE.forward(pe.astype(np.float64), frames[need], r, d, elo, ehi)
+    Zo = np.zeros((n_snap, r))
+    Zo[need] = zo
+    odec = OD.Decoder([w.astype(np.float64) for w in Ws], [b.astype(np.float64) for b in bs],
+                      lo, hi, mean, std)
+    L, _, _, gZ = OT.loss_and_grads(odec, Zo, X, np.repeat(snap, rpg), np.repeat(nxt, rpg), xt, Ft,
+                                    vt, dt, lam_F, lam_v)
+    ge = OE.backward(pe.astype(np.float64), cache, gZ[need], r)
+    got = pe_t.grad.cpu().numpy()
+    err = np.max(np.abs(got - ge)) / np.max(np.abs(ge))
+    print("encoder chain: loss rel %.2e, gradient err %.2e of its scale"
+          % (abs(loss.item() - L) / abs(L), err))
+    assert abs(loss.item() - L) < 1e-4 * abs(L)
+    assert err < 1e-3
+    tr.close()
+
+
+def test_training_with_the_encoder_reduces_the_loss(gpu):
+    """The snapshots of the test above, trained with codes from the encoder
+    network instead of free per-snapshot codes (bf16 decoder kernels, fp32
+    encoder)."""
+    s = scenes.scene_3d(n=32, cube_cells=8, seed=8)
+    inst = [(2e4, (0.5, -1.0, 0.0)), (5e4, (-0.5, -2.0, 0.3))]
+    snap = TR.generate_snapshots(s, inst, n_steps=100, every=5, n_sub=1024, seed=3)
+    Ws, bs, Z, norm, hist, pe = TR.train(snap, width=64, n_hidden=3, r=4, steps=400, n_groups=16,
+                                         rows_per_group=64, log_every=50, lr0=1e-2, lr1=1e-4,
+                                         encoder=True)
+    print("objective on the evaluation batch (encoder codes)", hist)
+    assert hist[-1][1] < 0.3 * hist[0][1]
+    assert np.all(np.isfinite(Z)) and np.all(np.isfinite(pe))
+    # distinct snapshots get distinct codes
+    assert np.min(np.linalg.norm(Z[1:] - Z[:-1], axis=1)) > 0.0

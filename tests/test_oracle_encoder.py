@@ -95,3 +95,16 @@ def test_gradient_matches_central_differences():
         zm, _ = OE.forward(p - e, x, r, d, lo, hi)
         fd[i] = np.sum(dz * (zp - zm)) / (2 * h)
     np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8)
+
+
+def test_library_layout_matches_the_oracle():
+    """The library's encoder layout query (host code, no GPU) gives the
+    oracle's lengths and parameter count."""
+    from paper_2109_12390_amd import binding as B
+    for L, r in ((196608, 16), (80, 3), (3 * 1000, 8), (32 * 3 + 6, 5)):
+        lens = OE.conv_lengths(L)
+        if len(lens) == 1:
+            continue
+        nc, dc, npar, act, work = B.encoder_layout(L, r)
+        assert (nc, dc, npar) == (len(lens) - 1, lens[-1], OE.param_count(L, r))
+        assert act == sum(lens[1:]) + 32 and work == 2 * lens[1]
