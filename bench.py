@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--batched-study-instances", type=int, default=256)
     ap.add_argument("--batched-study-steps", type=int, default=400)
     ap.add_argument("--batched-study-train-steps", type=int, default=8000)
+    ap.add_argument("--batched-study-codes", default="encoder", choices=("encoder", "free"))
+    ap.add_argument("--batched-study-quadratures", default="lagrangian,eulerian")
     ap.add_argument("--rom-pareto-steps", type=int, default=30,
                     help="steps per point of the quadrature / samples / projection sweep (0: off)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -280,7 +282,9 @@ def main():
         log("batched reduced-model study ...")
         out["batched_study"] = batched_study(B, scenes, s, n_inst=args.batched_study_instances,
                                              n_steps=args.batched_study_steps,
-                                             train_steps=args.batched_study_train_steps)
+                                             train_steps=args.batched_study_train_steps,
+                                             codes=args.batched_study_codes,
+                                             quadratures=args.batched_study_quadratures.split(","))
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(s)
@@ -731,7 +735,7 @@ SHAPE_NAMES = ["1 point tile per wave", "2 point tiles per wave", "4 point tiles
 
 def batched_study(B, scenes, s, n_inst=256, n_steps=400, record_every=20, train_steps=8000,
                   n_train=8, n_held=2, train_frames=200, every=5, n_eval=65536, r=16, width=128,
-                  n_hidden=5):
+                  n_hidden=5, codes="encoder", quadratures=("lagrangian", "eulerian")):
     """Training on several parameter instances and the batched reduced model
     judged per instance against the full-order model.
 
@@ -741,7 +745,10 @@ def batched_study(B, scenes, s, n_inst=256, n_steps=400, record_every=20, train_
     transfers); the decoder (bf16, then fp32, same initial weights and
     batches) is trained with Adam and judged by its final objective and by
     the best projection of n_held held-out instances' trajectories onto its
-    manifold.  Then n_inst instances (E log-uniform in [1e3, 1e5], v0
+    manifold; a third training (bf16) takes its codes from the encoder
+    network of Section 4.1 instead of free per-snapshot codes.  `codes`
+    picks the bf16 decoder that drives the reduced runs ("free" or
+    "encoder").  Then n_inst instances (E log-uniform in [1e3, 1e5], v0
     uniform in [-2, 2]^3, 256-1024 samples each, a second seed) start from
     the least-squares initial latents (position and velocity) and advance
     together, one HIP graph per batched step, with each quadrature; every
@@ -765,34 +772,54 @@ def batched_study(B, scenes, s, n_inst=256, n_steps=400, record_every=20, train_
     lam_F, lam_v = TR.balanced_penalties(snap)
     held_fom = [EV.fom_positions(s, E, v0, n_fom, 50, affine=False) for (E, v0) in held]
     fpi = n_fom // every + 1                               # frames per training instance
+    sub_train = torch.tensor(snap.sub, device=dev).long()
+
+    def as_frames(frs):
+        """[d][P] frames -> concatenated positions of the training subset."""
+        return torch.stack([f[:, sub_train].T.reshape(-1) for f in frs]).contiguous()
+
     decs, training = {}, {}
-    for prec, pname in ((B.PREC_BF16, "bf16"), (B.PREC_FP32, "fp32")):
+    # free codes train best from 1e-2; the encoder from the paper's 1e-3
+    # (from 1e-2 its objective stalls at 4x that of free codes)
+    for prec, pname, enc, lr0 in ((B.PREC_BF16, "bf16", False, 1e-2),
+                                  (B.PREC_FP32, "fp32", False, 1e-2),
+                                  (B.PREC_BF16, "bf16_encoder", True, 1e-3)):
         t0 = time.perf_counter()
-        Ws, bs, Z, norm, hist = TR.train(snap, width=width, n_hidden=n_hidden, r=r,
-                                         steps=train_steps, n_groups=64, rows_per_group=256,
-                                         precision=prec, lr0=1e-2, lr1=1e-4, lam_F=lam_F,
-                                         lam_v=lam_v, log_every=train_steps // 4)
+        out = TR.train(snap, width=width, n_hidden=n_hidden, r=r, steps=train_steps, n_groups=64,
+                       rows_per_group=256, precision=prec, lr0=lr0, lr1=lr0 * 1e-2, lam_F=lam_F,
+                       lam_v=lam_v, log_every=train_steps // 4, encoder=enc)
+        Ws, bs, Z, norm, hist = out[:5]
+        pe = torch.tensor(out[5], device=dev) if enc else None
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
         dec = B.Decoder(Ws, bs, *norm, B.OUT_DISPLACEMENT, prec)
+        enc_args = (r, 3, norm[0].astype(np.float32), norm[1].astype(np.float32))
         # held-out reconstruction: best projection of the held-out frames
-        # (every 50 steps), each from the training code that decodes closest
-        # to it
+        # (every 50 steps), each from the encoder's code of the frame, or
+        # without an encoder from the training code that decodes closest
         rec = []
         for fr in held_fom:
-            zg = EV.nearest_codes(dec, s, fr, Z)
+            if enc:
+                zg = TR.encode(pe, as_frames(fr), *enc_args).double().cpu().numpy()
+            else:
+                zg = EV.nearest_codes(dec, s, fr, Z)
             proj = EV.best_projection(dec, s, fr, zg)
             rec.append(round(EV.displacement_error(proj, fr, s["X"])[0], 4))
             del proj
-        training[pname] = {"objective": [(int(a), float(b)) for a, b in hist],
+        training[pname] = {"learning_rate": [lr0, lr0 * 1e-2],
+                           "objective": [(int(a), float(b)) for a, b in hist],
                            "final_objective": float(hist[-1][1]), "seconds": round(t_train, 1),
                            "rows_per_s": round(train_steps * 64 * 256 / t_train),
                            "held_out_best_projection_error": rec}
         log("batched study: training", pname, json.dumps(training[pname]))
-        decs[pname] = (dec, Z)
+        decs[pname] = (dec, Z, pe, enc_args)
+    snap_sub = snap.sub
     del snap
-    decs["fp32"][0].close()
-    dec, Z = decs["bf16"]
+    use = "bf16_encoder" if codes == "encoder" else "bf16"
+    for k in decs:
+        if k != use:
+            decs[k][0].close()
+    dec, Z, pe, enc_args = decs[use]
     # the batched instances
     Es, v0s = scenes.parameter_instances(n_inst, 32)
     rng = np.random.default_rng(33)
@@ -802,11 +829,18 @@ def batched_study(B, scenes, s, n_inst=256, n_steps=400, record_every=20, train_
     Xg = torch.tensor(np.ascontiguousarray(X.T), device=dev)
     sub_t = torch.tensor(sub, device=dev).long()
     Xe = Xg[:, sub_t].contiguous()
-    # initial latents: least squares from the training instances' first
-    # codes, each instance at the one whose tangent space fits its velocity
-    z_init, v_init, choice = EV.rom_initial_states(dec, s, v0s, Z.reshape(n_train, fpi, r)[:, 0])
-    log("batched study: initial codes chosen per training instance:",
-        np.bincount(choice, minlength=n_train).tolist())
+    # initial latents: least squares from the encoder's code of the
+    # reference configuration, or without an encoder from the training
+    # instances' first codes, each instance at the one whose tangent space
+    # fits its velocity
+    if pe is not None:
+        x_ref = torch.tensor(np.ascontiguousarray(X[snap_sub].reshape(1, -1)), device=dev)
+        cand = TR.encode(pe, x_ref, *enc_args).double().cpu().numpy()
+    else:
+        cand = Z.reshape(n_train, fpi, r)[:, 0]
+    z_init, v_init, choice = EV.rom_initial_states(dec, s, v0s, cand)
+    log("batched study: initial codes chosen per candidate:",
+        np.bincount(choice, minlength=len(cand)).tolist())
     # full-order reference per instance on the evaluation subset
     t0 = time.perf_counter()
     fom = []
@@ -821,7 +855,9 @@ def batched_study(B, scenes, s, n_inst=256, n_steps=400, record_every=20, train_
     Xs = X[sub].T.astype(np.float64)                      # [d][n_eval]
     grid = B.Grid(3, s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
     legs = {}
-    for qn, quad in (("lagrangian", B.QUAD_LAGRANGIAN), ("eulerian", B.QUAD_EULERIAN)):
+    qmap = {"lagrangian": B.QUAD_LAGRANGIAN, "eulerian": B.QUAD_EULERIAN}
+    for qn in quadratures:
+        quad = qmap[qn]
         rom = B.Rom(dec, grid, Xg, torch.tensor(Es.astype(np.float32), device=dev),
                     torch.tensor(ns, device=dev),
                     B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4, proj_fp32=1), seed=5,
@@ -885,10 +921,13 @@ def batched_study(B, scenes, s, n_inst=256, n_steps=400, record_every=20, train_
                                                if k != "e_u_per_instance"}))
     dec.close()
     return {"config": {"instances": n_inst, "particles": P, "samples": "256-1024 per instance",
-                       "r": r, "decoder": "bf16 MLP %d x %d, trained on %d instances" % (width, n_hidden, n_train),
+                       "r": r, "decoder": "bf16 MLP %d x %d, trained on %d instances, %s codes"
+                                          % (width, n_hidden, n_train, codes),
                        "E": "log-uniform [1e3, 1e5]", "v0": "uniform [-2, 2]^3",
                        "initial_latents": "least squares (position, then velocity) from the "
-                                          "training instance's first code that fits v0 best",
+                                          + ("encoder's code of the reference configuration"
+                                             if codes == "encoder" else
+                                             "training instance's first code that fits v0 best"),
                        "projection": "position-velocity, 3 Gauss-Newton iterations, damping 1e-4, "
                                      "positions of the projection decoded in fp32",
                        "steps": n_steps, "judged_every": record_every, "eval_particles": n_eval,

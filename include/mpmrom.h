@@ -461,7 +461,11 @@ typedef struct {
     int32_t newton_iters;    /* Eulerian: Newton iterations inverting the
                                 decoder, 1..16 (0 selects 2)              */
     float newton_tol;        /* Eulerian: largest residual max-norm of an
-                                accepted point, in cells (0 selects 1e-3) */
+                                accepted point, in cells (0 selects 1e-3);
+                                with a bf16 decoder at least 4 x 2^-8 of
+                                its largest output standard deviation (its
+                                positions' resolution, below which Newton
+                                cannot reduce the residual)               */
 } mr_rom_config;
 
 /* quadrature kinematics of the reduced step (mr_rom_config.quadrature).

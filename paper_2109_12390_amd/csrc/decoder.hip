@@ -1486,4 +1486,11 @@ namespace mr {
 int decoder_dim(const mr_decoder *dec) { return dec->d; }
 int decoder_latent(const mr_decoder *dec) { return dec->r; }
 int decoder_output_mode(const mr_decoder *dec) { return dec->mode; }
+int decoder_precision(const mr_decoder *dec) { return dec->prec; }
+float decoder_out_scale(const mr_decoder *dec)
+{
+    float m = 0.0f;
+    for (int a = 0; a < dec->d; ++a) m = fmaxf(m, fabsf(dec->stdv[a]));
+    return m;
+}
 }  // namespace mr

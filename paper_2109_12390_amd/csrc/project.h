@@ -8,6 +8,8 @@ namespace mr {
 int decoder_dim(const mr_decoder *dec);
 int decoder_latent(const mr_decoder *dec);
 int decoder_output_mode(const mr_decoder *dec);
+int decoder_precision(const mr_decoder *dec);
+float decoder_out_scale(const mr_decoder *dec);   // largest output standard deviation
 int32_t decoder_autotune(const mr_decoder *dec, int32_t B, int64_t n, int32_t cfg_mask,
                          int32_t reps, hipStream_t st);
 int32_t decode_jac_ex(const mr_decoder *dec, int32_t B, int64_t n_ref, const float *X, int64_t n,

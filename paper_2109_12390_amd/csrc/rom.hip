@@ -727,7 +727,12 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
         if (rc != MR_OK) return rc;
         const double hq = (double)g.dx / L;
         const float rho0_vq = (float)(R->cfg.rho0 * (d == 3 ? hq * hq * hq : hq * hq));
-        const float tol = R->newton_tol * g.dx;
+        // a bf16 decoder's positions carry about 2^-8 of its output scale
+        // (the inversion residual stalls there: 0.01-0.05 cells measured), so
+        // the acceptance test allows four times that
+        float tol = R->newton_tol * g.dx;
+        if (decoder_precision(R->dec) == MR_PREC_BF16)
+            tol = fmaxf(tol, 4.0f * 0.00390625f * decoder_out_scale(R->dec));
         if (d == 2)
             eul_finish_kernel<2><<<gq, TB, 0, st>>>(g, R->q_cap, R->q_count, R->qbase, R->qb_cap, L,
                                                     LD, R->XQ, R->xQ, R->FQ, R->rho, R->rn[0],

@@ -256,7 +256,7 @@ def normalisation(snap):
 
 def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B.PREC_BF16,
           lr0=1e-3, lr1=1e-6, lam_F=100.0, lam_v=0.01, seed=0, log_every=0, init=None,
-          eval_rows_per_frame=64, encoder=False, device="cuda"):
+          eval_rows_per_frame=64, encoder=False, encoder_lr_scale=1.0, device="cuda"):
     """Trains decoder weights and the snapshots' latent codes with Adam, the
     learning rate decaying exponentially from lr0 to lr1.  The codes are
     free per-snapshot variables, or with encoder=True the encoder network of
@@ -267,7 +267,8 @@ def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B
     holds every snapshot's code under the trained encoder); with
     log_every > 0 the history holds (step, objective) on a fixed evaluation
     batch of eval_rows_per_frame random particles of every frame, before
-    step 0, every log_every steps and after the last step."""
+    step 0, every log_every steps and after the last step.  The encoder's
+    learning rate is encoder_lr_scale times the decoder's."""
     from . import scenes
     d = snap.X_sub.shape[1]
     in_min, in_max, mean, std = normalisation(snap)
@@ -349,7 +350,7 @@ def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B
         loss.backward()
         adam_step(params, p.grad.contiguous(), m_p, v_p, it + 1, lr)
         if encoder:
-            adam_step(pe, pe_var.grad.contiguous(), m_e, v_e, it + 1, lr)
+            adam_step(pe, pe_var.grad.contiguous(), m_e, v_e, it + 1, lr * encoder_lr_scale)
         else:
             adam_step(Z, z.grad.contiguous(), m_z, v_z, it + 1, lr)
         if log_every and ((it + 1) % log_every == 0 or it == steps - 1):
