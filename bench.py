@@ -127,6 +127,10 @@ def main():
                          "model (0: skip)")
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--rom-batched-steps", type=int, default=4)
+    ap.add_argument("--rom-batched-error-steps", type=int, default=100,
+                    help="steps of the batched reduced model (decoder trained with the encoder "
+                         "on 8 instances) judged per instance against the full-order model "
+                         "(0: skip)")
     ap.add_argument("--rom-study", action="store_true",
                     help="the reduced model's error attribution and sample-count sweep with a "
                          "trained decoder (adds a few minutes)")
@@ -271,6 +275,12 @@ def main():
         if args.rom_instances > 0:
             out["rom_batched"] = rom_batched_throughput(B, scenes, s, args.rom_instances,
                                                         args.rom_batched_steps)
+            if args.rom_batched_error_steps > 0:
+                log("batched instances judged against their own full-order runs ...")
+                out["rom_batched"]["error_vs_full_order"] = batched_study(
+                    B, scenes, s, n_inst=args.rom_instances, n_steps=args.rom_batched_error_steps,
+                    train_steps=8000, codes="encoder", quadratures=("lagrangian",),
+                    trainings=("bf16_encoder",))
         if args.rom_accuracy_steps > 0:
             log("training a decoder on full-order snapshots and judging the reduced model ...")
             out["rom_trained"] = rom_trained_accuracy(B, scenes, s, args.rom_accuracy_steps,
@@ -516,7 +526,7 @@ def rom_pareto(B, scenes, s, steps):
 
 
 def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_hidden=5,
-                         n_samples=512):
+                         n_samples=512, codes="encoder"):
     """The reduced model with a trained decoder on the same 2,097,152-particle
     scene and parameters (E = 5e4, v0 = (0, -1, 0)): full-order snapshots
     (every 5th step of n_steps, 65,536 particles), GPU training (bf16
@@ -540,15 +550,20 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
     t_data = time.perf_counter() - t0
     lam_F, lam_v = TR.balanced_penalties(snap)
     t0 = time.perf_counter()
-    Ws, bs, Z, norm, hist = TR.train(snap, width=width, n_hidden=n_hidden, r=r, steps=train_steps,
-                                     n_groups=64, rows_per_group=256, lr0=1e-2, lr1=1e-4,
-                                     lam_F=lam_F, lam_v=lam_v, log_every=train_steps)
+    # codes from the encoder network (Section 4.1) at the paper's starting
+    # rate 1e-3, or free per-snapshot codes at 1e-2
+    enc = codes == "encoder"
+    lr0 = 1e-3 if enc else 1e-2
+    out = TR.train(snap, width=width, n_hidden=n_hidden, r=r, steps=train_steps, n_groups=64,
+                   rows_per_group=256, lr0=lr0, lr1=lr0 * 1e-2, lam_F=lam_F, lam_v=lam_v,
+                   log_every=train_steps, encoder=enc)
+    Ws, bs, Z, norm, hist = out[:5]
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     lo, hi, mean, std = norm
     dec = B.Decoder(Ws, bs, lo, hi, mean, std, B.OUT_DISPLACEMENT, B.PREC_BF16)
-    x_rom, st = EV.rom_positions(dec, s, E, v0, n_steps, 10, n_samples=n_samples,
-                                 opts=B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4),
+    opts = B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4, proj_fp32=1)
+    x_rom, st = EV.rom_positions(dec, s, E, v0, n_steps, 10, n_samples=n_samples, opts=opts,
                                  z_guess=Z[0])
     err, pos = EV.displacement_error(x_rom, fom, s["X"])
     del x_rom
@@ -566,7 +581,7 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
     lin = {"best_projection_displacement_error": round(EV.displacement_error(proj, fom, s["X"])[0], 4)}
     del proj
     xl, sl = EV.rom_positions(ldec, s, E, v0, n_steps, 10, n_samples=n_samples,
-                              opts=B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4),
+                              opts=opts,
                               z_guess=Zl[0])
     lin.update({"displacement_error": round(EV.displacement_error(xl, fom, s["X"])[0], 4),
                 "status": sl["status"], "decoder": "one linear layer, r = %d, fp32" % r})
@@ -576,13 +591,16 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
     # the same decoder under the other quadrature and the paper's fast
     # configuration (few samples, velocity-only projection)
     variants = []
-    for qn, quad, ns, mode, mn in (("eulerian", B.QUAD_EULERIAN, n_samples, B.POS_VEL,
-                                    "position-velocity"),
-                                   ("lagrangian", B.QUAD_LAGRANGIAN, 50, B.VEL_ONLY,
-                                    "velocity-only"),
-                                   ("eulerian", B.QUAD_EULERIAN, 50, B.VEL_ONLY, "velocity-only")):
+    for qn, quad, ns, mode, mn, pf in (("eulerian", B.QUAD_EULERIAN, n_samples, B.POS_VEL,
+                                        "position-velocity", 1),
+                                       ("lagrangian", B.QUAD_LAGRANGIAN, n_samples, B.POS_VEL,
+                                        "position-velocity, all decodes in bf16", 0),
+                                       ("lagrangian", B.QUAD_LAGRANGIAN, 50, B.VEL_ONLY,
+                                        "velocity-only", 0),
+                                       ("eulerian", B.QUAD_EULERIAN, 50, B.VEL_ONLY,
+                                        "velocity-only", 0)):
         xr, sv = EV.rom_positions(dec, s, E, v0, n_steps, 10, n_samples=ns,
-                                  opts=B.gn_opts(mode=mode, max_iter=3, damping=1e-4),
+                                  opts=B.gn_opts(mode=mode, max_iter=3, damping=1e-4, proj_fp32=pf),
                                   z_guess=Z[0], quadrature=quad)
         e2, p2 = EV.displacement_error(xr, fom, s["X"])
         variants.append({"quadrature": qn, "samples": ns, "projection": mn,
@@ -600,7 +618,7 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
     super_res = []
     for qn, quad in (("eulerian", B.QUAD_EULERIAN), ("lagrangian", B.QUAD_LAGRANGIAN)):
         xr, sv = EV.rom_positions(dec, fine, E, v0, n_steps, 10, n_samples=n_samples,
-                                  opts=B.gn_opts(mode=B.POS_VEL, max_iter=3, damping=1e-4),
+                                  opts=opts,
                                   z_guess=Z[0], quadrature=quad)
         e2, p2 = EV.displacement_error(xr, fom_f, fine["X"])
         del xr
@@ -621,13 +639,15 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
             "best_projection_displacement_error": round(err_proj, 4),
             "linear_manifold": lin,
             "train": {"steps": train_steps, "rows_per_step": 64 * 256, "objective": hist,
+                      "codes": codes, "learning_rate": [lr0, lr0 * 1e-2],
                       "rows_per_s": train_steps * 64 * 256 / t_train,
                       "lam_F": lam_F, "lam_v": lam_v, "seconds": t_train,
                       "snapshot_seconds": t_data, "frames": snap.n_frames, "particles": 65536},
             "config": {"instances": 1, "particles": s["P"], "samples": n_samples, "r": r,
                        "decoder": "bf16 MLP %d x %d, trained" % (width, n_hidden),
-                       "projection": "position-velocity, 3 Gauss-Newton iterations, damping 1e-4",
-                       "quadrature": "Lagrangian",
+                       "projection": "position-velocity, 3 Gauss-Newton iterations, damping 1e-4, "
+                                     "positions of the projection decoded in fp32",
+                       "codes": codes, "quadrature": "Lagrangian",
                        "reference": "full-order model without the affine transfer term"},
             "variants": variants, "super_resolution": super_res}
 
@@ -735,7 +755,8 @@ SHAPE_NAMES = ["1 point tile per wave", "2 point tiles per wave", "4 point tiles
 
 def batched_study(B, scenes, s, n_inst=256, n_steps=400, record_every=20, train_steps=8000,
                   n_train=8, n_held=2, train_frames=200, every=5, n_eval=65536, r=16, width=128,
-                  n_hidden=5, codes="encoder", quadratures=("lagrangian", "eulerian")):
+                  n_hidden=5, codes="encoder", quadratures=("lagrangian", "eulerian"),
+                  trainings=("bf16", "fp32", "bf16_encoder")):
     """Training on several parameter instances and the batched reduced model
     judged per instance against the full-order model.
 
@@ -784,6 +805,8 @@ def batched_study(B, scenes, s, n_inst=256, n_steps=400, record_every=20, train_
     for prec, pname, enc, lr0 in ((B.PREC_BF16, "bf16", False, 1e-2),
                                   (B.PREC_FP32, "fp32", False, 1e-2),
                                   (B.PREC_BF16, "bf16_encoder", True, 1e-3)):
+        if pname not in trainings:
+            continue
         t0 = time.perf_counter()
         out = TR.train(snap, width=width, n_hidden=n_hidden, r=r, steps=train_steps, n_groups=64,
                        rows_per_group=256, precision=prec, lr0=lr0, lr1=lr0 * 1e-2, lam_F=lam_F,
