@@ -11,7 +11,8 @@ Modules:
   decoder  g(X; xhat), dg/dX, dg/dxhat
   project  Algorithms 6 and 7 (velocity least squares, Gauss-Newton)
   sampler  sample-point selection (stratified, SplitMix64)
-  rom      Algorithms 2 and 3, initial latents, error metrics
+  rom      Algorithms 2 and 3, initial latents, initial-condition
+           correction fields, error metrics
   train    training loss and its gradients
   encoder  the encoder network of Section 4.1 / Table 1 and its gradient
 

@@ -117,6 +117,40 @@ def decode_jac(dec, X, xhat, vhat=None, chunk=1024):
     return x, F, J, v
 
 
+def mixed_jac(dec, X, xhat, u):
+    """The mixed second derivative d/de [dg/dX (X; xhat + e u)] at e = 0,
+    (P, d, d), by forward mode over forward mode: along the layers, with s
+    the pre-activation, T the spatial tangents, t the tangent along u and M
+    the mixed tangents, M' = elu''(s) (W T)(W t) + elu'(s) W M; elu'' is
+    exp(s) for s <= 0 and 0 above (the derivative of elu' away from 0)."""
+    X = np.asarray(X, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    P, d, r = X.shape[0], dec.d, dec.r
+    h = _input(dec, X, xhat)
+    T = np.zeros((P, d + r, d))
+    T[:, :d, :] = np.diag(2.0 / (dec.in_max - dec.in_min))[None]
+    t = np.zeros((P, d + r))
+    t[:, d:] = u[None]
+    M = np.zeros((P, d + r, d))
+    L = len(dec.weights)
+    for l in range(L):
+        W = dec.weights[l]
+        s = h @ W.T + dec.biases[l]
+        WT = np.matmul(W, T)
+        Wt = t @ W.T
+        WM = np.matmul(W, M)
+        if l < L - 1:
+            e1 = elu_prime(s)
+            e2 = np.where(s > 0.0, 0.0, np.exp(np.minimum(s, 0.0)))
+            h = elu(s)
+            M = (e2 * Wt)[:, :, None] * WT + e1[:, :, None] * WM
+            T = e1[:, :, None] * WT
+            t = e1 * Wt
+        else:
+            M = WM
+    return dec.out_std[None, :, None] * M
+
+
 def flatten_params(dec):
     """Pack [W_0 (row-major), b_0, W_1, b_1, ...] into one float64 vector."""
     parts = []

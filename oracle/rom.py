@@ -258,15 +258,37 @@ def eulerian_quadrature(dec, dim, n, dx, x_samples, zhat, vhat, ell, iters, tol,
             "X_all": X, "x_candidates": xq, "rho": rho, "tau": tau}
 
 
+def initial_fields(dec, X_all, xhat0, vhat0, V0):
+    """The correction fields that make the initial conditions exact
+    (Section 3.1, eqs. defMapApproxForm and essentialSpec, with the time
+    function t -> t) for a uniform initial velocity V0 (d,):
+        a(X) = X - g(X; xhat0)             grad a = I - dg/dX (X; xhat0)
+        b(X) = V0 - dg/dxhat (X; xhat0) vhat0
+        grad b = - d/dX [dg/dxhat (X; xhat0) vhat0]   (grad V0 = 0)
+    at every row of X_all.  Returns dict a, b (P, d), Ga, Gb (P, d, d)."""
+    X = np.asarray(X_all, dtype=np.float64)
+    x0, F0, _, v = _dec.decode_jac(dec, X, xhat0, vhat0)
+    d = X.shape[1]
+    return {"a": X - x0, "b": np.asarray(V0, dtype=np.float64)[None] - v,
+            "Ga": np.eye(d)[None] - F0, "Gb": -_dec.mixed_jac(dec, X, xhat0, vhat0)}
+
+
 def rom_step(dec, scene, X_all, m_all, V0_all, zhat, zhat_prev, vhat, dt,
              samples, opts, quadrature="lagrangian", ell=2, newton_iters=2, newton_tol=None,
-             rho0=None, rho_ref=None):
+             rho0=None, rho_ref=None, fields=None, t=0.0):
     """One ROM step (Algorithm 2) with Lagrangian (Algorithm 3) or Eulerian
     (Algorithm 4) quadrature kinematics.  Returns (zhat_next, vhat_next,
     info).  Eulerian: rho0 and the reference density lattice are required;
-    newton_tol defaults to 1e-3 dx."""
+    newton_tol defaults to 1e-3 dx.  fields (Lagrangian only): the output
+    of initial_fields; the kinematics are then those of
+    g~(X, xhat, t) = g(X; xhat) + a(X) + b(X) t at the step's start time t
+    (positions g + a + b t, deformation gradient dg/dX + grad a + t grad b,
+    velocity (dg/dxhat) vhat + b), and the projection fits g~ at t + dt:
+    positions to x_trial - a - b (t + dt), velocities to v_trial - b."""
     dim, n, dx = scene["dim"], scene["n"], scene["dx"]
     samples = np.asarray(samples, dtype=np.int64)
+    if fields is not None and quadrature != "lagrangian":
+        raise ValueError("correction fields need the Lagrangian quadrature")
     if quadrature == "eulerian":
         x_s = _dec.decode(dec, X_all[samples], zhat)
         tol = 1e-3 * dx if newton_tol is None else newton_tol
@@ -277,13 +299,25 @@ def rom_step(dec, scene, X_all, m_all, V0_all, zhat, zhat_prev, vhat, dt,
         info = {"I": eq["I"], "eulerian": eq}
     else:
         x_all = _dec.decode(dec, X_all, zhat)
+        if fields is not None:
+            x_all = x_all + fields["a"] + fields["b"] * t
         I, Q, N = neighbour_set(dim, n, dx, x_all, samples)
         xQ, FQ, JQ, vQ = _dec.decode_jac(dec, X_all[Q], zhat, vhat)
+        if fields is not None:
+            xQ = xQ + fields["a"][Q] + fields["b"][Q] * t
+            FQ = FQ + fields["Ga"][Q] + fields["Gb"][Q] * t
+            vQ = vQ + fields["b"][Q]
         pos = np.searchsorted(Q, samples)
         x_trial, v_trial = substep(scene, xQ, FQ, vQ, np.asarray(m_all)[Q],
                                    np.asarray(V0_all)[Q], xQ[pos], dt)
         info = {"I": I, "Q": Q, "N": N}
-    z, vh, it, f, status = _proj.project(dec, X_all[samples], x_trial, v_trial,
+    if fields is not None:
+        # g~ at t + dt is g + a + b (t + dt): the fields move to the targets
+        x_fit = x_trial - fields["a"][samples] - fields["b"][samples] * (t + dt)
+        v_fit = v_trial - fields["b"][samples]
+    else:
+        x_fit, v_fit = x_trial, v_trial
+    z, vh, it, f, status = _proj.project(dec, X_all[samples], x_fit, v_fit,
                                          zhat, zhat_prev, dt, opts)
     info.update({"x_trial": x_trial, "v_trial": v_trial, "iters": it, "objective": f,
                  "status": status})
