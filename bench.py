@@ -595,13 +595,15 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
                                         "position-velocity", 1),
                                        ("lagrangian", B.QUAD_LAGRANGIAN, n_samples, B.POS_VEL,
                                         "position-velocity, all decodes in bf16", 0),
+                                       ("lagrangian", B.QUAD_LAGRANGIAN, n_samples, B.POS_VEL,
+                                        "position-velocity, initial-condition fields", 1),
                                        ("lagrangian", B.QUAD_LAGRANGIAN, 50, B.VEL_ONLY,
                                         "velocity-only", 0),
                                        ("eulerian", B.QUAD_EULERIAN, 50, B.VEL_ONLY,
                                         "velocity-only", 0)):
         xr, sv = EV.rom_positions(dec, s, E, v0, n_steps, 10, n_samples=ns,
                                   opts=B.gn_opts(mode=mode, max_iter=3, damping=1e-4, proj_fp32=pf),
-                                  z_guess=Z[0], quadrature=quad)
+                                  z_guess=Z[0], quadrature=quad, exact_ic="fields" in mn)
         e2, p2 = EV.displacement_error(xr, fom, s["X"])
         variants.append({"quadrature": qn, "samples": ns, "projection": mn,
                          "latent_steps_per_s": round(1e3 / sv["ms_per_step"], 1),

@@ -527,6 +527,34 @@ int32_t rom_step(mr_rom *rom, int32_t n_steps, int64_t step0, double dt,
                  double *xhat, double *xhat_prev, double *vhat,
                  int32_t *status_out, int32_t use_graph, void *stream);
 
+/* Initial-condition correction fields (Section 3.1, eqs. defMapApproxForm
+ * and essentialSpec, time function t -> t): after this call the runner's
+ * kinematics are those of g~(X, xhat, t) = g(X; xhat) + a(X) + b(X) t with
+ *   a = X - g(X; xhat0),  b = V0 - (dg/dxhat)(X; xhat0) vhat0,
+ * grad a = I - dg/dX (X; xhat0), grad b = -d/dX [(dg/dxhat)(X; xhat0) vhat0]
+ * at every reference particle, so that positions, velocities and
+ * deformation gradients at t = 0 are exactly X, V0 and I for any initial
+ * latents; t = step counter x dt of rom_step (start the run at step0 = 0).
+ * Positions get a + b t, deformation gradients grad a + t grad b,
+ * velocities b, and the projection fits g~ at the step's end (its trial
+ * velocities shifted by -b).  xhat0, vhat0: device float64 [B][r]; v0:
+ * host or device float32 [B][d], a uniform initial velocity per instance
+ * (so grad V0 = 0).  grad b is a central difference of dg/dX along vhat0
+ * with a latent step of 1e-2 (max norm), fp32 decodes.  Lagrangian
+ * quadrature only (the Eulerian points would need the fields and their
+ * gradients at the inverted, non-particle reference positions inside every
+ * Newton step): MR_EINVAL otherwise.  xhat0 == NULL switches the fields off.
+ * Allocates 24 floats per particle and instance once, plus temporaries, and
+ * synchronises the stream (a set-up call). */
+int32_t rom_set_fields(mr_rom *rom, const double *xhat0, const double *vhat0,
+                       const float *v0, void *stream);
+
+/* Positions of every particle (the caller's order) for latents xhat
+ * (device float64 [B][r]) at time t: g(X; xhat), plus a + b t when the
+ * correction fields are on.  x_out: device float32 [B][d][P]. */
+int32_t rom_positions(const mr_rom *rom, const double *xhat, double t,
+                      float *x_out, void *stream);
+
 /* Diagnostics of the last step of instance b: quadrature-point count |Q|
  * and active-node count |I| (device values copied to the host; this call
  * synchronises the stream). */

@@ -127,6 +127,8 @@ SIGNATURES = {
     "rom_destroy": (None, [_vp]),
     "rom_step": (_i32, [_vp, _i32, _i64, _f64, _vp, _vp, _vp, _vp, _i32, _vp]),
     "rom_last_counts": (_i32, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _vp]),
+    "rom_set_fields": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "rom_positions": (_i32, [_vp, _vp, _f64, _vp, _vp]),
     "rom_train_param_count": (_i64, [_i32, _i32, _i32, _i32]),
     "rom_trainer_create": (_i32, [_i32, _i32, _i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _i32,
                                   ctypes.POINTER(_vp)]),
@@ -571,6 +573,25 @@ class Rom:
                                            _ptr(xhat, torch.float64), _ptr(xhat_prev, torch.float64),
                                            _ptr(vhat, torch.float64), _ptr(status, torch.int32),
                                            1 if use_graph else 0, _stream(stream)))
+
+    def set_fields(self, xhat0, vhat0, v0, stream=None):
+        """Initial-condition correction fields (rom_set_fields); v0 is a
+        (B, d) array of uniform initial velocities; xhat0=None turns them
+        off."""
+        if xhat0 is None:
+            _check("rom_set_fields", load().rom_set_fields(self.handle, None, None, None,
+                                                           _stream(stream)))
+            return
+        v = torch.as_tensor(np.asarray(v0, dtype=np.float32), device=xhat0.device).contiguous()
+        _check("rom_set_fields", load().rom_set_fields(
+            self.handle, _ptr(xhat0, torch.float64), _ptr(vhat0, torch.float64),
+            _ptr(v, torch.float32), _stream(stream)))
+
+    def positions(self, xhat, t, x_out, stream=None):
+        """Every particle's position (caller order) at latents xhat, time t."""
+        _check("rom_positions", load().rom_positions(self.handle, _ptr(xhat, torch.float64),
+                                                     float(t), _ptr(x_out, torch.float32),
+                                                     _stream(stream)))
 
     def last_counts(self, b=0, stream=None):
         q, a = ctypes.c_int64(), ctypes.c_int64()

@@ -93,6 +93,10 @@ struct mr_rom {
     // the per-instance grids and bitmaps are all zero between steps: a step
     // clears only what it marked; set when a step was left unfinished
     int dirty;
+    // initial-condition correction fields (Lagrangian quadrature), runner
+    // order: a, b [B][d][P], grad a, grad b [B][d*d][P]; used when fields_on
+    float *fa, *fb, *fGa, *fGb;
+    int fields_on;
 };
 
 namespace mr {
@@ -619,6 +623,127 @@ __global__ void advance_kernel(int B, int r, double *z, double *zp, double *v, c
 
 __global__ void set_counter_kernel(int64_t *counter, int64_t v) { *counter = v; }
 
+// --- initial-condition correction fields (Section 3.1, eq. defMapApproxForm)
+// g~(X, xhat, t) = g(X; xhat) + a(X) + b(X) t, t = step counter x dt.
+
+// decoded positions of every particle (runner order) += a + b t
+__global__ void field_positions_kernel(int d, int64_t P, const int64_t *counter, double dt,
+                                       const float *fa, const float *fb, float *x_all)
+{
+    const int b = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const float t = (float)((double)*counter * dt);
+    for (int a = 0; a < d; ++a) {
+        const int64_t i = ((int64_t)b * d + a) * P + p;
+        x_all[i] += fa[i] + fb[i] * t;
+    }
+}
+
+// quadrature kinematics: x += a + b t, F += grad a + t grad b, v += b
+__global__ void field_quad_kernel(int d, int64_t P, int64_t q_cap, const int32_t *q_count,
+                                  const int32_t *Q, const int64_t *counter, double dt,
+                                  const float *fa, const float *fb, const float *fGa,
+                                  const float *fGb, float *xQ, float *FQ, float *vQ)
+{
+    const int b = blockIdx.y;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= q_count[b]) return;
+    const int64_t p = Q[(int64_t)b * q_cap + s];
+    const float t = (float)((double)*counter * dt);
+    for (int a = 0; a < d; ++a) {
+        const int64_t i = ((int64_t)b * d + a) * P + p;
+        const int64_t o = ((int64_t)b * d + a) * q_cap + s;
+        xQ[o] += fa[i] + fb[i] * t;
+        vQ[o] += fb[i];
+    }
+    for (int k = 0; k < d * d; ++k) {
+        const int64_t i = ((int64_t)b * d * d + k) * P + p;
+        FQ[((int64_t)b * d * d + k) * q_cap + s] += fGa[i] + fGb[i] * t;
+    }
+}
+
+// the projection fits g~ at t + dt: with x_trial = g(xhat_n) + dt v_trial
+// (positions on displacements), shifting the trial velocities by -b moves
+// both fields to the targets (x_trial - a - b (t + dt), v_trial - b)
+__global__ void field_velocity_kernel(int d, int64_t P, int ns_max, const int32_t *n_samples,
+                                      const int32_t *samples, const float *fb, float *vt)
+{
+    const int b = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ns_max || k >= n_samples[b]) return;
+    const int64_t p = samples[(int64_t)b * ns_max + k];
+    for (int a = 0; a < d; ++a)
+        vt[((int64_t)b * d + a) * ns_max + k] -= fb[((int64_t)b * d + a) * P + p];
+}
+
+// fields from the decodes at xhat0: a = X - g, grad a = I - dg/dX,
+// b = V0 - (dg/dxhat) vhat0 (in place over the decoded x, F, v)
+__global__ void field_init_kernel(int d, int64_t P, const float *X, const float *v0, float *fa,
+                                  float *fb, float *fGa)
+{
+    const int b = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    for (int a = 0; a < d; ++a) {
+        const int64_t i = ((int64_t)b * d + a) * P + p;
+        fa[i] = X[(int64_t)a * P + p] - fa[i];
+        fb[i] = v0[b * d + a] - fb[i];
+    }
+    for (int a = 0; a < d; ++a)
+        for (int c = 0; c < d; ++c) {
+            const int64_t i = ((int64_t)b * d * d + a * d + c) * P + p;
+            fGa[i] = (a == c ? 1.0f : 0.0f) - fGa[i];
+        }
+}
+
+// latents xhat0 +- eps_b vhat0 with eps_b = h / max_k |vhat0_k| (0 when
+// vhat0 = 0); inv2e[b] = 1 / (2 eps_b) or 0
+__global__ void field_fd_latents_kernel(int B, int r, double h, const double *z0, const double *v0,
+                                        double *zp, double *zm, double *inv2e)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double m = 0.0;
+    for (int k = 0; k < r; ++k) m = fmax(m, fabs(v0[b * r + k]));
+    const double eps = m > 0.0 ? h / m : 0.0;
+    for (int k = 0; k < r; ++k) {
+        zp[b * r + k] = z0[b * r + k] + eps * v0[b * r + k];
+        zm[b * r + k] = z0[b * r + k] - eps * v0[b * r + k];
+    }
+    inv2e[b] = m > 0.0 ? 0.5 / eps : 0.0;
+}
+
+// grad b = -(dg/dX (xhat0 + eps vhat0) - dg/dX (xhat0 - eps vhat0)) / (2 eps)
+// for instances b0 .. b0 + gridDim.y - 1 (Fp in place)
+__global__ void field_grad_b_kernel(int d, int64_t P, int b0, const double *inv2e, float *Fp,
+                                    const float *Fm)
+{
+    const int bl = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const float s = (float)inv2e[b0 + bl];
+    for (int k = 0; k < d * d; ++k) {
+        const int64_t i = ((int64_t)bl * d * d + k) * P + p;
+        Fp[i] = -(Fp[i] - Fm[i]) * s;
+    }
+}
+
+// caller-order positions += a + b t (fields in runner order, internal_of
+// maps the caller's particle to the runner's)
+__global__ void field_caller_positions_kernel(int d, int64_t P, const int32_t *internal_of,
+                                              float t, const float *fa, const float *fb, float *x)
+{
+    const int b = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int64_t q = internal_of[p];
+    for (int a = 0; a < d; ++a) {
+        const int64_t o = ((int64_t)b * d + a) * P;
+        x[o + p] += fa[o + q] + fb[o + q] * t;
+    }
+}
+
 // After the substep has read the grid: zero the grid nodes of every
 // instance's marked set I and the marks themselves (node bitmap and, for the
 // Eulerian quadrature, the stencil-base bitmap), so that the next step
@@ -748,6 +873,9 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
     // Algorithm 3: decode every particle, mark I, collect Q
     rc = rom_decode(R->dec, B, R->P, R->X, R->P, nullptr, xhat, R->x_all, st);
     if (rc != MR_OK) return rc;
+    const dim3 gp((unsigned)ceil_div(R->P, TB), (unsigned)B);
+    if (R->fields_on)
+        field_positions_kernel<<<gp, TB, 0, st>>>(d, R->P, R->counter, dt, R->fa, R->fb, R->x_all);
     if (d == 2)
         gather_mark_kernel<2><<<gs, TB, 0, st>>>(g, R->P, (int)R->ns_max, R->n_samples, R->samples,
                                                  R->x_all, R->xs, R->bitmap, R->words, R->status_step);
@@ -767,6 +895,9 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
     rc = decode_jac_ex(R->dec, B, R->P, R->X, R->q_cap, R->Q, 1, R->q_count, xhat, vhat, R->xQ,
                        R->FQ, R->vQ, nullptr, st);
     if (rc != MR_OK) return rc;
+    if (R->fields_on)
+        field_quad_kernel<<<gq, TB, 0, st>>>(d, R->P, R->q_cap, R->q_count, R->Q, R->counter, dt,
+                                             R->fa, R->fb, R->fGa, R->fGb, R->xQ, R->FQ, R->vQ);
     }
     // Algorithm 5
     const bool eul = R->quad == MR_QUAD_EULERIAN;
@@ -793,6 +924,9 @@ int32_t rom_one_step(mr_rom *R, double dt, double *xhat, double *xhat_prev, doub
             R->n_active);
     }
     MR_LAUNCH_CHECK();
+    if (R->fields_on)
+        field_velocity_kernel<<<gs, TB, 0, st>>>(d, R->P, (int)R->ns_max, R->n_samples, R->samples,
+                                                 R->fb, R->vt);
     // Algorithm 6 / 7
     ProjWS w = proj_ws_carve(R->proj_ws, d, r, B, R->ns_max, R->opts.max_backtrack);
     rc = project_impl(R->dec, d, r, B, R->P, R->X, R->ns_max, R->samples, R->n_samples, nullptr,
@@ -817,7 +951,8 @@ extern "C" void rom_destroy(mr_rom *R)
                     R->bitmap, R->Q,
                     R->q_count, R->n_active, R->xQ, R->FQ, R->vQ, R->grid, R->xs, R->xt, R->vt,
                     R->z_next, R->v_next, R->status_step, R->counter, R->proj_ws,
-                    R->qb_bitmap, R->qbase, R->qb_count, R->XQ, R->mQ, R->rho};
+                    R->qb_bitmap, R->qbase, R->qb_count, R->XQ, R->mQ, R->rho,
+                    R->fa, R->fb, R->fGa, R->fGb};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     if (R->graph) (void)hipGraphExecDestroy(R->graph);
@@ -1119,5 +1254,97 @@ extern "C" int32_t rom_last_counts(const mr_rom *R, int32_t b, int64_t *n_quad, 
     MR_CHECK_HIP(hipStreamSynchronize(st));
     *n_quad = q;
     *n_active = a;
+    return MR_OK;
+}
+
+extern "C" int32_t rom_set_fields(mr_rom *R, const double *xhat0, const double *vhat0,
+                                  const float *v0, void *stream)
+{
+    if (!R) return MR_EINVAL;
+    if (!xhat0) {
+        R->fields_on = 0;
+        return MR_OK;
+    }
+    if (!vhat0 || !v0 || R->quad != MR_QUAD_LAGRANGIAN) return MR_EINVAL;
+    const int d = R->d, r = R->r, B = R->B;
+    const int64_t P = R->P;
+    hipStream_t st = as_stream(stream);
+    MR_CHECK_HIP(hipStreamSynchronize(st));
+    if (!R->fa) {
+        bool ok = hipMalloc(&R->fa, 4 * (int64_t)B * d * P) == hipSuccess &&
+                  hipMalloc(&R->fb, 4 * (int64_t)B * d * P) == hipSuccess &&
+                  hipMalloc(&R->fGa, 4 * (int64_t)B * d * d * P) == hipSuccess &&
+                  hipMalloc(&R->fGb, 4 * (int64_t)B * d * d * P) == hipSuccess;
+        if (!ok) {
+            for (float **q : {&R->fa, &R->fb, &R->fGa, &R->fGb}) {
+                if (*q) (void)hipFree(*q);
+                *q = nullptr;
+            }
+            return MR_ENOMEM;
+        }
+    }
+    R->fields_on = 0;
+    const int TB = 256;
+    float *v0d = nullptr;
+    double *lat = nullptr;
+    float *Fm = nullptr;
+    const int CH = B < 8 ? B : 8;               // instances per difference pass
+    int32_t rc = MR_OK;
+    if (hipMalloc(&v0d, 4 * (int64_t)B * d) != hipSuccess ||
+        hipMalloc(&lat, 8 * ((int64_t)2 * B * r + B)) != hipSuccess ||
+        hipMalloc(&Fm, 4 * (int64_t)CH * d * d * P) != hipSuccess)
+        rc = MR_ENOMEM;
+    if (rc == MR_OK && hipMemcpyAsync(v0d, v0, 4 * (int64_t)B * d, hipMemcpyDefault, st) != hipSuccess)
+        rc = MR_EDEVICE;
+    // a, b, grad a from x, v, F at xhat0 (fp32 decodes)
+    if (rc == MR_OK)
+        rc = decode_jac_ex(R->dec, B, P, R->X, P, nullptr, 0, nullptr, xhat0, vhat0, R->fa, R->fGa,
+                           R->fb, nullptr, st, 0, 0, 1);
+    if (rc == MR_OK) {
+        field_init_kernel<<<dim3((unsigned)ceil_div(P, TB), (unsigned)B), TB, 0, st>>>(
+            d, P, R->X, v0d, R->fa, R->fb, R->fGa);
+        // grad b by a central difference of dg/dX along vhat0: a latent step
+        // of 1e-2 (max norm) keeps the truncation error near 1e-4 of grad b
+        // and the fp32 rounding of the difference near 1e-4 as well
+        double *zp = lat, *zm = lat + (int64_t)B * r, *inv2e = lat + (int64_t)2 * B * r;
+        field_fd_latents_kernel<<<(unsigned)ceil_div(B, 64), 64, 0, st>>>(B, r, 1e-2, xhat0, vhat0,
+                                                                           zp, zm, inv2e);
+        if (hipGetLastError() != hipSuccess) rc = MR_EDEVICE;
+        for (int b0 = 0; b0 < B && rc == MR_OK; b0 += CH) {
+            const int nb = B - b0 < CH ? B - b0 : CH;
+            float *Fp = R->fGb + (int64_t)b0 * d * d * P;
+            rc = decode_jac_ex(R->dec, nb, P, R->X, P, nullptr, 0, nullptr, zp + (int64_t)b0 * r,
+                               nullptr, nullptr, Fp, nullptr, nullptr, st, 0, 0, 1);
+            if (rc == MR_OK)
+                rc = decode_jac_ex(R->dec, nb, P, R->X, P, nullptr, 0, nullptr,
+                                   zm + (int64_t)b0 * r, nullptr, nullptr, Fm, nullptr, nullptr, st,
+                                   0, 0, 1);
+            if (rc == MR_OK)
+                field_grad_b_kernel<<<dim3((unsigned)ceil_div(P, TB), (unsigned)nb), TB, 0, st>>>(
+                    d, P, b0, inv2e, Fp, Fm);
+        }
+    }
+    if (rc == MR_OK && (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess))
+        rc = MR_EDEVICE;
+    if (v0d) (void)hipFree(v0d);
+    if (lat) (void)hipFree(lat);
+    if (Fm) (void)hipFree(Fm);
+    if (rc == MR_OK) R->fields_on = 1;
+    return rc;
+}
+
+extern "C" int32_t rom_positions(const mr_rom *R, const double *xhat, double t, float *x_out,
+                                 void *stream)
+{
+    if (!R || !xhat || !x_out) return MR_EINVAL;
+    hipStream_t st = as_stream(stream);
+    // row p of the output is the caller's particle p, the runner's internal_of[p]
+    int32_t rc = decode_jac_ex(R->dec, R->B, R->P, R->X, R->P, R->internal_of, 0, nullptr, xhat,
+                               nullptr, x_out, nullptr, nullptr, nullptr, st);
+    if (rc != MR_OK || !R->fields_on) return rc;
+    field_caller_positions_kernel<<<dim3((unsigned)ceil_div(R->P, 256), (unsigned)R->B), 256, 0,
+                                    st>>>(R->d, R->P, R->internal_of, (float)t, R->fa, R->fb,
+                                          x_out);
+    MR_LAUNCH_CHECK();
     return MR_OK;
 }

@@ -197,11 +197,14 @@ def best_projection(dec, scene, frames, z_guesses, n_quad=65536, seed=0, iters=6
 
 
 def rom_positions(dec, scene, E, v0, n_steps, record_every, n_samples, opts, seed=7,
-                  use_graph=True, z_guess=None, device="cuda", progress=None, **rom_kwargs):
+                  use_graph=True, z_guess=None, device="cuda", progress=None, exact_ic=False,
+                  **rom_kwargs):
     """Reduced-order positions of every particle at the recorded steps and
     the step statistics.  rom_kwargs go to the runner (e.g. the Eulerian
     quadrature options); progress(step) is called after each recorded
-    chunk."""
+    chunk.  exact_ic: the runner carries the initial-condition correction
+    fields of the least-squares initial latents (rom_set_fields), and the
+    positions include them."""
     P, d = scene["P"], scene["dim"]
     X = torch.tensor(np.ascontiguousarray(scene["X"].T), device=device)
     grid = _grid(scene)
@@ -210,10 +213,12 @@ def rom_positions(dec, scene, E, v0, n_steps, record_every, n_samples, opts, see
                 rho0=float(scene["rho"]), m_uniform=float(scene["m"]),
                 model=scene["model"], nu=scene["nu"], **rom_kwargs)
     z, vh = rom_initial_state(dec, scene, v0, z_guess=z_guess, device=device)
+    if exact_ic:
+        rom.set_fields(z.clone(), vh.clone(), np.asarray(v0, np.float64)[None])
     zp = z.clone()
     st = torch.zeros(1, dtype=torch.int32, device=device)
     xbuf = torch.zeros(1, d, P, device=device)
-    B.rom_decode(dec, X, z, xbuf)
+    rom.positions(z, 0.0, xbuf)
     out = [xbuf[0].clone()]
     done = 0
     times = []
@@ -224,7 +229,7 @@ def rom_positions(dec, scene, E, v0, n_steps, record_every, n_samples, opts, see
         a.record()
         rom.step(k, done, scene["dt"], z, zp, vh, status=st, use_graph=use_graph)
         b.record()
-        B.rom_decode(dec, X, z, xbuf)
+        rom.positions(z, (done + k) * scene["dt"], xbuf)
         torch.cuda.synchronize()
         times.append(a.elapsed_time(b) / k)
         done += k

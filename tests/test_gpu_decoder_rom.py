@@ -652,3 +652,113 @@ def test_lagrangian_quadrature_list_at_high_particle_density(gpu):
     assert st.item() == 0
     assert q == int(near.sum()) and a == len(nodes)
     assert q > ns * 125 * 16      # more than 16 particles per base cell of every box
+
+
+def test_fields_make_the_initial_state_exact(gpu):
+    """rom_set_fields (Section 3.1, eq. essentialSpec): at the initial
+    latents and t = 0 every particle sits at its reference position, for
+    arbitrary initial latents and a trained-scale random decoder."""
+    s = _rom_inputs(seed=6)
+    d, r = 3, 8
+    X = s["X"]
+    _, gdec = make_decoder(d, r, 32, 3, 81, X, out_std=0.01)
+    grid = B.Grid(3, s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
+    Es = np.array([5e4, 2e4], np.float32)
+    rom = B.Rom(gdec, grid, T(soa(X)), T(Es), T(np.array([24, 12], np.int32), torch.int32),
+                B.gn_opts(), seed=99, rho0=1000.0, m_uniform=float(s["m"]))
+    rng = np.random.default_rng(82)
+    z0 = T(0.3 * rng.standard_normal((2, r)), torch.float64)
+    v0h = T(0.5 * rng.standard_normal((2, r)), torch.float64)
+    x = torch.zeros(2, d, s["P"], device=dev)
+    rom.positions(z0, 0.0, x)
+    off = np.max(np.abs(x.cpu().numpy() - soa(X)[None]))
+    rom.set_fields(z0, v0h, [[0.2, -1.0, 0.1], [0.0, 0.5, 0.0]])
+    rom.positions(z0, 0.0, x)
+    err = np.max(np.abs(x.cpu().numpy() - soa(X)[None]))
+    print("initial positions: %.2e off without the fields, %.2e with them" % (off, err))
+    assert off > 1e-3 and err < 2e-7
+    rom.close()
+
+
+def test_rom_step_with_fields_matches_oracle(gpu):
+    """Lagrangian reduced steps with the correction fields against the
+    oracle (exact mixed derivative for grad b), started at step 400 so that
+    t b and t grad b are far from zero; random fp32 decoder, two instances."""
+    s = _rom_inputs(seed=6)
+    d, r = 3, 8
+    X = s["X"]
+    odec, gdec = make_decoder(d, r, 32, 3, 53, X, out_std=0.01)
+    grid = B.Grid(3, s["n"], s["dx"], s["bound"], s["floor_mode"], s["mu_f"], s["gravity"])
+    Es = np.array([5e4, 2e4], np.float32)
+    nss = np.array([24, 12], np.int32)
+    opts = B.gn_opts(mode=B.POS_VEL, max_iter=3)
+    rom = B.Rom(gdec, grid, T(soa(X)), T(Es), T(nss, torch.int32), opts, seed=99, rho0=1000.0,
+                m_uniform=float(s["m"]))
+    rng = np.random.default_rng(54)
+    z0 = 0.2 * rng.standard_normal((2, r))
+    v0h = 0.5 * rng.standard_normal((2, r))
+    V0 = np.array([[0.3, -1.0, 0.2], [-0.4, 0.6, 0.0]])
+    rom.set_fields(T(z0, torch.float64), T(v0h, torch.float64), V0)
+    z = T(z0, torch.float64)
+    zp = T(z0, torch.float64)
+    vh = T(v0h, torch.float64)
+    st = torch.zeros(2, dtype=torch.int32, device=dev)
+    step0, nst, dt = 400, 3, s["dt"]
+    rom.step(nst, step0, dt, z, zp, vh, status=st)
+    sc = oracle_scene(s)
+    P = s["P"]
+    Xd = X.astype(np.float64)
+    from oracle import mpm as OM
+    for b in range(2):
+        sc_b = dict(sc)
+        sc_b["mu"], sc_b["la"] = OM.lame(float(Es[b]), s["nu"])
+        f = OR.initial_fields(odec, Xd, z0[b], v0h[b], V0[b])
+        zz, zzp, vv = z0[b].copy(), z0[b].copy(), v0h[b].copy()
+        oopts = OP.GNOptions(mode=OP.MODE_POS_VEL, max_iter=3, fixed_iters=True)
+        for k in range(nst):
+            samples = OR.sample_indices(99, b, step0 + k, int(nss[b]), P)
+            zn, vn, info = OR.rom_step(odec, sc_b, Xd, sc["m"], sc["V0"], zz, zzp, vv, dt, samples,
+                                       oopts, fields=f, t=(step0 + k) * dt)
+            zzp, zz, vv = zz, zn, vn
+        dz = np.max(np.abs(z.cpu().numpy()[b] - zz))
+        ez = dz / (1.0 + np.max(np.abs(zz)))
+        ev = np.max(np.abs(vh.cpu().numpy()[b] - vv)) / np.max(np.abs(vv))
+        print("instance %d with fields: latent err %.2e, velocity err %.2e, |t grad b| %.2e"
+              % (b, ez, ev, step0 * dt * np.max(np.abs(f["Gb"]))))
+        assert ez < 1e-5 and ev < 1e-3
+    assert st.cpu().numpy().tolist() == [0, 0]
+    rom.close()
+
+
+def test_fields_turn_arbitrary_latents_into_the_ballistic_trajectory(gpu):
+    """Translation manifold g = X + xhat, free fall, arbitrary initial
+    latents: with the fields of the true initial state (X, V0) the reduced
+    positions follow X + t V0 + symplectic-Euler gravity, in both
+    projection modes (the oracle's pin of the same fact, on the GPU)."""
+    s = _rom_inputs()
+    d = 3
+    W = np.concatenate([np.zeros((d, d)), np.eye(d)], axis=1).astype(np.float32)
+    X = s["X"]
+    gdec = B.Decoder([W], [np.zeros(d, np.float32)], X.min(0), X.max(0), np.zeros(d), np.ones(d))
+    grid = B.Grid(3, s["n"], s["dx"], 0, B.FLOOR_STICKY, 0.0, s["gravity"])
+    E = T(np.array([5e4], np.float32))
+    ns = T(np.array([16], np.int32), torch.int32)
+    V0 = np.array([[0.2, -0.4, 0.1]])
+    g = np.asarray(s["gravity"], np.float64)
+    for mode in (B.POS_VEL, B.VEL_ONLY):
+        rom = B.Rom(gdec, grid, T(soa(X)), E, ns, B.gn_opts(mode=mode, max_iter=2), seed=3,
+                    rho0=1000.0, m_uniform=float(s["m"]))
+        z = T(np.array([[0.01, -0.02, 0.005]]), torch.float64)
+        vh = T(np.array([[1.0, 0.5, -0.3]]), torch.float64)
+        rom.set_fields(z.clone(), vh.clone(), V0)
+        zp = z.clone()
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        nst, dt = 6, s["dt"]
+        rom.step(nst, 0, dt, z, zp, vh, status=st)
+        x = torch.zeros(1, d, s["P"], device=dev)
+        rom.positions(z, nst * dt, x)
+        xexp = soa(X) + (nst * dt * V0[0] + dt * dt * g * nst * (nst + 1) / 2)[:, None]
+        err = np.max(np.abs(x.cpu().numpy()[0] - xexp))
+        print("mode %d: positions off the ballistic closed form by %.2e" % (mode, err))
+        assert st.item() == 0 and err < 2e-6
+        rom.close()
