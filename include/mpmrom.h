@@ -612,6 +612,14 @@ int32_t rom_train_backward(mr_trainer *t, const float *dg, const float *dG,
                            const float *dGv, float *dparams, float *dZ,
                            void *stream);
 
+/* Reproducible training: with on != 0 every batch reduction of
+ * rom_train_backward (split-K weight gradients, bias gradients, the
+ * snapshots' latent gradients) is written as partial sums and added in a
+ * fixed order instead of with float atomics, so two runs from the same
+ * inputs give bitwise identical gradients.  Allocates about 17 MB on first
+ * use.  (rom_train_loss is reproducible in either mode.) */
+int32_t rom_trainer_set_deterministic(mr_trainer *t, int32_t on);
+
 /* Training objective (Section 4.2): batch mean of |g - x|^2 +
  * lam_F |G - F|_F^2 + lam_v |Gv - v|^2, the velocity term dropped for
  * groups with next < 0.  loss: device float scalar (overwritten);
@@ -686,15 +694,17 @@ int32_t rom_encoder_forward(int32_t d, int32_t r, int64_t in_len, int32_t n,
 /* Gradient of sum_f dz[f] . z[f] with respect to the parameters, for the
  * frames and the activation record of the matching rom_encoder_forward
  * call.  dz: device float32 [n][r]; grad: device float32 [n_params],
- * overwritten; work: device float32 [n][work_floats] scratch.  Weight
- * gradients are summed with float atomics (their last bits depend on the
- * schedule).  Errors as rom_encoder_forward. */
+ * overwritten; work: device float32 [n][work_floats] scratch.  With
+ * deterministic == 0 the weight gradients are summed with float atomics
+ * (their last bits depend on the schedule); otherwise every partial sum
+ * goes to the work buffer and is added in a fixed order (bitwise
+ * reproducible).  Errors as rom_encoder_forward. */
 int32_t rom_encoder_backward(int32_t d, int32_t r, int64_t in_len, int32_t n,
                              const float *x, const int32_t *frame_idx,
                              const float *params, const float *in_min,
                              const float *in_max, const float *act,
                              const float *dz, float *grad, float *work,
-                             void *stream);
+                             int32_t deterministic, void *stream);
 
 #ifdef __cplusplus
 }

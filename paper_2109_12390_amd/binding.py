@@ -145,7 +145,8 @@ SIGNATURES = {
     "rom_encoder_forward": (_i32, [_i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    _vp]),
     "rom_encoder_backward": (_i32, [_i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                    _vp, _vp, _vp]),
+                                    _vp, _vp, _i32, _vp]),
+    "rom_trainer_set_deterministic": (_i32, [_vp, _i32]),
     "rom_train_gather": (_i32, [_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, _vp, _vp]),
     "mr_sync_status": (_i32, [_vp, _vp, _i32, _vp]),
@@ -534,7 +535,7 @@ def encoder_forward(d, r, x, params, in_min, in_max, act, z, frame_idx=None, n=N
 
 
 def encoder_backward(d, r, x, params, in_min, in_max, act, dz, grad, work, frame_idx=None,
-                     n=None, stream=None):
+                     n=None, deterministic=False, stream=None):
     in_len = x.shape[-1]
     n = (frame_idx.numel() if frame_idx is not None else x.shape[0]) if n is None else n
     lo, plo = _host_f32(in_min)
@@ -543,7 +544,7 @@ def encoder_backward(d, r, x, params, in_min, in_max, act, dz, grad, work, frame
         d, r, in_len, n, _ptr(x, torch.float32), _ptr(frame_idx, torch.int32),
         _ptr(params, torch.float32), plo, phi, _ptr(act, torch.float32),
         _ptr(dz, torch.float32), _ptr(grad, torch.float32), _ptr(work, torch.float32),
-        _stream(stream)))
+        1 if deterministic else 0, _stream(stream)))
 
 
 class Rom:

@@ -26,6 +26,7 @@ struct EncLayout {
     int nc;                     // convolutions
     int64_t dc;                 // d_conv
     int64_t n_params, act_floats, work_floats;
+    int64_t plane_floats, dense_floats, conv_blocks;
     std::vector<int64_t> act_off;   // offset of conv l's output in a frame's record
     int64_t h1_off;
 };
@@ -51,8 +52,14 @@ bool enc_layout(int64_t in_len, int r, EncLayout &L)
     }
     L.h1_off = o;
     L.act_floats = o + ENC_H;
-    // two gradient planes of the longest convolution output (or of d_conv)
-    L.work_floats = 2 * (L.nc > 0 ? L.len[1] : L.dc);
+    // two gradient planes of the longest convolution output (or of d_conv),
+    // then (reproducible mode) the frame's dense-layer gradient and the
+    // per-block convolution partial sums of its longest layer
+    const int64_t l1 = L.nc > 0 ? L.len[1] : L.dc;
+    L.plane_floats = l1;
+    L.dense_floats = ENC_H * L.dc + ENC_H + (int64_t)r * ENC_H + r;
+    L.conv_blocks = (l1 + ENC_TB - 1) / ENC_TB;
+    L.work_floats = 2 * l1 + L.dense_floats + (ENC_K + 1) * L.conv_blocks;
     return true;
 }
 
@@ -121,12 +128,15 @@ __global__ void __launch_bounds__(64) enc_dense_fwd_kernel(float *act, int64_t a
 
 // backward of the dense layers for one frame: parameter gradients (atomics
 // per frame) and the gradient of the last convolution's output
+// fgrad (nullable): this frame's gradient record (W1, b1, W2, b2 layout) at
+// fgrad + f fstride, written instead of the atomics (reproducible mode)
 __global__ void __launch_bounds__(64) enc_dense_bwd_kernel(const float *act, int64_t act_stride,
                                                            int64_t a_off, int64_t h1_off, int dc,
                                                            int r, const float *W1, const float *W2,
                                                            const float *dz, float *gW1, float *gb1,
                                                            float *gW2, float *gb2, float *da,
-                                                           int64_t da_stride)
+                                                           int64_t da_stride, float *fgrad,
+                                                           int64_t fstride)
 {
     __shared__ float a[2 * ENC_MIN + ENC_K];
     __shared__ float ds1[ENC_H];
@@ -135,24 +145,46 @@ __global__ void __launch_bounds__(64) enc_dense_bwd_kernel(const float *act, int
     const float *rec = act + (int64_t)f * act_stride;
     for (int i = t; i < dc; i += 64) a[i] = rec[a_off + i];
     if (t < r) g[t] = dz[(int64_t)f * r + t];
+    if (fgrad) {
+        // the frame's own record: plain stores, summed over frames in order
+        float *o = fgrad + (int64_t)f * fstride;
+        gW1 = o;
+        gb1 = o + ENC_H * dc;
+        gW2 = gb1 + ENC_H;
+        gb2 = gW2 + r * ENC_H;
+    }
     __syncthreads();
     if (t < ENC_H) {
         const float h = rec[h1_off + t];
         float s = 0.0f;
         for (int q = 0; q < r; ++q) {
             s = fmaf(W2[q * ENC_H + t], g[q], s);
-            atomicAdd(gW2 + q * ENC_H + t, g[q] * h);
+            if (fgrad)
+                gW2[q * ENC_H + t] = g[q] * h;
+            else
+                atomicAdd(gW2 + q * ENC_H + t, g[q] * h);
         }
         ds1[t] = s * elu_prime_a(h);
-        atomicAdd(gb1 + t, ds1[t]);
+        if (fgrad)
+            gb1[t] = ds1[t];
+        else
+            atomicAdd(gb1 + t, ds1[t]);
     }
-    if (t < r) atomicAdd(gb2 + t, g[t]);
+    if (t < r) {
+        if (fgrad)
+            gb2[t] = g[t];
+        else
+            atomicAdd(gb2 + t, g[t]);
+    }
     __syncthreads();
     for (int i = t; i < dc; i += 64) {
         float s = 0.0f;
         for (int o = 0; o < ENC_H; ++o) {
             s = fmaf(W1[o * dc + i], ds1[o], s);
-            atomicAdd(gW1 + o * dc + i, ds1[o] * a[i]);
+            if (fgrad)
+                gW1[o * dc + i] = ds1[o] * a[i];
+            else
+                atomicAdd(gW1 + o * dc + i, ds1[o] * a[i]);
         }
         da[(int64_t)f * da_stride + i] = s;
     }
@@ -185,7 +217,7 @@ __global__ void __launch_bounds__(ENC_TB) enc_conv_bwd_data_kernel(
 __global__ void __launch_bounds__(ENC_TB) enc_conv_bwd_weight_kernel(
     const float *x, const int32_t *frame_idx, int64_t in_stride, const float *act_prev,
     int64_t act_stride, const float *da, int64_t da_stride, const float *y, int64_t Lout,
-    EncNorm nm, float *gwb)
+    EncNorm nm, float *gwb, float *part)
 {
     __shared__ float red[ENC_K + 1][ENC_TB / 64];
     const int f = blockIdx.y;
@@ -213,8 +245,22 @@ __global__ void __launch_bounds__(ENC_TB) enc_conv_bwd_weight_kernel(
     if (threadIdx.x <= ENC_K) {
         float s = 0.0f;
         for (int w = 0; w < ENC_TB / 64; ++w) s += red[threadIdx.x][w];
-        atomicAdd(gwb + threadIdx.x, s);
+        if (part)   // block (x, frame y) -> slot y gridDim.x + x
+            part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (ENC_K + 1) + threadIdx.x] = s;
+        else
+            atomicAdd(gwb + threadIdx.x, s);
     }
+}
+
+// grad[k] += sum over the slots of part[slot][k], in slot order
+__global__ void enc_slot_reduce_kernel(int64_t width, int64_t nslots, int64_t stride,
+                                       const float *part, float *grad)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= width) return;
+    float s = 0.0f;
+    for (int64_t q = 0; q < nslots; ++q) s += part[q * stride + k];
+    grad[k] += s;
 }
 
 __global__ void enc_fill_kernel(float *a, int64_t n)
@@ -295,7 +341,8 @@ extern "C" int32_t rom_encoder_backward(int32_t d, int32_t r, int64_t in_len, in
                                         const float *x, const int32_t *frame_idx,
                                         const float *params, const float *in_min,
                                         const float *in_max, const float *act, const float *dz,
-                                        float *grad, float *work, void *stream)
+                                        float *grad, float *work, int32_t deterministic,
+                                        void *stream)
 {
     EncLayout L;
     EncNorm nm;
@@ -314,13 +361,20 @@ extern "C" int32_t rom_encoder_backward(int32_t d, int32_t r, int64_t in_len, in
     float *gb1 = gW1 + ENC_H * L.dc;
     float *gW2 = gb1 + ENC_H;
     float *gb2 = gW2 + (int64_t)r * ENC_H;
-    // two gradient planes per frame, alternating between layers
-    const int64_t ws = L.work_floats / 2;
+    // two gradient planes per frame, alternating between layers; then the
+    // per-frame dense gradients and the convolution block partials
+    const int64_t ws = L.plane_floats;
     float *plane[2] = {work, work + (int64_t)n * ws};
+    float *fgrad = deterministic ? work + 2 * (int64_t)n * ws : nullptr;
+    float *cpart = deterministic ? fgrad + (int64_t)n * L.dense_floats : nullptr;
     int cur = 0;
     enc_dense_bwd_kernel<<<(unsigned)n, 64, 0, st>>>(act, L.act_floats, L.act_off[L.nc - 1],
                                                      L.h1_off, (int)L.dc, r, W1, W2, dz, gW1, gb1,
-                                                     gW2, gb2, plane[cur], ws);
+                                                     gW2, gb2, plane[cur], ws, fgrad,
+                                                     L.dense_floats);
+    if (fgrad)
+        enc_slot_reduce_kernel<<<(unsigned)ceil_div(L.dense_floats, 256), 256, 0, st>>>(
+            L.dense_floats, n, L.dense_floats, fgrad, gW1);
     MR_LAUNCH_CHECK();
     for (int l = L.nc - 1; l >= 0; --l) {
         const int64_t Lin = L.len[l], Lout = L.len[l + 1];
@@ -330,7 +384,10 @@ extern "C" int32_t rom_encoder_backward(int32_t d, int32_t r, int64_t in_len, in
         dim3 gw((unsigned)ceil_div(Lout, ENC_TB), (unsigned)n);
         enc_conv_bwd_weight_kernel<<<gw, ENC_TB, 0, st>>>(x, frame_idx, in_len, prev, L.act_floats,
                                                           plane[cur], ws, y, Lout, nm,
-                                                          grad + l * (ENC_K + 1));
+                                                          grad + l * (ENC_K + 1), cpart);
+        if (cpart)
+            enc_slot_reduce_kernel<<<1, 64, 0, st>>>(ENC_K + 1, (int64_t)gw.x * n, ENC_K + 1,
+                                                     cpart, grad + l * (ENC_K + 1));
         if (l > 0) {
             dim3 gd((unsigned)ceil_div(Lin, ENC_TB), (unsigned)n);
             enc_conv_bwd_data_kernel<<<gd, ENC_TB, 0, st>>>(plane[cur], ws, y, L.act_floats, Lin,

@@ -47,6 +47,7 @@ struct GemmArgs {
     int64_t scm, scn;
     int mode;     // 0: C = AB, 1: C += AB, 2: atomicAdd(C, AB)
     int k_chunk;  // K range per blockIdx.z
+    int64_t scz;  // C offset per blockIdx.z (split-K slices; 0: one C)
 };
 
 constexpr int GBM = 64, GBN = 64, GBK = 32;
@@ -173,7 +174,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
                 int gm = m0 + wm + a * 16 + 4 * q4 + q;
                 int gn = n0 + wn + b * 16 + j;
                 if (gm >= g.M || gn >= g.N) continue;
-                float *c = g.C + (int64_t)gm * g.scm + (int64_t)gn * g.scn;
+                float *c = g.C + (int64_t)blockIdx.z * g.scz + (int64_t)gm * g.scm +
+                           (int64_t)gn * g.scn;
                 float v = acc[a][b][q];
                 if (g.mode == 0)
                     *c = v;
@@ -194,9 +196,25 @@ static bool vec_ok(const float *P, int64_t sr, int64_t sk, int R, int K)
     return false;
 }
 
+// sums the split-K slices stage[z][m][n] (z = 0 .. splits - 1, in order)
+// into C: C[m][n] += sum_z stage[z][m][n]
+__global__ void split_reduce_kernel(int M, int N, int splits, const float *stage, float *C,
+                                    int64_t scm, int64_t scn)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)M * N) return;
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s += stage[(int64_t)z * M * N + i];
+    const int64_t m = i / N, n = i % N;
+    C[m * scm + n * scn] += s;
+}
+
 // splits < 0: split the k range (a batch reduction, accumulated with
-// atomics) so that about 1,024 blocks run, each over at least 256 k
-int32_t gemm(bool bf16, GemmArgs g, hipStream_t st, int splits = 1)
+// atomics) so that about 1,024 blocks run, each over at least 256 k.
+// stage (nullable): a buffer of at least 1024 x 64 x 64 floats; the split
+// results then go to separate slices summed in slice order afterwards (no
+// atomics: reproducible), instead of being added with atomics.
+int32_t gemm(bool bf16, GemmArgs g, hipStream_t st, int splits = 1, float *stage = nullptr)
 {
     if (g.M <= 0 || g.N <= 0) return MR_OK;
     if (g.K <= 0) return MR_OK;
@@ -209,7 +227,20 @@ int32_t gemm(bool bf16, GemmArgs g, hipStream_t st, int splits = 1)
     int chunk = (int)ceil_div(ceil_div(g.K, splits), GBK) * GBK;
     splits = (int)ceil_div(g.K, chunk);
     g.k_chunk = chunk;
-    if (splits > 1) g.mode = 2;
+    float *C = g.C;
+    const int64_t scm = g.scm, scn = g.scn;
+    const bool staged = stage && splits > 1 && g.mode == 2;
+    if (staged) {
+        // slice z of C at stage + z M N (row-major); the kernel addresses
+        // C + m scm + n scn, so the slice index rides on the z stride below
+        g.C = stage;
+        g.scm = g.N;
+        g.scn = 1;
+        g.scz = (int64_t)g.M * g.N;
+        g.mode = 0;
+    } else if (splits > 1) {
+        g.mode = 2;
+    }
     dim3 grid((unsigned)ceil_div(g.M, GBM), (unsigned)ceil_div(g.N, GBN), (unsigned)splits);
     const bool va = vec_ok(g.A, g.sam, g.sak, g.M, g.K);
     const bool vb = vec_ok(g.B, g.sbn, g.sbk, g.N, g.K);
@@ -219,6 +250,12 @@ int32_t gemm(bool bf16, GemmArgs g, hipStream_t st, int splits = 1)
                            : (vb ? gemm_kernel<false, false, true> : gemm_kernel<false, false, false>));
     kern<<<grid, 256, 0, st>>>(g);
     MR_LAUNCH_CHECK();
+    if (staged) {
+        const int64_t mn = (int64_t)g.M * g.N;
+        split_reduce_kernel<<<(unsigned)ceil_div(mn, 256), 256, 0, st>>>(g.M, g.N, splits, stage, C,
+                                                                         scm, scn);
+        MR_LAUNCH_CHECK();
+    }
     return MR_OK;
 }
 
@@ -300,10 +337,38 @@ __global__ void output_adjoint_kernel(TrainDims td, int64_t rows, const float *d
     for (int a = 0; a < d; ++a) {
         float yb = td.stdv[a] * dg[row * d + a];
         Ybar[c0 * d + a] = yb;
-        atomicAdd(dbL + a, yb);
+        if (dbL) atomicAdd(dbL + a, yb);
         for (int b = 0; b < d; ++b) Ybar[(c0 + 1 + b) * d + a] = td.stdv[a] * dG[(row * d + a) * d + b];
         Ybar[(c0 + d + 1) * d + a] = td.stdv[a] * dGv[row * d + a];
     }
+}
+
+// reproducible output-bias gradient: dbL[a] += sum over rows, in row order
+// per thread and a fixed tree across the block (one block per component)
+__global__ void __launch_bounds__(256) output_bias_kernel(TrainDims td, int64_t rows,
+                                                          const float *Ybar, float *dbL)
+{
+    __shared__ float red[256];
+    const int a = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t row = threadIdx.x; row < rows; row += 256) s += Ybar[row * td.S * td.d + a];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dbL[a] += red[0];
+}
+
+// db[u] += sum over the slots of part[slot][u], in slot order
+__global__ void slot_reduce_kernel(int W, int64_t nslots, const float *part, float *db)
+{
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= W) return;
+    float s = 0.0f;
+    for (int64_t k = 0; k < nslots; ++k) s += part[k * W + u];
+    db[u] += s;
 }
 
 // adjoint of the pre-activations of a hidden layer:
@@ -331,9 +396,12 @@ __device__ __forceinline__ float activate_backward_row(const TrainDims &td, int6
     return pb;
 }
 
+// part (nullable): the bias-gradient partial sums go to part[slot][unit]
+// (W <= 256: slot = block x rows per pass + row lane; wider: slot = block)
+// for slot_reduce_kernel, instead of atomics
 __global__ void __launch_bounds__(256) activate_backward_kernel(TrainDims td, int64_t rows,
                                                                 const float *P, const float *Abar,
-                                                                float *Pbar, float *db)
+                                                                float *Pbar, float *db, float *part)
 {
     if (td.W <= 256) {
         const int rpp = 256 / td.W;
@@ -344,14 +412,20 @@ __global__ void __launch_bounds__(256) activate_backward_kernel(TrainDims td, in
         float bsum = 0.0f;
         for (int64_t row = r0; row < rows; row += stride)
             bsum += activate_backward_row(td, row, i, P, Abar, Pbar);
-        if (r0 < rows) atomicAdd(db + i, bsum);
+        if (part)
+            part[r0 * td.W + i] = bsum;
+        else if (r0 < rows)
+            atomicAdd(db + i, bsum);
         return;
     }
     for (int i = threadIdx.x; i < td.W; i += blockDim.x) {
         float bsum = 0.0f;
         for (int64_t row = blockIdx.x; row < rows; row += gridDim.x)
             bsum += activate_backward_row(td, row, i, P, Abar, Pbar);
-        if ((int64_t)blockIdx.x < rows) atomicAdd(db + i, bsum);
+        if (part)
+            part[(int64_t)blockIdx.x * td.W + i] = bsum;
+        else if ((int64_t)blockIdx.x < rows)
+            atomicAdd(db + i, bsum);
     }
 }
 
@@ -363,7 +437,7 @@ constexpr int ABV_MAXS = 5;
 __global__ void __launch_bounds__(256) activate_backward_vec_kernel(TrainDims td, int64_t rows,
                                                                     const float *P,
                                                                     const float *Abar, float *Pbar,
-                                                                    float *db)
+                                                                    float *db, float *part)
 {
     __shared__ float red[1024];
     const int W = td.W, S = td.S, W4 = W / 4;
@@ -415,7 +489,10 @@ __global__ void __launch_bounds__(256) activate_backward_vec_kernel(TrainDims td
     for (int u = threadIdx.x; u < W; u += blockDim.x) {
         float sum = 0.0f;
         for (int k = 0; k < rpp; ++k) sum += red[k * W + u];
-        atomicAdd(db + u, sum);
+        if (part)
+            part[(int64_t)blockIdx.x * W + u] = sum;
+        else
+            atomicAdd(db + u, sum);
     }
 }
 
@@ -427,7 +504,8 @@ __global__ void __launch_bounds__(256) activate_backward_vec_kernel(TrainDims td
 __global__ void __launch_bounds__(256) latent_grad_kernel(TrainDims td, int64_t rows,
                                                           int rows_per_group, const int32_t *snap,
                                                           const int32_t *next, float inv_dt,
-                                                          const float *A0bar, float *dZ)
+                                                          const float *A0bar, float *dZ,
+                                                          float *part)
 {
     __shared__ float red0[256], red1[256];
     const int grp = blockIdx.x;
@@ -453,11 +531,35 @@ __global__ void __launch_bounds__(256) latent_grad_kernel(TrainDims td, int64_t 
             t0 += red0[q * td.r + threadIdx.x];
             t1 += red1[q * td.r + threadIdx.x];
         }
+        const float w = nx >= 0 ? t1 * inv_dt : 0.0f;
+        if (part) {
+            part[((int64_t)grp * 2) * td.r + threadIdx.x] = t0;
+            part[((int64_t)grp * 2 + 1) * td.r + threadIdx.x] = w;
+            return;
+        }
         atomicAdd(dZ + (int64_t)s * td.r + threadIdx.x, t0);
         if (nx >= 0) {
-            const float w = t1 * inv_dt;
             atomicAdd(dZ + (int64_t)nx * td.r + threadIdx.x, w);
             atomicAdd(dZ + (int64_t)s * td.r + threadIdx.x, -w);
+        }
+    }
+}
+
+// the groups' latent gradients applied in group order (one thread per
+// latent component): reproducible where groups share snapshots
+__global__ void latent_apply_kernel(int r, int n_groups, const int32_t *snap, const int32_t *next,
+                                    const float *part, float *dZ)
+{
+    const int k = threadIdx.x;
+    if (k >= r) return;
+    for (int grp = 0; grp < n_groups; ++grp) {
+        const int s = snap[grp], nx = next[grp];
+        const float t0 = part[((int64_t)grp * 2) * r + k];
+        const float w = part[((int64_t)grp * 2 + 1) * r + k];
+        dZ[(int64_t)s * r + k] += t0;
+        if (nx >= 0) {
+            dZ[(int64_t)nx * r + k] += w;
+            dZ[(int64_t)s * r + k] -= w;
         }
     }
 }
@@ -470,24 +572,26 @@ __global__ void __launch_bounds__(256) loss_kernel(int d, int64_t rows, int rows
                                                    float *loss, float *dg, float *dG, float *dGv)
 {
     __shared__ float red[256];
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float l = 0.0f;
-    if (row < rows) {
+    // one block: each thread takes rows t, t + 256, ... in order, then a
+    // fixed tree (the objective is reproducible)
+    for (int64_t row = threadIdx.x; row < rows; row += 256) {
         const float inv = 1.0f / (float)rows;
+        float lr = 0.0f;
         const float mv = next[row / rows_per_group] >= 0 ? 1.0f : 0.0f;
         for (int a = 0; a < d; ++a) {
             float rx = g[row * d + a] - xt[row * d + a];
             float rv = Gv[row * d + a] - vt[row * d + a];
-            l += rx * rx + lam_v * mv * rv * rv;
+            lr += rx * rx + lam_v * mv * rv * rv;
             if (dg) dg[row * d + a] = 2.0f * rx * inv;
             if (dGv) dGv[row * d + a] = 2.0f * lam_v * mv * rv * inv;
             for (int b = 0; b < d; ++b) {
                 float rF = G[(row * d + a) * d + b] - Ft[(row * d + a) * d + b];
-                l += lam_F * rF * rF;
+                lr += lam_F * rF * rF;
                 if (dG) dG[(row * d + a) * d + b] = 2.0f * lam_F * rF * inv;
             }
         }
-        l *= inv;
+        l += lr * inv;
     }
     red[threadIdx.x] = l;
     __syncthreads();
@@ -495,7 +599,7 @@ __global__ void __launch_bounds__(256) loss_kernel(int d, int64_t rows, int rows
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(loss, red[0]);
+    if (threadIdx.x == 0) *loss = red[0];
 }
 
 __global__ void adam_kernel(int64_t n, float *p, const float *grad, float *m, float *v, float lr,
@@ -549,6 +653,9 @@ struct mr_trainer {
     const float *params, *X;
     const int32_t *snap, *next;
     float inv_dt;
+    // reproducible mode: split-K slices, bias partial sums, group latents
+    int det;
+    float *stage, *part, *gpart;
 };
 
 static size_t param_count(int d, int r, int width, int nh)
@@ -566,7 +673,8 @@ extern "C" int64_t rom_train_param_count(int32_t d, int32_t r, int32_t width, in
 extern "C" void rom_trainer_destroy(mr_trainer *t)
 {
     if (!t) return;
-    float *bufs[] = {t->A0, t->Y, t->Ybar, t->Abar, t->Pbar, t->A0bar};
+    float *bufs[] = {t->A0, t->Y, t->Ybar, t->Abar, t->Pbar, t->A0bar, t->stage, t->part,
+                     t->gpart};
     for (float *b : bufs)
         if (b) (void)hipFree(b);
     for (int l = 0; l < 9; ++l) {
@@ -716,8 +824,11 @@ extern "C" int32_t rom_train_backward(mr_trainer *t, const float *dg, const floa
     // the batch reductions of the weight gradients are split over ~1,024 blocks
     const int splits = -1;
     int32_t rc;
-    output_adjoint_kernel<<<(unsigned)ceil_div(rows, TB), TB, 0, st>>>(td, rows, dg, dG, dGv, t->Ybar,
-                                                                       dparams + t->ob[td.nh]);
+    float *stage = t->det ? t->stage : nullptr;
+    output_adjoint_kernel<<<(unsigned)ceil_div(rows, TB), TB, 0, st>>>(
+        td, rows, dg, dG, dGv, t->Ybar, t->det ? nullptr : dparams + t->ob[td.nh]);
+    if (t->det)
+        output_bias_kernel<<<(unsigned)td.d, 256, 0, st>>>(td, rows, t->Ybar, dparams + t->ob[td.nh]);
     MR_LAUNCH_CHECK();
     // dW_L[a][i] += sum_col Ybar[col][a] A_last[col][i]
     GemmArgs gw{};
@@ -726,7 +837,7 @@ extern "C" int32_t rom_train_backward(mr_trainer *t, const float *dg, const floa
     gw.B = t->A[td.nh - 1]; gw.sbk = td.W; gw.sbn = 1;
     gw.C = dparams + t->oW[td.nh]; gw.scm = td.W; gw.scn = 1;
     gw.mode = 2;
-    if ((rc = gemm(false, gw, st, splits)) != MR_OK) return rc;
+    if ((rc = gemm(false, gw, st, splits, stage)) != MR_OK) return rc;
     // Abar[col][i] = sum_a W_L[a][i] Ybar[col][a]
     GemmArgs ga{};
     ga.M = td.W; ga.N = (int)cols; ga.K = td.d;
@@ -736,17 +847,26 @@ extern "C" int32_t rom_train_backward(mr_trainer *t, const float *dg, const floa
     ga.mode = 0;
     if ((rc = gemm(false, ga, st)) != MR_OK) return rc;
     for (int l = td.nh - 1; l >= 0; --l) {
+        float *part = t->det ? t->part : nullptr;
+        int64_t nslots = 0;
         if (td.W % 4 == 0 && td.W <= 1024 && td.S <= ABV_MAXS) {
             const int64_t rpp = 256 / (td.W / 4);
             const int64_t passes = ceil_div(rows, rpp);
-            activate_backward_vec_kernel<<<(unsigned)(passes < 1024 ? passes : 1024), 256, 0, st>>>(
-                td, rows, t->P[l], t->Abar, t->Pbar, dparams + t->ob[l]);
+            const int64_t grid = passes < 1024 ? passes : 1024;
+            activate_backward_vec_kernel<<<(unsigned)grid, 256, 0, st>>>(
+                td, rows, t->P[l], t->Abar, t->Pbar, dparams + t->ob[l], part);
+            nslots = grid;
         } else {
             const int64_t rpp = td.W <= 256 ? 256 / td.W : 1;
             const int64_t passes = ceil_div(rows, rpp);
-            activate_backward_kernel<<<(unsigned)(passes < 1024 ? passes : 1024), 256, 0, st>>>(
-                td, rows, t->P[l], t->Abar, t->Pbar, dparams + t->ob[l]);
+            const int64_t grid = passes < 1024 ? passes : 1024;
+            activate_backward_kernel<<<(unsigned)grid, 256, 0, st>>>(
+                td, rows, t->P[l], t->Abar, t->Pbar, dparams + t->ob[l], part);
+            nslots = grid * rpp;
         }
+        if (part)
+            slot_reduce_kernel<<<(unsigned)ceil_div(td.W, 256), 256, 0, st>>>(
+                td.W, nslots, part, dparams + t->ob[l]);
         MR_LAUNCH_CHECK();
         const int Kin = (l == 0) ? td.K0 : td.W;
         const float *in = (l == 0) ? t->A0 : t->A[l - 1];
@@ -757,7 +877,7 @@ extern "C" int32_t rom_train_backward(mr_trainer *t, const float *dg, const floa
         gd.B = in; gd.sbk = Kin; gd.sbn = 1;
         gd.C = dparams + t->oW[l]; gd.scm = Kin; gd.scn = 1;
         gd.mode = 2;
-        if ((rc = gemm(bf && l > 0, gd, st, splits)) != MR_OK) return rc;
+        if ((rc = gemm(bf && l > 0, gd, st, splits, stage)) != MR_OK) return rc;
         if (l > 0) {
             // Abar[col][k] = sum_i W_l[i][k] Pbar[col][i]
             GemmArgs gi{};
@@ -778,8 +898,12 @@ extern "C" int32_t rom_train_backward(mr_trainer *t, const float *dg, const floa
             if ((rc = gemm(false, gz, st)) != MR_OK) return rc;
         }
     }
-    latent_grad_kernel<<<(unsigned)ceil_div(rows, (int64_t)t->rows_per_group), 256, 0, st>>>(
-        td, rows, t->rows_per_group, t->snap, t->next, t->inv_dt, t->A0bar, dZ);
+    const int64_t n_groups = ceil_div(rows, (int64_t)t->rows_per_group);
+    latent_grad_kernel<<<(unsigned)n_groups, 256, 0, st>>>(
+        td, rows, t->rows_per_group, t->snap, t->next, t->inv_dt, t->A0bar, dZ,
+        t->det ? t->gpart : nullptr);
+    if (t->det)
+        latent_apply_kernel<<<1, 64, 0, st>>>(td.r, (int)n_groups, t->snap, t->next, t->gpart, dZ);
     MR_LAUNCH_CHECK();
     return MR_OK;
 }
@@ -795,10 +919,8 @@ extern "C" int32_t rom_train_loss(int32_t d, int32_t n_groups, int32_t rows_per_
         return MR_EINVAL;
     const int64_t rows = (int64_t)n_groups * rows_per_group;
     hipStream_t st = as_stream(stream);
-    MR_CHECK_HIP(hipMemsetAsync(loss, 0, sizeof(float), st));
-    loss_kernel<<<(unsigned)ceil_div(rows, 256), 256, 0, st>>>(d, rows, rows_per_group, next, g, G,
-                                                               Gv, x_t, F_t, v_t, lam_F, lam_v,
-                                                               loss, dg, dG, dGv);
+    loss_kernel<<<1, 256, 0, st>>>(d, rows, rows_per_group, next, g, G, Gv, x_t, F_t, v_t, lam_F,
+                                   lam_v, loss, dg, dG, dGv);
     MR_LAUNCH_CHECK();
     return MR_OK;
 }
@@ -830,5 +952,28 @@ extern "C" int32_t rom_train_gather(int32_t d, int32_t n_groups, int32_t rows_pe
         d, rows, rows_per_group, P_sub, X_sub, frame_x, frame_F, frame_v, snap, pid, X, x_t, F_t,
         v_t);
     MR_LAUNCH_CHECK();
+    return MR_OK;
+}
+
+extern "C" int32_t rom_trainer_set_deterministic(mr_trainer *t, int32_t on)
+{
+    if (!t) return MR_EINVAL;
+    if (on && !t->stage) {
+        // split-K slices: splits x M x N <= 1024 x 64 x 64 (gemm's rule);
+        // bias partials: at most 1024 blocks x 256 row lanes or 1024 x W;
+        // group latents: 2 r per group, at most max_rows groups
+        const int64_t W = t->td.W;
+        const int64_t nbias = W <= 256 ? 1024 * 256 : 1024 * W;
+        if (hipMalloc(&t->stage, sizeof(float) * 1024 * 64 * 64) != hipSuccess ||
+            hipMalloc(&t->part, sizeof(float) * nbias) != hipSuccess ||
+            hipMalloc(&t->gpart, sizeof(float) * 2 * t->td.r * t->max_rows) != hipSuccess) {
+            for (float **q : {&t->stage, &t->part, &t->gpart}) {
+                if (*q) (void)hipFree(*q);
+                *q = nullptr;
+            }
+            return MR_ENOMEM;
+        }
+    }
+    t->det = on ? 1 : 0;
     return MR_OK;
 }

@@ -102,23 +102,23 @@ class EncoderFn(torch.autograd.Function):
     (rom_encoder_forward / rom_encoder_backward)."""
 
     @staticmethod
-    def forward(ctx, params, x, frame_idx, r, d, in_min, in_max):
+    def forward(ctx, params, x, frame_idx, r, d, in_min, in_max, deterministic=False):
         n = frame_idx.numel()
         _, _, _, actf, workf = B.encoder_layout(x.shape[1], r)
         act = torch.empty(n, actf, device=x.device)
         z = torch.empty(n, r, device=x.device)
         B.encoder_forward(d, r, x, params, in_min, in_max, act, z, frame_idx=frame_idx)
-        ctx.keep = (params, x, frame_idx, act, r, d, in_min, in_max, workf)
+        ctx.keep = (params, x, frame_idx, act, r, d, in_min, in_max, workf, deterministic)
         return z
 
     @staticmethod
     def backward(ctx, dz):
-        params, x, frame_idx, act, r, d, in_min, in_max, workf = ctx.keep
+        params, x, frame_idx, act, r, d, in_min, in_max, workf, det = ctx.keep
         g = torch.empty_like(params)
         work = torch.empty(frame_idx.numel(), workf, device=x.device)
         B.encoder_backward(d, r, x, params, in_min, in_max, act, dz.contiguous(), g, work,
-                           frame_idx=frame_idx)
-        return g, None, None, None, None, None, None
+                           frame_idx=frame_idx, deterministic=det)
+        return g, None, None, None, None, None, None, None
 
 
 def encoder_init(in_len, r, seed):
@@ -256,7 +256,8 @@ def normalisation(snap):
 
 def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B.PREC_BF16,
           lr0=1e-3, lr1=1e-6, lam_F=100.0, lam_v=0.01, seed=0, log_every=0, init=None,
-          eval_rows_per_frame=64, encoder=False, encoder_lr_scale=1.0, device="cuda"):
+          eval_rows_per_frame=64, encoder=False, encoder_lr_scale=1.0, deterministic=False,
+          device="cuda"):
     """Trains decoder weights and the snapshots' latent codes with Adam, the
     learning rate decaying exponentially from lr0 to lr1.  The codes are
     free per-snapshot variables, or with encoder=True the encoder network of
@@ -268,7 +269,8 @@ def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B
     log_every > 0 the history holds (step, objective) on a fixed evaluation
     batch of eval_rows_per_frame random particles of every frame, before
     step 0, every log_every steps and after the last step.  The encoder's
-    learning rate is encoder_lr_scale times the decoder's."""
+    learning rate is encoder_lr_scale times the decoder's.  deterministic:
+    every gradient reduction in a fixed order (bitwise reproducible runs)."""
     from . import scenes
     d = snap.X_sub.shape[1]
     in_min, in_max, mean, std = normalisation(snap)
@@ -276,6 +278,9 @@ def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B
     eval_rows = snap.n_frames * eval_rows_per_frame if log_every else 0
     tr = Trainer(d, r, width, n_hidden, precision, max(rows, eval_rows), in_min, in_max, mean,
                  std)
+    if deterministic:
+        B._check("rom_trainer_set_deterministic",
+                 B.load().rom_trainer_set_deterministic(tr.handle, 1))
     if init is None:
         Ws, bs = scenes.xavier_decoder(d, r, width, n_hidden, seed)
     else:
@@ -292,7 +297,7 @@ def train(snap, width, n_hidden, r, steps, n_groups, rows_per_group, precision=B
 
         def codes(frame_ids):
             """Z with the rows frame_ids encoded (differentiable), others 0."""
-            z = EncoderFn.apply(pe_var, frames, frame_ids, *enc_args)
+            z = EncoderFn.apply(pe_var, frames, frame_ids, *enc_args, deterministic)
             return torch.zeros(snap.n_frames, r, device=device).index_copy(0, frame_ids.long(), z)
     nf = torch.tensor(snap.next_frame, device=device)
     rng = np.random.default_rng(seed + 1)

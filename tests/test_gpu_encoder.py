@@ -30,7 +30,7 @@ def _case(L, r, n_frames, pick, seed):
     return d, X, p.astype(np.float32), idx, dz, lo.astype(np.float32), hi.astype(np.float32)
 
 
-def _run(d, r, X, p, idx, dz, lo, hi):
+def _run(d, r, X, p, idx, dz, lo, hi, deterministic=False):
     L = X.shape[1]
     nc, dc, npar, actf, workf = B.encoder_layout(L, r)
     n = len(idx)
@@ -43,7 +43,7 @@ def _run(d, r, X, p, idx, dz, lo, hi):
     g = torch.zeros(npar, device=dev)
     work = torch.zeros(n, workf, device=dev)
     B.encoder_backward(d, r, x, pt, lo, hi, act, torch.tensor(dz.astype(np.float32), device=dev),
-                       g, work, frame_idx=it)
+                       g, work, frame_idx=it, deterministic=deterministic)
     torch.cuda.synchronize()
     return z.cpu().numpy(), g.cpu().numpy()
 
@@ -93,3 +93,18 @@ def test_encoder_rejects_bad_sizes(gpu):
         B.encoder_forward(3, 3, torch.zeros(2, 30, device=dev), p, [0] * 3, [1] * 3, act, z)
     with pytest.raises(B.MrError):           # empty box
         B.encoder_forward(3, 3, x, p, [0] * 3, [0] * 3, act, z)
+
+
+def test_encoder_backward_reproducible_mode(gpu):
+    """deterministic = 1: the gradient matches the oracle like the atomic
+    mode and two calls agree bit for bit (the training snapshots' length)."""
+    L, r = 3 * 65536, 16
+    d, X, p, idx, dz, lo, hi = _case(L, r, 5, [4, 0, 2, 1, 3], 61)
+    z1, g1 = _run(d, r, X, p, idx, dz, lo, hi, deterministic=True)
+    z2, g2 = _run(d, r, X, p, idx, dz, lo, hi, deterministic=True)
+    assert np.array_equal(g1, g2) and np.array_equal(z1, z2)
+    zr, cache = OE.forward(p.astype(np.float64), X[idx], r, d, lo, hi)
+    gr = OE.backward(p.astype(np.float64), cache, dz, r)
+    for (a, b) in _blocks(L, r):
+        eg = np.max(np.abs(g1[a:b] - gr[a:b])) / np.max(np.abs(gr[a:b]))
+        assert eg < 1e-3, (a, b, eg)

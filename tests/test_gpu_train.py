@@ -180,3 +180,67 @@ def test_training_with_the_encoder_reduces_the_loss(gpu):
     assert np.all(np.isfinite(Z)) and np.all(np.isfinite(pe))
     # distinct snapshots get distinct codes
     assert np.min(np.linalg.norm(Z[1:] - Z[:-1], axis=1)) > 0.0
+
+
+@pytest.mark.parametrize("prec", [B.PREC_FP32, B.PREC_BF16])
+def test_reproducible_training_gradients(gpu, prec):
+    """rom_trainer_set_deterministic: the gradients of a batch match the
+    oracle as in the atomic mode, and two backward passes give bitwise
+    identical parameter and latent gradients (several groups share
+    snapshots, so the latent sums overlap)."""
+    rng = np.random.default_rng(91 + prec)
+    d, r, width, nh = 3, 16, 128, 5
+    n_groups, rpg, n_snap = 24, 96, 5
+    X, snap, nxt, Z, xt, Ft, vt = _batch(rng, d, r, n_groups, rpg, n_snap)
+    Ws, bs = scenes.random_decoder(d, r, width, nh, 7, scale=1.0, bias_scale=0.1)
+    lo, hi = np.zeros(d, np.float32), np.ones(d, np.float32)
+    mean, std = np.full(d, 0.01, np.float32), np.full(d, 0.05, np.float32)
+    dt, lam_F, lam_v = 0.01, 100.0, 0.01
+    T = lambda a, dt_=torch.float32: torch.tensor(np.ascontiguousarray(a), device=dev, dtype=dt_)
+    tr = TR.Trainer(d, r, width, nh, prec, n_groups * rpg, lo, hi, mean, std)
+    B._check("rom_trainer_set_deterministic", B.load().rom_trainer_set_deterministic(tr.handle, 1))
+    outs = []
+    for rep in range(2):
+        params = torch.tensor(B.pack_params(Ws, bs), device=dev, requires_grad=True)
+        Zt = torch.tensor(Z, device=dev, requires_grad=True)
+        g, G, Gv = TR.DecoderTrainFn.apply(params, Zt, T(X), T(snap, torch.int32),
+                                           T(nxt, torch.int32), tr, n_groups, rpg, dt)
+        loss = TR.TrainLossFn.apply(g, G, Gv, T(xt), T(Ft), T(vt), T(nxt, torch.int32), n_groups,
+                                    rpg, lam_F, lam_v)
+        loss.backward()
+        outs.append((loss.item(), params.grad.cpu().numpy(), Zt.grad.cpu().numpy()))
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][2], outs[1][2])
+    odec = OD.Decoder([w.astype(np.float64) for w in Ws], [b.astype(np.float64) for b in bs],
+                      lo, hi, mean, std)
+    L, gW, gb, gZ = OT.loss_and_grads(odec, Z, X, np.repeat(snap, rpg), np.repeat(nxt, rpg), xt, Ft,
+                                      vt, dt, lam_F, lam_v)
+    tol = 1e-4 if prec == B.PREC_FP32 else 5e-2
+    flat = outs[0][1]
+    o = 0
+    worst = 0.0
+    for W, b in zip(gW, gb):
+        for ref in (W, b):
+            got = flat[o:o + ref.size].reshape(ref.shape)
+            o += ref.size
+            if prec == B.PREC_FP32:
+                worst = max(worst, np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+            else:
+                worst = max(worst, np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    ez = np.linalg.norm(outs[0][2] - gZ) / np.linalg.norm(gZ)
+    print("reproducible mode prec %d: worst block %.2e, latent %.2e" % (prec, worst, ez))
+    assert worst < tol and ez < tol
+    tr.close()
+
+
+def test_reproducible_training_runs_agree_bitwise(gpu):
+    """Two training runs with deterministic=True (bf16 decoder kernels,
+    encoder codes) end with bitwise identical parameters and codes."""
+    s = scenes.scene_3d(n=32, cube_cells=8, seed=8)
+    inst = [(2e4, (0.5, -1.0, 0.0)), (5e4, (-0.5, -2.0, 0.3))]
+    snap = TR.generate_snapshots(s, inst, n_steps=60, every=5, n_sub=1024, seed=3)
+    runs = [TR.train(snap, width=64, n_hidden=3, r=4, steps=60, n_groups=16, rows_per_group=64,
+                     lr0=1e-3, lr1=1e-5, encoder=True, deterministic=True) for _ in range(2)]
+    for a, b in zip(runs[0][0] + runs[0][1], runs[1][0] + runs[1][1]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(runs[0][2], runs[1][2]) and np.array_equal(runs[0][5], runs[1][5])

@@ -107,4 +107,6 @@ def test_library_layout_matches_the_oracle():
             continue
         nc, dc, npar, act, work = B.encoder_layout(L, r)
         assert (nc, dc, npar) == (len(lens) - 1, lens[-1], OE.param_count(L, r))
-        assert act == sum(lens[1:]) + 32 and work == 2 * lens[1]
+        dense = 32 * lens[-1] + 32 + 32 * r + r
+        assert act == sum(lens[1:]) + 32
+        assert work == 2 * lens[1] + dense + 7 * ((lens[1] + 255) // 256)
