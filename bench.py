@@ -556,7 +556,7 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
     lr0 = 1e-3 if enc else 1e-2
     out = TR.train(snap, width=width, n_hidden=n_hidden, r=r, steps=train_steps, n_groups=64,
                    rows_per_group=256, lr0=lr0, lr1=lr0 * 1e-2, lam_F=lam_F, lam_v=lam_v,
-                   log_every=train_steps, encoder=enc)
+                   log_every=train_steps, encoder=enc, deterministic=True)
     Ws, bs, Z, norm, hist = out[:5]
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
@@ -641,7 +641,7 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
             "best_projection_displacement_error": round(err_proj, 4),
             "linear_manifold": lin,
             "train": {"steps": train_steps, "rows_per_step": 64 * 256, "objective": hist,
-                      "codes": codes, "learning_rate": [lr0, lr0 * 1e-2],
+                      "codes": codes, "learning_rate": [lr0, lr0 * 1e-2], "reproducible": True,
                       "rows_per_s": train_steps * 64 * 256 / t_train,
                       "lam_F": lam_F, "lam_v": lam_v, "seconds": t_train,
                       "snapshot_seconds": t_data, "frames": snap.n_frames, "particles": 65536},
