@@ -812,6 +812,10 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
 }
 
 // ---------------------------------------------------------------------------
+#ifndef MR_FLUSH_T
+#define MR_FLUSH_T 1
+#endif
+
 // sorted P2G in 3D: per-cell sums in registers
 //
 // One wave per 4 x 4 x 4 tile, lane c = local cell c, as in the tile scatter
@@ -1113,6 +1117,30 @@ __global__ void __launch_bounds__(64, 2) cell_sum_p2g_kernel(
     lds_order();
     // flush the region: one global atomic per non-zero node channel
     constexpr int RN = CT::R * CT::R * CT::R;
+#if MR_FLUSH_T
+    // lane l takes channel l % 4 of node l / 4: one atomic instruction
+    // covers 16 nodes = two 8-node rows, i.e. two contiguous 128-byte
+    // stretches of the grid instead of eight with every lane on its own node
+    // (R = 8: a lane keeps its x index lane / 4 % 8 and channel lane % 4;
+    // its rows are lane / 32 + 2 j, j = 0..3, of every z layer)
+    static_assert(CT::R == 8, "flush mapping assumes 8-node region rows");
+    const float *accf = reinterpret_cast<const float *>(acc);
+    const int c = lane & 3, i0 = (lane >> 2) & 7, j0 = lane >> 5;
+    const int gi = r0 + i0;
+    if (gi >= 0 && gi < g.n0) {
+        for (int i2 = 0; i2 < CT::R; ++i2) {
+            const int gk = r2 + i2;
+            if (gk < 0 || gk >= g.n2) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i1 = j0 + 2 * j, gj = r1 + i1;
+                const int slot = i0 + CT::SY * i1 + CT::SZ * i2;
+                if (gj < 0 || gj >= g.n1 || accf[4 * slot] == 0.0f) continue;
+                atomicAdd(grid_out + 4 * node_lin(g, gi, gj, gk) + c, accf[4 * slot + c]);
+            }
+        }
+    }
+#else
     for (int li = lane; li < RN; li += 64) {
         const int i0 = li % CT::R, i1 = (li / CT::R) % CT::R, i2 = li / (CT::R * CT::R);
         const float4 q = acc[i0 + CT::SY * i1 + CT::SZ * i2];
@@ -1125,6 +1153,7 @@ __global__ void __launch_bounds__(64, 2) cell_sum_p2g_kernel(
         atomicAdd(gp + 2, q.z);
         atomicAdd(gp + 3, q.w);
     }
+#endif
 }
 
 // Deterministic mode: node i of the grid sums the staged regions of the
