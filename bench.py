@@ -657,13 +657,15 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
 def rom_study(B, scenes, s, n_steps=500, train_steps=4000, r=16, width=128, n_hidden=5):
     """Where the reduced model's error comes from, on the 2,097,152-particle
     scene (E = 5e4, v0 = (0, -1, 0), n_steps steps, errors every 10 steps)
-    with one trained bf16 decoder (as in rom_trained_accuracy):
+    with one trained bf16 decoder (as in rom_trained_accuracy: encoder codes,
+    reproducible training, projection positions in fp32):
       - error floors: the decoder's best projection of every full-order frame
         (the latent fitting all positions, by Gauss-Newton), and the reduced
         model with every particle sampled (Lagrangian quadrature);
       - the sample-count sweep |P| in {10, 50, 100, 512} x {position-velocity,
         velocity-only} x {Lagrangian, Eulerian quadrature}, plus the
-        undamped position-velocity scheme at 512;
+        position-velocity scheme at 512 with damping 1e-5, 1e-6 and 0 and
+        with the initial-condition correction fields;
       - the same weights with fp32 hidden layers at 512 samples;
       - the linear-manifold baseline (one linear layer, same r and objective)
         at 512 samples, with its own best projection;
@@ -680,9 +682,11 @@ def rom_study(B, scenes, s, n_steps=500, train_steps=4000, r=16, width=128, n_hi
     snap = TR.generate_snapshots(s, [(E, v0)], n_steps=n_steps, every=5, n_sub=65536, seed=4,
                                  affine=False)
     lam_F, lam_v = TR.balanced_penalties(snap)
-    Ws, bs, Z, norm, _ = TR.train(snap, width=width, n_hidden=n_hidden, r=r, steps=train_steps,
-                                  n_groups=64, rows_per_group=256, lr0=1e-2, lr1=1e-4,
-                                  lam_F=lam_F, lam_v=lam_v)
+    # encoder codes (Section 4.1), the paper's starting rate, reproducible
+    out_t = TR.train(snap, width=width, n_hidden=n_hidden, r=r, steps=train_steps, n_groups=64,
+                     rows_per_group=256, lr0=1e-3, lr1=1e-5, lam_F=lam_F, lam_v=lam_v,
+                     encoder=True, deterministic=True)
+    Ws, bs, Z, norm = out_t[:4]
     lo, hi, mean, std = norm
     dec = B.Decoder(Ws, bs, lo, hi, mean, std, B.OUT_DISPLACEMENT, B.PREC_BF16)
     Zs = [Z[min(2 * k, Z.shape[0] - 1)] for k in range(len(fom_pic))]   # frames every 5 steps
@@ -695,8 +699,9 @@ def rom_study(B, scenes, s, n_steps=500, train_steps=4000, r=16, width=128, n_hi
                 "position_error_percent_vs_pic": round(p1, 4)}
 
     out = {"config": {"particles": s["P"], "steps": n_steps, "r": r,
-                      "decoder": "bf16 MLP %d x %d, trained" % (width, n_hidden),
-                      "damping": 1e-4, "gauss_newton_iterations": 3},
+                      "decoder": "bf16 MLP %d x %d, trained with encoder codes" % (width, n_hidden),
+                      "damping": 1e-4, "gauss_newton_iterations": 3,
+                      "projection_positions": "fp32"},
            "fom_pic_vs_apic": errs(fom_pic)["e_u_vs_apic"]}
     proj = EV.best_projection(dec, s, fom_pic, Zs)
     out["best_projection"] = errs(proj)
@@ -704,12 +709,14 @@ def rom_study(B, scenes, s, n_steps=500, train_steps=4000, r=16, width=128, n_hi
     log("study: best projection", json.dumps(out["best_projection"]))
     runs = []
 
-    def run(quad, qn, ns, mode, mn, damping=1e-4, d=dec, zg=Z[0], tag=None):
+    def run(quad, qn, ns, mode, mn, damping=1e-4, d=dec, zg=Z[0], tag=None, exact_ic=False):
         prog = (lambda k: log("study: %d samples, step %d" % (ns, k)) if k % 100 == 0 else None)
         x, st = EV.rom_positions(d, s, E, v0, n_steps, rec, n_samples=ns,
-                                 opts=B.gn_opts(mode=mode, max_iter=3, damping=damping),
-                                 z_guess=zg, quadrature=quad, progress=prog)
+                                 opts=B.gn_opts(mode=mode, max_iter=3, damping=damping,
+                                                proj_fp32=1),
+                                 z_guess=zg, quadrature=quad, progress=prog, exact_ic=exact_ic)
         row = {"quadrature": qn, "samples": ns, "projection": mn, "damping": damping,
+               "initial_condition_fields": exact_ic,
                "latent_steps_per_s": round(1e3 / st["ms_per_step"], 1),
                "quadrature_points": st["n_quadrature_points"], "status": st["status"]}
         if tag:
@@ -725,7 +732,9 @@ def rom_study(B, scenes, s, n_steps=500, train_steps=4000, r=16, width=128, n_hi
         for ns in (10, 50, 100, 512):
             for mode, mn in ((B.POS_VEL, "position-velocity"), (B.VEL_ONLY, "velocity-only")):
                 run(quad, qn, ns, mode, mn)
-    run(B.QUAD_LAGRANGIAN, "lagrangian", 512, B.POS_VEL, "position-velocity", damping=0.0)
+    for damping in (1e-5, 1e-6, 0.0):
+        run(B.QUAD_LAGRANGIAN, "lagrangian", 512, B.POS_VEL, "position-velocity", damping=damping)
+    run(B.QUAD_LAGRANGIAN, "lagrangian", 512, B.POS_VEL, "position-velocity", exact_ic=True)
     dec.close()
     # the same weights with fp32 hidden layers (the precision's share)
     dec32 = B.Decoder(Ws, bs, lo, hi, mean, std, B.OUT_DISPLACEMENT, B.PREC_FP32)
