@@ -285,6 +285,9 @@ def main():
             log("training a decoder on full-order snapshots and judging the reduced model ...")
             out["rom_trained"] = rom_trained_accuracy(B, scenes, s, args.rom_accuracy_steps,
                                                       args.train_steps)
+            if out["rom_trained"]["status"]:
+                log("the trained reduced run raised status flags:",
+                    out["rom_trained"]["status_flags"])
     if args.rom_study:
         log("reduced-model study ...")
         out["rom_study"] = rom_study(B, scenes, s)
@@ -584,7 +587,8 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
                               opts=opts,
                               z_guess=Zl[0])
     lin.update({"displacement_error": round(EV.displacement_error(xl, fom, s["X"])[0], 4),
-                "status": sl["status"], "decoder": "one linear layer, r = %d, fp32" % r})
+                "status": sl["status"], "status_flags": B.flag_names(sl["status"]),
+                "decoder": "one linear layer, r = %d, fp32" % r})
     del xl
     ldec.close()
     log("linear manifold:", json.dumps(lin))
@@ -609,7 +613,7 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
                          "latent_steps_per_s": round(1e3 / sv["ms_per_step"], 1),
                          "ms_per_step": round(sv["ms_per_step"], 4),
                          "displacement_error": round(e2, 4), "position_error_percent": round(p2, 4),
-                         "status": sv["status"]})
+                         "status": sv["status"], "status_flags": B.flag_names(sv["status"])})
         log("trained variant:", json.dumps(variants[-1]))
     # zero-shot super-resolution: the same body sampled 2x finer per
     # dimension (4 particles per cell per dimension, a new jitter), which the
@@ -630,14 +634,15 @@ def rom_trained_accuracy(B, scenes, s, n_steps, train_steps, r=16, width=128, n_
                           "ms_per_step": round(sv["ms_per_step"], 4),
                           "quadrature_points": sv["n_quadrature_points"],
                           "displacement_error": round(e2, 4), "position_error_percent": round(p2, 4),
-                          "status": sv["status"]})
+                          "status": sv["status"], "status_flags": B.flag_names(sv["status"])})
         log("super-resolution:", json.dumps(super_res[-1]))
     del fom_f
     dec.close()
     return {"metric": "ROM latent steps/s at the measured displacement error",
             "value": float(1e3 / st["ms_per_step"]), "unit": "latent steps/s",
             "ms_per_step": st["ms_per_step"], "displacement_error": err,
-            "position_error_percent": pos, "status": st["status"], "steps": n_steps,
+            "position_error_percent": pos, "status": st["status"],
+            "status_flags": B.flag_names(st["status"]), "steps": n_steps,
             "best_projection_displacement_error": round(err_proj, 4),
             "linear_manifold": lin,
             "train": {"steps": train_steps, "rows_per_step": 64 * 256, "objective": hist,
@@ -718,7 +723,8 @@ def rom_study(B, scenes, s, n_steps=500, train_steps=4000, r=16, width=128, n_hi
         row = {"quadrature": qn, "samples": ns, "projection": mn, "damping": damping,
                "initial_condition_fields": exact_ic,
                "latent_steps_per_s": round(1e3 / st["ms_per_step"], 1),
-               "quadrature_points": st["n_quadrature_points"], "status": st["status"]}
+               "quadrature_points": st["n_quadrature_points"], "status": st["status"],
+               "status_flags": B.flag_names(st["status"])}
         if tag:
             row["decoder"] = tag
         row.update(errs(x))

@@ -369,6 +369,13 @@ def mpm_g2p2g(grid, material, parts, dt, grid_in, grid_out, workspace, flags=0, 
                                       _ptr(status, torch.int32), _stream(stream)))
 
 
+def flag_names(flags):
+    """Names of the MR_FLAG_* bits set in an int (empty list for 0)."""
+    names = [(FLAG_DOMAIN, "DOMAIN"), (FLAG_SINGULAR, "SINGULAR"), (FLAG_NOCONV, "NOCONV"),
+             (FLAG_LINESEARCH, "LINESEARCH"), (FLAG_DRIFT, "DRIFT")]
+    return [n for bit, n in names if int(flags) & bit]
+
+
 def sync_status(flags_dev, stream=None):
     """Returns (code, host flags list) after synchronising the stream."""
     lib = load()
