@@ -863,20 +863,22 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
 // over all of the lane's particles; the top layer (9 nodes) is added to the
 // tile's LDS region particle by particle (ordered read-modify-write: lanes
 // sit in distinct cells, so one instruction touches 64 distinct nodes) --
-// all 27 in registers would not fit two waves per SIMD.  The next slot's
-// particle is loaded while the current one is summed.  After the slots the
-// lane adds its register sums to the region once; particles that left their
+// all 27 in registers would not fit the register budget.  The kernel runs
+// three waves per SIMD (168 VGPRs, a few spilled), which hides the loads of
+// a slot behind the other waves' sums better than loading one slot ahead
+// at two waves per SIMD did (128 vs 135 us on the 2.1M-particle scene).
+// After the slots the lane adds its register sums to the region once;
+// particles that left their
 // home cell since the sort are deferred (the first DEFER_CAP in LDS, the
 // rest in the tile's own range of a spill array) and scattered into the
 // region afterwards in claim rounds (those beyond the region with global
 // atomics); the region is flushed with one atomic per non-zero node
 // channel.  MODEL is the constitutive law (compiled separately, so that each
 // law's registers are allocated on their own); PER_PARTICLE selects
-// per-particle masses and volumes.  The loads of a slot are unconditional
-// (Cl is C, or any 9-plane array when the affine term is off, then scaled
-// by 0), so that they stay in flight while the previous slot is summed.
+// per-particle masses and volumes.  Cl is C, or any 9-plane array when the
+// affine term is off (then scaled by 0), so the loads need no branch.
 template <int MODEL, bool PER_PARTICLE>
-__global__ void __launch_bounds__(64, 2) cell_sum_p2g_kernel(
+__global__ void __launch_bounds__(64, 3) cell_sum_p2g_kernel(
     GridK g, TileGeom tg, const float *__restrict__ x, const float *__restrict__ v,
     const float *__restrict__ Cl, const float *__restrict__ F, const float *__restrict__ m,
     const float *__restrict__ V0, float m_u, float V0_u, int64_t n,
@@ -914,61 +916,31 @@ __global__ void __launch_bounds__(64, 2) cell_sum_p2g_kernel(
         for (int c = 0; c < 4; ++c) sum[q][c] = 0.0f;
     int ndef = 0;                                   // wave-uniform
 
-    // particle state of the next slot, loaded one slot ahead
-    float nx[3], nv[3], nC[9], nF[9], nm = m_u, nV = V0_u;
     int64_t base = c0;
     uint64_t mask = __ballot(0 < cnt);
-    int64_t np_ = base + __popcll(mask & below);
-    if (0 < cnt) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            nx[a] = x[a * n + np_];
-            nv[a] = v[a * n + np_];
-        }
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            nF[q] = F[q * n + np_];
-            nC[q] = Cl[q * n + np_];
-        }
-        if (PER_PARTICLE) {
-            nm = m[np_];
-            nV = V0[np_];
-        }
-    }
     for (int k = 0; mask != 0; ++k) {
         const bool act = k < cnt;
-        const int64_t p = np_;
+        const int64_t p = base + __popcll(mask & below);
         float xp[3], vp[3], Cp[9], Fp[9];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            xp[a] = nx[a];
-            vp[a] = nv[a];
-        }
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            Cp[q] = nC[q];
-            Fp[q] = nF[q];
-        }
-        const float mp = nm, Vp = nV;
-        base += __popcll(mask);
-        const uint64_t mask1 = __ballot(k + 1 < cnt);
-        np_ = base + __popcll(mask1 & below);
-        if (k + 1 < cnt) {
+        float mp = m_u, Vp = V0_u;
+        if (act) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                nx[a] = x[a * n + np_];
-                nv[a] = v[a * n + np_];
+                xp[a] = x[a * n + p];
+                vp[a] = v[a * n + p];
             }
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
-                nF[q] = F[q * n + np_];
-                nC[q] = Cl[q * n + np_];
+                Fp[q] = F[q * n + p];
+                Cp[q] = Cl[q * n + p];
             }
             if (PER_PARTICLE) {
-                nm = m[np_];
-                nV = V0[np_];
+                mp = m[p];
+                Vp = V0[p];
             }
         }
+        base += __popcll(mask);
+        const uint64_t mask1 = __ballot(k + 1 < cnt);
         bool drifted = false;
         if (act) {
             float w[3][3], dw[3][3], f[3];
