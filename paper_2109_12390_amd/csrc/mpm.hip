@@ -864,9 +864,12 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
 // tile's LDS region particle by particle (ordered read-modify-write: lanes
 // sit in distinct cells, so one instruction touches 64 distinct nodes) --
 // all 27 in registers would not fit the register budget.  The kernel runs
-// three waves per SIMD (168 VGPRs, a few spilled), which hides the loads of
-// a slot behind the other waves' sums better than loading one slot ahead
-// at two waves per SIMD did (128 vs 135 us on the 2.1M-particle scene).
+// three waves per SIMD, which hides the loads of a slot behind the other
+// waves' sums better than loading one slot ahead at two waves per SIMD did;
+// a slot loads x and F first and v and C only after the stress, for the
+// particles summed here, so that no more than 168 VGPRs are live (162-165,
+// no spills: 117 vs 136 us on the 2.1M-particle scene; with spilled
+// registers the scratch traffic also slowed the gather that follows).
 // After the slots the lane adds its register sums to the region once;
 // particles that left their
 // home cell since the sort are deferred (the first DEFER_CAP in LDS, the
@@ -921,19 +924,13 @@ __global__ void __launch_bounds__(64, 3) cell_sum_p2g_kernel(
     for (int k = 0; mask != 0; ++k) {
         const bool act = k < cnt;
         const int64_t p = base + __popcll(mask & below);
-        float xp[3], vp[3], Cp[9], Fp[9];
+        float xp[3], Fp[9];
         float mp = m_u, Vp = V0_u;
         if (act) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                xp[a] = x[a * n + p];
-                vp[a] = v[a * n + p];
-            }
+            for (int a = 0; a < 3; ++a) xp[a] = x[a * n + p];
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                Fp[q] = F[q * n + p];
-                Cp[q] = Cl[q * n + p];
-            }
+            for (int q = 0; q < 9; ++q) Fp[q] = F[q * n + p];
             if (PER_PARTICLE) {
                 mp = m[p];
                 Vp = V0[p];
@@ -957,6 +954,14 @@ __global__ void __launch_bounds__(64, 3) cell_sum_p2g_kernel(
             if (!ok) {
                 raise_flag(flag, MR_FLAG_DOMAIN);
             } else if (b[0] - r0 == h0 && b[1] - r1 == h1 && b[2] - r2 == h2) {
+                // v and C only for the particles summed here (the deferred
+                // ones read theirs when they are scattered), and only once
+                // the stress is done: fewer registers live across it
+                float vp[3], Cp[9];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) vp[a] = v[a * n + p];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) Cp[q] = Cl[q * n + p];
                 const float sc = dt * Vp;
                 float P[3][3], Q[3][3], R[3][3];   // [a][o]
 #pragma unroll
