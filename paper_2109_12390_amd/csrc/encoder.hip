@@ -252,6 +252,25 @@ __global__ void __launch_bounds__(ENC_TB) enc_conv_bwd_weight_kernel(
     }
 }
 
+// grad[k] += sum over many slots of part[slot][k] for a few k: one block per
+// k, thread t sums slots t, t + 256, ... in order, then a fixed tree
+// (reproducible, and parallel over the tens of thousands of block partials)
+__global__ void __launch_bounds__(256) enc_slot_tree_kernel(int64_t nslots, int64_t stride,
+                                                            const float *part, float *grad)
+{
+    __shared__ float red[256];
+    const int k = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t q = threadIdx.x; q < nslots; q += 256) s += part[q * stride + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[k] += red[0];
+}
+
 // grad[k] += sum over the slots of part[slot][k], in slot order
 __global__ void enc_slot_reduce_kernel(int64_t width, int64_t nslots, int64_t stride,
                                        const float *part, float *grad)
@@ -386,8 +405,8 @@ extern "C" int32_t rom_encoder_backward(int32_t d, int32_t r, int64_t in_len, in
                                                           plane[cur], ws, y, Lout, nm,
                                                           grad + l * (ENC_K + 1), cpart);
         if (cpart)
-            enc_slot_reduce_kernel<<<1, 64, 0, st>>>(ENC_K + 1, (int64_t)gw.x * n, ENC_K + 1,
-                                                     cpart, grad + l * (ENC_K + 1));
+            enc_slot_tree_kernel<<<ENC_K + 1, 256, 0, st>>>((int64_t)gw.x * n, ENC_K + 1, cpart,
+                                                            grad + l * (ENC_K + 1));
         if (l > 0) {
             dim3 gd((unsigned)ceil_div(Lin, ENC_TB), (unsigned)n);
             enc_conv_bwd_data_kernel<<<gd, ENC_TB, 0, st>>>(plane[cur], ws, y, L.act_floats, Lin,

@@ -361,14 +361,22 @@ __global__ void __launch_bounds__(256) output_bias_kernel(TrainDims td, int64_t 
     if (threadIdx.x == 0) dbL[a] += red[0];
 }
 
-// db[u] += sum over the slots of part[slot][u], in slot order
-__global__ void slot_reduce_kernel(int W, int64_t nslots, const float *part, float *db)
+// db[u] += sum over the slots of part[slot][u]: one block per unit, thread t
+// sums slots t, t + 256, ... in order, then a fixed tree (reproducible)
+__global__ void __launch_bounds__(256) slot_reduce_kernel(int W, int64_t nslots,
+                                                          const float *part, float *db)
 {
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= W) return;
+    __shared__ float red[256];
+    const int u = blockIdx.x;
     float s = 0.0f;
-    for (int64_t k = 0; k < nslots; ++k) s += part[k * W + u];
-    db[u] += s;
+    for (int64_t k = threadIdx.x; k < nslots; k += 256) s += part[k * W + u];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[u] += red[0];
 }
 
 // adjoint of the pre-activations of a hidden layer:
@@ -865,8 +873,8 @@ extern "C" int32_t rom_train_backward(mr_trainer *t, const float *dg, const floa
             nslots = grid * rpp;
         }
         if (part)
-            slot_reduce_kernel<<<(unsigned)ceil_div(td.W, 256), 256, 0, st>>>(
-                td.W, nslots, part, dparams + t->ob[l]);
+            slot_reduce_kernel<<<(unsigned)td.W, 256, 0, st>>>(td.W, nslots, part,
+                                                               dparams + t->ob[l]);
         MR_LAUNCH_CHECK();
         const int Kin = (l == 0) ? td.K0 : td.W;
         const float *in = (l == 0) ? t->A0 : t->A[l - 1];
