@@ -144,6 +144,9 @@ def main():
     ap.add_argument("--batched-study-quadratures", default="lagrangian,eulerian")
     ap.add_argument("--rom-pareto-steps", type=int, default=30,
                     help="steps per point of the quadrature / samples / projection sweep (0: off)")
+    ap.add_argument("--decoder-profile", action="store_true",
+                    help="only run the reduced step's two decoder launches (positions of every "
+                         "particle; x, F, v at a quadrature-sized subset), for counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB ten times (the reference "
                          "kernel that scales the HBM byte counters)")
@@ -170,6 +173,9 @@ def main():
     dev = "cuda:0"
     s = scenes.scene_3d()
     P = s["P"]
+    if args.decoder_profile:
+        print(json.dumps(decoder_profile(B, scenes, s)), flush=True)
+        return
     st = scenes.initial_state(s)
     soa = lambda a: torch.tensor(np.ascontiguousarray(a.reshape(P, -1).T), device=dev)
     parts = B.Particles(soa(st["x"]), soa(st["v"]), soa(st["C"]), soa(st["F"]),
@@ -339,6 +345,52 @@ def measured_peaks(B):
     flop = blocks * 4 * iters * 8 * 16384
     mfma = flop / (e0.elapsed_time(e1) * 1e-3) / 1e12
     return {"hbm_copy_GBps": round(hbm, 1), "mfma_bf16_TFLOPs": round(mfma, 1)}
+
+
+def decoder_profile(B, scenes, s, reps=10, n_tan=435_200, r=16, width=128, n_hidden=5):
+    """The reduced step's two decoder launches alone (bf16, random weights),
+    each repeated `reps` times: the positions of every particle of the 3D
+    scene (one primal stream) and x, F and v (the primal and four tangent
+    streams) at a quadrature-sized subset of it.  Reports the time per launch
+    and the hidden layers' matrix-core FLOP, which the bf16 MFMA counters
+    (512 FLOP per MOPS unit) should reproduce."""
+    import torch
+    dev = "cuda:0"
+    X = s["X"]
+    P = s["P"]
+    Ws, bs = scenes.xavier_decoder(3, r, width, n_hidden, 11)
+    dec = B.Decoder(Ws, bs, X.min(0), X.max(0), np.zeros(3, np.float32),
+                    np.full(3, 1e-3, np.float32), B.OUT_DISPLACEMENT, B.PREC_BF16)
+    Xg = torch.tensor(np.ascontiguousarray(X.T), device=dev)
+    rng = np.random.default_rng(5)
+    z = torch.tensor(rng.uniform(-0.5, 0.5, (1, r)), device=dev)
+    vh = torch.tensor(rng.uniform(-0.5, 0.5, (1, r)), device=dev)
+    idx = torch.tensor(np.sort(rng.choice(P, n_tan, replace=False)).astype(np.int32), device=dev)
+    xo = torch.empty(1, 3, P, device=dev)
+    xt = torch.empty(1, 3, n_tan, device=dev)
+    Ft = torch.empty(1, 9, n_tan, device=dev)
+    vt = torch.empty(1, 3, n_tan, device=dev)
+    hidden_flop = 2 * (n_hidden - 1) * width * width
+    out = {"decoder": "%d x %d bf16, r = %d" % (width, n_hidden, r), "reps": reps}
+    for name, run, n, streams in (
+            ("positions_all", lambda: B.rom_decode(dec, Xg, z, xo), P, 1),
+            ("x_F_v_subset", lambda: B.rom_decode_jac(dec, Xg, z, idx=idx, vhat=vh, x=xt, F=Ft, v=vt),
+             n_tan, 5)):
+        run()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            run()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        flop = n * streams * hidden_flop
+        out[name] = {"points": n, "streams": streams, "ms": round(ms, 4),
+                     "hidden_mfma_flop": flop, "tflops": round(flop / (ms * 1e-3) / 1e12, 1)}
+    dec.close()
+    return out
 
 
 def fom_two_dimensional(B, scenes, steps=100, sort_every=10):

@@ -275,7 +275,7 @@ struct DecSmem {
 
 // c0 = W_z xhat + b0 and u = W_z vhat of instance b, the spatial columns of
 // W0 and the output weights into the block's fixed LDS
-template <int W>
+template <int W, bool WLS = true>
 __device__ __forceinline__ void load_block_vectors(const DecK &P, const double *xh,
                                                    const double *vh, float *c0, float *u,
                                                    float *w0x, float *wls)
@@ -294,7 +294,7 @@ __device__ __forceinline__ void load_block_vectors(const DecK &P, const double *
     for (int i = threadIdx.x; i < 3 * W; i += blockDim.x) {
         const int row = i / 3, a = i % 3;
         w0x[i] = a < P.d ? P.W0[(size_t)row * in0 + a] : 0.0f;
-        wls[i] = i / W < P.d ? P.WL[i] : 0.0f;
+        if (WLS) wls[i] = i / W < P.d ? P.WL[i] : 0.0f;
     }
 }
 
@@ -649,10 +649,14 @@ __global__ void __launch_bounds__(64 * (W / 16)) decoder_rows_kernel(DecK P, Str
 // decoder_kernel, but the hidden layers keep their activations in registers.
 // Under the panel unit order a lane's activated, converted accumulators of
 // row tiles 2m and 2m + 1 are exactly its B operand of k-step m for the next
-// layer, so only the staged weights (A operands) come from LDS.  The last
-// hidden layer's activations pass through a small per-wave LDS panel, one
-// column tile at a time, for the fp32 output layer.  Every value is formed
-// by the same arithmetic in the same order as in the panel shapes.
+// layer, so only the staged weights (A operands) come from LDS.  The
+// output layer runs on the matrix cores too, from those registers: its fp32
+// weights are split into bf16 high and low parts (hi = bf16(w), lo =
+// bf16(w - hi), rows 0..d-1 of two A operands), the products with the bf16
+// activations are exact in fp32 and the MFMA sums them in fp32, so the layer
+// keeps fp32 accuracy (the split leaves an error below 2^-16 of each weight)
+// and only its summation order differs from the panel shapes'.  Every hidden
+// activation is formed by the same arithmetic in the same order as there.
 typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
 
 template <int W, int S, int NP, int WPB>
@@ -676,10 +680,19 @@ __global__ void __launch_bounds__(64 * WPB) decoder_reg_kernel(DecK P, StreamSpe
     float *w0x = u + W;
     float *wls = w0x + 3 * W;
     T *wsh = reinterpret_cast<T *>(smem + SM::vec);
-    T *panel = reinterpret_cast<T *>(smem + SM::fixed) + (size_t)wave * 16 * LD;
     const double *xh = io.xhat + (size_t)b * P.r;
     const double *vh = io.vhat ? io.vhat + (size_t)b * P.r : nullptr;
-    load_block_vectors<W>(P, xh, vh, c0, u, w0x, wls);
+    load_block_vectors<W, false>(P, xh, vh, c0, u, w0x, wls);
+    // the output weights' bf16 high and low parts in panel order, [part][a][p],
+    // in the slot of the fp32 copy (3 W floats = 2 x 3 W bf16)
+    T *wob = reinterpret_cast<T *>(wls);
+    for (int i = threadIdx.x; i < 3 * W; i += 64 * WPB) {
+        const int a = i / W;
+        const float w = a < P.d ? P.WL[(size_t)a * W + pos_unit(i % W)] : 0.0f;
+        const uint16_t hi = bf16_bits(w);
+        wob[i] = hi;
+        wob[3 * W + i] = bf16_bits(w - __uint_as_float((uint32_t)hi << 16));
+    }
     __syncthreads();
 
     const int64_t wbase = ((int64_t)blockIdx.x * WPB + wave) * (NP * 16);
@@ -790,34 +803,29 @@ __global__ void __launch_bounds__(64 * WPB) decoder_reg_kernel(DecK P, StreamSpe
             for (int ct = 0; ct < NCT; ++ct) Bop[ks][ct] = Bn[ks][ct];
     }
 
-    // ---- output layer (fp32), one column tile at a time through the panel
+    // ---- output layer on matrix cores: lane (j, g = 0) ends with outputs
+    // a = 0..3 of point j of the column tile (rows 3 and up of A are zero)
     const int D = P.d;
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) {
+        f32x4 y = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks)
-            *reinterpret_cast<bf16x8v *>(panel + j * LD + ks * 32 + 8 * g) = Bop[ks][ct];
-        // the panel is this wave's own and the LDS pipeline keeps a wave's
-        // accesses in program order; the compiler barriers keep the compiler
-        // from moving the reads above these stores (or the next column
-        // tile's stores above these reads): their pointer types differ
-        asm volatile("" ::: "memory");
-        const int pt = ct / S, st = ct % S;
-        for (int it = lane; it < 16 * D; it += 64) {
-            const int col = it / D, a = it % D;
-            const int64_t s = wbase + pt * 16 + col;
-            if (s >= n_b) continue;
-            const T *h = panel + (size_t)col * LD;
-            const float *wl = wls + a * W;
-            float y = 0.0f;
-            for (int i = 0; i < W; i += 4) {
-                const f32x4 h4 = E::load4(h + i);
-                const int k = E::unit(i);
-                y += wl[k] * h4[0] + wl[k + 1] * h4[1] + wl[k + 2] * h4[2] + wl[k + 3] * h4[3];
+        for (int ks = 0; ks < NKS; ++ks) {
+            bf16x8v ahi = {}, alo = {};
+            if (j < 3) {
+                ahi = *reinterpret_cast<const bf16x8v *>(wob + j * W + ks * 32 + 8 * g);
+                alo = *reinterpret_cast<const bf16x8v *>(wob + 3 * W + j * W + ks * 32 + 8 * g);
             }
-            emit_output(P, ss, io, b, s, st, a, y);
+            y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, Bop[ks][ct], y, 0, 0, 0);
+            y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, Bop[ks][ct], y, 0, 0, 0);
         }
-        asm volatile("" ::: "memory");
+        const int pt = ct / S, st = ct % S;
+        const int64_t s = wbase + pt * 16 + j;
+        if (g == 0 && s < n_b) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (a < D) emit_output(P, ss, io, b, s, st, a, y[a]);
+        }
     }
 }
 
@@ -880,8 +888,7 @@ template <int W, int S, int NP>
 int32_t launch_reg(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStream_t st)
 {
     constexpr int WPB = MR_DEC_REG_WPB;
-    constexpr size_t lds = DecSmem<uint16_t, W>::fixed +
-                           (size_t)WPB * 16 * (W + Elem<uint16_t>::PAD) * sizeof(uint16_t);
+    constexpr size_t lds = DecSmem<uint16_t, W>::fixed;
     static_assert(lds <= 160 * 1024, "decoder block does not fit the LDS of a compute unit");
     dim3 grid((unsigned)ceil_div(io.n, (int64_t)WPB * NP * 16), (unsigned)io.B, z_blocks(ss, P.r));
     auto kern = decoder_reg_kernel<W, S, NP, WPB>;
