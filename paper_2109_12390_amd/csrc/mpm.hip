@@ -871,12 +871,12 @@ __global__ void __launch_bounds__(64 * MR_TILE_WPB, MR_TILE_MIN_WAVES) tile_scat
 // no spills: 117 vs 136 us on the 2.1M-particle scene; with spilled
 // registers the scratch traffic also slowed the gather that follows).
 // After the slots the lane adds its register sums to the region once;
-// particles that left their
-// home cell since the sort are deferred (the first DEFER_CAP in LDS, the
-// rest in the tile's own range of a spill array) and scattered into the
-// region afterwards in claim rounds (those beyond the region with global
-// atomics); the region is flushed with one atomic per non-zero node
-// channel.  MODEL is the constitutive law (compiled separately, so that each
+// particles that left their home cell since the sort, and those of a cell
+// beyond the tile's slot cap (its mean count per occupied cell, rounded
+// up), are deferred (the first DEFER_CAP in LDS, the rest in the tile's own
+// range of a spill array) and scattered into the region afterwards in claim
+// rounds (those beyond the region with global atomics); the region is
+// flushed with one atomic per non-zero node channel.  MODEL is the constitutive law (compiled separately, so that each
 // law's registers are allocated on their own); PER_PARTICLE selects
 // per-particle masses and volumes.  Cl is C, or any 9-plane array when the
 // affine term is off (then scaled by 0), so the loads need no branch.
@@ -908,6 +908,18 @@ __global__ void __launch_bounds__(64, 3) cell_sum_p2g_kernel(
     const int h0 = lane % CT::TS + 1, h1 = (lane / CT::TS) % CT::TS + 1, h2 = lane / 16 + 1;
     const int cnt = counts[t * Tiling<3>::CELLS + lane];
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // slots summed in registers: the tile's mean count per occupied cell,
+    // rounded up, plus a slack; a cell's particles beyond it take the
+    // deferred way, so a few crowded cells do not keep the whole wave in
+    // slots where most lanes have nothing left.  The slack trades idle
+    // lanes in the last slots against the dearer claim rounds, and the
+    // stress sets the balance (2.1M-particle scene, 1,000 steps): with the
+    // Neo-Hookean law slack 0 / 1 / 2 gave 118.6 / 116.7 / 118.0 us against
+    // 120.9 us with no cap; with the fixed-corotated law's eigen-solve per
+    // particle 178.2 / 182.1 / 188.8 against 196.9 us.
+    constexpr int SLACK = MODEL == MR_FIXED_COROTATED ? 0 : 1;
+    const int occ = __popcll(__ballot(cnt > 0));    // >= 1: c1 > c0
+    const int cap = (int)((c1 - c0 + occ - 1) / occ) + SLACK;
     const float cscale = apic ? 1.0f : 0.0f;
     const int nb = h0 + CT::SY * h1 + CT::SZ * h2;  // the home stencil's base node
     float4 *top = acc + nb + 2 * CT::SZ;            // its top layer
@@ -922,7 +934,7 @@ __global__ void __launch_bounds__(64, 3) cell_sum_p2g_kernel(
     int64_t base = c0;
     uint64_t mask = __ballot(0 < cnt);
     for (int k = 0; mask != 0; ++k) {
-        const bool act = k < cnt;
+        const bool act = k < cnt && k < cap;
         const int64_t p = base + __popcll(mask & below);
         float xp[3], Fp[9];
         float mp = m_u, Vp = V0_u;
@@ -938,7 +950,7 @@ __global__ void __launch_bounds__(64, 3) cell_sum_p2g_kernel(
         }
         base += __popcll(mask);
         const uint64_t mask1 = __ballot(k + 1 < cnt);
-        bool drifted = false;
+        bool drifted = k < cnt && k >= cap;             // beyond the cap
         if (act) {
             float w[3][3], dw[3][3], f[3];
             int b[3];
@@ -1012,9 +1024,9 @@ __global__ void __launch_bounds__(64, 3) cell_sum_p2g_kernel(
                 drifted = true;
             }
         }
-        // particles that left their home cell wait for the claim rounds
-        // after the slots (each is deferred once, so a tile never defers
-        // more than its c1 - c0 particles)
+        // particles that left their home cell (or lie beyond the cap) wait
+        // for the claim rounds after the slots (each is deferred once, so a
+        // tile never defers more than its c1 - c0 particles)
         const uint64_t dm = __ballot(drifted);
         if (dm != 0) {
             if (drifted) {
@@ -1075,9 +1087,9 @@ __global__ void __launch_bounds__(64, 3) cell_sum_p2g_kernel(
                     Fq[q] = F[q * n + p];
                     Cq[q] = Cl[q * n + p];
                 }
-                // both succeeded when the particle was deferred
-                make_stencil<3>(g, xn, sn);
-                kirchhoff<3>(MODEL, mu, la, Fq, tau);
+                // a drifted particle passed both checks in its slot; one
+                // beyond the cap meets them here first
+                const bool ok = make_stencil<3>(g, xn, sn) && kirchhoff<3>(MODEL, mu, la, Fq, tau);
                 const float mp = PER_PARTICLE ? m[p] : m_u;
                 const float sc = dt * (PER_PARTICLE ? V0[p] : V0_u);
                 pl.m = mp;
@@ -1089,7 +1101,9 @@ __global__ void __launch_bounds__(64, 3) cell_sum_p2g_kernel(
                     pl.S[q] = sc * tau[q];
                 }
                 const int m0 = sn.base[0] - r0, m1 = sn.base[1] - r1, m2 = sn.base[2] - r2;
-                if (m0 >= 0 && m0 < CT::RC && m1 >= 0 && m1 < CT::RC && m2 >= 0 && m2 < CT::RC) {
+                if (!ok) {
+                    raise_flag(flag, MR_FLAG_DOMAIN);
+                } else if (m0 >= 0 && m0 < CT::RC && m1 >= 0 && m1 < CT::RC && m2 >= 0 && m2 < CT::RC) {
                     key = m0 + CT::RC * (m1 + CT::RC * m2);
                     nbd = m0 + CT::SY * m1 + CT::SZ * m2;
                     pending = true;
