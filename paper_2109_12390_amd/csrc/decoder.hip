@@ -698,51 +698,102 @@ __global__ void __launch_bounds__(64 * WPB) decoder_reg_kernel(DecK P, StreamSpe
     const int64_t wbase = ((int64_t)blockIdx.x * WPB + wave) * (NP * 16);
     const int j = lane & 15;
     const int g = lane >> 4;
-    const int in0 = P.d + P.r;
     bf16x8v Bop[NKS][NCT];
     bf16x4 lo[NCT];
 
-    // ---- first layer (fp32 vector arithmetic, as in decoder_kernel)
+    // ---- first layer (fp32 vector arithmetic, the same products as in
+    // decoder_kernel)
+    if constexpr (S == 1) {
+        // the primal alone: straight-line code, the row tiles outer so that
+        // one tile's first-layer weights serve both point tiles, and all
+        // three input terms (w0x and Xn are zero beyond d).  (With tangent
+        // streams this form leaves the B operands where the hidden loop's
+        // register assignment needs copies, and spills at five streams.)
+        float Xn[NP][3];
 #pragma unroll
-    for (int pt = 0; pt < NP; ++pt) {
-        const int64_t s = wbase + pt * 16 + j;
-        float Xn[3] = {0.0f, 0.0f, 0.0f};
-        if (s < n_b) {
-            int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * io.n : 0) + s] : s;
-            for (int a = 0; a < P.d; ++a) Xn[a] = io.X[(int64_t)b * io.x_stride + a * io.n_ref + row] * P.scale[a] + P.shift[a];
+        for (int pt = 0; pt < NP; ++pt) {
+            const int64_t s = wbase + pt * 16 + j;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) Xn[pt][a] = 0.0f;
+            if (s < n_b) {
+                int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * io.n : 0) + s] : s;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    if (a < P.d) Xn[pt][a] = io.X[(int64_t)b * io.x_stride + a * io.n_ref + row] * P.scale[a] + P.shift[a];
+            }
         }
 #pragma unroll
         for (int m = 0; m < NRT; ++m) {
             const int i0 = 16 * m + 4 * g;
-            f32x4 h4, e4;
+            float cw[4], ww[4][3];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float *w0 = w0x + (i0 + q) * 3;
-                float z = c0[i0 + q];
-                for (int a = 0; a < P.d; ++a) z += w0[a] * Xn[a];
-                float h, e;
-                E::act(z, h, e);
-                h4[q] = h;
-                e4[q] = e;
+                cw[q] = c0[i0 + q];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) ww[q][a] = w0x[(i0 + q) * 3 + a];
             }
 #pragma unroll
-            for (int st = 0; st < S; ++st) {
-                int kind, arg;
-    stream_of(ss, P.r, st, kind, arg);
-                f32x4 val;
+            for (int pt = 0; pt < NP; ++pt) {
+                f32x4 h4;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    if (kind == SK_PRIMAL) val[q] = h4[q];
-                    else if (kind == SK_SPATIAL) val[q] = e4[q] * w0x[(i0 + q) * 3 + arg] * P.scale[arg];
-                    else if (kind == SK_VELOCITY) val[q] = e4[q] * u[i0 + q];
-                    else if (kind == SK_LATENT) val[q] = e4[q] * P.W0[(size_t)(i0 + q) * in0 + P.d + arg];
-                    else val[q] = 0.0f;
+                    float z = cw[q];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) z += ww[q][a] * Xn[pt][a];
+                    float h, e;
+                    E::act(z, h, e);
+                    h4[q] = h;
                 }
-                const bf16x4 v4 = __builtin_convertvector(val, bf16x4);
+                const bf16x4 v4 = __builtin_convertvector(h4, bf16x4);
                 if (m & 1)
-                    Bop[m >> 1][pt * S + st] = __builtin_shufflevector(lo[pt * S + st], v4, 0, 1, 2, 3, 4, 5, 6, 7);
+                    Bop[m >> 1][pt] = __builtin_shufflevector(lo[pt], v4, 0, 1, 2, 3, 4, 5, 6, 7);
                 else
-                    lo[pt * S + st] = v4;
+                    lo[pt] = v4;
+            }
+        }
+    } else {
+        const int in0 = P.d + P.r;
+#pragma unroll
+        for (int pt = 0; pt < NP; ++pt) {
+            const int64_t s = wbase + pt * 16 + j;
+            float Xn[3] = {0.0f, 0.0f, 0.0f};
+            if (s < n_b) {
+                int64_t row = io.idx ? (int64_t)io.idx[(io.idx_per_inst ? (int64_t)(b / io.idx_div) * io.n : 0) + s] : s;
+                for (int a = 0; a < P.d; ++a) Xn[a] = io.X[(int64_t)b * io.x_stride + a * io.n_ref + row] * P.scale[a] + P.shift[a];
+            }
+#pragma unroll
+            for (int m = 0; m < NRT; ++m) {
+                const int i0 = 16 * m + 4 * g;
+                f32x4 h4, e4;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float *w0 = w0x + (i0 + q) * 3;
+                    float z = c0[i0 + q];
+                    for (int a = 0; a < P.d; ++a) z += w0[a] * Xn[a];
+                    float h, e;
+                    E::act(z, h, e);
+                    h4[q] = h;
+                    e4[q] = e;
+                }
+#pragma unroll
+                for (int st = 0; st < S; ++st) {
+                    int kind, arg;
+                    stream_of(ss, P.r, st, kind, arg);
+                    f32x4 val;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (kind == SK_PRIMAL) val[q] = h4[q];
+                        else if (kind == SK_SPATIAL) val[q] = e4[q] * w0x[(i0 + q) * 3 + arg] * P.scale[arg];
+                        else if (kind == SK_VELOCITY) val[q] = e4[q] * u[i0 + q];
+                        else if (kind == SK_LATENT) val[q] = e4[q] * P.W0[(size_t)(i0 + q) * in0 + P.d + arg];
+                        else val[q] = 0.0f;
+                    }
+                    const bf16x4 v4 = __builtin_convertvector(val, bf16x4);
+                    if (m & 1)
+                        Bop[m >> 1][pt * S + st] = __builtin_shufflevector(lo[pt * S + st], v4, 0, 1, 2, 3, 4, 5, 6, 7);
+                    else
+                        lo[pt * S + st] = v4;
+                }
             }
         }
     }
@@ -891,6 +942,8 @@ int32_t launch_reg(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStre
     constexpr size_t lds = DecSmem<uint16_t, W>::fixed;
     static_assert(lds <= 160 * 1024, "decoder block does not fit the LDS of a compute unit");
     dim3 grid((unsigned)ceil_div(io.n, (int64_t)WPB * NP * 16), (unsigned)io.B, z_blocks(ss, P.r));
+    // the primal-only first layer takes stream 0 to be the primal
+    if (ss.kind[0] != SK_PRIMAL) return MR_EINVAL;
     auto kern = decoder_reg_kernel<W, S, NP, WPB>;
     static bool attr_set = false;
     if (!attr_set) {
