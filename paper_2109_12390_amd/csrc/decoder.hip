@@ -752,7 +752,22 @@ __global__ void __launch_bounds__(64 * WPB) decoder_reg_kernel(DecK P, StreamSpe
             }
         }
     } else {
-        const int in0 = P.d + P.r;
+        // tangent streams: each scales ELU' by a column of one LDS table
+        // (w0x for a spatial tangent, u for the velocity; a zero stream by
+        // 0), chosen once here instead of per element (the launcher admits
+        // only these kinds).  The products are those of the panel shapes:
+        // (e w0x) scale, (e u) 1.
+        const float *cft[S];
+        int cfk[S];
+        float cfs[S];
+#pragma unroll
+        for (int st = 1; st < S; ++st) {
+            int kind, arg;
+            stream_of(ss, P.r, st, kind, arg);
+            cft[st] = kind == SK_SPATIAL ? w0x + arg : u;
+            cfk[st] = kind == SK_SPATIAL ? 3 : 1;
+            cfs[st] = kind == SK_SPATIAL ? P.scale[arg] : (kind == SK_VELOCITY ? 1.0f : 0.0f);
+        }
 #pragma unroll
         for (int pt = 0; pt < NP; ++pt) {
             const int64_t s = wbase + pt * 16 + j;
@@ -777,17 +792,10 @@ __global__ void __launch_bounds__(64 * WPB) decoder_reg_kernel(DecK P, StreamSpe
                 }
 #pragma unroll
                 for (int st = 0; st < S; ++st) {
-                    int kind, arg;
-                    stream_of(ss, P.r, st, kind, arg);
                     f32x4 val;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        if (kind == SK_PRIMAL) val[q] = h4[q];
-                        else if (kind == SK_SPATIAL) val[q] = e4[q] * w0x[(i0 + q) * 3 + arg] * P.scale[arg];
-                        else if (kind == SK_VELOCITY) val[q] = e4[q] * u[i0 + q];
-                        else if (kind == SK_LATENT) val[q] = e4[q] * P.W0[(size_t)(i0 + q) * in0 + P.d + arg];
-                        else val[q] = 0.0f;
-                    }
+                    for (int q = 0; q < 4; ++q)
+                        val[q] = st == 0 ? h4[q] : e4[q] * cft[st][(i0 + q) * cfk[st]] * cfs[st];
                     const bf16x4 v4 = __builtin_convertvector(val, bf16x4);
                     if (m & 1)
                         Bop[m >> 1][pt * S + st] = __builtin_shufflevector(lo[pt * S + st], v4, 0, 1, 2, 3, 4, 5, 6, 7);
@@ -942,8 +950,12 @@ int32_t launch_reg(const DecK &P, const StreamSpec &ss, const DecIO &io, hipStre
     constexpr size_t lds = DecSmem<uint16_t, W>::fixed;
     static_assert(lds <= 160 * 1024, "decoder block does not fit the LDS of a compute unit");
     dim3 grid((unsigned)ceil_div(io.n, (int64_t)WPB * NP * 16), (unsigned)io.B, z_blocks(ss, P.r));
-    // the primal-only first layer takes stream 0 to be the primal
+    // the first layer takes stream 0 to be the primal and the others to be
+    // spatial, velocity or zero streams
     if (ss.kind[0] != SK_PRIMAL) return MR_EINVAL;
+    for (int st = 1; st < S; ++st)
+        if (ss.kind[st] != SK_SPATIAL && ss.kind[st] != SK_VELOCITY && ss.kind[st] != SK_ZERO)
+            return MR_EINVAL;
     auto kern = decoder_reg_kernel<W, S, NP, WPB>;
     static bool attr_set = false;
     if (!attr_set) {
