@@ -107,6 +107,41 @@ def test_every_shape_agrees(gpu, width, nh):
     dec.close()
 
 
+def test_every_shape_agrees_in_two_dimensions(gpu):
+    """The same agreement for a planar (d = 2) bf16 decoder, where the
+    first layer's third input term and the third spatial tangent are zero
+    (the register-resident shape sums all three terms and runs a zero
+    stream)."""
+    rng = np.random.default_rng(12)
+    n, r = 20000 + 37, 8
+    Ws, bs = scenes.random_decoder(2, r, 128, 5, 5, scale=1.0, bias_scale=0.1)
+    dec = B.Decoder(Ws, bs, np.zeros(2, np.float32), np.ones(2, np.float32),
+                    np.zeros(2, np.float32), np.full(2, 0.05, np.float32), B.OUT_DISPLACEMENT,
+                    B.PREC_BF16)
+    X = torch.tensor(rng.uniform(0, 1, size=(2, n)).astype(np.float32), device=dev)
+    z = torch.tensor(0.3 * rng.standard_normal((1, r)), device=dev)
+    vh = torch.tensor(0.3 * rng.standard_normal((1, r)), device=dev)
+    outs = {}
+    for shape in (0, 1, 2, 3, 4):
+        dec.set_shape(1, 1, n, shape)
+        if shape in (0, 3, 4):
+            dec.set_shape(5, 1, n, shape)
+        xo = torch.zeros(1, 2, n, device=dev)
+        B.rom_decode(dec, X, z, xo)
+        o = {"x_only": xo}
+        if shape in (0, 3, 4):
+            o.update(x=torch.zeros(1, 2, n, device=dev), F=torch.zeros(1, 4, n, device=dev),
+                     v=torch.zeros(1, 2, n, device=dev))
+            B.rom_decode_jac(dec, X, z, vhat=vh, x=o["x"], F=o["F"], v=o["v"])
+        outs[shape] = o
+    for shape, o in outs.items():
+        for k, t in o.items():
+            ref = outs[0][k]
+            e = float((t - ref).abs().max() / (ref.abs().max() + 1e-30))
+            assert e < 1e-5, (shape, k, e)
+    dec.close()
+
+
 def test_set_shape_rejects_unavailable_shapes(gpu):
     dec32 = _dec(B.PREC_FP32, width=32, nh=2, r=4)
     dec16 = _dec(B.PREC_BF16, width=32, nh=2, r=4)
